@@ -1,0 +1,331 @@
+"""Pins of the CPU oracle against what the paper and arithmetic fix (no GPU).
+
+Each pin is chosen so that a plausible slip in ``oracle.c`` (digit order, most-
+vs least-significant base first, N vs UNK, a dropped tail token, a wrong pad
+side, a BPE round that merges the wrong occurrences) fails at least one test.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rows(strings):
+    data = np.frombuffer("".join(strings).encode("latin-1"), dtype=np.uint8).copy()
+    offs = np.zeros(len(strings) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum([len(s) for s in strings])
+    return data, offs
+
+
+def _golden(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            rows.append(line.rstrip("\n").split("\t"))
+    return rows
+
+
+# ---------------------------------------------------------------- LUT256 / SINGLE
+
+def test_fallback_lut_selftest_golden():
+    (text, expected), = _golden("fallback_lut_selftest.txt")
+    data, offs = _rows([text])
+    ids, out_off = oracle.encode(oracle.LUT256, data, offs, lut=oracle.fallback_lut())
+    assert ids.tolist() == [int(x) for x in expected.split()]
+    assert out_off.tolist() == [0, 10]
+
+
+def test_fallback_lut_other_bytes_zero():
+    data = np.arange(256, dtype=np.uint8)
+    ids, _ = oracle.encode(oracle.LUT256, data, np.array([0, 256]), lut=oracle.fallback_lut())
+    dna = {ord(c): v for c, v in zip("ACGTNacgtn", [1, 2, 3, 4, 0] * 2)}
+    assert ids.tolist() == [dna.get(b, 0) for b in range(256)]
+
+
+def test_single_selftest_and_all_bytes():
+    data, offs = _rows(["ACGTNacgtn"])
+    ids, _ = oracle.encode(oracle.SINGLE, data, offs)
+    assert ids.tolist() == [5, 6, 7, 8, 9, 5, 6, 7, 8, 9]
+    all_bytes = np.arange(256, dtype=np.uint8)
+    ids, _ = oracle.encode(oracle.SINGLE, all_bytes, np.array([0, 256]))
+    want = {ord(c): 5 + i for i, c in enumerate("ACGT")}
+    want.update({ord(c): 5 + i for i, c in enumerate("acgt")})
+    want[ord("N")] = want[ord("n")] = 9
+    assert ids.tolist() == [want.get(b, 1) for b in range(256)]
+
+
+def test_single_specials_and_lengths():
+    data, offs = _rows(["", "A", "acgtn#"])
+    ids, out_off = oracle.encode(oracle.SINGLE, data, offs, add_cls_sep=True)
+    assert ids.tolist() == [2, 3, 2, 5, 3, 2, 5, 6, 7, 8, 9, 1, 3]
+    assert out_off.tolist() == [0, 2, 5, 13]
+    ids, out_off = oracle.encode(oracle.SINGLE, data, offs, add_cls_sep=False)
+    assert out_off.tolist() == [0, 0, 1, 7]
+
+
+def test_lut256_specials_use_given_ids():
+    data, offs = _rows(["AC"])
+    ids, _ = oracle.encode(oracle.LUT256, data, offs, lut=oracle.fallback_lut(), add_cls_sep=True,
+                           cls_id=101, sep_id=102)
+    assert ids.tolist() == [101, 1, 2, 102]
+
+
+# ---------------------------------------------------------------- KMER
+
+def test_kmer_closed_forms_golden():
+    for k, text, expected in _golden("kmer_closed_forms.txt"):
+        data, offs = _rows([text])
+        ids, _ = oracle.encode(oracle.KMER, data, offs, k=int(k))
+        assert ids.tolist() == [int(x) for x in expected.split()], (k, text)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
+def test_kmer_every_kmer_against_base4(k):
+    strings = ["".join(p) for p in itertools.product("ACGT", repeat=k)]
+    data, offs = _rows(strings)
+    ids, out_off = oracle.encode(oracle.KMER, data, offs, k=k)
+    assert np.all(np.diff(out_off) == 1)
+    assert ids.tolist() == [brute.kmer_id(s) for s in strings]
+    # ids are a bijection onto [5, 5 + 4^k)
+    assert sorted(ids.tolist()) == list(range(5, 5 + 4 ** k))
+    lower = [s.lower() for s in strings]
+    ids_l, _ = oracle.encode(oracle.KMER, *_rows(lower), k=k)
+    assert np.array_equal(ids, ids_l)
+
+
+def test_kmer_long_k_extremes():
+    for k in (7, 11, 15):
+        for ch, val in (("A", 0), ("T", 4 ** k - 1)):
+            ids, _ = oracle.encode(oracle.KMER, *_rows([ch * k]), k=k)
+            assert ids.tolist() == [5 + val]
+        s = ("ACGT" * 4)[:k]
+        ids, _ = oracle.encode(oracle.KMER, *_rows([s]), k=k)
+        assert ids.tolist() == [brute.kmer_id(s)]
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_kmer_lengths_closed_form(k):
+    rng = np.random.default_rng(k)
+    lens = list(range(0, 70)) + [int(x) for x in rng.integers(0, 5000, 20)]
+    strings = ["".join(rng.choice(list("ACGTN"), size=L)) for L in lens]
+    data, offs = _rows(strings)
+    for cls in (False, True):
+        ids, out_off = oracle.encode(oracle.KMER, data, offs, k=k, add_cls_sep=cls)
+        want = [math.ceil(L / k) + 2 * cls for L in lens]
+        assert np.diff(out_off).tolist() == want
+        for i, L in enumerate(lens):
+            row = ids[out_off[i]:out_off[i + 1]]
+            if cls:
+                assert row[0] == 2 and row[-1] == 3
+                row = row[1:-1]
+            if L % k:
+                assert row[-1] == 1  # short final frame
+
+
+def test_kmer_benchmark_shapes():
+    # 8,192-base rows with CLS/SEP: k = 3, 4, 5, 6 -> 2733, 2050, 1641, 1368 tokens
+    for k, want in ((3, 2733), (4, 2050), (5, 1641), (6, 1368)):
+        _, out_off = oracle.encode(oracle.KMER, np.full(8192, ord("A"), np.uint8), np.array([0, 8192]),
+                                   k=k, add_cls_sep=True)
+        assert out_off[1] == want
+    # 16,384-base row, 6-mers: 2,731 tokens, the last a short frame -> UNK
+    ids, out_off = oracle.encode(oracle.KMER, np.full(16384, ord("C"), np.uint8), np.array([0, 16384]), k=6)
+    assert out_off[1] == 2731 and ids[-1] == 1 and ids[0] == brute.kmer_id("CCCCCC")
+
+
+def test_kmer_frames_not_reset_by_n():
+    ids, _ = oracle.encode(oracle.KMER, *_rows(["ACGNACGTACGT"]), k=6)
+    assert ids.tolist() == [1, brute.kmer_id("GTACGT")]
+
+
+def test_kmer_matches_bruteforce_on_random_rows():
+    rng = np.random.default_rng(7)
+    alphabet = list("ACGTacgtNn#x")
+    for k in (2, 3, 5, 6):
+        strings = ["".join(rng.choice(alphabet, size=int(L), p=[.11] * 8 + [.04, .04, .02, .02]))
+                   for L in rng.integers(0, 200, 40)]
+        ids, out_off = oracle.encode(oracle.KMER, *_rows(strings), k=k)
+        for i, s in enumerate(strings):
+            want = []
+            for j in range(0, len(s), k):
+                fr = s[j:j + k]
+                ok = len(fr) == k and all(c in "ACGTacgt" for c in fr)
+                want.append(brute.kmer_id(fr) if ok else 1)
+            assert ids[out_off[i]:out_off[i + 1]].tolist() == want
+
+
+# ---------------------------------------------------------------- padding
+
+def test_padding_invariants_and_sides():
+    rng = np.random.default_rng(3)
+    strings = ["".join(rng.choice(list("ACGTN"), size=int(L))) for L in rng.integers(0, 60, 30)]
+    data, offs = _rows(strings)
+    ids, out_off = oracle.encode(oracle.KMER, data, offs, k=3, add_cls_sep=True)
+    lens = np.diff(out_off)
+    W = int(lens.max()) + 5
+    r_ids, r_mask = oracle.pad(ids, out_off, W, oracle.RIGHT)
+    l_ids, l_mask = oracle.pad(ids, out_off, W, oracle.LEFT)
+    assert r_mask.sum() == lens.sum() == l_mask.sum()
+    assert np.all(r_ids[r_mask == 0] == 0) and np.all(l_ids[l_mask == 0] == 0)
+    for i, L in enumerate(lens):
+        assert r_mask[i].tolist() == [1] * L + [0] * (W - L)
+        assert np.array_equal(np.roll(r_ids[i], W - L), l_ids[i])
+        assert r_ids[i, :L].tolist() == ids[out_off[i]:out_off[i + 1]].tolist()
+    with pytest.raises(ValueError):
+        oracle.pad(ids, out_off, int(lens.max()) - 1)
+
+
+# ---------------------------------------------------------------- decode
+
+def test_decode_roundtrip_single_kmer():
+    rng = np.random.default_rng(11)
+    strings = ["".join(rng.choice(list("ACGT"), size=int(L))) for L in rng.integers(0, 90, 25)]
+    data, offs = _rows(strings)
+    ids, out_off = oracle.encode(oracle.SINGLE, data, offs, add_cls_sep=True)
+    dec, dec_off = oracle.decode(oracle.SINGLE, ids, out_off)
+    assert np.array_equal(dec, data) and np.array_equal(dec_off, offs)
+    for k in (2, 3, 6):
+        strings_k = [s[:len(s) - len(s) % k] for s in strings]
+        data_k, offs_k = _rows(strings_k)
+        ids, out_off = oracle.encode(oracle.KMER, data_k, offs_k, k=k, add_cls_sep=True)
+        dec, dec_off = oracle.decode(oracle.KMER, ids, out_off, k=k)
+        assert np.array_equal(dec, data_k) and np.array_equal(dec_off, offs_k)
+
+
+def test_decode_unk_width_and_specials():
+    ids = np.array([2, 1, 9, 3, 0, 4, 999], dtype=np.int32)
+    dec, _ = oracle.decode(oracle.SINGLE, ids, np.array([0, 7]))
+    assert bytes(dec) == b"NNN"
+    dec, _ = oracle.decode(oracle.KMER, np.array([1, 5, 4100], np.int32), np.array([0, 3]), k=6)
+    assert bytes(dec) == b"NNNNNN" + b"AAAAAA" + b"TTTTTT"
+
+
+# ---------------------------------------------------------------- BPE
+
+COUNTER_EXAMPLE = [(5, 6), (10, 7), (7, 8)]  # (A,C)->AC, (AC,G)->ACG, (G,T)->GT
+
+
+def _tables():
+    rng = np.random.default_rng(5)
+    corp1 = "".join(rng.choice(list("ACGT"), size=3000, p=[.4, .1, .1, .4]))
+    corp2 = "".join(rng.choice(list("ACGT"), size=3000))
+    t1, _ = brute.bpe_train_recount(corp1, 40)
+    t2, _ = brute.bpe_train_recount(corp2, 25)
+    return [COUNTER_EXAMPLE, [(5, 5), (10, 10), (10, 5), (11, 11)], t1, t2]
+
+
+def test_bpe_counterexample():
+    ids, _ = oracle.encode(oracle.BPE, *_rows(["ACGT"]), merges=COUNTER_EXAMPLE)
+    assert ids.tolist() == [11, 8]  # [ACG, T], not [AC, GT]
+    assert brute.bpe_encode_text("ACGT", COUNTER_EXAMPLE) == [11, 8]
+
+
+@pytest.mark.parametrize("ti", range(4))
+def test_bpe_exhaustive_short_strings(ti):
+    table = _tables()[ti]
+    assert oracle.bpe_check(table) == 0
+    strings = ["".join(p) for L in range(1, 8) for p in itertools.product("ACGT", repeat=L)]
+    ids, out_off = oracle.encode(oracle.BPE, *_rows(strings), merges=table)
+    for i, s in enumerate(strings):
+        assert ids[out_off[i]:out_off[i + 1]].tolist() == brute.bpe_encode_text(s, table), s
+
+
+def test_bpe_random_rows_with_barriers():
+    rng = np.random.default_rng(9)
+    tables = _tables()
+    strings = ["".join(rng.choice(list("ACGTacgtNn#"), size=int(L), p=[.12] * 8 + [.02, .02, .0]
+                                  if L % 2 else [.115] * 8 + [.03, .03, .02]))
+               for L in rng.integers(0, 300, 60)]
+    for table in tables:
+        ids, out_off = oracle.encode(oracle.BPE, *_rows(strings), merges=table, add_cls_sep=True)
+        for i, s in enumerate(strings):
+            assert ids[out_off[i]:out_off[i + 1]].tolist() == [2] + brute.bpe_encode_text(s, table) + [3]
+
+
+def test_bpe_zero_merges_is_single():
+    rng = np.random.default_rng(2)
+    data = rng.integers(0, 256, 5000).astype(np.uint8)
+    data[::3] = np.frombuffer(b"ACGTNacgtn", np.uint8)[rng.integers(0, 10, data[::3].size)]
+    offs = np.array([0, 1000, 1000, 4000, 5000])
+    a, ao = oracle.encode(oracle.BPE, data, offs, merges=np.zeros((0, 2), np.int32), add_cls_sep=True)
+    b, bo = oracle.encode(oracle.SINGLE, data, offs, add_cls_sep=True)
+    assert np.array_equal(a, b) and np.array_equal(ao, bo)
+
+
+def test_bpe_decode_concatenates_to_input():
+    rng = np.random.default_rng(4)
+    table = _tables()[2]
+    strings = ["".join(rng.choice(list("ACGT"), size=int(L))) for L in rng.integers(1, 400, 30)]
+    data, offs = _rows(strings)
+    ids, out_off = oracle.encode(oracle.BPE, data, offs, merges=table)
+    dec, dec_off = oracle.decode(oracle.BPE, ids, out_off, merges=table)
+    assert np.array_equal(dec, data) and np.array_equal(dec_off, offs)
+    for i, s in enumerate(strings):
+        toks = ids[out_off[i]:out_off[i + 1]].tolist()
+        assert "".join(brute.expand(t, table) for t in toks) == s
+
+
+# ---------------------------------------------------------------- trainer
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_trainer_matches_recount(seed):
+    rng = np.random.default_rng(100 + seed)
+    probs = rng.dirichlet([1, 1, 1, 1])
+    text = "".join(rng.choice(list("ACGT"), size=1500, p=probs))
+    if seed % 2:  # barriers and soft-masking
+        t = list(text)
+        for p in rng.integers(0, len(t), 20):
+            t[p] = "N"
+        for p in rng.integers(0, len(t), 200):
+            t[p] = t[p].lower()
+        text = "".join(t)
+    want, runs = brute.bpe_train_recount(text, 60)
+    got = oracle.bpe_train(np.frombuffer(text.encode(), np.uint8), 60)
+    assert [tuple(x) for x in got.tolist()] == want
+    assert oracle.bpe_check(got) == 0
+    # encoding the corpus with the learned table reproduces the trainer's segmentation
+    ids, _ = oracle.encode(oracle.BPE, np.frombuffer(text.encode(), np.uint8), np.array([0, len(text)]),
+                           merges=got)
+    assert [t for t in ids.tolist() if t >= 5 and t != 9] == [t for run in runs for t in run]
+
+
+def test_trainer_first_merge_of_a_dominated_corpus():
+    got = oracle.bpe_train(np.frombuffer(b"AAAAAAAAAAAAAAAAAAAAAC", np.uint8), 1)
+    assert got.tolist() == [[5, 5]]
+    # counts below 2 stop the trainer
+    assert oracle.bpe_train(np.frombuffer(b"ACGT", np.uint8), 5).shape == (0, 2)
+
+
+def test_trainer_deterministic_and_well_formed():
+    import synth
+    corpus = synth.bpe_corpus(n=200_000, seed=123)
+    a = oracle.bpe_train(corpus, 300)
+    b = oracle.bpe_train(corpus, 300)
+    assert a.shape == (300, 2) and np.array_equal(a, b)
+    assert oracle.bpe_check(a) == 0
+
+
+def test_bpe_check_rejects_bad_tables():
+    assert oracle.bpe_check([(5, 6), (5, 6)]) == 2       # duplicate pair
+    assert oracle.bpe_check([(5, 11)]) == 1             # refers to a later merge
+    assert oracle.bpe_check([(9, 5)]) == 1              # N is never merged
+    assert oracle.bpe_check([(5, 6), (10, 7)]) == 0
+
+
+# ---------------------------------------------------------------- windows
+
+def test_windows_closed_form():
+    lens = [0, 1, 5999, 6000, 6001, 12000, 25_000]
+    offs = oracle.windows(lens, 6000)
+    assert len(offs) - 1 == sum(math.ceil(L / 6000) for L in lens)
+    assert offs[-1] == sum(lens)
+    assert np.all(np.diff(offs) <= 6000) and np.all(np.diff(offs) > 0)
