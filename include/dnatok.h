@@ -1,0 +1,211 @@
+/*
+ * dnatok.h — C-ABI of the MI355X DNA byte->identifier tokenizer.
+ *
+ * The operation (paper, Design): genomic tokenization reduces to mapping the
+ * ASCII bytes of DNA strings to the integer identifiers an embedder consumes
+ * (embed_tokens: Z^{B x T} -> R^{B x T x D}); the bytes path stages raw 8-bit
+ * ASCII, moves it to the device once and applies a device-resident 256-entry
+ * lookup table there (Design, "Encoding paths", bytes path; the bytes branch
+ * of the EmbedFromStrings algorithm). This library is that bytes path for a
+ * ragged batch, for single-nucleotide, non-overlapping k-mer and ranked-merge
+ * BPE vocabularies (introduction; table of genomic tokenization schemes).
+ *
+ * Conventions
+ *  - Every function returns an int status: DNATOK_OK (0) or a negative code.
+ *    dnatok_last_error() describes the most recent failure of the calling
+ *    thread. Nothing aborts and no C++ exception crosses this boundary.
+ *  - Pointers named d_* are device memory of the device that was current
+ *    when the vocabulary was created; h_* are host memory. The caller owns
+ *    every buffer it passes; the library owns the handles it returns and the
+ *    device tables and workspaces behind them.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls that take a stream only enqueue work on it and return at once;
+ *    their device outputs are ready when the stream reaches that point.
+ *  - All offsets and sizes are int64 (a 2 GiB stream already overflows
+ *    32-bit indexing, cf. the 32-bit index overflow the paper guards against
+ *    in "Robustness and compatibility").
+ *  - Vocabulary handles are immutable after creation and may be shared by
+ *    threads. Stream handles have a single owner.
+ *
+ * Id space (the paper delegates special ids to the upstream vocabulary; the
+ * fixed reading used here): PAD=0 (the discovery algorithm's default pad
+ * id), UNK=1, CLS=2, SEP=3, MASK=4, then the vocabulary's own ids.
+ */
+#ifndef DNATOK_H
+#define DNATOK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define DNATOK_OK 0
+#define DNATOK_EINVAL (-1)    /* bad argument (null pointer, size, enum) */
+#define DNATOK_EVOCAB (-2)    /* vocabulary description rejected */
+#define DNATOK_ENOMEM (-3)    /* device or pinned allocation failed */
+#define DNATOK_EBUDGET (-4)   /* request exceeds a memory budget */
+#define DNATOK_EDEVICE (-5)   /* a HIP runtime call failed */
+#define DNATOK_ESTATE (-6)    /* handle in the wrong state for this call */
+#define DNATOK_ETOOSMALL (-7) /* an output capacity is too small */
+
+/* ---- device-side error flags (dnatok_sync_status) ------------------------ */
+#define DNATOK_DERR_OFFSETS 1u   /* offsets not non-decreasing within [0, nbytes] */
+#define DNATOK_DERR_CAPACITY 2u  /* PACKED output exceeds ids_capacity (excess not written) */
+#define DNATOK_DERR_ROW_WIDTH 4u /* PADDED row longer than pad_to (excess not written) */
+
+/* ---- ids and enums --------------------------------------------------------- */
+#define DNATOK_ID_PAD 0
+#define DNATOK_ID_UNK 1
+#define DNATOK_ID_CLS 2
+#define DNATOK_ID_SEP 3
+#define DNATOK_ID_MASK 4
+
+enum dnatok_kind {
+    DNATOK_SINGLE = 0, /* A5 C6 G7 T8 N9 (either case), other bytes UNK; |V| = 10 */
+    DNATOK_LUT256 = 1, /* id = lut256[byte]; the user's table defines the id space */
+    DNATOK_KMER = 2,   /* non-overlapping k-mers: 5 + radix-4 value, else UNK; |V| = 5 + 4^k */
+    DNATOK_BPE = 3     /* ranked merges over ACGT runs: merge r -> id 10 + r; |V| = 10 + R */
+};
+enum dnatok_layout { DNATOK_PACKED = 0, DNATOK_PADDED = 1 };
+enum dnatok_pad_side { DNATOK_PAD_RIGHT = 0, DNATOK_PAD_LEFT = 1 };
+
+typedef struct dnatok_vocab dnatok_vocab;
+
+/*
+ * Vocabulary description (host memory, read during dnatok_vocab_create only).
+ *  kind      dnatok_kind.
+ *  k         KMER frame length, 1..15 (ids fit in int32). Ignored otherwise.
+ *  lut256    LUT256: 256 host int32 ids, indexed by byte value (the paper's
+ *            ascii_lut[0..255], Design, discovery algorithm). Ids must be >= 0.
+ *  pad_id, cls_id, sep_id
+ *            LUT256 only: the ids written for pads and specials (the
+ *            discovery algorithm's id_pad). Other kinds use 0, 2, 3.
+ *  merges    BPE: host int32[n_merges][2], row r = (left id, right id) of the
+ *            merge of rank r. Each operand must be a base id 5..8 or 10 + r'
+ *            with r' < r, and no pair may repeat (a well-formed table; the
+ *            rank-ordered rounds the device runs equal the one-merge-at-a-time
+ *            definition only for such tables).
+ */
+typedef struct dnatok_vocab_desc {
+    int32_t kind;
+    int32_t k;
+    const int32_t *lut256;
+    int32_t pad_id;
+    int32_t cls_id;
+    int32_t sep_id;
+    int32_t n_merges;
+    const int32_t *merges;
+} dnatok_vocab_desc;
+
+/*
+ * Encode options.
+ *  add_cls_sep  0/1: each row becomes [CLS] body [SEP].
+ *  layout       PACKED: rows back to back, row i at d_out_offsets[i].
+ *               PADDED: an n x pad_to matrix plus an int8 mask (1 on tokens,
+ *               CLS/SEP included; 0 on pads), pads = PAD id.
+ *  pad_side     PADDED: RIGHT keeps tokens at the row start; LEFT right-aligns
+ *               them (the paper's left padding, EmbedFromStrings algorithm).
+ *  pad_to       PADDED row width W (> 0). The paper pads and never truncates,
+ *               so W must be at least the longest row (dnatok_encode_plan
+ *               returns it).
+ *  offset_base  added to every value written to d_out_offsets (lets chunked
+ *               callers write one global offsets array).
+ */
+typedef struct dnatok_encode_opts {
+    int32_t add_cls_sep;
+    int32_t layout;
+    int32_t pad_side;
+    int32_t reserved;
+    int64_t pad_to;
+    int64_t offset_base;
+} dnatok_encode_opts;
+
+/* Human-readable description of the calling thread's last failure. */
+const char *dnatok_last_error(void);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int32_t dnatok_version(void);
+
+/*
+ * Build a vocabulary and upload its device tables to the current device
+ * (the paper's static vocabulary built once and copied to GPU memory at
+ * initialization, Discussion, "Dynamic Vocabularies and Online BPE"; the
+ * 256-entry table that "fits easily in L1 cache or shared memory", bytes
+ * path). On success *out owns the tables until dnatok_vocab_destroy.
+ * Errors: EINVAL (null), EVOCAB (bad kind/k/table), ENOMEM/EDEVICE.
+ */
+int dnatok_vocab_create(const dnatok_vocab_desc *desc, dnatok_vocab **out);
+
+/* Free a vocabulary. Work already enqueued with it must have completed. */
+int dnatok_vocab_destroy(dnatok_vocab *v);
+
+/*
+ * vocab_size: number of ids (max id + 1). max_token_bytes: the most bases one
+ * id decodes to (1, k, or the longest merge). Either pointer may be NULL.
+ */
+int dnatok_vocab_info(const dnatok_vocab *v, int32_t *vocab_size, int32_t *max_token_bytes);
+
+/*
+ * Host-side sizing of an encode from host offsets (n + 1 non-decreasing
+ * int64). total_tokens: exact PACKED length for SINGLE/LUT256/KMER (L, or
+ * ceil(L/k) per row, plus 2 with CLS/SEP), an upper bound (L + specials) for
+ * BPE. max_len: the longest row in the same sense — the smallest valid
+ * PADDED pad_to (the paper's rule T' = max(token_len, T) is max(pad_to,
+ * max_len)). Either output may be NULL. Errors: EINVAL.
+ */
+int dnatok_encode_plan(const dnatok_vocab *v, const int64_t *h_offsets, int32_t n,
+                       const dnatok_encode_opts *opts, int64_t *total_tokens, int64_t *max_len);
+
+/*
+ * Encode a ragged batch on the device (bytes path: the LUT, k-mer packing,
+ * specials and padding all run in one HIP launch; BPE adds its merge rounds).
+ *  d_bytes        device uint8[nbytes], any alignment.
+ *  d_offsets      device int64[n + 1]: row i is d_bytes[off[i] .. off[i+1]).
+ *                 Must be non-decreasing within [0, nbytes].
+ *  d_ids          device int32 output, ids_capacity elements. PACKED: row i
+ *                 at [out_off[i], out_off[i+1]). PADDED: n x pad_to.
+ *  d_out_offsets  device int64[n + 1], always written: offset_base + the
+ *                 PACKED offsets of the true row lengths.
+ *  d_mask         device int8[n x pad_to], PADDED only (else NULL).
+ * The call is asynchronous on `stream`. Host-checkable errors return at
+ * once: EINVAL, ETOOSMALL (PADDED and ids_capacity < n * pad_to), ENOMEM.
+ * Violations only the device can see (bad offsets, PACKED overflow, a row
+ * longer than pad_to) never write outside the given buffers; they raise a
+ * DNATOK_DERR_* flag read by dnatok_sync_status, and d_out_offsets still
+ * reports the true sizes. Concurrent calls on different streams are safe;
+ * the library keeps one small device workspace per stream.
+ */
+int dnatok_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets,
+                  int32_t n, int32_t *d_ids, int64_t ids_capacity, int64_t *d_out_offsets, int8_t *d_mask,
+                  const dnatok_encode_opts *opts, void *stream);
+
+/*
+ * Wait for `stream`, then return (and clear) the DNATOK_DERR_* flags the
+ * device raised for calls on it since the last check. *flags may be NULL.
+ */
+int dnatok_sync_status(void *stream, uint32_t *flags);
+
+/*
+ * Decode PACKED rows of ids back to bases (the inverse table the paper lists
+ * as future work, "Decode Operations"): base, k-mer and merge ids -> their
+ * uppercase bases; N -> 'N'; UNK -> 'N' repeated over the width it stands for
+ * (k for KMER, 1 otherwise); PAD/CLS/SEP/MASK -> nothing; ids outside the
+ * vocabulary decode like UNK. Not defined for LUT256 (EVOCAB): a user table
+ * has no canonical inverse.
+ *  d_ids          device int32[n_ids].
+ *  d_offsets      device int64[n + 1] into d_ids (non-decreasing, <= n_ids).
+ *  d_out          device uint8 output, out_capacity bytes; an upper bound is
+ *                 n_ids * max_token_bytes.
+ *  d_out_offsets  device int64[n + 1] byte offsets of the decoded rows.
+ * Asynchronous; overflow and bad offsets raise DNATOK_DERR_* as for encode.
+ */
+int dnatok_decode(const dnatok_vocab *v, const int32_t *d_ids, int64_t n_ids, const int64_t *d_offsets,
+                  int32_t n, uint8_t *d_out, int64_t out_capacity, int64_t *d_out_offsets, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DNATOK_H */

@@ -1,0 +1,258 @@
+"""Python binding of ``libdnatok.so`` (the MI355X DNA byte->identifier tokenizer).
+
+Argument marshalling only: every step of the tokenizer runs in the HIP
+library behind ``include/dnatok.h``. The functions named ``dnatok_*`` mirror
+the C-ABI one to one (ints for device pointers and streams). The lower-case
+helpers (``Vocab``, ``encode``, ``decode``) take PyTorch tensors, which serve
+only as device memory and streams.
+
+There is no fallback: if the library is not built, importing the binding
+works but the first call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdnatok.so")
+
+OK, EINVAL, EVOCAB, ENOMEM, EBUDGET, EDEVICE, ESTATE, ETOOSMALL = 0, -1, -2, -3, -4, -5, -6, -7
+DERR_OFFSETS, DERR_CAPACITY, DERR_ROW_WIDTH = 1, 2, 4
+SINGLE, LUT256, KMER, BPE = 0, 1, 2, 3
+PACKED, PADDED = 0, 1
+PAD_RIGHT, PAD_LEFT = 0, 1
+ID_PAD, ID_UNK, ID_CLS, ID_SEP, ID_MASK = 0, 1, 2, 3, 4
+
+
+class DnatokError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("dnatok error %d: %s" % (code, msg))
+        self.code = code
+
+
+class dnatok_vocab_desc(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32),
+        ("k", ctypes.c_int32),
+        ("lut256", ctypes.POINTER(ctypes.c_int32)),
+        ("pad_id", ctypes.c_int32),
+        ("cls_id", ctypes.c_int32),
+        ("sep_id", ctypes.c_int32),
+        ("n_merges", ctypes.c_int32),
+        ("merges", ctypes.POINTER(ctypes.c_int32)),
+    ]
+
+
+class dnatok_encode_opts(ctypes.Structure):
+    _fields_ = [
+        ("add_cls_sep", ctypes.c_int32),
+        ("layout", ctypes.c_int32),
+        ("pad_side", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("pad_to", ctypes.c_int64),
+        ("offset_base", ctypes.c_int64),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded ``libdnatok.so`` (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libdnatok.so is not built (run __graft_entry__.build()); "
+                               "there is no CPU fallback")
+        # PyTorch ships its own HIP runtime (soname libamdhip64.so.7, loaded by
+        # file name libamdhip64.so). Loading torch first lets the dynamic
+        # loader satisfy this library's libamdhip64.so.7 dependency with that
+        # same runtime, so torch's stream handles and allocations are valid
+        # here; loading this library first would bring up a second runtime.
+        import torch  # noqa: F401
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.dnatok_last_error.restype = ctypes.c_char_p
+        L.dnatok_last_error.argtypes = []
+        L.dnatok_version.restype = i32
+        L.dnatok_vocab_create.argtypes = [ctypes.POINTER(dnatok_vocab_desc), ctypes.POINTER(vp)]
+        L.dnatok_vocab_destroy.argtypes = [vp]
+        L.dnatok_vocab_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.dnatok_encode_plan.argtypes = [vp, vp, i32, ctypes.POINTER(dnatok_encode_opts),
+                                         ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.dnatok_encode.argtypes = [vp, vp, i64, vp, i32, vp, i64, vp, vp,
+                                    ctypes.POINTER(dnatok_encode_opts), vp]
+        L.dnatok_sync_status.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32)]
+        L.dnatok_decode.argtypes = [vp, vp, i64, vp, i32, vp, i64, vp, vp]
+        for name in ("dnatok_vocab_create", "dnatok_vocab_destroy", "dnatok_vocab_info", "dnatok_encode_plan",
+                     "dnatok_encode", "dnatok_sync_status", "dnatok_decode"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise DnatokError(rc, lib().dnatok_last_error().decode())
+    return rc
+
+
+# ---- C-ABI mirrors ------------------------------------------------------------
+
+def dnatok_last_error() -> str:
+    return lib().dnatok_last_error().decode()
+
+
+def dnatok_version() -> int:
+    return lib().dnatok_version()
+
+
+def dnatok_vocab_create(desc: dnatok_vocab_desc) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().dnatok_vocab_create(ctypes.byref(desc), ctypes.byref(h)))
+    return h.value
+
+
+def dnatok_vocab_destroy(handle: int) -> int:
+    return _check(lib().dnatok_vocab_destroy(handle))
+
+
+def dnatok_vocab_info(handle: int):
+    vs, mt = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().dnatok_vocab_info(handle, ctypes.byref(vs), ctypes.byref(mt)))
+    return vs.value, mt.value
+
+
+def dnatok_encode_plan(handle: int, h_offsets: np.ndarray, n: int, opts: dnatok_encode_opts):
+    tot, mx = ctypes.c_int64(), ctypes.c_int64()
+    h_offsets = np.ascontiguousarray(h_offsets, dtype=np.int64)
+    _check(lib().dnatok_encode_plan(handle, h_offsets.ctypes.data, n, ctypes.byref(opts),
+                                    ctypes.byref(tot), ctypes.byref(mx)))
+    return tot.value, mx.value
+
+
+def dnatok_encode(handle, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets, d_mask, opts,
+                  stream) -> int:
+    return _check(lib().dnatok_encode(handle, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets,
+                                      d_mask, ctypes.byref(opts), stream))
+
+
+def dnatok_sync_status(stream) -> int:
+    f = ctypes.c_uint32()
+    _check(lib().dnatok_sync_status(stream, ctypes.byref(f)))
+    return f.value
+
+
+def dnatok_decode(handle, d_ids, n_ids, d_offsets, n, d_out, out_capacity, d_out_offsets, stream) -> int:
+    return _check(lib().dnatok_decode(handle, d_ids, n_ids, d_offsets, n, d_out, out_capacity, d_out_offsets,
+                                      stream))
+
+
+# ---- torch-facing helpers ----------------------------------------------------------
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+class Vocab:
+    """Owning wrapper of a ``dnatok_vocab`` handle on the current device."""
+
+    def __init__(self, kind: int, k: int = 1, lut256=None, merges=None, pad_id: int = ID_PAD,
+                 cls_id: int = ID_CLS, sep_id: int = ID_SEP):
+        self.kind, self.k = kind, k
+        d = dnatok_vocab_desc()
+        d.kind, d.k = kind, k
+        d.pad_id, d.cls_id, d.sep_id = pad_id, cls_id, sep_id
+        self._lut = None if lut256 is None else np.ascontiguousarray(lut256, dtype=np.int32)
+        self._merges = None if merges is None else np.ascontiguousarray(merges, dtype=np.int32).reshape(-1, 2)
+        if self._lut is not None:
+            d.lut256 = self._lut.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        if self._merges is not None:
+            d.n_merges = len(self._merges)
+            d.merges = self._merges.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        self.handle = dnatok_vocab_create(d)
+        self.vocab_size, self.max_token_bytes = dnatok_vocab_info(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            dnatok_vocab_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_opts(add_cls_sep=False, layout=PACKED, pad_side=PAD_RIGHT, pad_to=0, offset_base=0):
+    o = dnatok_encode_opts()
+    o.add_cls_sep, o.layout, o.pad_side, o.pad_to, o.offset_base = int(add_cls_sep), layout, pad_side, pad_to, offset_base
+    return o
+
+
+def plan(vocab: Vocab, h_offsets, add_cls_sep=False):
+    h_offsets = np.ascontiguousarray(h_offsets, dtype=np.int64)
+    return dnatok_encode_plan(vocab.handle, h_offsets, len(h_offsets) - 1, make_opts(add_cls_sep))
+
+
+def encode(vocab: Vocab, d_bytes, d_offsets, h_offsets=None, add_cls_sep=False, layout=PACKED,
+           pad_side=PAD_RIGHT, pad_to=None, out=None, stream=None):
+    """Encode a ragged batch held in device tensors.
+
+    ``d_bytes``: uint8 cuda tensor; ``d_offsets``: int64 cuda tensor [n+1];
+    ``h_offsets``: the same offsets on the host (numpy) for output sizing
+    (copied from the device when omitted). Returns ``(ids, out_offsets, mask)``
+    (``mask`` is None for PACKED). ``out`` may pass preallocated
+    ``(ids, out_offsets, mask)``.
+    """
+    import torch
+    n = d_offsets.numel() - 1
+    if h_offsets is None:
+        h_offsets = d_offsets.cpu().numpy()
+    total, max_len = plan(vocab, h_offsets, add_cls_sep)
+    dev = d_bytes.device
+    if layout == PADDED:
+        W = max_len if pad_to is None else max(int(pad_to), max_len)
+        cap = n * W
+    else:
+        W, cap = 0, total
+    if out is None:
+        ids = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        out_off = torch.empty(n + 1, dtype=torch.int64, device=dev)
+        mask = torch.empty(max(cap, 1), dtype=torch.int8, device=dev) if layout == PADDED else None
+    else:
+        ids, out_off, mask = out
+    opts = make_opts(add_cls_sep, layout, pad_side, W)
+    dnatok_encode(vocab.handle, _ptr(d_bytes), d_bytes.numel(), _ptr(d_offsets), n, _ptr(ids), ids.numel(),
+                  _ptr(out_off), _ptr(mask), opts, _stream_ptr(stream))
+    if layout == PADDED:
+        return ids[:cap].view(n, W) if n else ids[:0].view(0, W), out_off, mask[:cap].view(n, W) if n else mask[:0]
+    return ids[:total], out_off, None
+
+
+def decode(vocab: Vocab, d_ids, d_offsets, out_capacity=None, stream=None):
+    """Decode PACKED rows. Returns ``(bytes uint8 cuda tensor, out_offsets)``;
+    the bytes tensor is sized by ``out_capacity`` (default n_ids * max_token_bytes)."""
+    import torch
+    n = d_offsets.numel() - 1
+    cap = out_capacity if out_capacity is not None else max(1, d_ids.numel() * vocab.max_token_bytes)
+    out = torch.empty(max(cap, 1), dtype=torch.uint8, device=d_ids.device)
+    out_off = torch.empty(n + 1, dtype=torch.int64, device=d_ids.device)
+    dnatok_decode(vocab.handle, _ptr(d_ids), d_ids.numel(), _ptr(d_offsets), n, _ptr(out), cap, _ptr(out_off),
+                  _stream_ptr(stream))
+    return out, out_off
+
+
+def sync_status(stream=None) -> int:
+    return dnatok_sync_status(_stream_ptr(stream))

@@ -1,0 +1,313 @@
+// Exported C-ABI: argument checks, vocabulary construction and per-stream
+// workspaces. Device work lives in encode.hip, decode.hip and bpe.hip.
+#include <algorithm>
+#include <memory>
+#include <cstdarg>
+#include <map>
+#include <unordered_set>
+
+#include "common.hpp"
+
+namespace dnatok {
+
+namespace {
+thread_local std::string g_err = "no error";
+std::mutex g_ws_mu;
+std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
+std::mutex g_dev_mu;
+std::map<int, int> g_cu;
+}  // namespace
+
+int set_error(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+void clear_error() { g_err = "no error"; }
+
+int device_cu_count() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    auto it = g_cu.find(dev);
+    if (it != g_cu.end()) return it->second;
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0) cu = 256;
+    g_cu[dev] = cu;
+    return cu;
+}
+
+Workspace *find_workspace(hipStream_t stream) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto it = g_ws.find({dev, stream});
+    return it == g_ws.end() ? nullptr : it->second;
+}
+
+static int grow_allowed(hipStream_t stream) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &st) == hipSuccess && st != hipStreamCaptureStatusNone)
+        return set_error(DNATOK_ESTATE,
+                         "the stream's workspace must grow, which cannot happen during graph capture; "
+                         "run one uncaptured call of at least this size first");
+    return DNATOK_OK;
+}
+
+int get_workspace(hipStream_t stream, int64_t tiles, Workspace **out) {
+    int dev = 0;
+    DNATOK_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Workspace *&ws = g_ws[{dev, stream}];
+    if (!ws) {
+        ws = new Workspace();
+        ws->device = dev;
+        ws->stream = stream;
+    }
+    if (tiles > ws->cap) {
+        int rc = grow_allowed(stream);
+        if (rc) return rc;
+        int64_t cap = std::max<int64_t>({tiles, 2 * ws->cap, 4096});
+        DNATOK_HIP(hipStreamSynchronize(stream));
+        uint32_t err_keep = 0;
+        if (ws->d_hdr) {
+            DNATOK_HIP(hipMemcpy(&err_keep, ws->d_hdr + HDR_ERR, sizeof(uint32_t), hipMemcpyDeviceToHost));
+            DNATOK_HIP(hipFree(ws->d_hdr));
+            ws->d_hdr = nullptr;
+            ws->d_status = nullptr;
+            ws->cap = 0;
+        }
+        size_t bytes = 256 + (size_t)cap * 2 * sizeof(uint64_t);
+        void *p = nullptr;
+        DNATOK_HIP(hipMalloc(&p, bytes));
+        DNATOK_HIP(hipMemset(p, 0, bytes));
+        ws->d_hdr = static_cast<uint32_t *>(p);
+        ws->d_status = reinterpret_cast<uint64_t *>(static_cast<uint8_t *>(p) + 256);
+        ws->cap = cap;
+        ws->high_water = 0;
+        if (err_keep) DNATOK_HIP(hipMemcpy(ws->d_hdr + HDR_ERR, &err_keep, sizeof(uint32_t), hipMemcpyHostToDevice));
+    }
+    *out = ws;
+    return DNATOK_OK;
+}
+
+int ensure_scratch(Workspace *ws, int64_t bytes) {
+    if (bytes <= ws->scratch_bytes) return DNATOK_OK;
+    int rc = grow_allowed(ws->stream);
+    if (rc) return rc;
+    int64_t nb = std::max<int64_t>(bytes, 2 * ws->scratch_bytes);
+    DNATOK_HIP(hipStreamSynchronize(ws->stream));
+    if (ws->d_scratch) DNATOK_HIP(hipFree(ws->d_scratch));
+    ws->d_scratch = nullptr;
+    ws->scratch_bytes = 0;
+    void *p = nullptr;
+    DNATOK_HIP(hipMalloc(&p, (size_t)nb));
+    ws->d_scratch = static_cast<uint8_t *>(p);
+    ws->scratch_bytes = nb;
+    return DNATOK_OK;
+}
+
+// ---- vocabulary construction ----------------------------------------------------
+
+static int check_merges(const int32_t *m, int32_t R) {
+    std::unordered_set<uint64_t> seen;
+    seen.reserve((size_t)R * 2);
+    for (int32_t r = 0; r < R; ++r) {
+        for (int s = 0; s < 2; ++s) {
+            int32_t x = m[2 * r + s];
+            bool ok = (x >= 5 && x <= 8) || (x >= 10 && x < 10 + r);
+            if (!ok)
+                return set_error(DNATOK_EVOCAB,
+                                 "merge %d: operand %d is neither a base id (5..8) nor an earlier merge", r, x);
+        }
+        uint64_t key = ((uint64_t)(uint32_t)m[2 * r] << 32) | (uint32_t)m[2 * r + 1];
+        if (!seen.insert(key).second) return set_error(DNATOK_EVOCAB, "merge %d repeats an earlier pair", r);
+    }
+    return DNATOK_OK;
+}
+
+int build_bpe_tables(dnatok_vocab *v);  // bpe.hip
+void free_bpe_tables(dnatok_vocab *v);  // bpe.hip
+
+}  // namespace dnatok
+
+using namespace dnatok;
+
+extern "C" {
+
+const char *dnatok_last_error(void) { return g_err.c_str(); }
+
+int32_t dnatok_version(void) { return 100; }
+
+int dnatok_vocab_destroy(dnatok_vocab *v) {
+    if (!v) return set_error(DNATOK_EINVAL, "null vocabulary");
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(v->device);
+    if (v->d_lut) (void)hipFree(v->d_lut);
+    free_bpe_tables(v);
+    (void)hipSetDevice(prev);
+    delete v;
+    return DNATOK_OK;
+}
+
+int dnatok_vocab_create(const dnatok_vocab_desc *d, dnatok_vocab **out) {
+    if (!d || !out) return set_error(DNATOK_EINVAL, "null argument");
+    *out = nullptr;
+    std::unique_ptr<dnatok_vocab> v(new dnatok_vocab());
+    v->kind = d->kind;
+    DNATOK_HIP(hipGetDevice(&v->device));
+    int32_t lut[256];
+    switch (d->kind) {
+    case DNATOK_SINGLE:
+    case DNATOK_BPE: {
+        for (int b = 0; b < 256; ++b) lut[b] = DNATOK_ID_UNK;
+        const char *up = "ACGT", *lo = "acgt";
+        for (int j = 0; j < 4; ++j) {
+            lut[(uint8_t)up[j]] = 5 + j;
+            lut[(uint8_t)lo[j]] = 5 + j;
+        }
+        lut['N'] = lut['n'] = 9;
+        v->vocab_size = 10;
+        v->max_token_bytes = 1;
+        break;
+    }
+    case DNATOK_LUT256: {
+        if (!d->lut256) return set_error(DNATOK_EVOCAB, "LUT256 needs a 256-entry table");
+        int32_t mx = std::max({d->pad_id, d->cls_id, d->sep_id});
+        if (d->pad_id < 0 || d->cls_id < 0 || d->sep_id < 0) return set_error(DNATOK_EVOCAB, "negative special id");
+        for (int b = 0; b < 256; ++b) {
+            if (d->lut256[b] < 0) return set_error(DNATOK_EVOCAB, "negative id for byte %d", b);
+            lut[b] = d->lut256[b];
+            mx = std::max(mx, lut[b]);
+        }
+        v->pad_id = d->pad_id;
+        v->cls_id = d->cls_id;
+        v->sep_id = d->sep_id;
+        v->vocab_size = mx + 1;
+        v->max_token_bytes = 1;
+        break;
+    }
+    case DNATOK_KMER:
+        if (d->k < 1 || d->k > 15) return set_error(DNATOK_EVOCAB, "k must be in 1..15 (got %d)", d->k);
+        v->k = d->k;
+        v->vocab_size = 5 + (int32_t)(1u << (2 * d->k));
+        v->max_token_bytes = d->k;
+        for (int b = 0; b < 256; ++b) lut[b] = 0;
+        break;
+    default:
+        return set_error(DNATOK_EVOCAB, "unknown vocabulary kind %d", d->kind);
+    }
+    if (d->kind == DNATOK_BPE) {
+        if (d->n_merges < 0 || (d->n_merges > 0 && !d->merges))
+            return set_error(DNATOK_EVOCAB, "BPE needs n_merges >= 0 and a merge table");
+        if (d->n_merges > (1 << 24)) return set_error(DNATOK_EVOCAB, "too many merges");
+        int rc = check_merges(d->merges, d->n_merges);
+        if (rc) return rc;
+        v->h_merges.assign(d->merges, d->merges + 2 * (size_t)d->n_merges);
+        v->vocab_size = 10 + d->n_merges;
+    }
+    void *p = nullptr;
+    DNATOK_HIP(hipMalloc(&p, 256 * sizeof(int32_t)));
+    v->d_lut = static_cast<int32_t *>(p);
+    DNATOK_HIP(hipMemcpy(v->d_lut, lut, sizeof(lut), hipMemcpyHostToDevice));
+    if (d->kind == DNATOK_BPE) {
+        int rc = build_bpe_tables(v.get());
+        if (rc) {
+            dnatok_vocab_destroy(v.release());
+            return rc;
+        }
+    }
+    *out = v.release();
+    return DNATOK_OK;
+}
+
+int dnatok_vocab_info(const dnatok_vocab *v, int32_t *vocab_size, int32_t *max_token_bytes) {
+    if (!v) return set_error(DNATOK_EINVAL, "null vocabulary");
+    if (vocab_size) *vocab_size = v->vocab_size;
+    if (max_token_bytes) *max_token_bytes = v->max_token_bytes;
+    return DNATOK_OK;
+}
+
+int dnatok_encode_plan(const dnatok_vocab *v, const int64_t *h_offsets, int32_t n, const dnatok_encode_opts *opts,
+                       int64_t *total_tokens, int64_t *max_len) {
+    if (!v || n < 0 || (!h_offsets && n > 0)) return set_error(DNATOK_EINVAL, "bad argument");
+    const int64_t sp = (opts && opts->add_cls_sep) ? 2 : 0;
+    const int64_t k = (v->kind == DNATOK_KMER) ? v->k : 1;
+    int64_t tot = 0, mx = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        int64_t L = h_offsets[i + 1] - h_offsets[i];
+        if (L < 0) return set_error(DNATOK_EINVAL, "offsets decrease at row %d", i);
+        int64_t len = (L + k - 1) / k + sp;
+        tot += len;
+        mx = std::max(mx, len);
+    }
+    if (total_tokens) *total_tokens = tot;
+    if (max_len) *max_len = mx;
+    return DNATOK_OK;
+}
+
+int dnatok_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets, int32_t n,
+                  int32_t *d_ids, int64_t ids_capacity, int64_t *d_out_offsets, int8_t *d_mask,
+                  const dnatok_encode_opts *opts, void *stream) {
+    if (!v) return set_error(DNATOK_EINVAL, "null vocabulary");
+    dnatok_encode_opts o = {};
+    if (opts) o = *opts;
+    if (n < 0 || nbytes < 0 || ids_capacity < 0) return set_error(DNATOK_EINVAL, "negative size");
+    if (!d_offsets || !d_out_offsets) return set_error(DNATOK_EINVAL, "offsets and out_offsets are required");
+    if (nbytes > 0 && !d_bytes) return set_error(DNATOK_EINVAL, "null bytes");
+    if (ids_capacity > 0 && !d_ids) return set_error(DNATOK_EINVAL, "null ids");
+    if ((reinterpret_cast<uintptr_t>(d_ids) & 3) != 0) return set_error(DNATOK_EINVAL, "ids must be 4-byte aligned");
+    if (o.layout != DNATOK_PACKED && o.layout != DNATOK_PADDED) return set_error(DNATOK_EINVAL, "bad layout");
+    if (o.pad_side != DNATOK_PAD_RIGHT && o.pad_side != DNATOK_PAD_LEFT) return set_error(DNATOK_EINVAL, "bad pad side");
+    if (o.layout == DNATOK_PADDED) {
+        if (o.pad_to <= 0) return set_error(DNATOK_EINVAL, "PADDED needs pad_to > 0");
+        if (!d_mask) return set_error(DNATOK_EINVAL, "PADDED needs a mask buffer");
+        if ((int64_t)n > 0 && o.pad_to > ids_capacity / (int64_t)n)
+            return set_error(DNATOK_ETOOSMALL, "ids_capacity %lld < n * pad_to", (long long)ids_capacity);
+    }
+    int dev = 0;
+    DNATOK_HIP(hipGetDevice(&dev));
+    if (dev != v->device) return set_error(DNATOK_EINVAL, "vocabulary lives on device %d, current is %d", v->device, dev);
+    clear_error();
+    if (v->kind == DNATOK_BPE) return set_error(DNATOK_EVOCAB, "BPE encode is not available in this build");
+    return launch_encode(v, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets, d_mask, o,
+                         static_cast<hipStream_t>(stream));
+}
+
+int dnatok_sync_status(void *stream, uint32_t *flags) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DNATOK_HIP(hipStreamSynchronize(s));
+    uint32_t f = 0;
+    Workspace *ws = find_workspace(s);
+    if (ws && ws->d_hdr) {
+        DNATOK_HIP(hipMemcpy(&f, ws->d_hdr + HDR_ERR, sizeof(f), hipMemcpyDeviceToHost));
+        uint32_t z = 0;
+        DNATOK_HIP(hipMemcpy(ws->d_hdr + HDR_ERR, &z, sizeof(z), hipMemcpyHostToDevice));
+    }
+    if (flags) *flags = f;
+    return DNATOK_OK;
+}
+
+int dnatok_decode(const dnatok_vocab *v, const int32_t *d_ids, int64_t n_ids, const int64_t *d_offsets, int32_t n,
+                  uint8_t *d_out, int64_t out_capacity, int64_t *d_out_offsets, void *stream) {
+    if (!v) return set_error(DNATOK_EINVAL, "null vocabulary");
+    if (v->kind == DNATOK_LUT256) return set_error(DNATOK_EVOCAB, "decode is not defined for LUT256");
+    if (n < 0 || n_ids < 0 || out_capacity < 0) return set_error(DNATOK_EINVAL, "negative size");
+    if (!d_offsets || !d_out_offsets) return set_error(DNATOK_EINVAL, "offsets and out_offsets are required");
+    if (n_ids > 0 && !d_ids) return set_error(DNATOK_EINVAL, "null ids");
+    if (out_capacity > 0 && !d_out) return set_error(DNATOK_EINVAL, "null output");
+    int dev = 0;
+    DNATOK_HIP(hipGetDevice(&dev));
+    if (dev != v->device) return set_error(DNATOK_EINVAL, "vocabulary lives on device %d, current is %d", v->device, dev);
+    clear_error();
+    return launch_decode(v, d_ids, n_ids, d_offsets, n, d_out, out_capacity, d_out_offsets,
+                         static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,99 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/dnatok.h"
+
+namespace dnatok {
+
+// ---- errors -----------------------------------------------------------------
+
+int set_error(int code, const char *fmt, ...);
+void clear_error();
+
+#define DNATOK_HIP(call)                                                                      \
+    do {                                                                                      \
+        hipError_t _e = (call);                                                               \
+        if (_e != hipSuccess)                                                                 \
+            return ::dnatok::set_error(_e == hipErrorOutOfMemory ? DNATOK_ENOMEM : DNATOK_EDEVICE, \
+                                       "%s failed: %s", #call, hipGetErrorString(_e));        \
+    } while (0)
+
+// ---- vocabulary ----------------------------------------------------------------
+
+// Device-side merge lookup: open-addressing table of (left, right) -> rank,
+// sized to a power of two at least twice the merge count.
+struct BpeTables {
+    int32_t n_merges = 0;
+    uint32_t hash_mask = 0;        // slots - 1
+    uint64_t *d_hash = nullptr;    // key (left << 32 | right) + 1 in high bits? see bpe.hip
+    int32_t *d_merges = nullptr;   // [R][2]
+    int32_t *d_tok_len = nullptr;  // decoded length per id, [vocab]
+    int64_t *d_tok_off = nullptr;  // offset of each id's bases in d_tok_chars, [vocab]
+    uint8_t *d_tok_chars = nullptr;
+};
+
+}  // namespace dnatok
+
+struct dnatok_vocab {
+    int32_t kind = 0;
+    int32_t k = 1;
+    int32_t pad_id = DNATOK_ID_PAD, cls_id = DNATOK_ID_CLS, sep_id = DNATOK_ID_SEP;
+    int32_t vocab_size = 0;
+    int32_t max_token_bytes = 1;
+    int device = 0;
+    int32_t *d_lut = nullptr;  // 256 ids (SINGLE table or the user's LUT256)
+    std::vector<int32_t> h_merges;
+    dnatok::BpeTables bpe;
+};
+
+namespace dnatok {
+
+// ---- per-stream device workspace ----------------------------------------------
+//
+// One-pass scans (decoupled look-back) need, per launch, a ticket counter, a
+// done counter, a parity bit and a status word per tile. The header is
+// self-resetting: the last block of each launch zeroes the counters and flips
+// the parity, and every launch zeroes the status array of the other parity for
+// the next one, so no memset is ever enqueued between launches (graph capture
+// friendly). One workspace exists per (device, stream).
+enum HdrSlot { HDR_TICKET = 0, HDR_DONE = 1, HDR_PARITY = 2, HDR_ERR = 3, HDR_WORDS = 4 };
+
+struct Workspace {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    uint32_t *d_hdr = nullptr;     // HDR_WORDS
+    uint64_t *d_status = nullptr;  // 2 * cap words (parity 0 then parity 1)
+    int64_t cap = 0;               // tiles
+    int64_t high_water = 0;        // tiles that may hold non-zero status
+    uint8_t *d_scratch = nullptr;  // general scratch for multi-pass kernels (BPE)
+    int64_t scratch_bytes = 0;
+};
+
+// Workspace for (current device, stream) with room for `tiles` tiles, grown
+// (synchronously, outside graph capture) when needed.
+int get_workspace(hipStream_t stream, int64_t tiles, Workspace **out);
+// Ensure the workspace scratch holds at least `bytes` bytes.
+int ensure_scratch(Workspace *ws, int64_t bytes);
+// Workspace of (current device, stream) if one exists.
+Workspace *find_workspace(hipStream_t stream);
+
+int device_cu_count();
+
+// ---- launchers (encode.hip / decode.hip / bpe.hip) ------------------------------
+
+int launch_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets,
+                  int32_t n, int32_t *d_ids, int64_t cap, int64_t *d_out_offsets, int8_t *d_mask,
+                  const dnatok_encode_opts &o, hipStream_t stream);
+
+int launch_decode(const dnatok_vocab *v, const int32_t *d_ids, int64_t n_ids, const int64_t *d_offsets,
+                  int32_t n, uint8_t *d_out, int64_t out_capacity, int64_t *d_out_offsets, hipStream_t stream);
+
+}  // namespace dnatok

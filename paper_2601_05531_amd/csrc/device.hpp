@@ -1,0 +1,133 @@
+// Device-side building blocks: wave64 scans, block scans, and the one-pass
+// (decoupled look-back) tile prefix used by the encode and decode kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dnatok {
+namespace dev {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ uint64_t ld_relaxed(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_relaxed32(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed32(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Inclusive scan across the 64 lanes of a wave.
+__device__ __forceinline__ int64_t wave_incl_scan(int64_t v) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        int64_t u = __shfl_up(v, d, kWave);
+        if (lane >= d) v += u;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int64_t wave_sum(int64_t v) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+// Block-wide exclusive scan (NT threads, NT a multiple of 64). `tmp` holds
+// NT/64 + 1 int64 in LDS. Returns the exclusive prefix; *total gets the sum.
+template <int NT>
+__device__ __forceinline__ int64_t block_excl_scan(int64_t v, int64_t *tmp, int64_t *total) {
+    constexpr int NW = NT / kWave;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    int64_t inc = wave_incl_scan(v);
+    if (lane == kWave - 1) tmp[w] = inc;
+    __syncthreads();
+    int64_t before = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        int64_t t = tmp[i];
+        if (i < w) before += t;
+        all += t;
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - v;
+}
+
+template <int NT>
+__device__ __forceinline__ int64_t block_sum(int64_t v, int64_t *tmp) {
+    constexpr int NW = NT / kWave;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    v = wave_sum(v);
+    if (lane == 0) tmp[w] = v;
+    __syncthreads();
+    int64_t all = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) all += tmp[i];
+    __syncthreads();
+    return all;
+}
+
+// Tile status word: 2-bit flag in the top bits, 62-bit value below.
+constexpr uint64_t kFlagAgg = 1ull << 62;
+constexpr uint64_t kFlagInc = 2ull << 62;
+constexpr uint64_t kValMask = (1ull << 62) - 1;
+
+// Publish this tile's aggregate and return the exclusive prefix of all earlier
+// tiles (single lane). Tiles are handed out in ticket order, so every
+// predecessor is held by a block that started earlier and never waits on a
+// later tile: the wait below always ends.
+__device__ __forceinline__ int64_t lookback(uint64_t *status, int64_t tile, int64_t agg) {
+    if (tile == 0) {
+        st_relaxed(status, kFlagInc | (uint64_t)agg);
+        return 0;
+    }
+    st_relaxed(status + tile, kFlagAgg | (uint64_t)agg);
+    int64_t excl = 0;
+    int64_t j = tile - 1;
+    for (;;) {
+        uint64_t w = ld_relaxed(status + j);
+        uint64_t f = w & ~kValMask;
+        if (f == 0) {
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        excl += (int64_t)(w & kValMask);
+        if (f == kFlagInc) break;
+        --j;
+    }
+    st_relaxed(status + tile, kFlagInc | (uint64_t)(excl + agg));
+    return excl;
+}
+
+// Workspace header protocol shared by one-pass kernels.
+struct TileQueue {
+    uint32_t *hdr;       // [ticket, done, parity, err]
+    uint64_t *status0;   // parity 0 status words
+    uint64_t *status1;   // parity 1 status words
+    int64_t clear_n;     // status words of the other parity to zero
+};
+
+__device__ __forceinline__ void raise_error(uint32_t *hdr, uint32_t flag) { atomicOr(hdr + 3, flag); }
+
+// Called by thread 0 of every block after its last tile: the last block to
+// finish resets the counters and flips the parity for the next launch.
+__device__ __forceinline__ void finish_block(uint32_t *hdr) {
+    uint32_t d = atomicAdd(hdr + 1, 1u);
+    if (d == gridDim.x - 1) {
+        st_relaxed32(hdr + 0, 0u);
+        st_relaxed32(hdr + 1, 0u);
+        st_relaxed32(hdr + 2, ld_relaxed32(hdr + 2) ^ 1u);
+    }
+}
+
+}  // namespace dev
+}  // namespace dnatok

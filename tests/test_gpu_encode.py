@@ -1,0 +1,300 @@
+"""GPU parity of encode/decode: the HIP library (through its C-ABI) against the
+CPU oracle, element by element, bit-exact (integer work)."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2601_05531_amd as dt
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    return torch
+
+
+def _dev(a):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _vocab(kind, k=1, lut=None, merges=None, **kw):
+    return dt.Vocab(kind, k=k, lut256=lut, merges=merges, **kw)
+
+
+def _oracle(kind, data, offs, k=1, lut=None, merges=None, cls=False, cls_id=2, sep_id=3):
+    return oracle.encode(kind, data, offs, k=k, lut=lut, merges=merges, add_cls_sep=cls, cls_id=cls_id,
+                         sep_id=sep_id)
+
+
+def check_packed(v, data, offs, cls, k=1, lut=None, merges=None, cls_id=2, sep_id=3, byte_shift=0):
+    torch = _torch()
+    print("packed kind=%d k=%d n=%d nbytes=%d cls=%d shift=%d" % (v.kind, k, len(offs) - 1, len(data), cls,
+                                                                 byte_shift), flush=True)
+    want_ids, want_off = _oracle(v.kind, data, offs, k, lut, merges, cls, cls_id, sep_id)
+    buf = np.zeros(len(data) + 16, np.uint8)
+    buf[byte_shift:byte_shift + len(data)] = data
+    d_buf = _dev(buf)
+    d_bytes = d_buf[byte_shift:byte_shift + len(data)]
+    ids, out_off, _ = dt.encode(v, d_bytes, _dev(offs), h_offsets=offs, add_cls_sep=cls)
+    torch.cuda.synchronize()
+    assert dt.sync_status() == 0
+    assert np.array_equal(out_off.cpu().numpy(), want_off)
+    got = ids.cpu().numpy()
+    assert got.shape == want_ids.shape
+    bad = np.nonzero(got != want_ids)[0]
+    assert bad.size == 0, "first mismatch at %d: got %d want %d" % (bad[0], got[bad[0]], want_ids[bad[0]])
+
+
+def check_padded(v, data, offs, cls, side, k=1, lut=None, pad_extra=0, pad_id=0, cls_id=2, sep_id=3):
+    torch = _torch()
+    print("padded kind=%d k=%d n=%d side=%d cls=%d extra=%d" % (v.kind, k, len(offs) - 1, side, cls, pad_extra),
+          flush=True)
+    want_ids, want_off = _oracle(v.kind, data, offs, k, lut, None, cls, cls_id, sep_id)
+    W = int(np.diff(want_off).max(initial=0)) + pad_extra
+    W = max(W, 1)
+    w_ids, w_mask = oracle.pad(want_ids, want_off, W, side, pad_id)
+    ids, out_off, mask = dt.encode(v, _dev(data), _dev(offs), h_offsets=offs, add_cls_sep=cls, layout=dt.PADDED,
+                                   pad_side=side, pad_to=W)
+    torch.cuda.synchronize()
+    assert dt.sync_status() == 0
+    assert np.array_equal(out_off.cpu().numpy(), want_off)
+    assert np.array_equal(ids.cpu().numpy(), w_ids)
+    assert np.array_equal(mask.cpu().numpy(), w_mask)
+
+
+# ---------------------------------------------------------------- small workload (1 Mbase)
+
+@pytest.mark.parametrize("cls", [False, True])
+def test_iid_batch_single_and_6mer(cls):
+    data, offs = synth.workload_iid()
+    check_packed(_vocab(dt.SINGLE), data, offs, cls)
+    check_packed(_vocab(dt.KMER, 6), data, offs, cls, k=6)
+
+
+# ---------------------------------------------------------------- batched k-mer workload at full size
+
+@pytest.fixture(scope="module")
+def markov_batch():
+    return synth.workload_markov_batch()
+
+
+@pytest.mark.parametrize("k", [3, 4, 5, 6])
+def test_markov_batch_padded_full_size(markov_batch, k):
+    data, offs = markov_batch
+    check_padded(_vocab(dt.KMER, k), data, offs, True, dt.PAD_RIGHT, k=k)
+
+
+def test_markov_batch_single_packed_and_left(markov_batch):
+    data, offs = markov_batch
+    check_packed(_vocab(dt.SINGLE), data, offs, True)
+    sub = offs[:513]
+    check_padded(_vocab(dt.KMER, 5), data[:sub[-1]], sub, True, dt.PAD_LEFT, k=5, pad_extra=7)
+
+
+# ---------------------------------------------------------------- boundary fuzz
+
+def _fuzz_batch(seed, n, max_len, alphabet_mix=True):
+    rng = np.random.default_rng(seed)
+    lens = rng.integers(0, max_len + 1, n)
+    lens[rng.integers(0, n, max(1, n // 10))] = 0
+    total = int(lens.sum())
+    data = synth.uniform_bytes(seed, total)
+    if alphabet_mix:  # mostly DNA with every byte value present somewhere
+        dna = np.frombuffer(b"ACGTNacgtn", np.uint8)
+        pick = rng.random(total) < 0.9
+        data[pick] = dna[rng.integers(0, 10, int(pick.sum()))]
+    offs = synth.offsets_from_lengths(lens)
+    return data, offs
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 7, 8, 15])
+def test_fuzz_kmer_all_shapes(k):
+    data, offs = _fuzz_batch(1000 + k, 2500, 130)
+    v = _vocab(dt.KMER, k)
+    for shift in (0, 1, 7, 15):
+        check_packed(v, data, offs, cls=bool(shift % 2), k=k, byte_shift=shift)
+    check_padded(v, data, offs, True, dt.PAD_RIGHT, k=k, pad_extra=3)
+    check_padded(v, data, offs, False, dt.PAD_LEFT, k=k)
+
+
+def test_fuzz_single_and_lut256():
+    data, offs = _fuzz_batch(77, 3000, 130)
+    for shift in (0, 3, 8):
+        check_packed(_vocab(dt.SINGLE), data, offs, cls=True, byte_shift=shift)
+    lut = oracle.fallback_lut()
+    v = _vocab(dt.LUT256, lut=lut, pad_id=0, cls_id=101, sep_id=102)
+    check_packed(v, data, offs, True, lut=lut, cls_id=101, sep_id=102, byte_shift=5)
+    check_padded(v, data, offs, True, dt.PAD_LEFT, lut=lut, cls_id=101, sep_id=102, pad_extra=2)
+    rng = np.random.default_rng(5)
+    lut2 = rng.integers(0, 1 << 30, 256).astype(np.int32)
+    check_packed(_vocab(dt.LUT256, lut=lut2), data, offs, False, lut=lut2)
+
+
+def test_long_rows_cross_many_tiles():
+    rng = np.random.default_rng(3)
+    lens = rng.integers(15000, 70000, 40)
+    lens[5] = 0
+    lens[6] = 1
+    data = synth.genome(synth.substream(9, 1), 31337, 3, int(lens.sum()))
+    offs = synth.offsets_from_lengths(lens)
+    for k in (1, 3, 6):
+        v = _vocab(dt.KMER, k)
+        check_packed(v, data, offs, True, k=k, byte_shift=k)
+        check_padded(v, data, offs, True, dt.PAD_RIGHT, k=k)
+
+
+def test_selftest_strings():
+    data = np.frombuffer(b"ACGTNacgtn", np.uint8).copy()
+    offs = np.array([0, 10], np.int64)
+    lut = oracle.fallback_lut()
+    check_packed(_vocab(dt.LUT256, lut=lut), data, offs, False, lut=lut)
+    check_packed(_vocab(dt.SINGLE), data, offs, False)
+    all_bytes = np.arange(256, dtype=np.uint8)
+    check_packed(_vocab(dt.SINGLE), all_bytes, np.array([0, 256]), True)
+    check_packed(_vocab(dt.KMER, 2), all_bytes, np.array([0, 256]), True, k=2)
+
+
+# ---------------------------------------------------------------- edge cases
+
+def test_empty_batch_and_empty_rows():
+    torch = _torch()
+    v = _vocab(dt.KMER, 3)
+    # n = 0
+    ids, out_off, _ = dt.encode(v, torch.zeros(1, dtype=torch.uint8, device="cuda"),
+                                torch.zeros(1, dtype=torch.int64, device="cuda"), h_offsets=np.zeros(1, np.int64))
+    torch.cuda.synchronize()
+    assert out_off.cpu().tolist() == [0]
+    # only empty rows, with and without specials
+    offs = np.zeros(9, np.int64)
+    data = np.zeros(0, np.uint8)
+    for cls in (False, True):
+        check_packed(v, data, offs, cls, k=3)
+    check_padded(v, data, offs, True, dt.PAD_LEFT, k=3, pad_extra=4)
+    # rows that do not start at byte 0, unused bytes between and after rows
+    data = synth.iid(5, 50000, 0.05)
+    offs = np.array([100, 100, 7000, 7000, 33000, 49000], np.int64)
+    check_packed(_vocab(dt.KMER, 6), data, offs, True, k=6)
+
+
+def test_output_offset_base_and_repeated_calls():
+    torch = _torch()
+    v = _vocab(dt.KMER, 4)
+    for i, n in enumerate([300, 17, 1200, 5, 800]):
+        data, offs = _fuzz_batch(500 + i, n, 3000)
+        want_ids, want_off = _oracle(dt.KMER, data, offs, 4)
+        ids = torch.empty(len(want_ids) + 8, dtype=torch.int32, device="cuda")
+        out_off = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+        opts = dt.make_opts(offset_base=1000 + i)
+        d_bytes, d_offs = _dev(data), _dev(offs)
+        # write into ids[1:] so the output start is not 16-byte aligned
+        dt.dnatok_encode(v.handle, d_bytes.data_ptr(), len(data), d_offs.data_ptr(), n, ids.data_ptr() + 4,
+                         len(want_ids), out_off.data_ptr(), None, opts, torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        assert dt.sync_status() == 0
+        assert np.array_equal(out_off.cpu().numpy(), want_off + 1000 + i)
+        assert np.array_equal(ids[1:1 + len(want_ids)].cpu().numpy(), want_ids)
+
+
+def test_device_side_errors_are_flagged_and_bounded():
+    torch = _torch()
+    v = _vocab(dt.KMER, 3)
+    data, offs = _fuzz_batch(9, 400, 200)
+    want_ids, want_off = _oracle(dt.KMER, data, offs, 3)
+    d_bytes, d_offs = _dev(data), _dev(offs)
+    stream = torch.cuda.current_stream().cuda_stream
+    # PACKED capacity too small: nothing written past it
+    cap = len(want_ids) // 2
+    ids = torch.full((len(want_ids) + 64,), -7, dtype=torch.int32, device="cuda")
+    out_off = torch.empty(len(offs), dtype=torch.int64, device="cuda")
+    dt.dnatok_encode(v.handle, d_bytes.data_ptr(), len(data), d_offs.data_ptr(), len(offs) - 1, ids.data_ptr(), cap,
+                     out_off.data_ptr(), None, dt.make_opts(), stream)
+    assert dt.sync_status() == dt.DERR_CAPACITY
+    got = ids.cpu().numpy()
+    assert np.all(got[cap:] == -7) and np.array_equal(got[:cap], want_ids[:cap])
+    assert np.array_equal(out_off.cpu().numpy(), want_off)
+    # decreasing offsets
+    bad = offs.copy()
+    bad[10] = bad[12] + 5
+    dt.dnatok_encode(v.handle, d_bytes.data_ptr(), len(data), _dev(bad).data_ptr(), len(bad) - 1, ids.data_ptr(),
+                     ids.numel(), out_off.data_ptr(), None, dt.make_opts(), stream)
+    assert dt.sync_status() & dt.DERR_OFFSETS
+    # offsets beyond nbytes
+    bad = offs.copy()
+    bad[-1] = len(data) + 100
+    dt.dnatok_encode(v.handle, d_bytes.data_ptr(), len(data), _dev(bad).data_ptr(), len(bad) - 1, ids.data_ptr(),
+                     ids.numel(), out_off.data_ptr(), None, dt.make_opts(), stream)
+    assert dt.sync_status() & dt.DERR_OFFSETS
+    # PADDED width below the longest row
+    W = int(np.diff(want_off).max()) - 1
+    n = len(offs) - 1
+    pid = torch.full((n * W + 64,), -7, dtype=torch.int32, device="cuda")
+    pm = torch.full((n * W + 64,), -7, dtype=torch.int8, device="cuda")
+    dt.dnatok_encode(v.handle, d_bytes.data_ptr(), len(data), d_offs.data_ptr(), n, pid.data_ptr(), n * W,
+                     out_off.data_ptr(), pm.data_ptr(), dt.make_opts(layout=dt.PADDED, pad_to=W), stream)
+    assert dt.sync_status() == dt.DERR_ROW_WIDTH
+    assert np.all(pid.cpu().numpy()[n * W:] == -7) and np.all(pm.cpu().numpy()[n * W:] == -7)
+    # host-checkable errors return at once
+    with pytest.raises(dt.DnatokError) as e:
+        dt.dnatok_encode(v.handle, d_bytes.data_ptr(), len(data), d_offs.data_ptr(), n, pid.data_ptr(), 10,
+                         out_off.data_ptr(), pm.data_ptr(), dt.make_opts(layout=dt.PADDED, pad_to=W), stream)
+    assert e.value.code == dt.ETOOSMALL
+    with pytest.raises(dt.DnatokError) as e:
+        dt.Vocab(dt.KMER, 16)
+    assert e.value.code == dt.EVOCAB
+
+
+def test_two_streams_concurrently():
+    torch = _torch()
+    v = _vocab(dt.KMER, 6)
+    jobs = [_fuzz_batch(70 + i, 2000, 4000) for i in range(2)]
+    streams = [torch.cuda.Stream() for _ in jobs]
+    outs = []
+    for (data, offs), s in zip(jobs, streams):
+        with torch.cuda.stream(s):
+            d_bytes, d_offs = _dev(data), _dev(offs)
+            outs.append((dt.encode(v, d_bytes, d_offs, h_offsets=offs, stream=s), d_bytes, d_offs))
+    torch.cuda.synchronize()
+    for (data, offs), ((ids, out_off, _), _, _), s in zip(jobs, outs, streams):
+        assert dt.sync_status(s) == 0
+        want_ids, want_off = _oracle(dt.KMER, data, offs, 6)
+        assert np.array_equal(ids.cpu().numpy(), want_ids)
+        assert np.array_equal(out_off.cpu().numpy(), want_off)
+
+
+# ---------------------------------------------------------------- decode
+
+@pytest.mark.parametrize("kind,k", [(dt.SINGLE, 1), (dt.KMER, 3), (dt.KMER, 6)])
+def test_decode_matches_oracle(kind, k):
+    torch = _torch()
+    rng = np.random.default_rng(k)
+    vs = 10 if kind == dt.SINGLE else 5 + 4 ** k
+    ids = rng.integers(-3, vs + 5, 50000).astype(np.int32)
+    lens = rng.integers(0, 300, 400)
+    offs = synth.offsets_from_lengths(lens)
+    offs = offs[offs <= len(ids)]
+    v = _vocab(kind, k)
+    want, want_off = oracle.decode(kind, ids, offs, k=k)
+    out, out_off = dt.decode(v, _dev(ids), _dev(offs))
+    torch.cuda.synchronize()
+    assert dt.sync_status() == 0
+    assert np.array_equal(out_off.cpu().numpy(), want_off)
+    assert np.array_equal(out.cpu().numpy()[:want_off[-1]], want)
+
+
+def test_encode_decode_roundtrip_acgt():
+    torch = _torch()
+    rng = np.random.default_rng(1)
+    lens = rng.integers(0, 2000, 300) * 6
+    data = np.frombuffer(b"ACGT", np.uint8)[rng.integers(0, 4, int(lens.sum()))].copy()
+    offs = synth.offsets_from_lengths(lens)
+    for kind, k in ((dt.SINGLE, 1), (dt.KMER, 6), (dt.KMER, 2)):
+        v = _vocab(kind, k)
+        ids, out_off, _ = dt.encode(v, _dev(data), _dev(offs), h_offsets=offs, add_cls_sep=True)
+        out, dec_off = dt.decode(v, ids, out_off)
+        torch.cuda.synchronize()
+        assert np.array_equal(dec_off.cpu().numpy(), offs)
+        assert np.array_equal(out.cpu().numpy()[:offs[-1]], data)
