@@ -89,6 +89,12 @@ int device_cu_count();
 
 // ---- launchers (encode.hip / decode.hip / bpe.hip) ------------------------------
 
+struct EncodeTuning {
+    int64_t tile_bytes;  // bytes of input per tile (multiple of 16)
+    int blocks_per_cu;   // 0 = as many as occupancy allows
+};
+EncodeTuning encode_tuning(bool kmer);
+
 int launch_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets,
                   int32_t n, int32_t *d_ids, int64_t cap, int64_t *d_out_offsets, int8_t *d_mask,
                   const dnatok_encode_opts &o, hipStream_t stream);

@@ -76,15 +76,74 @@ __device__ __forceinline__ int64_t block_sum(int64_t v, int64_t *tmp) {
     return all;
 }
 
+// First index in [lo, hi) where the monotone predicate (false...true) holds,
+// or hi, found by one wave: 64 probes per round, so 2 rounds cover 4096
+// candidates and 3 rounds 262144. All 64 lanes must call it.
+template <class Pred>
+__device__ __forceinline__ int64_t wave_lower_bound(int64_t lo, int64_t hi, Pred pred) {
+    const int lane = threadIdx.x & (kWave - 1);
+    while (hi > lo) {
+        const int64_t span = hi - lo;
+        const int64_t stride = (span + kWave - 1) / kWave;
+        const int64_t q = lo + (int64_t)lane * stride;
+        const bool p = (q < hi) ? pred(q) : true;
+        const uint64_t b = __ballot(p);
+        const int f = b ? __builtin_ctzll(b) : kWave;
+        const int64_t nhi = lo + (int64_t)f * stride;
+        const int64_t nlo = (f == 0) ? lo : lo + (int64_t)(f - 1) * stride + 1;
+        hi = nhi < hi ? nhi : hi;
+        lo = nlo;
+        if (stride == 1) lo = hi;
+    }
+    return hi;
+}
+
 // Tile status word: 2-bit flag in the top bits, 62-bit value below.
 constexpr uint64_t kFlagAgg = 1ull << 62;
 constexpr uint64_t kFlagInc = 2ull << 62;
 constexpr uint64_t kValMask = (1ull << 62) - 1;
 
-// Publish this tile's aggregate and return the exclusive prefix of all earlier
-// tiles (single lane). Tiles are handed out in ticket order, so every
-// predecessor is held by a block that started earlier and never waits on a
-// later tile: the wait below always ends.
+// Publish this tile's aggregate (single lane) so later tiles can start
+// summing it before this tile knows its own prefix.
+__device__ __forceinline__ void publish_aggregate(uint64_t *status, int64_t tile, int64_t agg) {
+    st_relaxed(status + tile, (tile == 0 ? kFlagInc : kFlagAgg) | (uint64_t)agg);
+}
+
+// Exclusive prefix of all tiles before `tile`, computed by one full wave
+// (all 64 lanes call it): each round reads the 64 nearest unread
+// predecessors at once, sums back to the closest one that already knows its
+// inclusive prefix, and stops there; otherwise it adds all 64 aggregates and
+// moves 64 tiles further back. Tile indices below 0 read as an inclusive
+// prefix of 0. Afterwards lane 0 publishes this tile's inclusive prefix.
+// Tiles are handed out in ticket order, so every predecessor is held by a
+// block that started earlier and never waits on a later tile: the wait ends.
+__device__ __forceinline__ int64_t wave_lookback(uint64_t *status, int64_t tile, int64_t agg) {
+    const int lane = threadIdx.x & (kWave - 1);
+    int64_t excl = 0;
+    int64_t top = tile - 1;
+    while (top >= 0) {
+        const int64_t j = top - lane;
+        uint64_t w = (j >= 0) ? ld_relaxed(status + j) : kFlagInc;
+        const uint64_t f = w & ~kValMask;
+        const uint64_t inc_mask = __ballot(f == kFlagInc);
+        const uint64_t zero_mask = __ballot(f == 0);
+        const int first_inc = inc_mask ? __builtin_ctzll(inc_mask) : kWave;
+        // lanes that must be known: 0 .. first_inc (all 64 if no inclusive one)
+        const uint64_t need = (first_inc >= kWave - 1) ? ~0ull : ((2ull << first_inc) - 1);
+        if (zero_mask & need) {
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        int64_t v = (lane <= first_inc) ? (int64_t)(w & kValMask) : 0;
+        excl += wave_sum(v);
+        if (first_inc < kWave) break;
+        top -= kWave;
+    }
+    if (lane == 0) st_relaxed(status + tile, kFlagInc | (uint64_t)(excl + agg));
+    return excl;
+}
+
+// Single-lane variant: publish the aggregate and walk back one tile at a time.
 __device__ __forceinline__ int64_t lookback(uint64_t *status, int64_t tile, int64_t agg) {
     if (tile == 0) {
         st_relaxed(status, kFlagInc | (uint64_t)agg);

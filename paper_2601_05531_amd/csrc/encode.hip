@@ -1,30 +1,35 @@
-// Byte -> identifier encode of a ragged batch in one persistent HIP launch.
+// Byte -> identifier encode of a ragged batch (SINGLE, LUT256, KMER).
 //
-// Paper: Design, "Encoding paths", bytes path (device-resident 256-entry LUT
-// applied to staged ASCII) and the bytes branch of the EmbedFromStrings
+// Paper: Design, "Encoding paths", bytes path (a device-resident 256-entry
+// LUT applied to staged ASCII) and the bytes branch of the EmbedFromStrings
 // algorithm (MapKmer for k-mer vocabularies, left padding to token_len).
 //
-// Work decomposition (MI355X-first; the paper applies ascii_lut[Bytes] as a
+// MI355X-first decomposition (the paper applies ascii_lut[Bytes] as a
 // framework tensor op on an equal-length B x T matrix):
-//  * The concatenated input is cut into fixed tiles of B bytes (B a multiple
-//    of 16, addressed from the 16-byte-aligned base so every tile load is a
-//    full 16-byte vector load). Every output cell is owned by the tile that
-//    holds its anchor byte: CLS at the row start, body token j at
+//  * Row scan (k_rowscan): every row's token count has a closed form
+//    (L, or ceil(L/k), plus 2 with CLS/SEP), so out_offsets is a scan over
+//    rows. Units of 4096 rows are handed out by ticket and chained with a
+//    decoupled look-back; a batch of a few thousand rows is one unit.
+//  * Cell kernel (k_cells): the concatenated input is cut into fixed tiles
+//    of B bytes, addressed from the 16-byte-aligned base so every tile load
+//    is a full 16-byte vector load. Every output cell is owned by the tile
+//    holding its anchor byte: CLS at the row start, body token j at
 //    off + j*k, SEP at the row's last byte, pads at the CLS (left) or SEP
 //    (right) anchor. A tile therefore owns one contiguous run of cells per
-//    row it touches, and its PACKED output is one contiguous range, so the
-//    work per tile is bounded by B whatever the row lengths are.
-//  * Output positions need the token count of all earlier tiles: a one-pass
-//    decoupled look-back over per-tile counts (tickets hand tiles out in
-//    order, so a tile only ever waits on tiles that are already running).
-//  * The tile's bytes are staged into LDS once with coalesced 16-byte loads.
+//    row it touches and its work is bounded by B whatever the row lengths.
+//    Cell positions follow from out_offsets (PACKED) or row * width
+//    (PADDED), so tiles never wait on each other: blocks walk a static
+//    grid-stride tile sequence with no atomics at all.
+//  * Each tile is staged into LDS once with coalesced 16-byte loads; the
+//    next tile's loads are issued before the current tile is written.
 //    k-mer tiles are classified on the way in: 2-bit base digits packed
 //    most-significant-first (16 bases per word) plus one validity bit per
-//    base, so a k-mer id is one 64-bit funnel shift and one mask compare.
-//    Single-base tiles keep raw bytes and the 256-entry table sits in LDS.
+//    base, so a k-mer id is two funnel shifts and a mask compare.
+//    Single-base tiles keep raw bytes, with the 256-entry table in LDS.
 //  * Stores go out as aligned 16-byte groups of four ids (plus one 4-byte
-//    mask word in PADDED layout); ragged group edges fall back to scalar
-//    stores.
+//    mask word in PADDED layout); ragged group edges use scalar stores.
+//  * PADDED layout with a modest row count fuses the row scan into one
+//    extra block of the cell kernel: a single launch.
 #include "common.hpp"
 #include "device.hpp"
 
@@ -33,33 +38,17 @@ namespace dnatok {
 namespace {
 
 constexpr int NT = 256;
-
-struct EncodeArgs {
-    const uint8_t *abase;  // input base aligned down to 16 bytes
-    int64_t shift;         // d_bytes - abase
-    int64_t nbytes;
-    const int64_t *offs;
-    int32_t n;
-    int32_t k;
-    int32_t *ids;
-    int64_t cap;
-    int64_t *out_offs;
-    int8_t *mask;
-    const int32_t *lut;
-    int32_t cls;
-    int32_t padded;
-    int32_t left;
-    int32_t pad_id, cls_id, sep_id;
-    int64_t W;
-    int64_t base;
-    int64_t tileB;
-    int64_t ntiles;
-    dev::TileQueue q;
-};
+constexpr int kRowsPerThread = 16;                   // row scan: rows per thread per pass
+constexpr int64_t kUnitRows = (int64_t)NT * kRowsPerThread;
+constexpr int32_t kFuseMaxRows = 16384;              // PADDED: fold the row scan into the cell launch
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 
 // Number of body tokens of a row of L bytes.
 __device__ __forceinline__ int64_t body_tokens(int64_t L, int32_t k, bool kmer) {
-    return kmer ? (L + k - 1) / k : L;
+    if (!kmer) return L;
+    const int64_t span = L + k - 1;
+    return span < 0x7FFFFFFF ? (int64_t)((uint32_t)span / (uint32_t)k) : span / k;
 }
 
 struct Row {
@@ -71,7 +60,8 @@ __device__ __forceinline__ int64_t tokens_before(const Row &r, int64_t X, int32_
     int64_t c = 0;
     if (X > r.off) {
         // body anchors off + j*k < X  <=>  j < ceil((X - off) / k)
-        c += (X >= r.end) ? r.nb : (X - r.off + k - 1) / k;
+        const int64_t span = X - r.off + k - 1;
+        c += (X >= r.end) ? r.nb : (span < 0x7FFFFFFF ? (int64_t)((uint32_t)span / (uint32_t)k) : span / k);
         if (cls) c += 1;  // CLS anchored at off
     }
     if (cls) {
@@ -123,7 +113,168 @@ __device__ __forceinline__ void classify16(uint4 v, uint32_t &code, uint32_t &va
     }
 }
 
-__device__ __forceinline__ uint4 load_chunk(const EncodeArgs &a, int64_t q0) {
+// Id of the k-mer whose first base is tile byte idx: the 2k digit bits and k
+// validity bits are cut from two consecutive staged words with funnel shifts.
+__device__ __forceinline__ int32_t kmer_at(const uint32_t *codes, const uint32_t *valid, uint32_t idx, int32_t k) {
+    const uint32_t w = idx >> 4, o = idx & 15;
+    const uint32_t hi = codes[w], lo = codes[w + 1];
+    const uint32_t s = 64 - 2 * o - 2 * (uint32_t)k;  // 4 .. 62
+    const uint32_t x = (s >= 32) ? (hi >> (s & 31)) : __builtin_amdgcn_alignbit(hi, lo, s);
+    const uint32_t digits = x & ((1u << (2 * k)) - 1);
+    const uint32_t v32 = valid[w] | (valid[w + 1] >> 16);
+    const uint32_t km = (1u << k) - 1;
+    const bool ok = ((v32 >> (32 - o - (uint32_t)k)) & km) == km;
+    return ok ? (int32_t)(5 + digits) : DNATOK_ID_UNK;
+}
+
+// A relative cell index, or -1 when it lies before the segment (single
+// cells: CLS, SEP, short final frame).
+__device__ __forceinline__ int32_t clamp_rel(int64_t v, int64_t hi) {
+    return (int32_t)(v < -1 ? -1 : (v > hi ? hi : v));
+}
+// A bound of a relative cell range, clamped to the segment [0, hi].
+__device__ __forceinline__ int32_t clamp_cells(int64_t v, int64_t hi) {
+    return (int32_t)(v < 0 ? 0 : (v > hi ? hi : v));
+}
+
+// ---- row scan ------------------------------------------------------------------
+
+struct RowScanArgs {
+    const int64_t *offs;
+    int32_t n;
+    int64_t nbytes;
+    int64_t *out_offs;
+    int32_t k;
+    int32_t kmer;
+    int32_t cls;
+    int32_t padded;
+    int64_t W;
+    int64_t base;
+    int64_t nunits;
+    dev::TileQueue q;
+};
+
+// Lengths of the up-to-kUnitRows rows starting at row0 (validated), their
+// exclusive scan written to out_offs after `Prefix(total)` supplies the
+// unit's starting value. Returns the unit's token total.
+template <class Prefix>
+__device__ __forceinline__ int64_t rowscan_unit(const RowScanArgs &a, int64_t row0, int64_t *s_tmp, uint32_t &err,
+                                                Prefix prefix) {
+    const int tid = threadIdx.x;
+    const int64_t i0 = row0 + (int64_t)tid * kRowsPerThread;
+    int64_t len[kRowsPerThread];
+    int64_t mine = 0;
+#pragma unroll
+    for (int j = 0; j < kRowsPerThread; ++j) {
+        const int64_t i = i0 + j;
+        len[j] = 0;
+        if (i < a.n) {
+            int64_t o0 = a.offs[i], o1 = a.offs[i + 1];
+            if (o0 < 0 || o1 < o0 || o1 > a.nbytes) err |= DNATOK_DERR_OFFSETS;
+            o0 = o0 < 0 ? 0 : (o0 > a.nbytes ? a.nbytes : o0);
+            o1 = o1 < o0 ? o0 : (o1 > a.nbytes ? a.nbytes : o1);
+            len[j] = body_tokens(o1 - o0, a.k, a.kmer) + 2 * a.cls;
+            if (a.padded && len[j] > a.W) err |= DNATOK_DERR_ROW_WIDTH;
+        }
+        mine += len[j];
+    }
+    int64_t total;
+    const int64_t pre = dev::block_excl_scan<NT>(mine, s_tmp, &total);
+    int64_t run = a.base + prefix(total) + pre;
+#pragma unroll
+    for (int j = 0; j < kRowsPerThread; ++j) {
+        const int64_t i = i0 + j;
+        if (i < a.n) a.out_offs[i] = run;
+        run += len[j];
+    }
+    return total;
+}
+
+// Whole batch by one block, units in order (the fused PADDED case).
+__device__ void rowscan_single_block(const RowScanArgs &a, int64_t *s_tmp, uint32_t *err_hdr) {
+    uint32_t err = 0;
+    int64_t run = 0;
+    for (int64_t row0 = 0; row0 < a.n; row0 += kUnitRows) {
+        rowscan_unit(a, row0, s_tmp, err, [&](int64_t total) {
+            const int64_t b = run;
+            run += total;
+            return b;
+        });
+    }
+    if (threadIdx.x == 0) a.out_offs[a.n] = a.base + run;
+    if (err) dev::raise_error(err_hdr, err);
+}
+
+__global__ __launch_bounds__(NT) void k_rowscan(RowScanArgs a) {
+    __shared__ int64_t s_tmp[NT / dev::kWave + 1];
+    __shared__ int64_t s_unit, s_excl;
+    const int tid = threadIdx.x;
+    const uint32_t parity = dev::ld_relaxed32(a.q.hdr + 2);
+    uint64_t *st = parity ? a.q.status1 : a.q.status0;
+    uint64_t *st_other = parity ? a.q.status0 : a.q.status1;
+    uint32_t err = 0;
+    for (;;) {
+        if (tid == 0) s_unit = (int64_t)atomicAdd(a.q.hdr + 0, 1u);
+        __syncthreads();
+        const int64_t u = s_unit;
+        __syncthreads();
+        if (u >= a.nunits) break;
+        for (int64_t j = u + (int64_t)tid * a.nunits; j < a.q.clear_n; j += (int64_t)NT * a.nunits) st_other[j] = 0;
+        // Unit prefix through the decoupled look-back over units (wave 0).
+        const int64_t total = rowscan_unit(a, u * kUnitRows, s_tmp, err, [&](int64_t tot) {
+            if (threadIdx.x < dev::kWave) {
+                if (threadIdx.x == 0) dev::publish_aggregate(st, u, tot);
+                const int64_t ex = dev::wave_lookback(st, u, tot);
+                if (threadIdx.x == 0) s_excl = ex;
+            }
+            __syncthreads();
+            return s_excl;
+        });
+        if (u == a.nunits - 1 && tid == 0) a.out_offs[a.n] = a.base + s_excl + total;
+        __syncthreads();
+    }
+    if (err) dev::raise_error(a.q.hdr, err);
+    if (tid == 0) dev::finish_block(a.q.hdr);
+}
+
+// ---- cell kernel -------------------------------------------------------------------
+
+struct CellArgs {
+    const uint8_t *abase;  // input base aligned down to 16 bytes
+    int64_t shift;         // d_bytes - abase
+    int64_t nbytes;
+    const int64_t *offs;
+    int32_t n;
+    int32_t k;
+    int32_t *ids;
+    int64_t cap;
+    const int64_t *out_offs;  // PACKED: row starts (written by the row scan)
+    int8_t *mask;
+    const int32_t *lut;
+    int32_t cls;
+    int32_t padded;
+    int32_t left;
+    int32_t pad_id, cls_id, sep_id;
+    int64_t W;
+    int64_t base;
+    int64_t tileB;
+    int64_t ntiles;
+    int32_t fused_scan;  // the last block runs the row scan instead of tiles
+    uint32_t *err_hdr;
+    RowScanArgs scan;
+};
+
+// Per-row facts a tile needs for its owned cells (row chunk of up to NT rows).
+struct SegInfo {
+    int64_t dlo;       // destination element of the first owned cell
+    int64_t gpre;      // first 4-element store group of this segment in the chunk's group list
+    int64_t base_idx;  // tile-relative byte index of the body token at relative cell 0
+    int32_t ncell;     // owned cells
+    int32_t b0, b1;    // relative cells holding body tokens
+    int32_t cc_cls, cc_sep, cc_tail;  // relative cells of CLS, SEP and a short final k-mer (-1 if none)
+};
+
+__device__ __forceinline__ uint4 load_chunk(const CellArgs &a, int64_t q0) {
     if (q0 >= a.shift && q0 + 16 <= a.shift + a.nbytes)
         return *reinterpret_cast<const uint4 *>(a.abase + q0);
     uint32_t w[4] = {0, 0, 0, 0};
@@ -134,21 +285,48 @@ __device__ __forceinline__ uint4 load_chunk(const EncodeArgs &a, int64_t q0) {
     return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-template <bool KMER>
-__global__ __launch_bounds__(NT) void k_encode(EncodeArgs a) {
+// Put the 16-byte chunks of tile t that this thread stages in flight.
+// Tiles whose chunks all lie inside the input take branch-free vector
+// loads; only the first and last tile check bytes one by one.
+template <int U>
+__device__ __forceinline__ void fetch_tile(const CellArgs &a, int64_t t, int64_t nchunks, uint4 (&v)[U]) {
+    const int tid = threadIdx.x;
+    const bool interior = (t * a.tileB >= a.shift) && (t * a.tileB + nchunks * 16 <= a.shift + a.nbytes);
+    if (interior) {
+        const u32x4 *src = reinterpret_cast<const u32x4 *>(a.abase + t * a.tileB);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t m = (int64_t)u * NT + tid;
+            u32x4 x = {0, 0, 0, 0};
+            if (m < nchunks) x = __builtin_nontemporal_load(src + m);
+            v[u] = make_uint4(x[0], x[1], x[2], x[3]);
+        }
+    } else {
+        for (int u = 0; u < U; ++u) {
+            const int64_t m = (int64_t)u * NT + tid;
+            v[u] = (m < nchunks) ? load_chunk(a, t * a.tileB + 16 * m) : make_uint4(0, 0, 0, 0);
+        }
+    }
+}
+
+template <bool KMER, int U>
+__global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
     extern __shared__ __align__(16) uint8_t dyn[];
     __shared__ int32_t lut_s[256];
-    __shared__ int64_t s_off[NT], s_end[NT], s_nb[NT], s_clo[NT], s_chi[NT], s_dlo[NT], s_gpre[NT];
+    __shared__ SegInfo seg[NT];
     __shared__ int64_t s_tmp[NT / dev::kWave + 1];
-    __shared__ int64_t s_ticket, s_ia, s_ib, s_excl;
+    __shared__ int64_t s_ia, s_ib;
     __shared__ uint32_t s_err;
 
     const int tid = threadIdx.x;
+    if (a.fused_scan && blockIdx.x == gridDim.x - 1) {
+        rowscan_single_block(a.scan, s_tmp, a.err_hdr);
+        return;
+    }
+    const int64_t G = gridDim.x - (a.fused_scan ? 1 : 0);
     if (!KMER)
         for (int i = tid; i < 256; i += NT) lut_s[i] = a.lut[i];
-    const uint32_t parity = dev::ld_relaxed32(a.q.hdr + 2);
-    uint64_t *st = parity ? a.q.status1 : a.q.status0;
-    uint64_t *st_other = parity ? a.q.status0 : a.q.status1;
+    if (tid == 0) s_err = 0;
     const int64_t B = a.tileB;
     const int64_t nchunks = B / 16 + 1;
     uint32_t *codes = reinterpret_cast<uint32_t *>(dyn);
@@ -156,199 +334,197 @@ __global__ __launch_bounds__(NT) void k_encode(EncodeArgs a) {
     uint8_t *raw = dyn;
     const int32_t k = KMER ? a.k : 1;
     const int64_t al = (int64_t)((reinterpret_cast<uintptr_t>(a.ids) >> 2) & 3);
+    const int64_t off_first = (a.n > 0) ? a.offs[0] : 0;
+    const int64_t off_last = (a.n > 0) ? a.offs[a.n] : 0;
+    uint32_t err = 0;
 
-    for (;;) {
-        if (tid == 0) {
-            s_ticket = (int64_t)atomicAdd(a.q.hdr + 0, 1u);
-            s_err = 0;
-        }
-        __syncthreads();
-        const int64_t t = s_ticket;
-        if (t >= a.ntiles) break;
-        uint32_t err = 0;
+    auto load_row = [&](int64_t i) {
+        Row r;
+        int64_t o0 = a.offs[i], o1 = a.offs[i + 1];
+        o0 = o0 < 0 ? 0 : (o0 > a.nbytes ? a.nbytes : o0);
+        o1 = o1 < o0 ? o0 : (o1 > a.nbytes ? a.nbytes : o1);
+        r.off = o0;
+        r.end = o1;
+        r.nb = body_tokens(o1 - o0, k, KMER);
+        r.len = r.nb + 2 * a.cls;
+        return r;
+    };
 
-        // Housekeeping shares: zero the other parity's status words for the
-        // next launch, and check a strided slice of the offsets.
-        for (int64_t j = t + (int64_t)tid * a.ntiles; j < a.q.clear_n; j += (int64_t)NT * a.ntiles) st_other[j] = 0;
-        for (int64_t i = t + (int64_t)tid * a.ntiles; i < a.n; i += (int64_t)NT * a.ntiles) {
-            int64_t o0 = a.offs[i], o1 = a.offs[i + 1];
-            if (o0 < 0 || o1 < o0 || o1 > a.nbytes) err |= DNATOK_DERR_OFFSETS;
-        }
-
+    uint4 v[U];
+    int64_t t = blockIdx.x;
+    if (t < a.ntiles) fetch_tile<U>(a, t, nchunks, v);
+    for (; t < a.ntiles; t += G) {
         const int64_t P0 = t * B - a.shift;
         const int64_t P1 = (t == a.ntiles - 1) ? INT64_MAX : P0 + B;
 
-        // Stage the tile (and one halo chunk) into LDS.
-        for (int64_t m = tid; m < nchunks; m += NT) {
-            uint4 v = load_chunk(a, t * B + 16 * m);
-            if (KMER) {
-                uint32_t c, vb;
-                classify16(v, c, vb);
-                codes[m] = c;
-                valid[m] = vb;
-            } else {
-                reinterpret_cast<uint4 *>(raw)[m] = v;
+        // Stage this tile from registers into LDS, then put the next tile's
+        // loads in flight while this one is written.
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t m = (int64_t)u * NT + tid;
+            if (m < nchunks) {
+                if (KMER) {
+                    uint32_t c, vb;
+                    classify16(v[u], c, vb);
+                    codes[m] = c;
+                    valid[m] = vb;
+                } else {
+                    reinterpret_cast<uint4 *>(raw)[m] = v[u];
+                }
             }
         }
+        if (t + G < a.ntiles) fetch_tile<U>(a, t + G, nchunks, v);
 
-        // Rows with an anchor in [P0, P1): [ia, ib).
-        if (tid == 0) {
-            int64_t lo = 0, hi = a.n;
-            while (lo < hi) {
-                int64_t mid = (lo + hi) >> 1;
-                int64_t o0 = a.offs[mid], o1 = a.offs[mid + 1];
-                int64_t last = (o1 > o0) ? o1 - 1 : o0;
-                if (last >= P0) hi = mid;
-                else lo = mid + 1;
-            }
-            int64_t ia = lo;
-            hi = a.n;
+        // Wave 0: rows with an anchor in [P0, P1) are [ia, ib). The first
+        // probe window is centred on the row the byte position would fall in
+        // if rows were equally long; a miss falls back to a 64-way search.
+        if (tid < dev::kWave) {
+            auto pa = [&](int64_t i) {
+                const int64_t o0 = a.offs[i], o1 = a.offs[i + 1];
+                return ((o1 > o0) ? o1 - 1 : o0) >= P0;
+            };
+            auto pb = [&](int64_t i) { return a.offs[i] >= P1; };
+            const int64_t n = a.n;
+            int64_t guess = 0;
+            if (off_last > off_first && P0 > off_first)
+                guess = (int64_t)((double)(P0 - off_first) / (double)(off_last - off_first) * (double)n);
+            int64_t w0 = guess - dev::kWave / 2;
+            if (w0 + dev::kWave > n) w0 = n - dev::kWave;
+            if (w0 < 0) w0 = 0;
+            const int64_t w1 = (w0 + dev::kWave < n) ? w0 + dev::kWave : n;  // probe [w0, w1)
+            const int64_t q = w0 + tid;
+            const bool live = q < w1;
+            const uint64_t ba = __ballot(live ? pa(q) : true);
+            int64_t ia;
+            if (w0 > 0 && (ba & 1ull)) ia = dev::wave_lower_bound(0, w0, pa);  // answer left of the window
+            else ia = ba ? w0 + __builtin_ctzll(ba) : w1;  // inside, or w1 == n
+            if (ia == w1 && w1 < n) ia = dev::wave_lower_bound(w1, n, pa);  // right of the window
+            int64_t ib = n;
             if (P1 != INT64_MAX) {
-                while (lo < hi) {
-                    int64_t mid = (lo + hi) >> 1;
-                    if (a.offs[mid] >= P1) hi = mid;
-                    else lo = mid + 1;
+                // pb is monotone too and its answer is >= ia; reuse the window when it brackets it
+                const uint64_t bb = __ballot(live && q >= ia ? pb(q) : (q >= ia));
+                const int64_t lo = ia > w0 ? ia : w0;
+                if (lo < w1 && ia >= w0 && bb) {
+                    const int64_t cand = w0 + __builtin_ctzll(bb);
+                    ib = (cand < w1) ? cand : dev::wave_lower_bound(w1, n, pb);
+                } else {
+                    ib = dev::wave_lower_bound(ia, n, pb);
                 }
-            } else {
-                lo = a.n;
             }
-            s_ia = ia;
-            s_ib = lo;
+            if (tid == 0) {
+                s_ia = ia;
+                s_ib = ib;
+            }
         }
         __syncthreads();
         const int64_t ia = s_ia, ib = s_ib;
 
-        auto load_row = [&](int64_t i) {
-            Row r;
-            int64_t o0 = a.offs[i], o1 = a.offs[i + 1];
-            o0 = o0 < 0 ? 0 : (o0 > a.nbytes ? a.nbytes : o0);
-            o1 = o1 < o0 ? o0 : (o1 > a.nbytes ? a.nbytes : o1);
-            r.off = o0;
-            r.end = o1;
-            r.nb = body_tokens(o1 - o0, k, KMER);
-            r.len = r.nb + 2 * a.cls;
-            return r;
-        };
-
-        // Count pass: tokens owned by this tile.
-        int64_t agg = 0;
-        for (int64_t cb = ia; cb < ib; cb += NT) {
-            int64_t i = cb + tid;
-            int64_t cnt = 0;
-            if (i < ib) {
-                Row r = load_row(i);
-                cnt = tokens_before(r, P1, k, a.cls) - tokens_before(r, P0, k, a.cls);
-            }
-            agg += dev::block_sum<NT>(cnt, s_tmp);
-        }
-        if (tid == 0) s_excl = dev::lookback(st, t, agg);
-        __syncthreads();
-
         // Write pass, one chunk of up to NT rows at a time.
-        int64_t tokbase = s_excl;
         for (int64_t cb = ia; cb < ib; cb += NT) {
             const int64_t i = cb + tid;
             const int nrows = (int)((ib - cb) < NT ? (ib - cb) : NT);
-            int64_t tcnt = 0, gcnt = 0, clo = 0, chi = 0, dlo = 0;
-            Row r = {0, 0, 0, 0};
+            int64_t gcnt = 0;
             if (i < ib) {
-                r = load_row(i);
-                int64_t tlo = tokens_before(r, P0, k, a.cls), thi = tokens_before(r, P1, k, a.cls);
-                tcnt = thi - tlo;
-                if (a.padded && r.len > a.W) {
-                    err |= DNATOK_DERR_ROW_WIDTH;
-                } else {
+                const Row r = load_row(i);
+                int64_t clo = 0, chi = 0;
+                if (!(a.padded && r.len > a.W)) {
                     clo = cells_before(r, P0, k, a.cls, a.padded, a.left, a.W);
                     chi = cells_before(r, P1, k, a.cls, a.padded, a.left, a.W);
                 }
+                const int64_t ncell = chi - clo;
+                const int64_t lead = (a.padded && a.left) ? a.W - r.len : 0;
+                const int64_t tt0 = clo - lead;  // token index of the first owned cell
+                SegInfo sg;
+                sg.ncell = (int32_t)ncell;
+                sg.b0 = clamp_cells(a.cls - tt0, ncell);
+                sg.b1 = clamp_cells(a.cls + r.nb - tt0, ncell);
+                sg.cc_cls = a.cls ? clamp_rel(-tt0, ncell) : -1;
+                sg.cc_sep = a.cls ? clamp_rel(r.len - 1 - tt0, ncell) : -1;
+                sg.cc_tail = (KMER && r.nb > 0 && (r.end - r.off) % k) ? clamp_rel(a.cls + r.nb - 1 - tt0, ncell) : -1;
+                sg.base_idx = (r.off - P0) + (tt0 - a.cls) * k;
+                sg.dlo = a.padded ? i * a.W + clo : (a.out_offs[i] - a.base) + clo;
+                sg.gpre = 0;
+                seg[tid] = sg;
+                if (ncell > 0) gcnt = ((sg.dlo + al + ncell - 1) >> 2) - ((sg.dlo + al) >> 2) + 1;
             }
-            int64_t tot;
-            int64_t pre = dev::block_excl_scan<NT>(tcnt, s_tmp, &tot);
-            if (i < ib) {
-                if (r.off >= P0 && r.off < P1) a.out_offs[i] = a.base + tokbase + pre;
-                dlo = a.padded ? i * a.W + clo : tokbase + pre;
-                if (chi > clo) gcnt = ((dlo + al + (chi - clo) - 1) >> 2) - ((dlo + al) >> 2) + 1;
-            }
-            int64_t G;
-            int64_t gpre = dev::block_excl_scan<NT>(gcnt, s_tmp, &G);
-            if (i < ib) {
-                s_off[tid] = r.off;
-                s_end[tid] = r.end;
-                s_nb[tid] = r.nb;
-                s_clo[tid] = clo;
-                s_chi[tid] = chi;
-                s_dlo[tid] = dlo;
-                s_gpre[tid] = gpre;
-            }
+            int64_t G4;
+            const int64_t gpre = dev::block_excl_scan<NT>(gcnt, s_tmp, &G4);
+            if (i < ib) seg[tid].gpre = gpre;
             __syncthreads();
 
             int s = 0;
-            for (int64_t qi = tid; qi < G; qi += NT) {
+            for (int64_t qi = tid; qi < G4; qi += NT) {
                 // segment holding group qi: the last s with gpre[s] <= qi
-                if (!(s_gpre[s] <= qi && (s + 1 >= nrows || s_gpre[s + 1] > qi))) {
+                if (!(seg[s].gpre <= qi && (s + 1 >= nrows || seg[s + 1].gpre > qi))) {
                     int lo = 0, hi = nrows - 1;
                     while (lo < hi) {
                         int mid = (lo + hi + 1) >> 1;
-                        if (s_gpre[mid] <= qi) lo = mid;
+                        if (seg[mid].gpre <= qi) lo = mid;
                         else hi = mid - 1;
                     }
                     s = lo;
                 }
-                const int64_t off = s_off[s], end = s_end[s], nb = s_nb[s];
-                const int64_t len = nb + 2 * a.cls;
-                const int64_t sclo = s_clo[s], schi = s_chi[s], sdlo = s_dlo[s];
-                const int64_t eb = (((sdlo + al) >> 2) + (qi - s_gpre[s])) * 4 - al;
-                const int64_t lead = (a.padded && a.left) ? a.W - len : 0;
-                int32_t v[4];
+                const SegInfo sg = seg[s];
+                const int64_t eb = (((sg.dlo + al) >> 2) + (qi - sg.gpre)) * 4 - al;
+                const int32_t cc0 = (int32_t)(eb - sg.dlo);
+                int32_t *dst = a.ids + eb;
+                // Fast path: four body tokens, none of them a short final frame.
+                const bool fast = cc0 >= sg.b0 && cc0 + 3 < sg.b1 && (uint32_t)(sg.cc_tail - cc0) > 3u &&
+                                  (a.padded || (eb >= 0 && eb + 3 < a.cap));
+                if (fast) {
+                    const uint32_t idx0 = (uint32_t)sg.base_idx + (uint32_t)cc0 * (uint32_t)k;
+                    int32_t vv[4];
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr) {
+                        const uint32_t idx = idx0 + (uint32_t)(rr * k);
+                        if (KMER) vv[rr] = kmer_at(codes, valid, idx, k);
+                        else vv[rr] = lut_s[raw[idx]];
+                    }
+                    i32x4 x = {vv[0], vv[1], vv[2], vv[3]};
+                    __builtin_nontemporal_store(x, reinterpret_cast<i32x4 *>(dst));
+                    if (a.padded) {
+                        int8_t *md = a.mask + eb;
+                        if ((reinterpret_cast<uintptr_t>(md) & 3) == 0)
+                            __builtin_nontemporal_store(0x01010101u, reinterpret_cast<uint32_t *>(md));
+                        else
+                            for (int rr = 0; rr < 4; ++rr) md[rr] = 1;
+                    }
+                    continue;
+                }
+                int32_t vv[4];
                 uint32_t mk = 0;
                 bool in[4];
                 bool all_in = true;
 #pragma unroll
                 for (int rr = 0; rr < 4; ++rr) {
-                    const int64_t e = eb + rr;
-                    const int64_t c = sclo + (e - sdlo);
-                    in[rr] = (c >= sclo && c < schi);
-                    if (in[rr] && !a.padded && e >= a.cap) {
+                    const int32_t cc = cc0 + rr;
+                    in[rr] = (cc >= 0 && cc < sg.ncell);
+                    if (in[rr] && !a.padded && (eb + rr < 0 || eb + rr >= a.cap)) {
                         in[rr] = false;
                         err |= DNATOK_DERR_CAPACITY;
                     }
                     all_in = all_in && in[rr];
                     int32_t val = a.pad_id;
                     uint32_t m = 0;
-                    const int64_t tt = c - lead;
-                    if (in[rr] && tt >= 0 && tt < len) {
-                        m = 1;
-                        if (a.cls && tt == 0) {
+                    if (in[rr]) {
+                        if (cc >= sg.b0 && cc < sg.b1) {
+                            m = 1;
+                            const uint32_t idx = (uint32_t)sg.base_idx + (uint32_t)cc * (uint32_t)k;
+                            if (KMER) val = (cc == sg.cc_tail) ? DNATOK_ID_UNK : kmer_at(codes, valid, idx, k);
+                            else val = lut_s[raw[idx]];
+                        } else if (cc == sg.cc_cls) {
                             val = a.cls_id;
-                        } else if (a.cls && tt == len - 1) {
+                            m = 1;
+                        } else if (cc == sg.cc_sep) {
                             val = a.sep_id;
-                        } else {
-                            const int64_t j = tt - a.cls;
-                            if (KMER) {
-                                const int64_t p = off + j * k;
-                                if (p + k > end) {
-                                    val = DNATOK_ID_UNK;
-                                } else {
-                                    const int64_t idx = p - P0;
-                                    const int64_t w = idx >> 4;
-                                    const int o = (int)(idx & 15);
-                                    const uint64_t c64 = ((uint64_t)codes[w] << 32) | codes[w + 1];
-                                    const uint32_t digits = (uint32_t)((c64 << (2 * o)) >> (64 - 2 * k));
-                                    const uint32_t v32 = valid[w] | (valid[w + 1] >> 16);
-                                    const uint32_t okb = (v32 << o) >> (32 - k);
-                                    val = (okb == ((1u << k) - 1)) ? (int32_t)(5 + digits) : DNATOK_ID_UNK;
-                                }
-                            } else {
-                                val = lut_s[raw[off + j - P0]];
-                            }
+                            m = 1;
                         }
                     }
-                    v[rr] = val;
+                    vv[rr] = val;
                     mk |= m << (8 * rr);
                 }
-                int32_t *dst = a.ids + eb;
                 if (all_in) {
-                    *reinterpret_cast<int4 *>(dst) = make_int4(v[0], v[1], v[2], v[3]);
+                    *reinterpret_cast<int4 *>(dst) = make_int4(vv[0], vv[1], vv[2], vv[3]);
                     if (a.padded) {
                         int8_t *md = a.mask + eb;
                         if ((reinterpret_cast<uintptr_t>(md) & 3) == 0) {
@@ -362,30 +538,74 @@ __global__ __launch_bounds__(NT) void k_encode(EncodeArgs a) {
 #pragma unroll
                     for (int rr = 0; rr < 4; ++rr) {
                         if (!in[rr]) continue;
-                        dst[rr] = v[rr];
+                        dst[rr] = vv[rr];
                         if (a.padded) a.mask[eb + rr] = (int8_t)((mk >> (8 * rr)) & 1);
                     }
                 }
             }
             __syncthreads();
-            tokbase += tot;
         }
-        if (t == a.ntiles - 1 && tid == 0) a.out_offs[a.n] = a.base + s_excl + agg;
-        if (err) atomicOr(&s_err, err);
-        __syncthreads();
-        if (tid == 0 && s_err) dev::raise_error(a.q.hdr, s_err);
     }
-    if (tid == 0) dev::finish_block(a.q.hdr);
+    if (err) atomicOr(&s_err, err);
+    __syncthreads();
+    if (tid == 0 && s_err) dev::raise_error(a.err_hdr, s_err);
+}
+
+template <bool KMER>
+int launch_cells(const CellArgs &a, int U, int64_t grid, size_t dyn, hipStream_t stream) {
+    switch (U) {
+    case 1: hipLaunchKernelGGL((k_cells<KMER, 1>), dim3((unsigned)grid), dim3(NT), dyn, stream, a); break;
+    case 2: hipLaunchKernelGGL((k_cells<KMER, 2>), dim3((unsigned)grid), dim3(NT), dyn, stream, a); break;
+    case 4: hipLaunchKernelGGL((k_cells<KMER, 4>), dim3((unsigned)grid), dim3(NT), dyn, stream, a); break;
+    case 8: hipLaunchKernelGGL((k_cells<KMER, 8>), dim3((unsigned)grid), dim3(NT), dyn, stream, a); break;
+    case 16: hipLaunchKernelGGL((k_cells<KMER, 16>), dim3((unsigned)grid), dim3(NT), dyn, stream, a); break;
+    default: return set_error(DNATOK_EINVAL, "unsupported staging depth %d", U);
+    }
+    DNATOK_HIP(hipGetLastError());
+    return DNATOK_OK;
+}
+
+template <bool KMER>
+int blocks_per_cu(int U, size_t dyn, int *out) {
+    *out = 1;
+    switch (U) {
+    case 1: DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_cells<KMER, 1>, NT, dyn)); break;
+    case 2: DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_cells<KMER, 2>, NT, dyn)); break;
+    case 4: DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_cells<KMER, 4>, NT, dyn)); break;
+    case 8: DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_cells<KMER, 8>, NT, dyn)); break;
+    case 16: DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_cells<KMER, 16>, NT, dyn)); break;
+    default: break;
+    }
+    return DNATOK_OK;
 }
 
 }  // namespace
+
+EncodeTuning encode_tuning(bool kmer) {
+    EncodeTuning t;
+    t.tile_bytes = kmer ? 32752 : 16368;  // (U * 256 - 1) * 16: U staging loads per thread incl. the halo chunk
+    t.blocks_per_cu = 0;
+    const char *e = getenv(kmer ? "DNATOK_KMER_TILE_BYTES" : "DNATOK_LUT_TILE_BYTES");
+    if (e) {
+        long long v = atoll(e);
+        if (v >= 256 && v <= (1 << 18) && v % 16 == 0) t.tile_bytes = v;
+    }
+    e = getenv("DNATOK_BLOCKS_PER_CU");
+    if (e) t.blocks_per_cu = atoi(e);
+    return t;
+}
 
 int launch_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets,
                   int32_t n, int32_t *d_ids, int64_t cap, int64_t *d_out_offsets, int8_t *d_mask,
                   const dnatok_encode_opts &o, hipStream_t stream) {
     const bool kmer = (v->kind == DNATOK_KMER);
-    const int64_t B = kmer ? 16384 : 8192;
-    EncodeArgs a;
+    const EncodeTuning tune = encode_tuning(kmer);
+    const int64_t B = tune.tile_bytes;
+    const int64_t nchunks = B / 16 + 1;
+    int U = 1;
+    while ((int64_t)U * NT < nchunks) U <<= 1;
+
+    CellArgs a;
     const uintptr_t addr = reinterpret_cast<uintptr_t>(d_bytes);
     a.shift = (int64_t)(addr & 15);
     a.abase = d_bytes ? d_bytes - a.shift : nullptr;
@@ -409,30 +629,49 @@ int launch_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes,
     a.tileB = B;
     a.ntiles = (nbytes + a.shift) / B + 1;
 
-    Workspace *ws = nullptr;
-    int rc = get_workspace(stream, a.ntiles, &ws);
-    if (rc) return rc;
-    a.q.hdr = ws->d_hdr;
-    a.q.status0 = ws->d_status;
-    a.q.status1 = ws->d_status + ws->cap;
-    if (a.ntiles > ws->high_water) ws->high_water = a.ntiles;
-    a.q.clear_n = ws->high_water;
+    RowScanArgs &s = a.scan;
+    s.offs = d_offsets;
+    s.n = n;
+    s.nbytes = nbytes;
+    s.out_offs = d_out_offsets;
+    s.k = a.k;
+    s.kmer = kmer ? 1 : 0;
+    s.cls = a.cls;
+    s.padded = a.padded;
+    s.W = a.W;
+    s.base = a.base;
+    s.nunits = ((int64_t)n + kUnitRows - 1) / kUnitRows;
+    if (s.nunits < 1) s.nunits = 1;
 
-    const size_t dyn = kmer ? (size_t)(B / 16 + 1) * 8 : (size_t)(B / 16 + 1) * 16;
+    Workspace *ws = nullptr;
+    int rc = get_workspace(stream, s.nunits, &ws);
+    if (rc) return rc;
+    a.err_hdr = ws->d_hdr;
+    a.fused_scan = (a.padded && n <= kFuseMaxRows) ? 1 : 0;
+    if (!a.fused_scan) {
+        s.q.hdr = ws->d_hdr;
+        s.q.status0 = ws->d_status;
+        s.q.status1 = ws->d_status + ws->cap;
+        if (s.nunits > ws->high_water) ws->high_water = s.nunits;
+        s.q.clear_n = ws->high_water;
+        int per_cu = 0;
+        DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rowscan, NT, 0));
+        int64_t g = (int64_t)device_cu_count() * (per_cu > 0 ? per_cu : 1);
+        if (g > s.nunits) g = s.nunits;
+        hipLaunchKernelGGL(k_rowscan, dim3((unsigned)g), dim3(NT), 0, stream, s);
+        DNATOK_HIP(hipGetLastError());
+    }
+
+    const size_t dyn = kmer ? (size_t)nchunks * 8 : (size_t)nchunks * 16;
     int per_cu = 0;
-    if (kmer)
-        DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_encode<true>, NT, dyn));
-    else
-        DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_encode<false>, NT, dyn));
+    rc = kmer ? blocks_per_cu<true>(U, dyn, &per_cu) : blocks_per_cu<false>(U, dyn, &per_cu);
+    if (rc) return rc;
     if (per_cu < 1) per_cu = 1;
+    if (tune.blocks_per_cu > 0 && tune.blocks_per_cu < per_cu) per_cu = tune.blocks_per_cu;
     int64_t grid = (int64_t)device_cu_count() * per_cu;
     if (grid > a.ntiles) grid = a.ntiles;
-    if (kmer)
-        hipLaunchKernelGGL(k_encode<true>, dim3((unsigned)grid), dim3(NT), dyn, stream, a);
-    else
-        hipLaunchKernelGGL(k_encode<false>, dim3((unsigned)grid), dim3(NT), dyn, stream, a);
-    DNATOK_HIP(hipGetLastError());
-    return DNATOK_OK;
+    if (a.fused_scan) grid += 1;
+    return kmer ? launch_cells<true>(a, U, grid, dyn, stream) : launch_cells<false>(a, U, grid, dyn, stream);
 }
 
 }  // namespace dnatok
