@@ -6,8 +6,8 @@ Markov genome (40% soft-masked, 2% N runs, 1e-4 invalid bytes), encoded as
 non-overlapping k-mers for k = 3, 4, 5, 6 (four launches), CLS/SEP added,
 right-padded to the longest row, int32 ids plus int8 attention mask. Inputs
 are resident in HBM before timing starts; every launch reads a different
-input copy and writes a different output set (8 sets, > 1 GB) so the 256 MB
-last-level cache cannot serve a repeat.
+input copy (24 copies, 768 MiB) and writes to one of 8 output sets (1.3 GB),
+so the 256 MB last-level cache cannot serve a repeat.
 
 Extra objects on the same line:
   roofline      the encode kernel's algorithmic bytes per launch / its mean
@@ -33,7 +33,8 @@ METRIC = "tokens/s device encode + end-to-end H2D stream, % HBM/H2D peak; p50/p9
 HBM_PEAK_GBS = 8000.0
 KS = (3, 4, 5, 6)
 N_SEQS, SEQ_LEN = 4096, 8192
-SETS = 8
+SETS = 8       # output sets
+IN_SETS = 24   # input copies: 768 MiB of inputs, far beyond the 256 MB last-level cache
 
 
 def log(*a):
@@ -50,7 +51,7 @@ def encode_leg(steps: int, warmup: int):
     vocabs = {k: dt.Vocab(dt.KMER, k=k) for k in KS}
     plans = {k: dt.plan(vocabs[k], offs, add_cls_sep=True) for k in KS}  # (total, max_len)
     d_offs = torch.from_numpy(offs).cuda()
-    d_in = [torch.from_numpy(data).cuda() for _ in range(SETS)]
+    d_in = [torch.from_numpy(data).cuda() for _ in range(IN_SETS)]
     outs = []
     for s in range(SETS):
         o = {}
@@ -67,7 +68,7 @@ def encode_leg(steps: int, warmup: int):
     nbytes = data.size
 
     def launch(step, j, k):
-        x = d_in[(4 * step + j) % SETS]
+        x = d_in[(4 * step + j) % IN_SETS]
         ids, oo, mk = outs[step % SETS][k]
         dt.dnatok_encode(vocabs[k].handle, x.data_ptr(), nbytes, d_offs.data_ptr(), n, ids.data_ptr(), ids.numel(),
                          oo.data_ptr(), mk.data_ptr(), opts[k], sp)
@@ -127,6 +128,34 @@ def encode_leg(steps: int, warmup: int):
     return res
 
 
+def copy_leg(sizes=(45 << 20, 1 << 30), reps: int = 20):
+    """Plain device-to-device copies (torch's copy kernel), timed per launch
+    with HIP events like the encode: the practical HBM rate at the encode's
+    traffic size (45 MiB copy = 90 MiB moved, about one k=3 launch) and in
+    steady state (1 GiB), and the reference that calibrates the FETCH_SIZE /
+    WRITE_SIZE counters (2 * size bytes per copy)."""
+    import torch
+    out = {}
+    for nbytes in sizes:
+        srcs = [torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(7) for _ in range(4)]
+        dsts = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(4)]
+        for i in range(3):
+            dsts[i % 4].copy_(srcs[i % 4])
+        torch.cuda.synchronize()
+        evs = []
+        for i in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            dsts[i % 4].copy_(srcs[(i + 1) % 4])
+            b.record()
+            evs.append((a, b))
+        torch.cuda.synchronize()
+        ms = float(np.median([a.elapsed_time(b) for a, b in evs]))
+        out["%d_MiB" % (nbytes >> 20)] = {"ms": round(ms, 5), "GBps": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
+        del srcs, dsts
+    return out
+
+
 def cpu_baseline(data, offs, budget_s: float = 12.0):
     """The CPU oracle as written (single thread) on a bounded sample: whole
     rows of the same batch, all four k, until about ``budget_s`` seconds."""
@@ -155,6 +184,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-copy", action="store_true", help="skip the device-copy reference")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the tokenizer shards by sequences with no collective on the hot path, "
@@ -171,6 +201,11 @@ def main():
     enc = encode_leg(args.steps, args.warmup)
     log("encode: %.3e tokens/s, %.4f ms/step, per-launch ms %s" % (enc["value"], enc["ms_per_step"],
                                                                    enc["per_k_launch_ms"]))
+    copy = None
+    if not args.no_copy:
+        copy = copy_leg()
+        enc["roofline"]["device_copy"] = copy
+        log("device copy: %s" % copy)
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(enc["data"], enc["offs"])

@@ -90,40 +90,35 @@ __device__ __forceinline__ int64_t cells_before(const Row &r, int64_t X, int32_t
 }
 
 // 16 bytes -> 16 two-bit base digits (most significant first) and 16
-// validity bits (bit 31 = first byte) for the A/C/G/T/a/c/g/t test.
+// validity bits (bit 31 = first byte) for the A/C/G/T/a/c/g/t test. Per 4
+// bytes: fold case, read the digit off bits 1-2 (a->0 c->1 g->2 t->3), look
+// the canonical letter of that digit up with a byte permute, and compare;
+// multiplies gather the 2-bit digits and the validity bits.
 __device__ __forceinline__ void classify16(uint4 v, uint32_t &code, uint32_t &valid) {
-    uint32_t x[4] = {v.x, v.y, v.z, v.w};
+    const uint32_t x[4] = {v.x, v.y, v.z, v.w};
     code = 0;
     valid = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        uint32_t f = x[q] | 0x20202020u;  // fold case: only A/a (etc.) map to a (etc.)
-        uint32_t d = ((f >> 1) ^ (f >> 2)) & 0x03030303u;  // a->0 c->1 g->2 t->3
-        auto nz = [](uint32_t z) { return ((z & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | z; };
-        uint32_t hit = ~(nz(f ^ 0x61616161u) & nz(f ^ 0x63636363u) & nz(f ^ 0x67676767u) & nz(f ^ 0x74747474u)) &
-                       0x80808080u;
-        // digits of bytes 0..3 -> 8 bits, byte 0 most significant
-        uint32_t r = __builtin_bswap32(d);
-        uint32_t t = r | (r >> 6);
-        uint32_t p = (t & 0xFu) | ((t >> 12) & 0xF0u);
-        code |= p << (24 - 8 * q);
-        // validity bits of bytes 0..3 -> 4 bits, byte 0 most significant
-        uint32_t vb = ((hit >> 7) * 0x80402010u) >> 28;
-        valid |= vb << (28 - 4 * q);
+        const uint32_t f = x[q] | 0x20202020u;  // only A/a map to a (likewise c, g, t)
+        const uint32_t d = ((f >> 1) ^ (f >> 2)) & 0x03030303u;
+        const uint32_t canon = __builtin_amdgcn_perm(0u, 0x74676361u, d);  // "acgt"[d] per byte
+        const uint32_t z = f ^ canon;
+        const uint32_t bad = (((z & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | z) & 0x80808080u;  // byte != letter
+        code |= ((d * 0x40100401u) >> 24) << (24 - 8 * q);
+        valid |= ((((bad ^ 0x80808080u) >> 7) * 0x80402010u) >> 28) << (28 - 4 * q);
     }
 }
 
-// Id of the k-mer whose first base is tile byte idx: the 2k digit bits and k
-// validity bits are cut from two consecutive staged words with funnel shifts.
-__device__ __forceinline__ int32_t kmer_at(const uint32_t *codes, const uint32_t *valid, uint32_t idx, int32_t k) {
+// Id of the k-mer whose first base is tile byte idx. win64[m] holds the
+// digits of chunks m and m+1 (32 bases, first base in the top bits) and
+// val32[m] their validity bits, so any k-mer (k <= 15) starting in chunk m
+// is one shift of win64[m] and one of val32[m].
+__device__ __forceinline__ int32_t kmer_at(const uint64_t *win64, const uint32_t *val32, uint32_t idx, int32_t k) {
     const uint32_t w = idx >> 4, o = idx & 15;
-    const uint32_t hi = codes[w], lo = codes[w + 1];
-    const uint32_t s = 64 - 2 * o - 2 * (uint32_t)k;  // 4 .. 62
-    const uint32_t x = (s >= 32) ? (hi >> (s & 31)) : __builtin_amdgcn_alignbit(hi, lo, s);
-    const uint32_t digits = x & ((1u << (2 * k)) - 1);
-    const uint32_t v32 = valid[w] | (valid[w + 1] >> 16);
+    const uint32_t digits = (uint32_t)(win64[w] >> (64 - 2 * (o + (uint32_t)k))) & ((1u << (2 * k)) - 1);
     const uint32_t km = (1u << k) - 1;
-    const bool ok = ((v32 >> (32 - o - (uint32_t)k)) & km) == km;
+    const bool ok = ((val32[w] >> (32 - o - (uint32_t)k)) & km) == km;
     return ok ? (int32_t)(5 + digits) : DNATOK_ID_UNK;
 }
 
@@ -285,27 +280,30 @@ __device__ __forceinline__ uint4 load_chunk(const CellArgs &a, int64_t q0) {
     return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-// Put the 16-byte chunks of tile t that this thread stages in flight.
-// Tiles whose chunks all lie inside the input take branch-free vector
-// loads; only the first and last tile check bytes one by one.
+// Put the 16-byte chunks of tile t that this thread stages in flight:
+// chunk u * NT + tid for u < U, plus (thread 0) the halo chunk U * NT that
+// holds the first bytes of the next tile. Tiles whose chunks all lie inside
+// the input take branch-free vector loads; only the first and last tile
+// check bytes one by one.
 template <int U>
-__device__ __forceinline__ void fetch_tile(const CellArgs &a, int64_t t, int64_t nchunks, uint4 (&v)[U]) {
+__device__ __forceinline__ void fetch_tile(const CellArgs &a, int64_t t, uint4 (&v)[U], uint4 &halo) {
     const int tid = threadIdx.x;
+    constexpr int64_t nchunks = (int64_t)U * NT + 1;
     const bool interior = (t * a.tileB >= a.shift) && (t * a.tileB + nchunks * 16 <= a.shift + a.nbytes);
     if (interior) {
         const u32x4 *src = reinterpret_cast<const u32x4 *>(a.abase + t * a.tileB);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t m = (int64_t)u * NT + tid;
-            u32x4 x = {0, 0, 0, 0};
-            if (m < nchunks) x = __builtin_nontemporal_load(src + m);
+            const u32x4 x = __builtin_nontemporal_load(src + (int64_t)u * NT + tid);
             v[u] = make_uint4(x[0], x[1], x[2], x[3]);
         }
-    } else {
-        for (int u = 0; u < U; ++u) {
-            const int64_t m = (int64_t)u * NT + tid;
-            v[u] = (m < nchunks) ? load_chunk(a, t * a.tileB + 16 * m) : make_uint4(0, 0, 0, 0);
+        if (tid == 0) {
+            const u32x4 x = __builtin_nontemporal_load(src + (int64_t)U * NT);
+            halo = make_uint4(x[0], x[1], x[2], x[3]);
         }
+    } else {
+        for (int u = 0; u < U; ++u) v[u] = load_chunk(a, t * a.tileB + 16 * ((int64_t)u * NT + tid));
+        if (tid == 0) halo = load_chunk(a, t * a.tileB + 16 * (int64_t)U * NT);
     }
 }
 
@@ -327,10 +325,10 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
     if (!KMER)
         for (int i = tid; i < 256; i += NT) lut_s[i] = a.lut[i];
     if (tid == 0) s_err = 0;
-    const int64_t B = a.tileB;
-    const int64_t nchunks = B / 16 + 1;
-    uint32_t *codes = reinterpret_cast<uint32_t *>(dyn);
-    uint32_t *valid = codes + nchunks;
+    const int64_t B = a.tileB;  // == U * NT * 16
+    constexpr int64_t nchunks = (int64_t)U * NT + 1;
+    uint64_t *win64 = reinterpret_cast<uint64_t *>(dyn);                 // KMER: nchunks
+    uint32_t *val32 = reinterpret_cast<uint32_t *>(win64 + nchunks);     // KMER: nchunks
     uint8_t *raw = dyn;
     const int32_t k = KMER ? a.k : 1;
     const int64_t al = (int64_t)((reinterpret_cast<uintptr_t>(a.ids) >> 2) & 3);
@@ -351,29 +349,37 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
     };
 
     uint4 v[U];
+    uint4 halo = make_uint4(0, 0, 0, 0);
     int64_t t = blockIdx.x;
-    if (t < a.ntiles) fetch_tile<U>(a, t, nchunks, v);
+    if (t < a.ntiles) fetch_tile<U>(a, t, v, halo);
     for (; t < a.ntiles; t += G) {
         const int64_t P0 = t * B - a.shift;
         const int64_t P1 = (t == a.ntiles - 1) ? INT64_MAX : P0 + B;
 
         // Stage this tile from registers into LDS, then put the next tile's
         // loads in flight while this one is written.
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t m = (int64_t)u * NT + tid;
-            if (m < nchunks) {
-                if (KMER) {
-                    uint32_t c, vb;
-                    classify16(v[u], c, vb);
-                    codes[m] = c;
-                    valid[m] = vb;
-                } else {
-                    reinterpret_cast<uint4 *>(raw)[m] = v[u];
+        auto stage = [&](int64_t m, uint4 x) {
+            if (KMER) {
+                // chunk m's digits are the high half of window m and the low
+                // half of window m-1 (likewise its validity bits)
+                uint32_t c, vb;
+                classify16(x, c, vb);
+                uint32_t *w32 = reinterpret_cast<uint32_t *>(win64);
+                uint16_t *v16 = reinterpret_cast<uint16_t *>(val32);
+                w32[2 * m + 1] = c;
+                v16[2 * m + 1] = (uint16_t)(vb >> 16);
+                if (m > 0) {
+                    w32[2 * m - 2] = c;
+                    v16[2 * m - 2] = (uint16_t)(vb >> 16);
                 }
+            } else {
+                reinterpret_cast<uint4 *>(raw)[m] = x;
             }
-        }
-        if (t + G < a.ntiles) fetch_tile<U>(a, t + G, nchunks, v);
+        };
+#pragma unroll
+        for (int u = 0; u < U; ++u) stage((int64_t)u * NT + tid, v[u]);
+        if (tid == 0) stage(nchunks - 1, halo);
+        if (t + G < a.ntiles) fetch_tile<U>(a, t + G, v, halo);
 
         // Wave 0: rows with an anchor in [P0, P1) are [ia, ib). The first
         // probe window is centred on the row the byte position would fall in
@@ -452,21 +458,31 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
             if (i < ib) seg[tid].gpre = gpre;
             __syncthreads();
 
-            int s = 0;
+            // Groups walk segments in order: cache the current segment's facts
+            // in registers and reload them only when a group crosses into
+            // another segment.
+            int s = -1;
+            int64_t seg_lo = 0, seg_hi = -1;  // groups [seg_lo, seg_hi) belong to segment s
+            SegInfo sg{};
+            int64_t gb = 0;      // aligned group index of the segment's first group, minus gpre
+            int32_t ccb = 0;     // relative cell of the first element of group qi = ccb + 4 * (qi - seg_lo)
             for (int64_t qi = tid; qi < G4; qi += NT) {
-                // segment holding group qi: the last s with gpre[s] <= qi
-                if (!(seg[s].gpre <= qi && (s + 1 >= nrows || seg[s + 1].gpre > qi))) {
+                if (qi < seg_lo || qi >= seg_hi) {
                     int lo = 0, hi = nrows - 1;
-                    while (lo < hi) {
+                    while (lo < hi) {  // last segment with gpre <= qi
                         int mid = (lo + hi + 1) >> 1;
                         if (seg[mid].gpre <= qi) lo = mid;
                         else hi = mid - 1;
                     }
                     s = lo;
+                    sg = seg[s];
+                    seg_lo = sg.gpre;
+                    seg_hi = (s + 1 < nrows) ? seg[s + 1].gpre : G4;
+                    gb = ((sg.dlo + al) >> 2) - sg.gpre;
+                    ccb = (int32_t)((((sg.dlo + al) >> 2) * 4 - al) - sg.dlo);
                 }
-                const SegInfo sg = seg[s];
-                const int64_t eb = (((sg.dlo + al) >> 2) + (qi - sg.gpre)) * 4 - al;
-                const int32_t cc0 = (int32_t)(eb - sg.dlo);
+                const int64_t eb = (gb + qi) * 4 - al;
+                const int32_t cc0 = ccb + 4 * (int32_t)(qi - seg_lo);
                 int32_t *dst = a.ids + eb;
                 // Fast path: four body tokens, none of them a short final frame.
                 const bool fast = cc0 >= sg.b0 && cc0 + 3 < sg.b1 && (uint32_t)(sg.cc_tail - cc0) > 3u &&
@@ -477,7 +493,7 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
 #pragma unroll
                     for (int rr = 0; rr < 4; ++rr) {
                         const uint32_t idx = idx0 + (uint32_t)(rr * k);
-                        if (KMER) vv[rr] = kmer_at(codes, valid, idx, k);
+                        if (KMER) vv[rr] = kmer_at(win64, val32, idx, k);
                         else vv[rr] = lut_s[raw[idx]];
                     }
                     i32x4 x = {vv[0], vv[1], vv[2], vv[3]};
@@ -510,7 +526,7 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
                         if (cc >= sg.b0 && cc < sg.b1) {
                             m = 1;
                             const uint32_t idx = (uint32_t)sg.base_idx + (uint32_t)cc * (uint32_t)k;
-                            if (KMER) val = (cc == sg.cc_tail) ? DNATOK_ID_UNK : kmer_at(codes, valid, idx, k);
+                            if (KMER) val = (cc == sg.cc_tail) ? DNATOK_ID_UNK : kmer_at(win64, val32, idx, k);
                             else val = lut_s[raw[idx]];
                         } else if (cc == sg.cc_cls) {
                             val = a.cls_id;
@@ -583,12 +599,12 @@ int blocks_per_cu(int U, size_t dyn, int *out) {
 
 EncodeTuning encode_tuning(bool kmer) {
     EncodeTuning t;
-    t.tile_bytes = kmer ? 32752 : 16368;  // (U * 256 - 1) * 16: U staging loads per thread incl. the halo chunk
+    t.tile_bytes = kmer ? 32768 : 16384;
     t.blocks_per_cu = 0;
     const char *e = getenv(kmer ? "DNATOK_KMER_TILE_BYTES" : "DNATOK_LUT_TILE_BYTES");
     if (e) {
         long long v = atoll(e);
-        if (v >= 256 && v <= (1 << 18) && v % 16 == 0) t.tile_bytes = v;
+        if (v >= 4096 && v <= 65536) t.tile_bytes = v;  // rounded up to a power of two
     }
     e = getenv("DNATOK_BLOCKS_PER_CU");
     if (e) t.blocks_per_cu = atoi(e);
@@ -600,10 +616,10 @@ int launch_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes,
                   const dnatok_encode_opts &o, hipStream_t stream) {
     const bool kmer = (v->kind == DNATOK_KMER);
     const EncodeTuning tune = encode_tuning(kmer);
-    const int64_t B = tune.tile_bytes;
+    int U = 1;  // staging loads per thread: tiles are U * NT * 16 bytes
+    while (U < 16 && (int64_t)U * NT * 16 < tune.tile_bytes) U <<= 1;
+    const int64_t B = (int64_t)U * NT * 16;
     const int64_t nchunks = B / 16 + 1;
-    int U = 1;
-    while ((int64_t)U * NT < nchunks) U <<= 1;
 
     CellArgs a;
     const uintptr_t addr = reinterpret_cast<uintptr_t>(d_bytes);
@@ -627,7 +643,9 @@ int launch_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes,
     a.W = a.padded ? o.pad_to : 0;
     a.base = o.offset_base;
     a.tileB = B;
-    a.ntiles = (nbytes + a.shift) / B + 1;
+    // the last tile also owns the end position (anchors of trailing empty rows)
+    a.ntiles = (nbytes + a.shift + B - 1) / B;
+    if (a.ntiles < 1) a.ntiles = 1;
 
     RowScanArgs &s = a.scan;
     s.offs = d_offsets;
@@ -662,14 +680,17 @@ int launch_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes,
         DNATOK_HIP(hipGetLastError());
     }
 
-    const size_t dyn = kmer ? (size_t)nchunks * 8 : (size_t)nchunks * 16;
+    const size_t dyn = kmer ? (size_t)nchunks * 12 : (size_t)nchunks * 16;
     int per_cu = 0;
     rc = kmer ? blocks_per_cu<true>(U, dyn, &per_cu) : blocks_per_cu<false>(U, dyn, &per_cu);
     if (rc) return rc;
     if (per_cu < 1) per_cu = 1;
     if (tune.blocks_per_cu > 0 && tune.blocks_per_cu < per_cu) per_cu = tune.blocks_per_cu;
-    int64_t grid = (int64_t)device_cu_count() * per_cu;
-    if (grid > a.ntiles) grid = a.ntiles;
+    // As many blocks as fit, then evened out so every block walks the same
+    // number of tiles (no straggler round).
+    const int64_t gmax = (int64_t)device_cu_count() * per_cu;
+    const int64_t per_block = (a.ntiles + gmax - 1) / gmax;
+    int64_t grid = (a.ntiles + per_block - 1) / per_block;
     if (a.fused_scan) grid += 1;
     return kmer ? launch_cells<true>(a, U, grid, dyn, stream) : launch_cells<false>(a, U, grid, dyn, stream);
 }
