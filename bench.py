@@ -156,6 +156,99 @@ def copy_leg(sizes=(45 << 20, 1 << 30), reps: int = 20):
     return out
 
 
+STREAM_BYTES = 1 << 31
+STREAM_CHUNK = 64 << 20
+STREAM_WINDOW = 6000
+STREAM_K = 6
+
+
+def stream_leg(passes: int = 3):
+    """End-to-end pinned host -> device stream: 2 GiB of synthetic chromosomes
+    (16 records, log-uniform lengths scaled to 2 GiB, same genome model as
+    the batched workload) pushed in 64 MiB chunks, cut into 6000-base windows
+    and encoded as 6-mers on the device. Reported against the pinned H2D rate
+    measured on the same buffer (64 MiB copies back to back into a 3-slot
+    ring), for the overlapped stream and the sequential baseline."""
+    import torch
+    import paper_2601_05531_amd as dt
+    import synth
+
+    lens = synth.chromosome_lengths(total=STREAM_BYTES)
+    t0 = time.perf_counter()
+    h = torch.empty(STREAM_BYTES, dtype=torch.uint8, pin_memory=True)
+    synth.chromosomes(lens, out=h.numpy())
+    log("stream: generated %d bytes of chromosomes in %.1f s" % (STREAM_BYTES, time.perf_counter() - t0))
+    starts = np.concatenate([[0], np.cumsum(lens)])
+    n_windows = int(sum(-(-int(L) // STREAM_WINDOW) for L in lens))
+    n_tokens = 0
+    for L in lens:
+        full, rem = divmod(int(L), STREAM_WINDOW)
+        n_tokens += full * (-(-STREAM_WINDOW // STREAM_K)) + (-(-rem // STREAM_K))
+
+    # measured pinned H2D rate (copy engine), same chunking
+    ring = [torch.empty(STREAM_CHUNK, dtype=torch.uint8, device="cuda") for _ in range(3)]
+    rates = []
+    for p in range(passes):
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for i, c0 in enumerate(range(0, STREAM_BYTES, STREAM_CHUNK)):
+            ring[i % 3].copy_(h[c0:c0 + STREAM_CHUNK], non_blocking=True)
+        b.record()
+        torch.cuda.synchronize()
+        rates.append(STREAM_BYTES / (a.elapsed_time(b) * 1e-3) / 1e9)
+    h2d = float(np.median(rates))
+    del ring
+
+    v = dt.Vocab(dt.KMER, k=STREAM_K)
+    out = {"h2d_GBps": round(h2d, 2), "h2d_passes_GBps": [round(r, 2) for r in rates],
+           "bytes": STREAM_BYTES, "windows": n_windows, "tokens": n_tokens}
+    sample_ok = None
+    for mode, overlap in (("overlap", True), ("baseline", False)):
+        st = dt.Stream(v, STREAM_WINDOW, STREAM_CHUNK, n_tokens, n_windows, n_slots=3, overlap=overlap)
+        times = []
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for c0 in range(0, STREAM_BYTES, STREAM_CHUNK):
+                c1 = c0 + STREAM_CHUNK
+                ends = starts[1:][(starts[1:] > c0) & (starts[1:] <= c1)] - c0
+                st.push(h[c0:c1], ends)
+            ids, woff, r = st.flush(copy=False)
+            times.append(time.perf_counter() - t0)
+            assert r.n_tokens == n_tokens and r.n_windows == n_windows
+            if sample_ok is None:
+                sample_ok = _stream_sample_check(h, lens, ids, woff)
+            if rep == 0:
+                st.reset()
+        st.close()
+        t = min(times)
+        out[mode] = {"s": round(t, 4), "tokens_per_s": n_tokens / t, "GBps": STREAM_BYTES / t / 1e9,
+                     "frac_of_h2d": round(STREAM_BYTES / t / 1e9 / h2d, 4)}
+        log("stream %s: %.3e tokens/s, %.1f GB/s (%.0f%% of pinned H2D %.1f GB/s)" % (
+            mode, n_tokens / t, STREAM_BYTES / t / 1e9, 100 * STREAM_BYTES / t / 1e9 / h2d, h2d))
+    out["sample_check"] = sample_ok
+    del h
+    return out
+
+
+def _stream_sample_check(h, lens, ids, woff, n_windows_checked: int = 64):
+    """Oracle check of a seeded sample of the stream's windows."""
+    import oracle
+    woffs_all = oracle.windows(lens, STREAM_WINDOW)
+    rng = np.random.default_rng(0)
+    pick = np.sort(rng.choice(len(woffs_all) - 1, size=n_windows_checked, replace=False))
+    hb = h.numpy()
+    d_off = woff.cpu().numpy()
+    for w in pick:
+        a, b = int(woffs_all[w]), int(woffs_all[w + 1])
+        want, _ = oracle.encode(oracle.KMER, hb[a:b], np.array([0, b - a]), k=STREAM_K)
+        got = ids[int(d_off[w]):int(d_off[w + 1])].cpu().numpy()
+        if not np.array_equal(got, want):
+            return False
+    return True
+
+
 def cpu_baseline(data, offs, budget_s: float = 12.0):
     """The CPU oracle as written (single thread) on a bounded sample: whole
     rows of the same batch, all four k, until about ``budget_s`` seconds."""
@@ -185,6 +278,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-copy", action="store_true", help="skip the device-copy reference")
+    ap.add_argument("--no-stream", action="store_true", help="skip the 2 GiB host-to-device stream leg")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the tokenizer shards by sequences with no collective on the hot path, "
@@ -206,6 +300,9 @@ def main():
         copy = copy_leg()
         enc["roofline"]["device_copy"] = copy
         log("device copy: %s" % copy)
+    stream = None
+    if not args.no_stream:
+        stream = stream_leg()
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(enc["data"], enc["offs"])
@@ -232,6 +329,7 @@ def main():
         },
         "roofline": enc["roofline"],
         "cpu_baseline": cpu,
+        "stream": stream,
     }
     print(json.dumps(line), flush=True)
 

@@ -204,6 +204,82 @@ int dnatok_sync_status(void *stream, uint32_t *flags);
 int dnatok_decode(const dnatok_vocab *v, const int32_t *d_ids, int64_t n_ids, const int64_t *d_offsets,
                   int32_t n, uint8_t *d_out, int64_t out_capacity, int64_t *d_out_offsets, void *stream);
 
+/* ---- host-to-device stream ------------------------------------------------------
+ *
+ * A pinned-memory host-to-device stream overlapped with encode (paper:
+ * Design, "Pipelined streaming": separate streams, pre-allocated device
+ * buffers, events ordering copies against compute; the paper pipelines
+ * 32/64-bit ids, this stream moves raw bytes and encodes on the device, as
+ * the bytes path prescribes). Long records (chromosomes) are cut into
+ * windows of `window` bases counted from each record's start, the last
+ * window of a record being shorter; the output equals dnatok_encode over
+ * the ragged batch of all windows in order (PACKED).
+ *
+ * Pushed chunks land in a ring of `n_slots` device buffers. Each slot has a
+ * prefix area in front of its data so the unfinished window at the end of
+ * one chunk (at most window - 1 bytes) is copied device-to-device in front
+ * of the next chunk and every window stays contiguous. Copies run on a side
+ * stream the library owns; encodes run on the caller's compute stream;
+ * events order slot reuse, so the host never waits inside the loop.
+ * overlap = 0 issues copy and encode on the compute stream in order (the
+ * paper's streaming baseline).
+ */
+typedef struct dnatok_stream dnatok_stream;
+
+typedef struct dnatok_stream_opts {
+    int64_t window;       /* bases per window, >= 1 */
+    int64_t chunk_bytes;  /* largest push, > 0 */
+    int32_t n_slots;      /* device landing buffers, >= 2 (3 = triple buffering) */
+    int32_t add_cls_sep;  /* 0/1: [CLS] window [SEP] */
+    int32_t overlap;      /* 1: copies overlapped with encode; 0: sequential baseline */
+    int32_t reserved;
+    int64_t max_tokens;   /* capacity of the library-owned output id buffer */
+    int64_t max_windows;  /* capacity of the window offset buffer (max_windows + 1 entries) */
+} dnatok_stream_opts;
+
+typedef struct dnatok_stream_result {
+    const int32_t *d_ids;            /* device int32[n_tokens], library-owned */
+    const int64_t *d_window_offsets; /* device int64[n_windows + 1], library-owned */
+    int64_t n_windows;
+    int64_t n_tokens;
+    int64_t n_bytes;                 /* bytes pushed */
+} dnatok_stream_result;
+
+/*
+ * Create a stream for vocabulary v (SINGLE, LUT256 or KMER: their token
+ * counts are known on the host; BPE -> EVOCAB) whose encodes run on
+ * `compute_stream`. Allocates the slots, the output buffers and a copy
+ * stream. Errors: EINVAL, EVOCAB, ENOMEM, EDEVICE.
+ */
+int dnatok_stream_create(const dnatok_vocab *v, const dnatok_stream_opts *opts, void *compute_stream,
+                         dnatok_stream **out);
+
+/*
+ * Push nbytes (<= chunk_bytes) of pinned host memory (hipHostMalloc or
+ * torch pin_memory; pageable memory -> EINVAL). record_ends lists, in
+ * non-decreasing order, the positions in [0, nbytes] at which a record ends
+ * inside this chunk (n_ends may be 0: the current record continues). The
+ * call only enqueues work; h_pinned must stay valid and unchanged until
+ * dnatok_stream_flush returns. Capacity (ETOOSMALL) and argument errors are
+ * found on the host before anything is enqueued, so a failed push leaves no
+ * partial or duplicated windows; after a failure the stream refuses further
+ * pushes (ESTATE) until reset.
+ */
+int dnatok_stream_push(dnatok_stream *s, const uint8_t *h_pinned, int64_t nbytes, const int64_t *record_ends,
+                       int32_t n_ends);
+
+/*
+ * End the current record (its unfinished window becomes the last window),
+ * wait for all work, and describe the output. The stream then refuses
+ * pushes (ESTATE) until dnatok_stream_reset.
+ */
+int dnatok_stream_flush(dnatok_stream *s, dnatok_stream_result *out);
+
+/* Forget all windows and start a new stream, keeping the buffers. */
+int dnatok_stream_reset(dnatok_stream *s);
+
+int dnatok_stream_destroy(dnatok_stream *s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -57,6 +57,29 @@ class dnatok_encode_opts(ctypes.Structure):
     ]
 
 
+class dnatok_stream_opts(ctypes.Structure):
+    _fields_ = [
+        ("window", ctypes.c_int64),
+        ("chunk_bytes", ctypes.c_int64),
+        ("n_slots", ctypes.c_int32),
+        ("add_cls_sep", ctypes.c_int32),
+        ("overlap", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("max_tokens", ctypes.c_int64),
+        ("max_windows", ctypes.c_int64),
+    ]
+
+
+class dnatok_stream_result(ctypes.Structure):
+    _fields_ = [
+        ("d_ids", ctypes.c_void_p),
+        ("d_window_offsets", ctypes.c_void_p),
+        ("n_windows", ctypes.c_int64),
+        ("n_tokens", ctypes.c_int64),
+        ("n_bytes", ctypes.c_int64),
+    ]
+
+
 _lib = None
 
 
@@ -87,8 +110,14 @@ def lib():
                                     ctypes.POINTER(dnatok_encode_opts), vp]
         L.dnatok_sync_status.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32)]
         L.dnatok_decode.argtypes = [vp, vp, i64, vp, i32, vp, i64, vp, vp]
+        L.dnatok_stream_create.argtypes = [vp, ctypes.POINTER(dnatok_stream_opts), vp, ctypes.POINTER(vp)]
+        L.dnatok_stream_push.argtypes = [vp, vp, i64, vp, i32]
+        L.dnatok_stream_flush.argtypes = [vp, ctypes.POINTER(dnatok_stream_result)]
+        L.dnatok_stream_reset.argtypes = [vp]
+        L.dnatok_stream_destroy.argtypes = [vp]
         for name in ("dnatok_vocab_create", "dnatok_vocab_destroy", "dnatok_vocab_info", "dnatok_encode_plan",
-                     "dnatok_encode", "dnatok_sync_status", "dnatok_decode"):
+                     "dnatok_encode", "dnatok_sync_status", "dnatok_decode", "dnatok_stream_create",
+                     "dnatok_stream_push", "dnatok_stream_flush", "dnatok_stream_reset", "dnatok_stream_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -149,6 +178,30 @@ def dnatok_sync_status(stream) -> int:
 def dnatok_decode(handle, d_ids, n_ids, d_offsets, n, d_out, out_capacity, d_out_offsets, stream) -> int:
     return _check(lib().dnatok_decode(handle, d_ids, n_ids, d_offsets, n, d_out, out_capacity, d_out_offsets,
                                       stream))
+
+
+def dnatok_stream_create(vocab_handle, opts: dnatok_stream_opts, compute_stream) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().dnatok_stream_create(vocab_handle, ctypes.byref(opts), compute_stream, ctypes.byref(h)))
+    return h.value
+
+
+def dnatok_stream_push(handle, h_pinned, nbytes, record_ends, n_ends) -> int:
+    return _check(lib().dnatok_stream_push(handle, h_pinned, nbytes, record_ends, n_ends))
+
+
+def dnatok_stream_flush(handle) -> dnatok_stream_result:
+    r = dnatok_stream_result()
+    _check(lib().dnatok_stream_flush(handle, ctypes.byref(r)))
+    return r
+
+
+def dnatok_stream_reset(handle) -> int:
+    return _check(lib().dnatok_stream_reset(handle))
+
+
+def dnatok_stream_destroy(handle) -> int:
+    return _check(lib().dnatok_stream_destroy(handle))
 
 
 # ---- torch-facing helpers ----------------------------------------------------------
@@ -252,6 +305,68 @@ def decode(vocab: Vocab, d_ids, d_offsets, out_capacity=None, stream=None):
     dnatok_decode(vocab.handle, _ptr(d_ids), d_ids.numel(), _ptr(d_offsets), n, _ptr(out), cap, _ptr(out_off),
                   _stream_ptr(stream))
     return out, out_off
+
+
+class Stream:
+    """Owning wrapper of a ``dnatok_stream``: pinned host chunks in, windows of
+    ``window`` bases encoded on the device (see ``dnatok_stream_*``)."""
+
+    def __init__(self, vocab: Vocab, window: int, chunk_bytes: int, max_tokens: int, max_windows: int,
+                 n_slots: int = 3, add_cls_sep: bool = False, overlap: bool = True, stream=None):
+        o = dnatok_stream_opts()
+        o.window, o.chunk_bytes, o.n_slots = window, chunk_bytes, n_slots
+        o.add_cls_sep, o.overlap = int(add_cls_sep), int(overlap)
+        o.max_tokens, o.max_windows = max_tokens, max_windows
+        self.vocab = vocab
+        self.handle = dnatok_stream_create(vocab.handle, o, _stream_ptr(stream))
+
+    def push(self, h_chunk, record_ends=()):
+        """``h_chunk``: pinned uint8 CPU tensor (a slice of one is fine)."""
+        ends = np.ascontiguousarray(record_ends, dtype=np.int64)
+        dnatok_stream_push(self.handle, h_chunk.data_ptr(), h_chunk.numel(),
+                           ends.ctypes.data if len(ends) else None, len(ends))
+
+    def flush(self, copy: bool = True):
+        """Returns ``(ids, window_offsets, result)``: device tensors over the
+        stream's output (torch-owned copies, or zero-copy views valid until
+        reset/close when ``copy`` is False)."""
+        r = dnatok_stream_flush(self.handle)
+        ids = device_view(r.d_ids, r.n_tokens, "<i4")
+        woff = device_view(r.d_window_offsets, r.n_windows + 1, "<i8")
+        if copy:
+            ids, woff = ids.clone(), woff.clone()
+        return ids, woff, r
+
+    def reset(self):
+        dnatok_stream_reset(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            dnatok_stream_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _DeviceArray:
+    """Exposes library-owned device memory through __cuda_array_interface__."""
+
+    def __init__(self, ptr, n, typestr):
+        self.__cuda_array_interface__ = {"shape": (int(n),), "typestr": typestr, "data": (int(ptr or 0), False),
+                                         "version": 3, "strides": None}
+
+
+def device_view(ptr, n, typestr):
+    """Zero-copy torch tensor over device memory the library owns."""
+    import torch
+    if n == 0:
+        return torch.empty(0, dtype={"<i4": torch.int32, "<i8": torch.int64, "|u1": torch.uint8}[typestr],
+                           device="cuda")
+    return torch.as_tensor(_DeviceArray(ptr, n, typestr), device="cuda")
 
 
 def sync_status(stream=None) -> int:
