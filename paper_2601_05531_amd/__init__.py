@@ -291,6 +291,10 @@ def encode(vocab: Vocab, d_bytes, d_offsets, h_offsets=None, add_cls_sep=False, 
                   _ptr(out_off), _ptr(mask), opts, _stream_ptr(stream))
     if layout == PADDED:
         return ids[:cap].view(n, W) if n else ids[:0].view(0, W), out_off, mask[:cap].view(n, W) if n else mask[:0]
+    if vocab.kind == BPE:
+        # the plan is an upper bound for BPE (one token per base); the real
+        # total is known once the device has encoded (a synchronising read)
+        total = int(out_off[n].item())
     return ids[:total], out_off, None
 
 

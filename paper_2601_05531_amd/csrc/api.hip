@@ -275,7 +275,9 @@ int dnatok_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes,
     DNATOK_HIP(hipGetDevice(&dev));
     if (dev != v->device) return set_error(DNATOK_EINVAL, "vocabulary lives on device %d, current is %d", v->device, dev);
     clear_error();
-    if (v->kind == DNATOK_BPE) return set_error(DNATOK_EVOCAB, "BPE encode is not available in this build");
+    if (v->kind == DNATOK_BPE)
+        return launch_bpe_encode(v, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets, d_mask, o,
+                                 static_cast<hipStream_t>(stream));
     return launch_encode(v, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets, d_mask, o,
                          static_cast<hipStream_t>(stream));
 }

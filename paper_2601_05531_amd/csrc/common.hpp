@@ -28,15 +28,27 @@ void clear_error();
 
 // ---- vocabulary ----------------------------------------------------------------
 
-// Device-side merge lookup: open-addressing table of (left, right) -> rank,
-// sized to a power of two at least twice the merge count.
+// Pair -> rank lookup shared by the host (table build) and the device:
+// open addressing with linear probing over a power-of-two table; a slot
+// holds the key (left << 16) | right (never 0: left >= 5) and the rank.
+__host__ __device__ inline uint32_t bpe_pair_hash(uint32_t a, uint32_t b) {
+    uint32_t h = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u) * 0x85EBCA77u;
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 13;
+    return h;
+}
+
+constexpr int32_t kBpeMaxMerges = 8192;  // device tables (hash + rank counts) live in LDS
+
 struct BpeTables {
     int32_t n_merges = 0;
-    uint32_t hash_mask = 0;        // slots - 1
-    uint64_t *d_hash = nullptr;    // key (left << 32 | right) + 1 in high bits? see bpe.hip
-    int32_t *d_merges = nullptr;   // [R][2]
-    int32_t *d_tok_len = nullptr;  // decoded length per id, [vocab]
-    int64_t *d_tok_off = nullptr;  // offset of each id's bases in d_tok_chars, [vocab]
+    uint32_t slots = 0;             // power of two >= 2 * n_merges
+    uint32_t *d_hkey = nullptr;     // [slots] (left << 16) | right, 0 = empty
+    uint16_t *d_hrank = nullptr;    // [slots]
+    int32_t *d_merges = nullptr;    // [R][2]
+    int32_t *d_tok_len = nullptr;   // decoded length per id, [vocab]
+    int64_t *d_tok_off = nullptr;   // offset of each id's bases in d_tok_chars, [vocab]
     uint8_t *d_tok_chars = nullptr;
 };
 
@@ -98,6 +110,14 @@ EncodeTuning encode_tuning(bool kmer);
 int launch_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets,
                   int32_t n, int32_t *d_ids, int64_t cap, int64_t *d_out_offsets, int8_t *d_mask,
                   const dnatok_encode_opts &o, hipStream_t stream);
+
+// out[i] = sum over rows r < i of ceil(L_r / divisor) + 2 * cls (out[n] = total).
+int launch_rowscan(const int64_t *d_offsets, int32_t n, int64_t nbytes, int64_t *d_out, int32_t divisor, int32_t cls,
+                   hipStream_t stream);
+
+int launch_bpe_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets,
+                      int32_t n, int32_t *d_ids, int64_t cap, int64_t *d_out_offsets, int8_t *d_mask,
+                      const dnatok_encode_opts &o, hipStream_t stream);
 
 int launch_decode(const dnatok_vocab *v, const int32_t *d_ids, int64_t n_ids, const int64_t *d_offsets,
                   int32_t n, uint8_t *d_out, int64_t out_capacity, int64_t *d_out_offsets, hipStream_t stream);

@@ -178,13 +178,16 @@ struct TileQueue {
 __device__ __forceinline__ void raise_error(uint32_t *hdr, uint32_t flag) { atomicOr(hdr + 3, flag); }
 
 // Called by thread 0 of every block after its last tile: the last block to
-// finish resets the counters and flips the parity for the next launch.
-__device__ __forceinline__ void finish_block(uint32_t *hdr) {
+// finish resets the counters and, for kernels that used (and cleared) the
+// status words, flips the parity for the next launch. A kernel that only
+// takes tickets passes flip = false so the parity stays with the status
+// array the next scan expects to be clear.
+__device__ __forceinline__ void finish_block(uint32_t *hdr, bool flip = true) {
     uint32_t d = atomicAdd(hdr + 1, 1u);
     if (d == gridDim.x - 1) {
         st_relaxed32(hdr + 0, 0u);
         st_relaxed32(hdr + 1, 0u);
-        st_relaxed32(hdr + 2, ld_relaxed32(hdr + 2) ^ 1u);
+        if (flip) st_relaxed32(hdr + 2, ld_relaxed32(hdr + 2) ^ 1u);
     }
 }
 

@@ -597,6 +597,38 @@ int blocks_per_cu(int U, size_t dyn, int *out) {
 
 }  // namespace
 
+int launch_rowscan(const int64_t *d_offsets, int32_t n, int64_t nbytes, int64_t *d_out, int32_t divisor, int32_t cls,
+                   hipStream_t stream) {
+    RowScanArgs s;
+    s.offs = d_offsets;
+    s.n = n;
+    s.nbytes = nbytes;
+    s.out_offs = d_out;
+    s.k = divisor;
+    s.kmer = 1;
+    s.cls = cls;
+    s.padded = 0;
+    s.W = 0;
+    s.base = 0;
+    s.nunits = ((int64_t)n + kUnitRows - 1) / kUnitRows;
+    if (s.nunits < 1) s.nunits = 1;
+    Workspace *ws = nullptr;
+    int rc = get_workspace(stream, s.nunits, &ws);
+    if (rc) return rc;
+    s.q.hdr = ws->d_hdr;
+    s.q.status0 = ws->d_status;
+    s.q.status1 = ws->d_status + ws->cap;
+    if (s.nunits > ws->high_water) ws->high_water = s.nunits;
+    s.q.clear_n = ws->high_water;
+    int per_cu = 0;
+    DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rowscan, NT, 0));
+    int64_t g = (int64_t)device_cu_count() * (per_cu > 0 ? per_cu : 1);
+    if (g > s.nunits) g = s.nunits;
+    hipLaunchKernelGGL(k_rowscan, dim3((unsigned)g), dim3(NT), 0, stream, s);
+    DNATOK_HIP(hipGetLastError());
+    return DNATOK_OK;
+}
+
 EncodeTuning encode_tuning(bool kmer) {
     EncodeTuning t;
     t.tile_bytes = kmer ? 32768 : 16384;

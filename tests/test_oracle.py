@@ -7,6 +7,7 @@ side, a BPE round that merges the wrong occurrences) fails at least one test.
 import itertools
 import math
 import os
+import sys
 
 import numpy as np
 import pytest
@@ -329,3 +330,14 @@ def test_windows_closed_form():
     assert len(offs) - 1 == sum(math.ceil(L / 6000) for L in lens)
     assert offs[-1] == sum(lens)
     assert np.all(np.diff(offs) <= 6000) and np.all(np.diff(offs) > 0)
+
+
+def test_bpe4096_table_is_the_trainers_output():
+    # the stored table of the batched BPE workload is exactly what the oracle
+    # trainer writes for the seeded 64 Mbase order-5 corpus (about 30 s)
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    import make_bpe4096
+    stored = make_bpe4096.load()
+    assert stored.shape == (4096, 2)
+    assert oracle.bpe_check(stored) == 0
+    assert np.array_equal(make_bpe4096.make(), stored)
