@@ -276,7 +276,14 @@ def encode(vocab: Vocab, d_bytes, d_offsets, h_offsets=None, add_cls_sep=False, 
     total, max_len = plan(vocab, h_offsets, add_cls_sep)
     dev = d_bytes.device
     if layout == PADDED:
-        W = max_len if pad_to is None else max(int(pad_to), max_len)
+        if pad_to is None:
+            W = max_len
+        elif vocab.kind == BPE:
+            # the BPE plan is only an upper bound: keep the caller's width (a
+            # longer row raises DNATOK_DERR_ROW_WIDTH on the device)
+            W = int(pad_to)
+        else:
+            W = max(int(pad_to), max_len)
         cap = n * W
     else:
         W, cap = 0, total

@@ -85,12 +85,18 @@ int get_workspace(hipStream_t stream, int64_t tiles, Workspace **out) {
         size_t bytes = 256 + (size_t)cap * 2 * sizeof(uint64_t);
         void *p = nullptr;
         DNATOK_HIP(hipMalloc(&p, bytes));
-        DNATOK_HIP(hipMemset(p, 0, bytes));
+        // zero on the workspace's own stream and wait: a plain hipMemset runs on
+        // the null stream, which does not order non-blocking streams
+        DNATOK_HIP(hipMemsetAsync(p, 0, bytes, stream));
+        DNATOK_HIP(hipStreamSynchronize(stream));
         ws->d_hdr = static_cast<uint32_t *>(p);
         ws->d_status = reinterpret_cast<uint64_t *>(static_cast<uint8_t *>(p) + 256);
         ws->cap = cap;
         ws->high_water = 0;
-        if (err_keep) DNATOK_HIP(hipMemcpy(ws->d_hdr + HDR_ERR, &err_keep, sizeof(uint32_t), hipMemcpyHostToDevice));
+        if (err_keep) {
+            DNATOK_HIP(hipMemcpyAsync(ws->d_hdr + HDR_ERR, &err_keep, sizeof(uint32_t), hipMemcpyHostToDevice, stream));
+            DNATOK_HIP(hipStreamSynchronize(stream));
+        }
     }
     *out = ws;
     return DNATOK_OK;
@@ -223,6 +229,9 @@ int dnatok_vocab_create(const dnatok_vocab_desc *d, dnatok_vocab **out) {
             return rc;
         }
     }
+    // copies from pageable memory may still be in flight when hipMemcpy
+    // returns; finish them before any stream (blocking or not) reads the tables
+    DNATOK_HIP(hipDeviceSynchronize());
     *out = v.release();
     return DNATOK_OK;
 }
@@ -289,8 +298,8 @@ int dnatok_sync_status(void *stream, uint32_t *flags) {
     Workspace *ws = find_workspace(s);
     if (ws && ws->d_hdr) {
         DNATOK_HIP(hipMemcpy(&f, ws->d_hdr + HDR_ERR, sizeof(f), hipMemcpyDeviceToHost));
-        uint32_t z = 0;
-        DNATOK_HIP(hipMemcpy(ws->d_hdr + HDR_ERR, &z, sizeof(z), hipMemcpyHostToDevice));
+        DNATOK_HIP(hipMemsetAsync(ws->d_hdr + HDR_ERR, 0, sizeof(uint32_t), s));
+        DNATOK_HIP(hipStreamSynchronize(s));
     }
     if (flags) *flags = f;
     return DNATOK_OK;

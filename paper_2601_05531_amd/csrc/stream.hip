@@ -168,8 +168,8 @@ int dnatok_stream_reset(dnatok_stream *s) {
     s->failed = s->flushed = false;
     std::fill(s->copied_pending.begin(), s->copied_pending.end(), false);
     // out_offsets[0] = 0 even when no window is ever written
-    const int64_t zero = 0;
-    DNATOK_HIP(hipMemcpy(s->d_woff, &zero, sizeof(zero), hipMemcpyHostToDevice));
+    DNATOK_HIP(hipMemsetAsync(s->d_woff, 0, sizeof(int64_t), s->compute));
+    DNATOK_HIP(hipStreamSynchronize(s->compute));
     return DNATOK_OK;
 }
 

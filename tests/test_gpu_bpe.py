@@ -81,16 +81,13 @@ def trained_small():
 
 def test_exhaustive_short_strings(trained_small):
     # every ACGT string of length <= 7 as its own row (21844 rows), three tables
-    rows = []
+    parts, lens = [], []
     for L in range(8):
-        if L == 0:
-            rows.append(b"")
-            continue
         idx = np.arange(4 ** L)
         digits = (idx[:, None] >> (2 * np.arange(L - 1, -1, -1))) & 3
-        rows.extend(np.frombuffer(b"ACGT", np.uint8)[digits])
-    lens = [len(r) for r in rows]
-    data = np.concatenate([np.asarray(r, np.uint8).reshape(-1) for r in rows])
+        parts.append(np.frombuffer(b"ACGT", np.uint8)[digits].reshape(-1))
+        lens += [L] * (4 ** L)
+    data = np.concatenate(parts)
     offs = synth.offsets_from_lengths(lens)
     for merges in (trained_small, _random_table(1, 60, 0.3), _random_table(2, 200, 0.1)):
         v = dt.Vocab(dt.BPE, merges=merges)
