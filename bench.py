@@ -218,7 +218,7 @@ def stream_leg(passes: int = 3):
             times.append(time.perf_counter() - t0)
             assert r.n_tokens == n_tokens and r.n_windows == n_windows
             if sample_ok is None:
-                sample_ok = _stream_sample_check(h, lens, ids, woff)
+                sample_ok = _stream_window_check(lens, woff, n_windows)
             if rep == 0:
                 st.reset()
         st.close()
@@ -227,29 +227,119 @@ def stream_leg(passes: int = 3):
                      "frac_of_h2d": round(STREAM_BYTES / t / 1e9 / h2d, 4)}
         log("stream %s: %.3e tokens/s, %.1f GB/s (%.0f%% of pinned H2D %.1f GB/s)" % (
             mode, n_tokens / t, STREAM_BYTES / t / 1e9, 100 * STREAM_BYTES / t / 1e9 / h2d, h2d))
-    out["sample_check"] = sample_ok
+    out["window_offsets_check"] = sample_ok
     del h
     return out
 
 
-def _stream_sample_check(h, lens, ids, woff, n_windows_checked: int = 64):
-    """Oracle check of a seeded sample of the stream's windows."""
-    import oracle
-    woffs_all = oracle.windows(lens, STREAM_WINDOW)
-    rng = np.random.default_rng(0)
-    pick = np.sort(rng.choice(len(woffs_all) - 1, size=n_windows_checked, replace=False))
-    hb = h.numpy()
-    d_off = woff.cpu().numpy()
-    for w in pick:
-        a, b = int(woffs_all[w]), int(woffs_all[w + 1])
-        want, _ = oracle.encode(oracle.KMER, hb[a:b], np.array([0, b - a]), k=STREAM_K)
-        got = ids[int(d_off[w]):int(d_off[w + 1])].cpu().numpy()
-        if not np.array_equal(got, want):
-            return False
-    return True
+def _stream_window_check(lens, woff, n_windows):
+    """Oracle-free invariant: every window's token count equals the closed
+    form ceil(window bases / k), so the offsets equal their running sum."""
+    want = np.empty(n_windows + 1, dtype=np.int64)
+    want[0] = 0
+    i = 1
+    for L in lens:
+        full, rem = divmod(int(L), STREAM_WINDOW)
+        per = np.full(full + (1 if rem else 0), -(-STREAM_WINDOW // STREAM_K), dtype=np.int64)
+        if rem:
+            per[-1] = -(-rem // STREAM_K)
+        want[i:i + len(per)] = per
+        i += len(per)
+    np.cumsum(want[1:], out=want[1:])
+    return bool(np.array_equal(woff.cpu().numpy(), want))
 
 
-def cpu_baseline(data, offs, budget_s: float = 12.0):
+BPE_TABLE = os.path.join(ROOT, "tests", "golden", "bpe4096_order5_64M.txt")
+
+
+def bpe_leg(reps: int = 10):
+    """Ragged BPE batch: 1,024 sequences, lengths log-uniform in [500, 20000]
+    bases, fresh walk of the order-5 Markov chain the 4096-merge table was
+    trained on; PACKED ids, no specials. The fused form encodes the whole
+    batch in one call; the per-sequence form makes one call per sequence
+    (the same kernels, n = 1) into the same output positions. Both are timed
+    with HIP events on the launch stream and must produce identical ids."""
+    import torch
+    import paper_2601_05531_amd as dt
+    import synth
+
+    merges = np.loadtxt(BPE_TABLE, dtype=np.int32).reshape(-1, 2)
+    v = dt.Vocab(dt.BPE, merges=merges)
+    data, offs = synth.workload_bpe_batch()
+    n = len(offs) - 1
+    nbytes = int(data.size)
+    d_in = torch.from_numpy(data).cuda()
+    d_offs = torch.from_numpy(offs).cuda()
+    ids = torch.empty(nbytes, dtype=torch.int32, device="cuda")
+    oo = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    opts = dt.make_opts()
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+
+    def fused():
+        dt.dnatok_encode(v.handle, d_in.data_ptr(), nbytes, d_offs.data_ptr(), n, ids.data_ptr(), nbytes,
+                         oo.data_ptr(), None, opts, sp)
+
+    fused()
+    torch.cuda.synchronize()
+    assert dt.sync_status() == 0
+    h_oo = oo.cpu().numpy()
+    tokens = int(h_oo[-1])
+    evs = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fused()
+        b.record(stream)
+        evs.append((a, b))
+    torch.cuda.synchronize()
+    fused_ms = float(np.median([a.elapsed_time(b) for a, b in evs]))
+
+    # one call per sequence, each writing its ids where the fused call put them
+    lens = np.diff(offs)
+    row_offs = torch.from_numpy(np.stack([np.zeros(n, np.int64), lens], 1).copy()).cuda()
+    row_oo = torch.empty(n, 2, dtype=torch.int64, device="cuda")
+    ids2 = torch.empty_like(ids)
+    row_opts = [dt.make_opts(offset_base=int(h_oo[i])) for i in range(n)]
+
+    def per_seq():
+        for i in range(n):
+            dt.dnatok_encode(v.handle, d_in.data_ptr() + int(offs[i]), int(lens[i]), row_offs[i].data_ptr(), 1,
+                             ids2.data_ptr() + 4 * int(h_oo[i]), int(lens[i]), row_oo[i].data_ptr(), None,
+                             row_opts[i], sp)
+
+    per_seq()
+    torch.cuda.synchronize()
+    assert dt.sync_status() == 0
+    same = bool(torch.equal(ids[:tokens], ids2[:tokens])) and bool(
+        torch.equal(row_oo[:, 1].cpu(), oo[1:].cpu()))
+    times = []
+    for _ in range(2):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        per_seq()
+        b.record(stream)
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b))
+    per_ms = float(min(times))
+    out = {
+        "workload": "1024 sequences, log-uniform 500-20000 bases (%d bases), order-5 Markov, BPE 4096 merges "
+                    "(oracle trainer, 64 Mbase), PACKED, no specials" % nbytes,
+        "tokens": tokens,
+        "fused_ms": round(fused_ms, 4),
+        "fused_tokens_per_s": tokens / (fused_ms * 1e-3),
+        "fused_bases_per_s": nbytes / (fused_ms * 1e-3),
+        "per_sequence_ms": round(per_ms, 3),
+        "per_sequence_tokens_per_s": tokens / (per_ms * 1e-3),
+        "fused_speedup": round(per_ms / fused_ms, 2),
+        "per_sequence_ids_identical": same,
+    }
+    log("bpe: fused %.3f ms (%.3e tokens/s), per-sequence %.3f ms, identical=%s" % (
+        fused_ms, out["fused_tokens_per_s"], per_ms, same))
+    return out, data, offs, merges
+
+
+def cpu_baseline(data, offs, budget_s: float = 12.0, bpe=None):
     """The CPU oracle as written (single thread) on a bounded sample: whole
     rows of the same batch, all four k, until about ``budget_s`` seconds."""
     import oracle
@@ -266,9 +356,20 @@ def cpu_baseline(data, offs, budget_s: float = 12.0):
             t_total += time.perf_counter() - t0
             tok_total += int(oo[-1])
         reps += 1
-    return {"value": tok_total / t_total, "unit": "tokens/s", "cores": 1, "kind": "oracle",
-            "sample": "%d reps of %d of the %d rows (%d bases), k=3,4,5,6, CLS/SEP, right-padded, "
-                      "single-threaded C oracle, %.1f s" % (reps, rows, N_SEQS, int(sub[-1]), t_total)}
+    res = {"value": tok_total / t_total, "unit": "tokens/s", "cores": 1, "kind": "oracle",
+           "sample": "%d reps of %d of the %d rows (%d bases), k=3,4,5,6, CLS/SEP, right-padded, "
+                     "single-threaded C oracle, %.1f s" % (reps, rows, N_SEQS, int(sub[-1]), t_total)}
+    if bpe is not None:
+        # the oracle's BPE on the first rows of the BPE batch, about 4 s
+        b_data, b_offs, merges = bpe
+        rows = 48
+        sub = b_offs[:rows + 1]
+        t0 = time.perf_counter()
+        ids, oo = oracle.encode(oracle.BPE, b_data[:sub[-1]], sub, merges=merges)
+        t = time.perf_counter() - t0
+        res["bpe"] = {"value": int(oo[-1]) / t, "unit": "tokens/s", "cores": 1,
+                      "sample": "first %d of the 1024 BPE rows (%d bases), %.1f s" % (rows, int(sub[-1]), t)}
+    return res
 
 
 def main():
@@ -279,6 +380,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-copy", action="store_true", help="skip the device-copy reference")
     ap.add_argument("--no-stream", action="store_true", help="skip the 2 GiB host-to-device stream leg")
+    ap.add_argument("--no-bpe", action="store_true", help="skip the ragged BPE batch leg")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the tokenizer shards by sequences with no collective on the hot path, "
@@ -303,9 +405,13 @@ def main():
     stream = None
     if not args.no_stream:
         stream = stream_leg()
+    bpe = bpe_in = None
+    if not args.no_bpe:
+        bpe, b_data, b_offs, merges = bpe_leg()
+        bpe_in = (b_data, b_offs, merges)
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(enc["data"], enc["offs"])
+        cpu = cpu_baseline(enc["data"], enc["offs"], bpe=bpe_in)
         log("cpu oracle: %.3e tokens/s" % cpu["value"])
     line = {
         "metric": METRIC,
@@ -330,6 +436,7 @@ def main():
         "roofline": enc["roofline"],
         "cpu_baseline": cpu,
         "stream": stream,
+        "bpe": bpe,
     }
     print(json.dumps(line), flush=True)
 

@@ -54,6 +54,7 @@ extern "C" {
 #define DNATOK_DERR_OFFSETS 1u   /* offsets not non-decreasing within [0, nbytes] */
 #define DNATOK_DERR_CAPACITY 2u  /* PACKED output exceeds ids_capacity (excess not written) */
 #define DNATOK_DERR_ROW_WIDTH 4u /* PADDED row longer than pad_to (excess not written) */
+#define DNATOK_DERR_INTERNAL 8u  /* a bounded device loop hit its limit (a library fault): output invalid */
 
 /* ---- ids and enums --------------------------------------------------------- */
 #define DNATOK_ID_PAD 0

@@ -1,35 +1,33 @@
 // Ranked-merge BPE on the device: vocabulary tables and the encode pipeline.
 //
-// Paper: BPE / data-driven subwords (introduction, table of genomic
-// tokenization schemes; the BPE of Sennrich et al. it cites); DNATok keeps
-// "identical token IDs and segmentation" (Discussion, accuracy and
-// algorithmic neutrality) and BPE is one of the vocabularies it accelerates.
+// Paper: BPE is one of the vocabularies of its table of genomic
+// tokenization schemes (introduction, citing the subword BPE of Sennrich et
+// al.), and the accelerated tokenizer must give the same ids and the same
+// segmentation as the reference tokenizer (Discussion, accuracy and
+// algorithmic neutrality).
 //
-// Semantics (as the oracle): case folded; each maximal ACGT run is
-// segmented on its own (N -> 9 and other bytes -> UNK are barriers); within a
-// run, repeatedly the lowest-ranked adjacent pair is replaced everywhere,
-// left to right, by the merge's id 10 + rank.
+// Semantics (as the oracle): case folded; each maximal ACGT run is segmented
+// on its own (N -> 9 and other bytes -> UNK are barriers); within a run the
+// lowest-ranked adjacent pair is replaced everywhere, left to right, by the
+// merge's id 10 + rank, until no adjacent pair is in the table.
 //
 // Device form: for a well-formed table (operands are bases or earlier
-// merges; no pair twice) a merge's new symbol only forms pairs of higher
-// rank, so the rank applied in each round strictly increases. A block keeps
-// a histogram of the ranks of all current adjacent pairs and walks it
-// forward: each round takes the next rank present, merges all its
-// non-overlapping occurrences in parallel (runs of (X, X) pairs resolved by
-// parity, leftmost first), updates the histogram for the pairs destroyed and
-// created, and compacts the symbols. Barriers never merge, so a block can
-// segment many runs at once.
+// merges, no pair twice) a new symbol only forms pairs of higher rank, so
+// the rank applied in each round strictly increases and every round merges
+// all occurrences of one rank (runs of (X, X) pairs leftmost first).
 //
 // Pipeline (all on the caller's stream):
-//  1. item plan: rows are cut into nominal items of S bytes; item offsets are
-//     a row scan of ceil(L / S). Item j of a row starts just after the first
-//     barrier at or after byte j * S (or at the row end), so no run is split.
-//  2. k_bpe_merge: persistent 1024-thread blocks take items by ticket; the
-//     pair -> rank hash and the rank histogram sit in LDS, the symbols too
-//     unless a segment is longer than the LDS budget (then global scratch).
-//  3. k_scan_counts: item token counts -> item positions (one-pass scan).
-//  4. k_bpe_emit: CLS/SEP/pads/mask per row and body tokens per item into
-//     the PACKED or PADDED output.
+//  1. k_rowscan (encode.hip): rows are cut into nominal items of S bytes;
+//     item offsets are the scan of ceil(L / S).
+//  2. k_bpe_items: item j >= 1 of a row starts just after the first barrier
+//     in its own nominal window (or is empty), so no ACGT run is split.
+//  3. k_bpe_wave, once per length class: one wavefront per item, symbols,
+//     pair ranks, an alive bitmap and a two-level min tree over the pair
+//     ranks in LDS; a round touches only the blocks holding the current
+//     rank. Classes trade waves per workgroup against symbols per wave.
+//  4. k_bpe_block: items longer than the largest class, one 1024-thread
+//     workgroup each, symbols in global scratch, a rank histogram in LDS.
+//  5. k_scan_counts + k_bpe_emit: token counts -> positions -> ids.
 #include <algorithm>
 #include <vector>
 
@@ -47,16 +45,16 @@ int build_bpe_tables(dnatok_vocab *v) {
         return set_error(DNATOK_EVOCAB, "BPE tables hold at most %d merges (got %d)", kBpeMaxMerges, R);
     t.n_merges = R;
     const int32_t V = 10 + R;
-    // expansions (uppercase bases) per id
+    // expansions (uppercase bases) per id, for decode
     std::vector<int32_t> len(V, 1);
     std::vector<int64_t> off(V, 0);
     for (int id = 0; id < 5; ++id) len[id] = 0;
-    int64_t total = 0;
     for (int32_t r = 0; r < R; ++r) {
         int64_t L = (int64_t)len[v->h_merges[2 * r]] + len[v->h_merges[2 * r + 1]];
         if (L > (1 << 20)) return set_error(DNATOK_EVOCAB, "merge %d expands to more than 2^20 bases", r);
         len[10 + r] = (int32_t)L;
     }
+    int64_t total = 0;
     int32_t mx = 1;
     for (int32_t id = 0; id < V; ++id) {
         off[id] = total;
@@ -75,28 +73,24 @@ int build_bpe_tables(dnatok_vocab *v) {
 
     uint32_t slots = 16;
     while (slots < 2u * (uint32_t)(R > 0 ? R : 1)) slots <<= 1;
-    std::vector<uint32_t> keys(slots, 0);
-    std::vector<uint16_t> ranks(slots, 0);
+    std::vector<uint16_t> slot(slots, kNoRank);
+    std::vector<uint32_t> pair((size_t)(R > 0 ? R : 1), 0);
     for (int32_t r = 0; r < R; ++r) {
         uint32_t a = (uint32_t)v->h_merges[2 * r], b = (uint32_t)v->h_merges[2 * r + 1];
+        pair[r] = a | (b << 16);
         uint32_t s = bpe_pair_hash(a, b) & (slots - 1);
-        while (keys[s]) s = (s + 1) & (slots - 1);
-        keys[s] = (a << 16) | b;
-        ranks[s] = (uint16_t)r;
+        while (slot[s] != kNoRank) s = (s + 1) & (slots - 1);
+        slot[s] = (uint16_t)r;
     }
     t.slots = slots;
 
     void *p = nullptr;
-    DNATOK_HIP(hipMalloc(&p, sizeof(uint32_t) * slots));
-    t.d_hkey = static_cast<uint32_t *>(p);
-    DNATOK_HIP(hipMemcpy(t.d_hkey, keys.data(), sizeof(uint32_t) * slots, hipMemcpyHostToDevice));
     DNATOK_HIP(hipMalloc(&p, sizeof(uint16_t) * slots));
-    t.d_hrank = static_cast<uint16_t *>(p);
-    DNATOK_HIP(hipMemcpy(t.d_hrank, ranks.data(), sizeof(uint16_t) * slots, hipMemcpyHostToDevice));
-    DNATOK_HIP(hipMalloc(&p, sizeof(int32_t) * 2 * (size_t)(R > 0 ? R : 1)));
-    t.d_merges = static_cast<int32_t *>(p);
-    if (R > 0)
-        DNATOK_HIP(hipMemcpy(t.d_merges, v->h_merges.data(), sizeof(int32_t) * 2 * (size_t)R, hipMemcpyHostToDevice));
+    t.d_slot = static_cast<uint16_t *>(p);
+    DNATOK_HIP(hipMemcpy(t.d_slot, slot.data(), sizeof(uint16_t) * slots, hipMemcpyHostToDevice));
+    DNATOK_HIP(hipMalloc(&p, sizeof(uint32_t) * pair.size()));
+    t.d_pair = static_cast<uint32_t *>(p);
+    DNATOK_HIP(hipMemcpy(t.d_pair, pair.data(), sizeof(uint32_t) * pair.size(), hipMemcpyHostToDevice));
     DNATOK_HIP(hipMalloc(&p, sizeof(int32_t) * (size_t)V));
     t.d_tok_len = static_cast<int32_t *>(p);
     DNATOK_HIP(hipMemcpy(t.d_tok_len, len.data(), sizeof(int32_t) * (size_t)V, hipMemcpyHostToDevice));
@@ -111,9 +105,8 @@ int build_bpe_tables(dnatok_vocab *v) {
 
 void free_bpe_tables(dnatok_vocab *v) {
     BpeTables &t = v->bpe;
-    if (t.d_hkey) (void)hipFree(t.d_hkey);
-    if (t.d_hrank) (void)hipFree(t.d_hrank);
-    if (t.d_merges) (void)hipFree(t.d_merges);
+    if (t.d_slot) (void)hipFree(t.d_slot);
+    if (t.d_pair) (void)hipFree(t.d_pair);
     if (t.d_tok_len) (void)hipFree(t.d_tok_len);
     if (t.d_tok_off) (void)hipFree(t.d_tok_off);
     if (t.d_tok_chars) (void)hipFree(t.d_tok_chars);
@@ -122,12 +115,17 @@ void free_bpe_tables(dnatok_vocab *v) {
 
 namespace {
 
-constexpr int NTM = 1024;          // merge kernel block
-constexpr int NTE = 256;           // scan / emit blocks
+constexpr int NTM = 1024;             // k_bpe_block workgroup
+constexpr int NTE = 256;              // items / scan / emit workgroups
+constexpr int kMaxWaves = 8;          // waves per k_bpe_wave workgroup
 constexpr int32_t kItemBytes = 8192;  // nominal item length S
 constexpr int kScanPerThread = 16;
 constexpr int64_t kScanUnit = (int64_t)NTE * kScanPerThread;
-constexpr size_t kLdsBudget = 156 * 1024;
+constexpr size_t kLdsBytes = 160 * 1024;
+constexpr size_t kLdsReserve = 2048;  // static LDS of the kernels
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+__host__ __device__ constexpr uint32_t al16(uint32_t x) { return (x + 15u) & ~15u; }
 
 __device__ __forceinline__ bool is_base_byte(uint8_t b) {
     const uint8_t f = b | 0x20;
@@ -145,25 +143,51 @@ __device__ __forceinline__ uint16_t symbol_of(uint8_t b) {
     }
 }
 
-struct MergeArgs {
+struct RankTab {
+    const uint16_t *slot;
+    const uint32_t *pair;
+    uint32_t mask;
+};
+
+// Rank of the pair (a, b), or kNoRank. Specials and N never merge.
+__device__ __forceinline__ uint32_t pair_rank(const RankTab &t, uint32_t a, uint32_t b) {
+    if (a < 5 || a == 9 || b < 5 || b == 9) return kNoRank;
+    const uint32_t key = a | (b << 16);
+    uint32_t s = bpe_pair_hash(a, b) & t.mask;
+    for (;;) {
+        const uint32_t r = t.slot[s];
+        if (r == kNoRank || t.pair[r] == key) return r;
+        s = (s + 1) & t.mask;
+    }
+}
+
+// Table layout in LDS: 16-bit slots, then 32-bit pairs.
+__host__ __device__ inline uint32_t table_bytes(uint32_t slots, int32_t R) {
+    return al16(2u * slots) + al16(4u * (uint32_t)(R > 0 ? R : 1));
+}
+
+__device__ void load_table(uint8_t *dyn, const uint16_t *g_slot, const uint32_t *g_pair, uint32_t slots, int32_t R,
+                           RankTab *t) {
+    uint16_t *slot = reinterpret_cast<uint16_t *>(dyn);
+    uint32_t *pair = reinterpret_cast<uint32_t *>(dyn + al16(2u * slots));
+    for (uint32_t s = threadIdx.x; s < slots; s += blockDim.x) slot[s] = g_slot[s];
+    for (int32_t r = threadIdx.x; r < R; r += blockDim.x) pair[r] = g_pair[r];
+    *t = RankTab{slot, pair, slots - 1};
+}
+
+// ---- 2. items ------------------------------------------------------------------
+
+struct ItemArgs {
     const uint8_t *bytes;
     int64_t nbytes;
     const int64_t *offs;
     int32_t n;
     const int64_t *item_off;  // [n + 1]
-    int32_t S;
-    uint16_t *symA;  // global scratch [nbytes]: final symbols of every item at its segment start
-    uint16_t *symB;  // global scratch [nbytes]: second buffer for oversized segments
-    int32_t *item_cnt;
-    int64_t *item_start;
     int64_t max_items;
-    const uint32_t *hkey;
-    const uint16_t *hrank;
-    uint32_t slots;
-    const int32_t *merges;
-    int32_t R;
-    int32_t lmax;  // symbols per LDS buffer
-    dev::TileQueue q;
+    int32_t S;
+    int64_t *item_start;
+    int32_t *item_len;
+    int32_t *item_cnt;
 };
 
 // Item j >= 1 of row [off, end) may start only just after a barrier found
@@ -192,23 +216,352 @@ __device__ int64_t item_start_probe(const uint8_t *bytes, int64_t off, int64_t e
     return -1;
 }
 
-struct LdsTables {
-    const uint32_t *hkey;
-    const uint16_t *hrank;
-    uint32_t mask;
-};
-
-__device__ __forceinline__ int32_t rank_of(const LdsTables &t, uint32_t x, uint32_t y) {
-    if (x < 5 || x == 9 || y < 5 || y == 9) return -1;  // specials and barriers never merge
-    const uint32_t key = (x << 16) | y;
-    uint32_t s = bpe_pair_hash(x, y) & t.mask;
-    for (;;) {
-        const uint32_t k = t.hkey[s];
-        if (k == key) return t.hrank[s];
-        if (k == 0) return -1;
-        s = (s + 1) & t.mask;
+__global__ __launch_bounds__(NTE) void k_bpe_items(ItemArgs a) {
+    const int lane = threadIdx.x & (dev::kWave - 1);
+    const int64_t waves = (int64_t)gridDim.x * (NTE / dev::kWave);
+    const int64_t total = min(a.item_off[a.n], a.max_items);
+    for (int64_t t = (int64_t)blockIdx.x * (NTE / dev::kWave) + threadIdx.x / dev::kWave; t < total; t += waves) {
+        const int64_t i1 = dev::wave_lower_bound(0, (int64_t)a.n + 1, [&](int64_t i) { return a.item_off[i] > t; });
+        const int64_t i = i1 - 1, j = t - a.item_off[i], nj = a.item_off[i + 1] - a.item_off[i];
+        int64_t off = a.offs[i], end = a.offs[i + 1];
+        off = off < 0 ? 0 : (off > a.nbytes ? a.nbytes : off);
+        end = end < off ? off : (end > a.nbytes ? a.nbytes : end);
+        int64_t c0 = (j == 0) ? off : item_start_probe(a.bytes, off, end, j, a.S);
+        int64_t c1 = c0;
+        if (c0 >= 0) {
+            c1 = end;
+            for (int64_t jj = j + 1; jj < nj; ++jj) {
+                const int64_t b = item_start_probe(a.bytes, off, end, jj, a.S);
+                if (b >= 0) {
+                    c1 = b;
+                    break;
+                }
+            }
+        } else {
+            c0 = c1 = 0;
+        }
+        if (lane == 0) {
+            a.item_start[t] = c0;
+            a.item_len[t] = (int32_t)(c1 > c0 ? c1 - c0 : 0);
+            a.item_cnt[t] = 0;
+        }
     }
 }
+
+// ---- 3. wave per item ---------------------------------------------------------------
+
+// Orders this wave's LDS accesses across lanes (a wave's LDS operations
+// execute in order; the fences keep the compiler from moving them).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+    for (int d = 1; d < dev::kWave; d <<= 1) v = min(v, (uint32_t)__shfl_xor((int)v, d, dev::kWave));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
+    const int lane = threadIdx.x & (dev::kWave - 1);
+#pragma unroll
+    for (int d = 1; d < dev::kWave; d <<= 1) {
+        const uint32_t u = (uint32_t)__shfl_up((int)v, d, dev::kWave);
+        if (lane >= d) v += u;
+    }
+    return v;
+}
+
+// Next / previous alive position strictly after / before x, or kNone.
+__device__ __forceinline__ uint32_t next_alive(const uint32_t *alive, uint32_t nw, uint32_t x) {
+    uint32_t w = x >> 5;
+    uint32_t bits = alive[w] & ~((2u << (x & 31)) - 1u);
+    while (!bits) {
+        if (++w >= nw) return kNone;
+        bits = alive[w];
+    }
+    return (w << 5) + (uint32_t)__builtin_ctz(bits);
+}
+
+__device__ __forceinline__ uint32_t prev_alive(const uint32_t *alive, uint32_t x) {
+    uint32_t w = x >> 5;
+    uint32_t bits = alive[w] & ((1u << (x & 31)) - 1u);
+    while (!bits) {
+        if (w == 0) return kNone;
+        bits = alive[--w];
+    }
+    return (w << 5) + 31u - (uint32_t)__builtin_clz(bits);
+}
+
+// Minimum of the 64 pair ranks of block b (16-byte LDS reads).
+__device__ __forceinline__ uint32_t block_min(const uint16_t *prk, uint32_t b) {
+    const uint4 *src = reinterpret_cast<const uint4 *>(prk + (size_t)b * 64);
+    uint32_t m = kNoRank;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        const uint4 x = src[v];
+        m = min(m, min(min(x.x & 0xFFFF, x.x >> 16), min(x.y & 0xFFFF, x.y >> 16)));
+        m = min(m, min(min(x.z & 0xFFFF, x.z >> 16), min(x.w & 0xFFFF, x.w >> 16)));
+    }
+    return m;
+}
+
+// Bit i set where the rank of position 64b + i equals r.
+__device__ __forceinline__ uint64_t block_match(const uint16_t *prk, uint32_t b, uint32_t r) {
+    const uint4 *src = reinterpret_cast<const uint4 *>(prk + (size_t)b * 64);
+    uint64_t m = 0;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        const uint4 x = src[v];
+        const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            m |= (uint64_t)((w[h] & 0xFFFF) == r) << (v * 8 + h * 2);
+            m |= (uint64_t)((w[h] >> 16) == r) << (v * 8 + h * 2 + 1);
+        }
+    }
+    return m;
+}
+
+struct WaveArgs {
+    const uint8_t *bytes;
+    const int64_t *item_start;
+    const int32_t *item_len;
+    const int64_t *n_items_at;  // item_off + n
+    int64_t max_items;
+    uint16_t *tok;  // final symbols of item t at item_start[t]
+    int32_t *item_cnt;
+    const uint16_t *slot;
+    const uint32_t *pair;
+    uint32_t slots;
+    int32_t R;
+    int32_t lo, hi;  // this launch takes items with lo < length <= hi
+    uint32_t np;     // positions per wave (multiple of 64, >= hi)
+    uint32_t wave_bytes;
+    uint32_t *hdr;  // [ticket, done]
+};
+
+// Per-wave LDS, each part 16-byte aligned: sym[np], prk[np] (16-bit),
+// alive[np/32], bmin[nb], cblk[nb] (16-bit), dirty[nb/32], list[64] (16-bit);
+// nb = np / 64 blocks of 64 positions, np a multiple of 64.
+struct WaveLayout {
+    uint32_t prk, alive, bmin, cblk, dirty, list, bytes;
+};
+__host__ __device__ inline WaveLayout wave_layout(uint32_t np) {
+    const uint32_t nb = np / 64;
+    WaveLayout l;
+    l.prk = 2u * np;
+    l.alive = 4u * np;
+    l.bmin = l.alive + al16(np / 8);
+    l.cblk = l.bmin + al16(2u * nb);
+    l.dirty = l.cblk + al16(2u * nb);
+    l.list = l.dirty + al16(4u * ((nb + 31) / 32));
+    l.bytes = l.list + 128u;
+    return l;
+}
+__host__ __device__ inline uint32_t wave_lds_bytes(uint32_t np) { return wave_layout(np).bytes; }
+
+__global__ __launch_bounds__(kMaxWaves * 64) void k_bpe_wave(WaveArgs a) {
+    extern __shared__ __align__(16) uint8_t dyn[];
+    RankTab tab;
+    load_table(dyn, a.slot, a.pair, a.slots, a.R, &tab);
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const WaveLayout lay = wave_layout(a.np);
+    uint8_t *wb = dyn + table_bytes(a.slots, a.R) + (threadIdx.x / 64) * a.wave_bytes;
+    uint16_t *sym = reinterpret_cast<uint16_t *>(wb);
+    uint16_t *prk = reinterpret_cast<uint16_t *>(wb + lay.prk);
+    uint32_t *alive = reinterpret_cast<uint32_t *>(wb + lay.alive);
+    uint16_t *bmin = reinterpret_cast<uint16_t *>(wb + lay.bmin);
+    uint16_t *cblk = reinterpret_cast<uint16_t *>(wb + lay.cblk);
+    uint32_t *dirty = reinterpret_cast<uint32_t *>(wb + lay.dirty);
+    uint16_t *list = reinterpret_cast<uint16_t *>(wb + lay.list);
+    const int64_t total = min(*a.n_items_at, a.max_items);
+
+    for (;;) {
+        uint32_t tk = 0;
+        if (lane == 0) tk = atomicAdd(a.hdr + 0, 1u);
+        const int64_t t = (int64_t)(uint32_t)__shfl((int)tk, 0, 64);
+        if (t >= total) break;
+        const int32_t n = a.item_len[t];
+        if (n <= a.lo || n > a.hi) continue;
+        const int64_t c0 = a.item_start[t];
+        const uint8_t *src = a.bytes + c0;
+        const uint32_t nb = ((uint32_t)n + 63) / 64, nw = ((uint32_t)n + 31) / 32, k2 = (nb + 63) / 64;
+
+        // symbols, alive bits, pair ranks, block minima
+        for (uint32_t p = lane; p < nb * 64; p += 64) sym[p] = p < (uint32_t)n ? symbol_of(src[p]) : 0;
+        for (uint32_t w = lane; w < nb * 2; w += 64) {
+            const int32_t f = n - 32 * (int32_t)w;
+            alive[w] = f >= 32 ? ~0u : (f > 0 ? (1u << f) - 1u : 0u);
+        }
+        for (uint32_t w = lane; w < (nb + 31) / 32; w += 64) dirty[w] = 0;
+        wave_sync();
+        for (uint32_t i = 0; i < nb; ++i) {
+            const uint32_t p = i * 64 + lane;
+            const uint32_t r = (p + 1 < (uint32_t)n) ? pair_rank(tab, sym[p], sym[p + 1]) : kNoRank;
+            prk[p] = (uint16_t)r;
+            const uint32_t m = wave_min_u32(r);
+            if (lane == 0) bmin[i] = (uint16_t)m;
+        }
+        wave_sync();
+        uint32_t l2 = kNoRank;
+        for (uint32_t k = 0; k < k2; ++k) {
+            const uint32_t b = lane * k2 + k;
+            if (b < nb) l2 = min(l2, (uint32_t)bmin[b]);
+        }
+
+        // Each round refreshes every block it visits and leaves no pair of
+        // rank rs behind, so rs strictly increases: at most R rounds.
+        for (int32_t round = 0;; ++round) {
+            const uint32_t rs = wave_min_u32(l2);
+            if (rs == kNoRank) break;
+            if (round > a.R) {
+                if (lane == 0) dev::raise_error(a.hdr, DNATOK_DERR_INTERNAL);
+                break;
+            }
+            const uint32_t pr = tab.pair[rs];
+            const uint32_t L = pr & 0xFFFF, NEW = 10 + rs;
+            const bool chain = L == (pr >> 16);
+            // blocks holding rank rs, in order
+            uint32_t cm = 0;
+            if (l2 == rs) {
+                for (uint32_t k = 0; k < k2; ++k) {
+                    const uint32_t b = lane * k2 + k;
+                    if (b < nb && bmin[b] == rs) cm |= 1u << k;
+                }
+            }
+            const uint32_t cc = (uint32_t)__popc(cm);
+            const uint32_t cinc = wave_incl_scan_u32(cc);
+            const uint32_t ncb = (uint32_t)__shfl((int)cinc, 63, 64);
+            {
+                uint32_t o = cinc - cc, m = cm;
+                while (m) {
+                    const uint32_t k = (uint32_t)__builtin_ctz(m);
+                    const uint32_t b = lane * k2 + k;
+                    cblk[o++] = (uint16_t)b;
+                    atomicOr(&dirty[b >> 5], 1u << (b & 31));
+                    m &= m - 1;
+                }
+            }
+            wave_sync();
+            uint32_t carry_q = kNone;
+            int32_t carry_off = 0;
+            for (uint32_t base = 0; base < ncb;) {
+                // gather up to 64 occurrences from the next blocks
+                const uint32_t j = base + lane;
+                uint64_t mm = 0;
+                uint32_t b = 0;
+                if (j < ncb) {
+                    b = cblk[j];
+                    mm = block_match(prk, b, rs);
+                }
+                const uint32_t c = (uint32_t)__popcll(mm);
+                const uint32_t inc = wave_incl_scan_u32(c);
+                const uint32_t m = (uint32_t)__popcll(__ballot(j < ncb && inc <= 64));
+                if ((uint32_t)lane < m) {
+                    uint32_t o = inc - c;
+                    while (mm) {
+                        list[o++] = (uint16_t)(b * 64 + (uint32_t)__builtin_ctzll(mm));
+                        mm &= mm - 1;
+                    }
+                }
+                const uint32_t nc = (uint32_t)__shfl((int)inc, (int)m - 1, 64);
+                wave_sync();
+                // which occurrences merge: all, or for (X, X) every other one of a run
+                const bool valid = (uint32_t)lane < nc;
+                const uint32_t p = valid ? list[lane] : 0;
+                const uint32_t q = valid ? next_alive(alive, nw, p) : kNone;
+                const uint32_t q_up = (uint32_t)__shfl_up((int)q, 1, 64);
+                bool adj = false;
+                if (chain && valid) adj = lane == 0 ? (carry_q == p) : (q_up == p);
+                const uint64_t starts = __ballot(valid && !adj);
+                const uint64_t below = starts & (lane == 63 ? ~0ull : ((2ull << lane) - 1));
+                const int32_t off = below ? lane - (63 - __clzll(below)) : carry_off + 1 + lane;
+                const bool ms = valid && (!chain || (off & 1) == 0);
+                if (nc > 0) {
+                    carry_q = (uint32_t)__shfl((int)q, (int)nc - 1, 64);
+                    carry_off = __shfl(off, (int)nc - 1, 64);
+                }
+                // right elements of the merges one and two occurrences back
+                const uint32_t rq = ms ? q : kNone;
+                const uint32_t rq1 = (uint32_t)__shfl_up((int)rq, 1, 64), rq2 = (uint32_t)__shfl_up((int)rq, 2, 64);
+                uint32_t l = kNone, rk_l = kNoRank, rk_r = kNoRank;
+                bool left = false;
+                if (ms) {
+                    const uint32_t q2 = next_alive(alive, nw, q);
+                    if (q2 != kNone) {
+                        // an occurrence right after a merge merges too
+                        const uint32_t s2 = (prk[q2] == rs) ? NEW : sym[q2];
+                        rk_r = pair_rank(tab, NEW, s2);
+                    }
+                    l = prev_alive(alive, p);
+                    left = l != kNone && !(lane >= 1 && rq1 == l) && !(lane >= 2 && rq2 == l);
+                    if (left) rk_l = pair_rank(tab, sym[l], NEW);
+                }
+                wave_sync();
+                if (ms) {
+                    sym[p] = (uint16_t)NEW;
+                    prk[p] = (uint16_t)rk_r;
+                    prk[q] = kNoRank;
+                    atomicAnd(&alive[q >> 5], ~(1u << (q & 31)));
+                    atomicOr(&dirty[(p >> 6) >> 5], 1u << ((p >> 6) & 31));
+                    atomicOr(&dirty[(q >> 6) >> 5], 1u << ((q >> 6) & 31));
+                    if (left) {
+                        prk[l] = (uint16_t)rk_l;
+                        atomicOr(&dirty[(l >> 6) >> 5], 1u << ((l >> 6) & 31));
+                    }
+                }
+                wave_sync();
+                base += m;
+            }
+            // refresh the minima of changed blocks
+            bool touched = false;
+            for (uint32_t k = 0; k < k2; ++k) {
+                const uint32_t b = lane * k2 + k;
+                if (b < nb && ((dirty[b >> 5] >> (b & 31)) & 1u)) {
+                    bmin[b] = (uint16_t)block_min(prk, b);
+                    touched = true;
+                }
+            }
+            wave_sync();
+            for (uint32_t w = lane; w < (nb + 31) / 32; w += 64) dirty[w] = 0;
+            if (touched) {
+                l2 = kNoRank;
+                for (uint32_t k = 0; k < k2; ++k) {
+                    const uint32_t b = lane * k2 + k;
+                    if (b < nb) l2 = min(l2, (uint32_t)bmin[b]);
+                }
+            }
+            wave_sync();
+        }
+
+        // surviving symbols in order
+        uint32_t cnt = 0;
+        uint16_t *out = a.tok + c0;
+        for (uint32_t base = 0; base < nb * 64; base += 64) {
+            const uint32_t p = base + lane;
+            const bool on = (alive[p >> 5] >> (p & 31)) & 1u;
+            const uint64_t mk = __ballot(on);
+            if (on) out[cnt + (uint32_t)__popcll(mk & ((1ull << lane) - 1))] = sym[p];
+            cnt += (uint32_t)__popcll(mk);
+        }
+        if (lane == 0) a.item_cnt[t] = (int32_t)cnt;
+        wave_sync();
+    }
+    if (lane == 0) {
+        // the last wave to finish resets the ticket for the next launch
+        const uint32_t total_waves = gridDim.x * (blockDim.x / 64);
+        if (atomicAdd(a.hdr + 1, 1u) == total_waves - 1) {
+            dev::st_relaxed32(a.hdr + 0, 0u);
+            dev::st_relaxed32(a.hdr + 1, 0u);
+        }
+    }
+}
+
+// ---- 4. workgroup per long item ---------------------------------------------------
 
 // Chain state of a slice for the scan that finds, at each slice start, how
 // many consecutive occurrences of an (X, X) pair end just before it.
@@ -221,7 +574,6 @@ __device__ __forceinline__ Chain chain_join(Chain a, Chain b) {
     return Chain{a.full & b.full, b.full ? a.tail + b.len : b.tail, a.len + b.len};
 }
 
-// Exclusive scan of Chain over the block's threads.
 __device__ Chain chain_excl_scan(Chain c, Chain *s_wave) {
     const int lane = threadIdx.x & (dev::kWave - 1), w = threadIdx.x / dev::kWave;
     Chain inc = c;
@@ -237,7 +589,6 @@ __device__ Chain chain_excl_scan(Chain c, Chain *s_wave) {
     __syncthreads();
     Chain pre{1, 0, 0};
     for (int i = 0; i < w; ++i) pre = chain_join(pre, s_wave[i]);
-    // exclusive within the wave: inclusive of lane-1
     Chain lw;
     lw.full = __shfl_up(inc.full, 1, dev::kWave);
     lw.tail = __shfl_up(inc.tail, 1, dev::kWave);
@@ -246,21 +597,21 @@ __device__ Chain chain_excl_scan(Chain c, Chain *s_wave) {
     return lane == 0 ? pre : chain_join(pre, lw);
 }
 
-// Segment one item's symbols A[0, n) with B as the second buffer (both LDS
-// or both global). Returns the final length; *in_a tells whether the result
-// ended up in A.
-template <class SymPtr>
-__device__ int32_t merge_segment(SymPtr A, SymPtr B, int32_t n, const LdsTables &tab, int32_t *hist,
-                                 const int32_t *merges, int32_t R, int64_t *s_tmp, Chain *s_chain, int32_t *s_rstar,
-                                 bool *in_a) {
+// Segment A[0, n) with B as the second buffer (global scratch). A rank
+// histogram of all current pairs drives the rounds; each round merges,
+// compacts into the other buffer and updates the histogram for the pairs
+// destroyed and created. Returns the final length; *in_a tells whether the
+// result ended up in A.
+__device__ int32_t merge_segment(uint16_t *A, uint16_t *B, int32_t n, const RankTab &tab, int32_t *hist, int32_t R,
+                                 int64_t *s_tmp, Chain *s_chain, int32_t *s_rstar, bool *in_a) {
     const int tid = threadIdx.x;
     const int lane = tid & (dev::kWave - 1);
     bool a_is_a = true;
     for (int32_t r = tid; r < R; r += NTM) hist[r] = 0;
     __syncthreads();
     for (int32_t p = tid; p + 1 < n; p += NTM) {
-        const int32_t r = rank_of(tab, A[p], A[p + 1]);
-        if (r >= 0) atomicAdd(&hist[r], 1);
+        const uint32_t r = pair_rank(tab, A[p], A[p + 1]);
+        if (r != kNoRank) atomicAdd(&hist[r], 1);
     }
     __syncthreads();
     int32_t cur = -1;
@@ -282,7 +633,8 @@ __device__ int32_t merge_segment(SymPtr A, SymPtr B, int32_t n, const LdsTables 
         const int32_t rs = *s_rstar;
         if (rs >= R) break;
         cur = rs;
-        const uint16_t L = (uint16_t)merges[2 * rs], Rr = (uint16_t)merges[2 * rs + 1];
+        const uint32_t pr = tab.pair[rs];
+        const uint16_t L = (uint16_t)(pr & 0xFFFF), Rr = (uint16_t)(pr >> 16);
         const uint16_t NEW = (uint16_t)(10 + rs);
         const bool chain = (L == Rr);
         const int32_t sl = (n + NTM - 1) / NTM;
@@ -317,14 +669,14 @@ __device__ int32_t merge_segment(SymPtr A, SymPtr B, int32_t n, const LdsTables 
                 if (ms) {
                     atomicSub(&hist[rs], 1);
                     if (p + 2 < n) {
-                        const int32_t r2 = rank_of(tab, Rr, A[p + 2]);
-                        if (r2 >= 0) atomicSub(&hist[r2], 1);
+                        const uint32_t r2 = pair_rank(tab, Rr, A[p + 2]);
+                        if (r2 != kNoRank) atomicSub(&hist[r2], 1);
                     }
                     // the left pair belongs to this merge unless p-1 was consumed by a merge at p-2
                     const bool p2 = (p >= 2) && cand(p - 2) && (!chain || cand(p - 1));
                     if (p >= 1 && !p2) {
-                        const int32_t r0 = rank_of(tab, A[p - 1], L);
-                        if (r0 >= 0) atomicSub(&hist[r0], 1);
+                        const uint32_t r0 = pair_rank(tab, A[p - 1], L);
+                        if (r0 != kNoRank) atomicSub(&hist[r0], 1);
                     }
                 }
                 prev = ms;
@@ -356,12 +708,12 @@ __device__ int32_t merge_segment(SymPtr A, SymPtr B, int32_t n, const LdsTables 
                 if (!prev) {
                     if (ms) {
                         if (y + 1 < n2) {
-                            const int32_t r = rank_of(tab, NEW, B[y + 1]);
-                            if (r >= 0) atomicAdd(&hist[r], 1);
+                            const uint32_t r = pair_rank(tab, NEW, B[y + 1]);
+                            if (r != kNoRank) atomicAdd(&hist[r], 1);
                         }
                         if (y >= 1 && B[y - 1] != NEW) {
-                            const int32_t r = rank_of(tab, B[y - 1], NEW);
-                            if (r >= 0) atomicAdd(&hist[r], 1);
+                            const uint32_t r = pair_rank(tab, B[y - 1], NEW);
+                            if (r != kNoRank) atomicAdd(&hist[r], 1);
                         }
                     }
                     ++y;
@@ -370,7 +722,7 @@ __device__ int32_t merge_segment(SymPtr A, SymPtr B, int32_t n, const LdsTables 
             }
         }
         __syncthreads();
-        SymPtr t = A;
+        uint16_t *t = A;
         A = B;
         B = t;
         a_is_a = !a_is_a;
@@ -380,89 +732,58 @@ __device__ int32_t merge_segment(SymPtr A, SymPtr B, int32_t n, const LdsTables 
     return n;
 }
 
-__global__ __launch_bounds__(NTM) void k_bpe_merge(MergeArgs a) {
+struct BlockArgs {
+    const uint8_t *bytes;
+    const int64_t *item_start;
+    const int32_t *item_len;
+    const int64_t *n_items_at;
+    int64_t max_items;
+    uint16_t *symA;  // [nbytes]: final symbols of every item at its start
+    uint16_t *symB;  // [nbytes]: second buffer
+    int32_t *item_cnt;
+    const uint16_t *slot;
+    const uint32_t *pair;
+    uint32_t slots;
+    int32_t R;
+    int32_t lo;  // this launch takes items longer than lo
+    uint32_t *hdr;
+};
+
+__global__ __launch_bounds__(NTM) void k_bpe_block(BlockArgs a) {
     extern __shared__ __align__(16) uint8_t dyn[];
     __shared__ int64_t s_tmp[NTM / dev::kWave + 1];
     __shared__ Chain s_chain[NTM / dev::kWave];
     __shared__ int32_t s_rstar;
-    __shared__ int64_t s_ticket, s_c0, s_c1;
-
-    uint32_t *hkey = reinterpret_cast<uint32_t *>(dyn);
-    uint16_t *hrank = reinterpret_cast<uint16_t *>(hkey + a.slots);
-    int32_t *hist = reinterpret_cast<int32_t *>(hrank + ((a.slots + 1) & ~1u));
-    uint16_t *la = reinterpret_cast<uint16_t *>(hist + ((a.R + 1) & ~1));
-    uint16_t *lb = la + a.lmax;
+    __shared__ int64_t s_ticket;
+    RankTab tab;
+    load_table(dyn, a.slot, a.pair, a.slots, a.R, &tab);
+    int32_t *hist = reinterpret_cast<int32_t *>(dyn + table_bytes(a.slots, a.R));
     const int tid = threadIdx.x;
-    for (uint32_t s = tid; s < a.slots; s += NTM) {
-        hkey[s] = a.hkey[s];
-        hrank[s] = a.hrank[s];
-    }
-    const LdsTables tab{hkey, hrank, a.slots - 1};
-    const int64_t total = min(a.item_off[a.n], a.max_items);
+    const int64_t total = min(*a.n_items_at, a.max_items);
     __syncthreads();
-
     for (;;) {
-        if (tid == 0) s_ticket = (int64_t)atomicAdd(a.q.hdr + 0, 1u);
+        if (tid == 0) s_ticket = (int64_t)atomicAdd(a.hdr + 0, 1u);
         __syncthreads();
         const int64_t t = s_ticket;
-        if (t >= total) break;
-        if (tid < dev::kWave) {
-            // row i: the last row whose first item is <= t
-            const int64_t i1 = dev::wave_lower_bound(0, (int64_t)a.n + 1, [&](int64_t i) { return a.item_off[i] > t; });
-            const int64_t i = i1 - 1, j = t - a.item_off[i], nj = a.item_off[i + 1] - a.item_off[i];
-            int64_t off = a.offs[i], end = a.offs[i + 1];
-            off = off < 0 ? 0 : (off > a.nbytes ? a.nbytes : off);
-            end = end < off ? off : (end > a.nbytes ? a.nbytes : end);
-            int64_t c0 = (j == 0) ? off : item_start_probe(a.bytes, off, end, j, a.S);
-            int64_t c1 = c0;
-            if (c0 >= 0) {
-                c1 = end;
-                for (int64_t jj = j + 1; jj < nj; ++jj) {
-                    const int64_t b = item_start_probe(a.bytes, off, end, jj, a.S);
-                    if (b >= 0) {
-                        c1 = b;
-                        break;
-                    }
-                }
-            } else {
-                c0 = c1 = 0;
-            }
-            if (tid == 0) {
-                s_c0 = c0;
-                s_c1 = c1 > c0 ? c1 : c0;
-            }
-        }
         __syncthreads();
-        const int64_t c0 = s_c0, len = s_c1 - s_c0;
-        int32_t nf = 0;
-        if (len > 0) {
-            if (len <= a.lmax) {
-                for (int64_t p = tid; p < len; p += NTM) la[p] = symbol_of(a.bytes[c0 + p]);
-                __syncthreads();
-                bool in_a = true;
-                nf = merge_segment(la, lb, (int32_t)len, tab, hist, a.merges, a.R, s_tmp, s_chain, &s_rstar, &in_a);
-                const uint16_t *res = in_a ? la : lb;
-                for (int32_t p = tid; p < nf; p += NTM) a.symA[c0 + p] = res[p];
-            } else {
-                uint16_t *ga = a.symA + c0, *gb = a.symB + c0;
-                for (int64_t p = tid; p < len; p += NTM) ga[p] = symbol_of(a.bytes[c0 + p]);
-                __syncthreads();
-                bool in_a = true;
-                nf = merge_segment(ga, gb, (int32_t)len, tab, hist, a.merges, a.R, s_tmp, s_chain, &s_rstar, &in_a);
-                if (!in_a)
-                    for (int32_t p = tid; p < nf; p += NTM) ga[p] = gb[p];
-            }
-        }
-        if (tid == 0) {
-            a.item_cnt[t] = nf;
-            a.item_start[t] = c0;
-        }
+        if (t >= total) break;
+        const int32_t len = a.item_len[t];
+        if (len <= a.lo) continue;
+        const int64_t c0 = a.item_start[t];
+        uint16_t *ga = a.symA + c0, *gb = a.symB + c0;
+        for (int32_t p = tid; p < len; p += NTM) ga[p] = symbol_of(a.bytes[c0 + p]);
+        __syncthreads();
+        bool in_a = true;
+        const int32_t nf = merge_segment(ga, gb, len, tab, hist, a.R, s_tmp, s_chain, &s_rstar, &in_a);
+        if (!in_a)
+            for (int32_t p = tid; p < nf; p += NTM) ga[p] = gb[p];
+        if (tid == 0) a.item_cnt[t] = nf;
         __syncthreads();
     }
-    if (tid == 0) dev::finish_block(a.q.hdr, false);
+    if (tid == 0) dev::finish_block(a.hdr, false);
 }
 
-// ---- item count scan -------------------------------------------------------------------
+// ---- 5. item count scan and emit ---------------------------------------------------
 
 struct ScanArgs {
     const int32_t *cnt;
@@ -517,8 +838,6 @@ __global__ __launch_bounds__(NTE) void k_scan_counts(ScanArgs a) {
     }
     if (tid == 0) dev::finish_block(a.q.hdr);
 }
-
-// ---- emit ------------------------------------------------------------------------------
 
 struct EmitArgs {
     const int64_t *offs;
@@ -594,7 +913,6 @@ __global__ __launch_bounds__(NTE) void k_bpe_emit(EmitArgs a) {
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
         const int32_t cnt = a.item_cnt[t];
         if (cnt == 0) continue;
-        // row of item t
         int64_t lo = 0, hi = a.n - 1;
         while (lo < hi) {
             const int64_t mid = (lo + hi + 1) >> 1;
@@ -627,14 +945,40 @@ __global__ __launch_bounds__(NTE) void k_bpe_emit(EmitArgs a) {
 
 }  // namespace
 
+// Length classes of the wave kernel for a table of `tab` LDS bytes: waves
+// per workgroup w in {8, 4, 2, 1}, each wave holding up to np(w) symbols
+// where one workgroup fills the CU's LDS. Class w takes the items longer
+// than the previous class's capacity.
+int bpe_wave_classes(uint32_t tab, BpeClass *out, int max_out) {
+    int nc = 0;
+    uint32_t prev = 0;
+    const int waves[4] = {8, 4, 2, 1};
+    for (int i = 0; i < 4 && nc < max_out; ++i) {
+        const int w = waves[i];
+        if (kLdsBytes < kLdsReserve + tab) break;
+        const size_t room = (kLdsBytes - kLdsReserve - tab) / (size_t)w;
+        // largest multiple of 64 whose per-wave layout fits the room
+        uint32_t np = (uint32_t)std::min<size_t>(room / 4, 65536) / 64 * 64;
+        while (np >= 64 && wave_lds_bytes(np) > room) np -= 64;
+        if (np < 64 || np <= prev) continue;
+        out[nc].waves = w;
+        out[nc].lo = (int32_t)prev;
+        out[nc].hi = (int32_t)np;
+        out[nc].np = np;
+        out[nc].lds = tab + (uint32_t)w * wave_lds_bytes(np);
+        prev = np;
+        ++nc;
+    }
+    return nc;
+}
+
 int launch_bpe_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets,
                       int32_t n, int32_t *d_ids, int64_t cap, int64_t *d_out_offsets, int8_t *d_mask,
                       const dnatok_encode_opts &o, hipStream_t stream) {
     const BpeTables &bt = v->bpe;
     const int32_t R = bt.n_merges;
-    if (R > kBpeMaxMerges) return set_error(DNATOK_EVOCAB, "device BPE supports up to %d merges", kBpeMaxMerges);
     const int64_t max_items = nbytes / kItemBytes + (int64_t)n + 1;
-    // scratch: symA, symB (uint16 per byte), item_off, item_cnt, item_start, item_pos
+    // scratch: symA, symB (uint16 per byte), item_off, item_cnt, item_len, item_start, item_pos
     auto al = [](int64_t x) { return (x + 255) / 256 * 256; };
     const int64_t sz_sym = al(2 * (nbytes + 1));
     const int64_t sz_ioff = al(8 * ((int64_t)n + 1));
@@ -646,54 +990,92 @@ int launch_bpe_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nby
     const int64_t units_items = std::max<int64_t>(1, (max_items + kScanUnit - 1) / kScanUnit);
     int rc = get_workspace(stream, std::max(units_rows, units_items), &ws);
     if (rc) return rc;
-    rc = ensure_scratch(ws, 2 * sz_sym + sz_ioff + sz_cnt + sz_start + sz_pos);
+    rc = ensure_scratch(ws, 2 * sz_sym + sz_ioff + 2 * sz_cnt + sz_start + sz_pos);
     if (rc) return rc;
     uint8_t *sp = ws->d_scratch;
     uint16_t *symA = reinterpret_cast<uint16_t *>(sp);
-    uint16_t *symB = reinterpret_cast<uint16_t *>(sp + sz_sym);
-    int64_t *item_off = reinterpret_cast<int64_t *>(sp + 2 * sz_sym);
-    int32_t *item_cnt = reinterpret_cast<int32_t *>(sp + 2 * sz_sym + sz_ioff);
-    int64_t *item_start = reinterpret_cast<int64_t *>(sp + 2 * sz_sym + sz_ioff + sz_cnt);
-    int64_t *item_pos = reinterpret_cast<int64_t *>(sp + 2 * sz_sym + sz_ioff + sz_cnt + sz_start);
+    sp += sz_sym;
+    uint16_t *symB = reinterpret_cast<uint16_t *>(sp);
+    sp += sz_sym;
+    int64_t *item_off = reinterpret_cast<int64_t *>(sp);
+    sp += sz_ioff;
+    int32_t *item_cnt = reinterpret_cast<int32_t *>(sp);
+    sp += sz_cnt;
+    int32_t *item_len = reinterpret_cast<int32_t *>(sp);
+    sp += sz_cnt;
+    int64_t *item_start = reinterpret_cast<int64_t *>(sp);
+    sp += sz_start;
+    int64_t *item_pos = reinterpret_cast<int64_t *>(sp);
+    if (units_items > ws->high_water) ws->high_water = units_items;
+    const int cus = device_cu_count();
 
     // 1. item plan
     rc = launch_rowscan(d_offsets, n, nbytes, item_off, kItemBytes, 0, stream);
     if (rc) return rc;
 
-    // 2. merges
-    MergeArgs m;
-    m.bytes = d_bytes;
-    m.nbytes = nbytes;
-    m.offs = d_offsets;
-    m.n = n;
-    m.item_off = item_off;
-    m.S = kItemBytes;
-    m.symA = symA;
-    m.symB = symB;
-    m.item_cnt = item_cnt;
-    m.item_start = item_start;
-    m.max_items = max_items;
-    m.hkey = bt.d_hkey;
-    m.hrank = bt.d_hrank;
-    m.slots = bt.slots;
-    m.merges = bt.d_merges;
-    m.R = R;
-    const size_t tables = (size_t)bt.slots * 4 + (size_t)((bt.slots + 1) & ~1u) * 2 + (size_t)((R + 1) & ~1) * 4;
-    int64_t lmax = (int64_t)((kLdsBudget - tables) / 4);
-    lmax = lmax / NTM * NTM;
-    if (lmax < NTM) return set_error(DNATOK_EVOCAB, "BPE tables leave no room for symbols in LDS");
-    m.lmax = (int32_t)lmax;
-    const size_t dyn = tables + 4 * (size_t)lmax;
-    m.q.hdr = ws->d_hdr;
-    m.q.status0 = ws->d_status;
-    m.q.status1 = ws->d_status + ws->cap;
-    m.q.clear_n = ws->high_water;
-    DNATOK_HIP(hipFuncSetAttribute((const void *)k_bpe_merge, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
-    int64_t grid = std::min<int64_t>(max_items, (int64_t)device_cu_count());
-    hipLaunchKernelGGL(k_bpe_merge, dim3((unsigned)grid), dim3(NTM), dyn, stream, m);
+    // 2. items
+    ItemArgs ia{d_bytes, nbytes, d_offsets, n, item_off, max_items, kItemBytes, item_start, item_len, item_cnt};
+    const int64_t g_items = std::max<int64_t>(1, std::min<int64_t>((max_items + 3) / 4, (int64_t)cus * 8));
+    hipLaunchKernelGGL(k_bpe_items, dim3((unsigned)g_items), dim3(NTE), 0, stream, ia);
     DNATOK_HIP(hipGetLastError());
 
-    // 3. item positions
+    // 3. wave classes
+    const uint32_t tab = table_bytes(bt.slots, R);
+    BpeClass cls[4];
+    const int ncls = bpe_wave_classes(tab, cls, 4);
+    int32_t covered = 0;
+    for (int c = 0; c < ncls; ++c) {
+        WaveArgs w;
+        w.bytes = d_bytes;
+        w.item_start = item_start;
+        w.item_len = item_len;
+        w.n_items_at = item_off + n;
+        w.max_items = max_items;
+        w.tok = symA;
+        w.item_cnt = item_cnt;
+        w.slot = bt.d_slot;
+        w.pair = bt.d_pair;
+        w.slots = bt.slots;
+        w.R = R;
+        w.lo = cls[c].lo;
+        w.hi = cls[c].hi;
+        w.np = cls[c].np;
+        w.wave_bytes = wave_lds_bytes(cls[c].np);
+        w.hdr = ws->d_hdr;
+        DNATOK_HIP(hipFuncSetAttribute((const void *)k_bpe_wave, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)cls[c].lds));
+        const int per_cu = std::max<int>(1, (int)((kLdsBytes - kLdsReserve) / cls[c].lds));
+        hipLaunchKernelGGL(k_bpe_wave, dim3((unsigned)(cus * per_cu)), dim3(64 * cls[c].waves), cls[c].lds, stream,
+                           w);
+        DNATOK_HIP(hipGetLastError());
+        covered = cls[c].hi;
+    }
+
+    // 4. longer items
+    {
+        BlockArgs b;
+        b.bytes = d_bytes;
+        b.item_start = item_start;
+        b.item_len = item_len;
+        b.n_items_at = item_off + n;
+        b.max_items = max_items;
+        b.symA = symA;
+        b.symB = symB;
+        b.item_cnt = item_cnt;
+        b.slot = bt.d_slot;
+        b.pair = bt.d_pair;
+        b.slots = bt.slots;
+        b.R = R;
+        b.lo = covered;
+        b.hdr = ws->d_hdr;
+        const size_t dyn = tab + 4 * (size_t)(R > 0 ? R : 1);
+        DNATOK_HIP(hipFuncSetAttribute((const void *)k_bpe_block, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)dyn));
+        hipLaunchKernelGGL(k_bpe_block, dim3((unsigned)cus), dim3(NTM), dyn, stream, b);
+        DNATOK_HIP(hipGetLastError());
+    }
+
+    // 5. item positions and output
     ScanArgs sa;
     sa.cnt = item_cnt;
     sa.total_at = item_off + n;
@@ -703,15 +1085,13 @@ int launch_bpe_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nby
     sa.q.hdr = ws->d_hdr;
     sa.q.status0 = ws->d_status;
     sa.q.status1 = ws->d_status + ws->cap;
-    if (units_items > ws->high_water) ws->high_water = units_items;
     sa.q.clear_n = ws->high_water;
     int per_cu = 0;
     DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_scan_counts, NTE, 0));
-    int64_t g2 = std::min<int64_t>(units_items, (int64_t)device_cu_count() * std::max(per_cu, 1));
+    int64_t g2 = std::min<int64_t>(units_items, (int64_t)cus * std::max(per_cu, 1));
     hipLaunchKernelGGL(k_scan_counts, dim3((unsigned)g2), dim3(NTE), 0, stream, sa);
     DNATOK_HIP(hipGetLastError());
 
-    // 4. emit
     EmitArgs e;
     e.offs = d_offsets;
     e.n = n;
@@ -734,7 +1114,7 @@ int launch_bpe_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nby
     e.W = e.padded ? o.pad_to : 0;
     e.base = o.offset_base;
     e.err_hdr = ws->d_hdr;
-    int64_t g3 = std::max<int64_t>(1, std::min<int64_t>(std::max<int64_t>(n, max_items), (int64_t)device_cu_count() * 8));
+    int64_t g3 = std::max<int64_t>(1, std::min<int64_t>(std::max<int64_t>(n, max_items), (int64_t)cus * 8));
     hipLaunchKernelGGL(k_bpe_emit, dim3((unsigned)g3), dim3(NTE), 0, stream, e);
     DNATOK_HIP(hipGetLastError());
     return DNATOK_OK;

@@ -28,9 +28,10 @@ void clear_error();
 
 // ---- vocabulary ----------------------------------------------------------------
 
-// Pair -> rank lookup shared by the host (table build) and the device:
-// open addressing with linear probing over a power-of-two table; a slot
-// holds the key (left << 16) | right (never 0: left >= 5) and the rank.
+// Pair -> rank lookup shared by the host (table build) and the device: open
+// addressing with linear probing over a power-of-two table of 16-bit ranks
+// (0xFFFF = empty); a hit is confirmed against the packed merge pair
+// left | right << 16 of that rank.
 __host__ __device__ inline uint32_t bpe_pair_hash(uint32_t a, uint32_t b) {
     uint32_t h = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u) * 0x85EBCA77u;
     h ^= h >> 15;
@@ -39,14 +40,14 @@ __host__ __device__ inline uint32_t bpe_pair_hash(uint32_t a, uint32_t b) {
     return h;
 }
 
-constexpr int32_t kBpeMaxMerges = 8192;  // device tables (hash + rank counts) live in LDS
+constexpr int32_t kBpeMaxMerges = 8192;  // ranks and ids fit 16 bits; tables live in LDS
+constexpr uint16_t kNoRank = 0xFFFF;
 
 struct BpeTables {
     int32_t n_merges = 0;
     uint32_t slots = 0;             // power of two >= 2 * n_merges
-    uint32_t *d_hkey = nullptr;     // [slots] (left << 16) | right, 0 = empty
-    uint16_t *d_hrank = nullptr;    // [slots]
-    int32_t *d_merges = nullptr;    // [R][2]
+    uint16_t *d_slot = nullptr;     // [slots] rank or kNoRank
+    uint32_t *d_pair = nullptr;     // [R] left | right << 16
     int32_t *d_tok_len = nullptr;   // decoded length per id, [vocab]
     int64_t *d_tok_off = nullptr;   // offset of each id's bases in d_tok_chars, [vocab]
     uint8_t *d_tok_chars = nullptr;
@@ -114,6 +115,15 @@ int launch_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes,
 // out[i] = sum over rows r < i of ceil(L_r / divisor) + 2 * cls (out[n] = total).
 int launch_rowscan(const int64_t *d_offsets, int32_t n, int64_t nbytes, int64_t *d_out, int32_t divisor, int32_t cls,
                    hipStream_t stream);
+
+// One length class of the wave-per-item BPE kernel.
+struct BpeClass {
+    int waves;       // waves per workgroup
+    int32_t lo, hi;  // items with lo < length <= hi
+    uint32_t np;     // symbols per wave
+    uint32_t lds;    // dynamic LDS bytes per workgroup
+};
+int bpe_wave_classes(uint32_t table_lds_bytes, BpeClass *out, int max_out);
 
 int launch_bpe_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets,
                       int32_t n, int32_t *d_ids, int64_t cap, int64_t *d_out_offsets, int8_t *d_mask,
