@@ -258,22 +258,6 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
-#pragma unroll
-    for (int d = 1; d < dev::kWave; d <<= 1) v = min(v, (uint32_t)__shfl_xor((int)v, d, dev::kWave));
-    return v;
-}
-
-__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
-    const int lane = threadIdx.x & (dev::kWave - 1);
-#pragma unroll
-    for (int d = 1; d < dev::kWave; d <<= 1) {
-        const uint32_t u = (uint32_t)__shfl_up((int)v, d, dev::kWave);
-        if (lane >= d) v += u;
-    }
-    return v;
-}
-
 // Next / previous alive position strictly after / before x, or kNone.
 __device__ __forceinline__ uint32_t next_alive(const uint32_t *alive, uint32_t nw, uint32_t x) {
     uint32_t w = x >> 5;
@@ -383,7 +367,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) void k_bpe_wave(WaveArgs a) {
     for (;;) {
         uint32_t tk = 0;
         if (lane == 0) tk = atomicAdd(a.hdr + 0, 1u);
-        const int64_t t = (int64_t)(uint32_t)__shfl((int)tk, 0, 64);
+        const int64_t t = (int64_t)dev::wave_read_u32(tk, 0);
         if (t >= total) break;
         const int32_t n = a.item_len[t];
         if (n <= a.lo || n > a.hi) continue;
@@ -403,7 +387,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) void k_bpe_wave(WaveArgs a) {
             const uint32_t p = i * 64 + lane;
             const uint32_t r = (p + 1 < (uint32_t)n) ? pair_rank(tab, sym[p], sym[p + 1]) : kNoRank;
             prk[p] = (uint16_t)r;
-            const uint32_t m = wave_min_u32(r);
+            const uint32_t m = dev::wave_min_all_u32(r);
             if (lane == 0) bmin[i] = (uint16_t)m;
         }
         wave_sync();
@@ -416,7 +400,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) void k_bpe_wave(WaveArgs a) {
         // Each round refreshes every block it visits and leaves no pair of
         // rank rs behind, so rs strictly increases: at most R rounds.
         for (int32_t round = 0;; ++round) {
-            const uint32_t rs = wave_min_u32(l2);
+            const uint32_t rs = dev::wave_min_all_u32(l2);
             if (rs == kNoRank) break;
             if (round > a.R) {
                 if (lane == 0) dev::raise_error(a.hdr, DNATOK_DERR_INTERNAL);
@@ -434,8 +418,8 @@ __global__ __launch_bounds__(kMaxWaves * 64) void k_bpe_wave(WaveArgs a) {
                 }
             }
             const uint32_t cc = (uint32_t)__popc(cm);
-            const uint32_t cinc = wave_incl_scan_u32(cc);
-            const uint32_t ncb = (uint32_t)__shfl((int)cinc, 63, 64);
+            const uint32_t cinc = dev::wave_incl_sum_u32(cc);
+            const uint32_t ncb = dev::wave_read_u32(cinc, 63);
             {
                 uint32_t o = cinc - cc, m = cm;
                 while (m) {
@@ -459,7 +443,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) void k_bpe_wave(WaveArgs a) {
                     mm = block_match(prk, b, rs);
                 }
                 const uint32_t c = (uint32_t)__popcll(mm);
-                const uint32_t inc = wave_incl_scan_u32(c);
+                const uint32_t inc = dev::wave_incl_sum_u32(c);
                 const uint32_t m = (uint32_t)__popcll(__ballot(j < ncb && inc <= 64));
                 if ((uint32_t)lane < m) {
                     uint32_t o = inc - c;
@@ -468,26 +452,27 @@ __global__ __launch_bounds__(kMaxWaves * 64) void k_bpe_wave(WaveArgs a) {
                         mm &= mm - 1;
                     }
                 }
-                const uint32_t nc = (uint32_t)__shfl((int)inc, (int)m - 1, 64);
+                const uint32_t nc = dev::wave_read_u32(inc, m - 1);
                 wave_sync();
                 // which occurrences merge: all, or for (X, X) every other one of a run
                 const bool valid = (uint32_t)lane < nc;
                 const uint32_t p = valid ? list[lane] : 0;
                 const uint32_t q = valid ? next_alive(alive, nw, p) : kNone;
-                const uint32_t q_up = (uint32_t)__shfl_up((int)q, 1, 64);
-                bool adj = false;
-                if (chain && valid) adj = lane == 0 ? (carry_q == p) : (q_up == p);
+                // lane 0 compares with the last occurrence of the previous group
+                const uint32_t q_up = dev::wave_from_prev_u32(q, carry_q);
+                const bool adj = chain && valid && q_up == p;
                 const uint64_t starts = __ballot(valid && !adj);
                 const uint64_t below = starts & (lane == 63 ? ~0ull : ((2ull << lane) - 1));
                 const int32_t off = below ? lane - (63 - __clzll(below)) : carry_off + 1 + lane;
                 const bool ms = valid && (!chain || (off & 1) == 0);
                 if (nc > 0) {
-                    carry_q = (uint32_t)__shfl((int)q, (int)nc - 1, 64);
-                    carry_off = __shfl(off, (int)nc - 1, 64);
+                    carry_q = dev::wave_read_u32(q, nc - 1);
+                    carry_off = (int32_t)dev::wave_read_u32((uint32_t)off, nc - 1);
                 }
                 // right elements of the merges one and two occurrences back
                 const uint32_t rq = ms ? q : kNone;
-                const uint32_t rq1 = (uint32_t)__shfl_up((int)rq, 1, 64), rq2 = (uint32_t)__shfl_up((int)rq, 2, 64);
+                const uint32_t rq1 = dev::wave_from_prev_u32(rq, kNone);
+                const uint32_t rq2 = dev::wave_from_prev_u32(rq1, kNone);
                 uint32_t l = kNone, rk_l = kNoRank, rk_r = kNoRank;
                 bool left = false;
                 if (ms) {
@@ -498,7 +483,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) void k_bpe_wave(WaveArgs a) {
                         rk_r = pair_rank(tab, NEW, s2);
                     }
                     l = prev_alive(alive, p);
-                    left = l != kNone && !(lane >= 1 && rq1 == l) && !(lane >= 2 && rq2 == l);
+                    left = l != kNone && rq1 != l && rq2 != l;
                     if (left) rk_l = pair_rank(tab, sym[l], NEW);
                 }
                 wave_sync();

@@ -41,6 +41,51 @@ __device__ __forceinline__ int64_t wave_sum(int64_t v) {
     return v;
 }
 
+// Cross-lane moves through DPP (data-parallel primitives of the VALU, no LDS
+// round trip). Lanes whose source is outside the pattern, or whose row is
+// masked off, return `old`.
+template <int CTRL, int ROW_MASK = 0xF, int BANK_MASK = 0xF>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t old, uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROW_MASK, BANK_MASK, false);
+}
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143, kDppWaveShr1 = 0x138;
+
+// Inclusive sum over the 64 lanes: shifts of 1, 2, 4, 8 inside each row of
+// 16 lanes, then the last lane of row 0 / 2 into rows 1 / 3, then lane 31
+// into rows 2 and 3.
+__device__ __forceinline__ uint32_t wave_incl_sum_u32(uint32_t v) {
+    v += dpp_u32<kDppRowShr1>(0, v);
+    v += dpp_u32<kDppRowShr2>(0, v);
+    v += dpp_u32<kDppRowShr4>(0, v);
+    v += dpp_u32<kDppRowShr8>(0, v);
+    v += dpp_u32<kDppRowBcast15, 0xA>(0, v);
+    v += dpp_u32<kDppRowBcast31, 0xC>(0, v);
+    return v;
+}
+
+// Minimum over the 64 lanes, returned to every lane (a prefix minimum
+// whose last lane is read back as a scalar).
+__device__ __forceinline__ uint32_t wave_min_all_u32(uint32_t v) {
+    v = min(v, dpp_u32<kDppRowShr1>(~0u, v));
+    v = min(v, dpp_u32<kDppRowShr2>(~0u, v));
+    v = min(v, dpp_u32<kDppRowShr4>(~0u, v));
+    v = min(v, dpp_u32<kDppRowShr8>(~0u, v));
+    v = min(v, dpp_u32<kDppRowBcast15, 0xA>(~0u, v));
+    v = min(v, dpp_u32<kDppRowBcast31, 0xC>(~0u, v));
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Value of lane - 1 (lane 0 gets `first`).
+__device__ __forceinline__ uint32_t wave_from_prev_u32(uint32_t v, uint32_t first) {
+    return dpp_u32<kDppWaveShr1>(first, v);
+}
+
+// Value of a lane given by a wave-uniform index.
+__device__ __forceinline__ uint32_t wave_read_u32(uint32_t v, uint32_t lane) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)__builtin_amdgcn_readfirstlane((int)lane));
+}
+
 // Block-wide exclusive scan (NT threads, NT a multiple of 64). `tmp` holds
 // NT/64 + 1 int64 in LDS. Returns the exclusive prefix; *total gets the sum.
 template <int NT>
