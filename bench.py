@@ -339,6 +339,130 @@ def bpe_leg(reps: int = 10):
     return out, data, offs, merges
 
 
+SERVE_REQUESTS = 6000
+SERVE_RATE = 2000.0
+
+
+def serve_leg(n_requests: int = SERVE_REQUESTS):
+    """Serving trace: Poisson arrivals at 2,000 req/s, sizes log-uniform in
+    [100, 1e6] bases, vocabulary uniform over {single-nt, 3-mer, 6-mer,
+    BPE-4096}, CLS/SEP on, content drawn from a 64 Mbase genome of the
+    batched workload's model (pinned host memory). The trace is replayed in
+    real time twice: through the serving loop (16 GiB budget, 4 streams,
+    continuous batching) and through the plain path (per request: one H2D
+    copy, one dnatok_encode, one synchronisation, in arrival order on one
+    stream). Latency = completion seen by the host - arrival."""
+    import threading
+    import torch
+    import paper_2601_05531_amd as dt
+    import synth
+
+    merges = np.loadtxt(BPE_TABLE, dtype=np.int32).reshape(-1, 2)
+    vocabs = [dt.Vocab(dt.SINGLE), dt.Vocab(dt.KMER, k=3), dt.Vocab(dt.KMER, k=6), dt.Vocab(dt.BPE, merges=merges)]
+    arrivals, sizes, which = synth.serving_trace(n_requests=n_requests, rate=SERVE_RATE)
+    G = 64 << 20
+    h = torch.empty(G, dtype=torch.uint8, pin_memory=True)
+    synth.genome(synth.substream(5, 1), synth.substream(5, 2), 3, G, out=h.numpy())
+    rng = np.random.default_rng(synth.substream(5, 3))
+    starts = rng.integers(0, G - int(sizes.max()), n_requests)
+    total_bases = int(sizes.sum())
+
+    def pct(x, q):
+        return float(np.percentile(np.asarray(x), q)) * 1e3
+
+    # ---- serving loop
+    srv = dt.Server(budget_bytes=16 << 30, n_streams=4, max_batch=512, max_batch_bytes=32 << 20)
+    warm = [srv.submit(vocabs[i % 4], h[0:100000]) for i in range(8)]
+    for t in warm:
+        srv.wait(t)
+        srv.release(t)
+    tickets = [None] * n_requests
+    lat = np.zeros(n_requests)
+    tokens = np.zeros(n_requests, dtype=np.int64)
+    ready = threading.Semaphore(0)
+
+    def waiter():
+        for i in range(n_requests):
+            ready.acquire()
+            r = dt.dnatok_server_wait(srv.handle, tickets[i])
+            assert r.status == dt.OK and r.dev_flags == 0
+            lat[i] = r.t_done - r.t_submit
+            tokens[i] = r.n_tokens
+            dt.dnatok_server_release(srv.handle, tickets[i])
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    slip = np.zeros(n_requests)  # submission after the request's arrival time (host scheduling)
+    t0 = time.perf_counter()
+    for i in range(n_requests):
+        d = t0 + arrivals[i] - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        a, n = int(starts[i]), int(sizes[i])
+        slip[i] = max(0.0, time.perf_counter() - (t0 + arrivals[i]))
+        tickets[i] = dt.dnatok_server_submit(srv.handle, vocabs[which[i]].handle, h.data_ptr() + a, n, 1)
+        ready.release()
+    th.join()
+    lat += slip
+    t_srv = time.perf_counter() - t0
+    done, batches, peak = srv.stats()
+    srv.close()
+    server = {"p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "mean_ms": float(lat.mean()) * 1e3,
+              "tokens_per_s": float(tokens.sum()) / t_srv, "wall_s": round(t_srv, 3), "batches": int(batches),
+              "peak_arena_bytes": int(peak), "max_submit_slip_ms": float(slip.max()) * 1e3}
+    log("serve (batched): p50 %.3f ms p99 %.3f ms, %.3e tokens/s, %d batches" % (
+        server["p50_ms"], server["p99_ms"], server["tokens_per_s"], batches))
+
+    # ---- plain path: one copy + one encode + one sync per request, in arrival order
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    sp = stream.cuda_stream
+    cap = int(sizes.max()) + 2
+    d_in = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    d_ids = torch.empty(cap, dtype=torch.int32, device="cuda")
+    d_off = torch.empty(2, dtype=torch.int64, device="cuda")
+    d_oo = torch.empty(2, dtype=torch.int64, device="cuda")
+    h_off = torch.zeros(2, dtype=torch.int64, pin_memory=True)
+    opts = dt.make_opts(add_cls_sep=True)
+    lat2 = np.zeros(n_requests)
+    tok2 = np.zeros(n_requests, dtype=np.int64)
+    for i in range(4):  # warm every vocabulary
+        dt.dnatok_encode(vocabs[i].handle, h.data_ptr(), 1000, d_off.data_ptr(), 0, d_ids.data_ptr(), cap,
+                         d_oo.data_ptr(), None, opts, sp)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(n_requests):
+        d = t0 + arrivals[i] - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        a, n = int(starts[i]), int(sizes[i])
+        with torch.cuda.stream(stream):
+            d_in[:n].copy_(h[a:a + n], non_blocking=True)
+            h_off[1] = n
+            d_off.copy_(h_off, non_blocking=True)
+            dt.dnatok_encode(vocabs[which[i]].handle, d_in.data_ptr(), n, d_off.data_ptr(), 1, d_ids.data_ptr(),
+                             cap, d_oo.data_ptr(), None, opts, sp)
+        stream.synchronize()
+        lat2[i] = time.perf_counter() - (t0 + arrivals[i])
+        if which[i] == 3:
+            tok2[i] = int(d_oo[1].item())
+    t_plain = time.perf_counter() - t0
+    for i in np.nonzero(which != 3)[0]:
+        tok2[i] = int(dt.plan(vocabs[which[i]], np.array([0, int(sizes[i])]), True)[0])
+    same_counts = bool(np.array_equal(tok2, tokens))
+    tok2 = int(tok2.sum())
+    plain = {"p50_ms": pct(lat2, 50), "p99_ms": pct(lat2, 99), "mean_ms": float(lat2.mean()) * 1e3,
+             "tokens_per_s": tok2 / t_plain, "wall_s": round(t_plain, 3)}
+    log("serve (per request): p50 %.3f ms p99 %.3f ms, %.3e tokens/s" % (
+        plain["p50_ms"], plain["p99_ms"], plain["tokens_per_s"]))
+    del h
+    return {"workload": "%d requests, Poisson %.0f req/s, sizes log-uniform 100-1e6 bases (%d bases), vocab uniform "
+                        "over single/3-mer/6-mer/BPE-4096, CLS/SEP, 16 GiB budget" % (n_requests, SERVE_RATE,
+                                                                                        total_bases),
+            "server": server, "per_request": plain, "token_counts_agree": same_counts,
+            "p99_speedup": round(plain["p99_ms"] / server["p99_ms"], 2)}
+
+
 def cpu_baseline(data, offs, budget_s: float = 12.0, bpe=None):
     """The CPU oracle as written (single thread) on a bounded sample: whole
     rows of the same batch, all four k, until about ``budget_s`` seconds."""
@@ -381,6 +505,8 @@ def main():
     ap.add_argument("--no-copy", action="store_true", help="skip the device-copy reference")
     ap.add_argument("--no-stream", action="store_true", help="skip the 2 GiB host-to-device stream leg")
     ap.add_argument("--no-bpe", action="store_true", help="skip the ragged BPE batch leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving trace leg")
+    ap.add_argument("--serve-requests", type=int, default=SERVE_REQUESTS)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the tokenizer shards by sequences with no collective on the hot path, "
@@ -405,6 +531,9 @@ def main():
     stream = None
     if not args.no_stream:
         stream = stream_leg()
+    serve = None
+    if not args.no_serve:
+        serve = serve_leg(args.serve_requests)
     bpe = bpe_in = None
     if not args.no_bpe:
         bpe, b_data, b_offs, merges = bpe_leg()
@@ -437,6 +566,7 @@ def main():
         "cpu_baseline": cpu,
         "stream": stream,
         "bpe": bpe,
+        "serve": serve,
     }
     print(json.dumps(line), flush=True)
 

@@ -281,6 +281,73 @@ int dnatok_stream_reset(dnatok_stream *s);
 
 int dnatok_stream_destroy(dnatok_stream *s);
 
+/* ---- serving loop -----------------------------------------------------------
+ *
+ * Online tokenization (Discussion, "When Does DNATok Matter?": the serving
+ * use case, where tokenization sits on the latency path of every request,
+ * and the latency-bound real-model scenario of the Results). A server owns a
+ * worker thread, a device memory arena of budget_bytes and n_streams HIP
+ * streams. Requests (one sequence each, any of the server's vocabularies,
+ * host bytes) are admitted in arrival order while the arena has room for
+ * their input and output; admitted requests that share the vocabulary and
+ * the specials flag of the oldest waiting request are encoded together as
+ * one ragged batch (one dnatok_encode) on a free stream, so requests that
+ * arrive while others run join the next batch and batches on different
+ * streams overlap on the device (continuous batching). Vocabulary tables stay
+ * resident; results stay in the arena until released. A request's ids are
+ * exactly those of dnatok_encode on that sequence alone.
+ */
+typedef struct dnatok_server dnatok_server;
+
+typedef struct dnatok_server_opts {
+    int64_t budget_bytes;     /* device bytes for requests: inputs, outputs, offsets and BPE scratch */
+    int32_t n_streams;        /* batches in flight at once, 1..16 */
+    int32_t max_batch;        /* most requests in one batch, >= 1 */
+    int64_t max_batch_bytes;  /* most input bytes in one batch (a larger single request runs alone) */
+    int64_t staging_bytes;    /* pinned host staging per stream for pageable inputs, >= max_batch_bytes */
+} dnatok_server_opts;
+
+typedef struct dnatok_request_result {
+    const int32_t *d_ids; /* device int32[n_tokens] in the server's arena, valid until release */
+    int64_t n_tokens;
+    int32_t status;       /* DNATOK_OK, or the error that failed the request */
+    uint32_t dev_flags;   /* device error flags of the request's batch (dnatok_sync_status bits) */
+    double t_submit;      /* seconds on the server clock (dnatok_server_now) */
+    double t_start;       /* its batch was enqueued on a stream */
+    double t_done;        /* the worker saw its batch complete */
+} dnatok_request_result;
+
+/* Errors: EINVAL (bad options), ENOMEM (arena, pinned staging), EDEVICE. */
+int dnatok_server_create(const dnatok_server_opts *opts, dnatok_server **out);
+
+/*
+ * Queue one request. h_bytes may be pinned or pageable host memory and is
+ * copied before the call returns when pageable; pinned memory is read by the
+ * device later and must stay unchanged until the request is done. The
+ * vocabulary must outlive the request. Errors: EINVAL, EBUDGET (the request
+ * alone exceeds the budget), ESTATE (server shutting down).
+ */
+int dnatok_server_submit(dnatok_server *s, const dnatok_vocab *v, const uint8_t *h_bytes, int64_t nbytes,
+                         int32_t add_cls_sep, uint64_t *ticket);
+
+/* Non-blocking: 0 and *out filled when the request is done, 1 while it is pending, < 0 on error. */
+int dnatok_server_poll(dnatok_server *s, uint64_t ticket, dnatok_request_result *out);
+
+/* Block until the request is done; fills *out. EINVAL for an unknown ticket. */
+int dnatok_server_wait(dnatok_server *s, uint64_t ticket, dnatok_request_result *out);
+
+/* Return a done request's output memory to the arena (its d_ids become invalid). */
+int dnatok_server_release(dnatok_server *s, uint64_t ticket);
+
+/* Server clock (seconds, monotonic) used by the result timestamps. */
+double dnatok_server_now(const dnatok_server *s);
+
+/* Counters: requests done, batches launched, peak arena bytes in use. */
+int dnatok_server_stats(const dnatok_server *s, int64_t *requests, int64_t *batches, int64_t *peak_bytes);
+
+/* Finish queued work, stop the worker, free everything (outstanding results too). */
+int dnatok_server_destroy(dnatok_server *s);
+
 #ifdef __cplusplus
 }
 #endif

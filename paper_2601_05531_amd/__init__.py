@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdnatok.so")
 
 OK, EINVAL, EVOCAB, ENOMEM, EBUDGET, EDEVICE, ESTATE, ETOOSMALL = 0, -1, -2, -3, -4, -5, -6, -7
-DERR_OFFSETS, DERR_CAPACITY, DERR_ROW_WIDTH = 1, 2, 4
+DERR_OFFSETS, DERR_CAPACITY, DERR_ROW_WIDTH, DERR_INTERNAL = 1, 2, 4, 8
 SINGLE, LUT256, KMER, BPE = 0, 1, 2, 3
 PACKED, PADDED = 0, 1
 PAD_RIGHT, PAD_LEFT = 0, 1
@@ -80,6 +80,28 @@ class dnatok_stream_result(ctypes.Structure):
     ]
 
 
+class dnatok_server_opts(ctypes.Structure):
+    _fields_ = [
+        ("budget_bytes", ctypes.c_int64),
+        ("n_streams", ctypes.c_int32),
+        ("max_batch", ctypes.c_int32),
+        ("max_batch_bytes", ctypes.c_int64),
+        ("staging_bytes", ctypes.c_int64),
+    ]
+
+
+class dnatok_request_result(ctypes.Structure):
+    _fields_ = [
+        ("d_ids", ctypes.c_void_p),
+        ("n_tokens", ctypes.c_int64),
+        ("status", ctypes.c_int32),
+        ("dev_flags", ctypes.c_uint32),
+        ("t_submit", ctypes.c_double),
+        ("t_start", ctypes.c_double),
+        ("t_done", ctypes.c_double),
+    ]
+
+
 _lib = None
 
 
@@ -115,9 +137,21 @@ def lib():
         L.dnatok_stream_flush.argtypes = [vp, ctypes.POINTER(dnatok_stream_result)]
         L.dnatok_stream_reset.argtypes = [vp]
         L.dnatok_stream_destroy.argtypes = [vp]
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        L.dnatok_server_create.argtypes = [ctypes.POINTER(dnatok_server_opts), ctypes.POINTER(vp)]
+        L.dnatok_server_submit.argtypes = [vp, vp, vp, i64, i32, u64p]
+        L.dnatok_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(dnatok_request_result)]
+        L.dnatok_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(dnatok_request_result)]
+        L.dnatok_server_release.argtypes = [vp, ctypes.c_uint64]
+        L.dnatok_server_now.argtypes = [vp]
+        L.dnatok_server_now.restype = ctypes.c_double
+        L.dnatok_server_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.dnatok_server_destroy.argtypes = [vp]
         for name in ("dnatok_vocab_create", "dnatok_vocab_destroy", "dnatok_vocab_info", "dnatok_encode_plan",
                      "dnatok_encode", "dnatok_sync_status", "dnatok_decode", "dnatok_stream_create",
-                     "dnatok_stream_push", "dnatok_stream_flush", "dnatok_stream_reset", "dnatok_stream_destroy"):
+                     "dnatok_stream_push", "dnatok_stream_flush", "dnatok_stream_reset", "dnatok_stream_destroy",
+                     "dnatok_server_create", "dnatok_server_submit", "dnatok_server_poll", "dnatok_server_wait",
+                     "dnatok_server_release", "dnatok_server_stats", "dnatok_server_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -382,3 +416,103 @@ def device_view(ptr, n, typestr):
 
 def sync_status(stream=None) -> int:
     return dnatok_sync_status(_stream_ptr(stream))
+
+
+# ---- serving loop ------------------------------------------------------------------
+
+def dnatok_server_create(opts: dnatok_server_opts) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().dnatok_server_create(ctypes.byref(opts), ctypes.byref(h)))
+    return h.value
+
+
+def dnatok_server_submit(server: int, vocab: int, h_bytes: int, nbytes: int, add_cls_sep: int) -> int:
+    t = ctypes.c_uint64()
+    _check(lib().dnatok_server_submit(server, vocab, h_bytes, nbytes, add_cls_sep, ctypes.byref(t)))
+    return t.value
+
+
+def dnatok_server_poll(server: int, ticket: int):
+    r = dnatok_request_result()
+    rc = lib().dnatok_server_poll(server, ticket, ctypes.byref(r))
+    if rc < 0:
+        _check(rc)
+    return (r if rc == 0 else None)
+
+
+def dnatok_server_wait(server: int, ticket: int) -> dnatok_request_result:
+    r = dnatok_request_result()
+    _check(lib().dnatok_server_wait(server, ticket, ctypes.byref(r)))
+    return r
+
+
+def dnatok_server_release(server: int, ticket: int) -> int:
+    return _check(lib().dnatok_server_release(server, ticket))
+
+
+def dnatok_server_now(server: int) -> float:
+    return lib().dnatok_server_now(server)
+
+
+def dnatok_server_stats(server: int):
+    a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().dnatok_server_stats(server, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def dnatok_server_destroy(server: int) -> int:
+    return _check(lib().dnatok_server_destroy(server))
+
+
+class Server:
+    """Owning wrapper of a ``dnatok_server`` on the current device."""
+
+    def __init__(self, budget_bytes: int = 16 << 30, n_streams: int = 4, max_batch: int = 256,
+                 max_batch_bytes: int = 16 << 20, staging_bytes: int | None = None):
+        o = dnatok_server_opts()
+        o.budget_bytes, o.n_streams, o.max_batch = budget_bytes, n_streams, max_batch
+        o.max_batch_bytes = max_batch_bytes
+        o.staging_bytes = max_batch_bytes if staging_bytes is None else staging_bytes
+        self.handle = dnatok_server_create(o)
+        self._keep = {}
+
+    def submit(self, vocab: Vocab, data, add_cls_sep: bool = True) -> int:
+        """``data``: a numpy uint8 array (copied at once) or a pinned uint8
+        torch tensor (read by the device later: keep it until done)."""
+        if isinstance(data, np.ndarray):
+            a = np.ascontiguousarray(data, dtype=np.uint8)
+            t = dnatok_server_submit(self.handle, vocab.handle, a.ctypes.data, a.size, int(add_cls_sep))
+        else:
+            t = dnatok_server_submit(self.handle, vocab.handle, data.data_ptr(), data.numel(), int(add_cls_sep))
+            self._keep[t] = data
+        return t
+
+    def wait(self, ticket: int):
+        """Returns (device ids view, result struct); the view is valid until release."""
+        r = dnatok_server_wait(self.handle, ticket)
+        if r.status != OK:
+            raise DnatokError(r.status, "request %d failed" % ticket)
+        ids = device_view(r.d_ids, r.n_tokens, "<i4")
+        return ids, r
+
+    def release(self, ticket: int):
+        self._keep.pop(ticket, None)
+        dnatok_server_release(self.handle, ticket)
+
+    def now(self) -> float:
+        return dnatok_server_now(self.handle)
+
+    def stats(self):
+        return dnatok_server_stats(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            dnatok_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

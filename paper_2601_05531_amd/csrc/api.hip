@@ -50,6 +50,21 @@ Workspace *find_workspace(hipStream_t stream) {
     return it == g_ws.end() ? nullptr : it->second;
 }
 
+void drop_workspace(hipStream_t stream) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto it = g_ws.find({dev, stream});
+    if (it == g_ws.end()) return;
+    Workspace *ws = it->second;
+    if (ws) {
+        if (ws->d_hdr) (void)hipFree(ws->d_hdr);
+        if (ws->d_scratch) (void)hipFree(ws->d_scratch);
+        delete ws;
+    }
+    g_ws.erase(it);
+}
+
 static int grow_allowed(hipStream_t stream) {
     hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(stream, &st) == hipSuccess && st != hipStreamCaptureStatusNone)

@@ -957,25 +957,47 @@ int bpe_wave_classes(uint32_t tab, BpeClass *out, int max_out) {
     return nc;
 }
 
+namespace {
+// Scratch of one BPE encode: symA, symB (uint16 per byte), item offsets,
+// counts, lengths, starts and positions.
+struct BpeScratch {
+    int64_t max_items, sz_sym, sz_ioff, sz_cnt, sz_start, sz_pos, total;
+};
+BpeScratch bpe_scratch(int64_t nbytes, int32_t n) {
+    auto al = [](int64_t x) { return (x + 255) / 256 * 256; };
+    BpeScratch b;
+    b.max_items = nbytes / kItemBytes + (int64_t)n + 1;
+    b.sz_sym = al(2 * (nbytes + 1));
+    b.sz_ioff = al(8 * ((int64_t)n + 1));
+    b.sz_cnt = al(4 * b.max_items);
+    b.sz_start = al(8 * b.max_items);
+    b.sz_pos = al(8 * (b.max_items + 1));
+    b.total = 2 * b.sz_sym + b.sz_ioff + 2 * b.sz_cnt + b.sz_start + b.sz_pos;
+    return b;
+}
+}  // namespace
+
+int64_t bpe_scratch_bytes(int64_t nbytes, int32_t n) { return bpe_scratch(nbytes, n).total; }
+
+int64_t bpe_workspace_tiles(int64_t nbytes, int32_t n) {
+    const int64_t units_rows = std::max<int64_t>(1, ((int64_t)n + 4095) / 4096);
+    const int64_t units_items = std::max<int64_t>(1, (bpe_scratch(nbytes, n).max_items + kScanUnit - 1) / kScanUnit);
+    return std::max(units_rows, units_items);
+}
+
 int launch_bpe_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets,
                       int32_t n, int32_t *d_ids, int64_t cap, int64_t *d_out_offsets, int8_t *d_mask,
                       const dnatok_encode_opts &o, hipStream_t stream) {
     const BpeTables &bt = v->bpe;
     const int32_t R = bt.n_merges;
-    const int64_t max_items = nbytes / kItemBytes + (int64_t)n + 1;
-    // scratch: symA, symB (uint16 per byte), item_off, item_cnt, item_len, item_start, item_pos
-    auto al = [](int64_t x) { return (x + 255) / 256 * 256; };
-    const int64_t sz_sym = al(2 * (nbytes + 1));
-    const int64_t sz_ioff = al(8 * ((int64_t)n + 1));
-    const int64_t sz_cnt = al(4 * max_items);
-    const int64_t sz_start = al(8 * max_items);
-    const int64_t sz_pos = al(8 * (max_items + 1));
+    const BpeScratch bs = bpe_scratch(nbytes, n);
+    const int64_t max_items = bs.max_items;
+    const int64_t sz_sym = bs.sz_sym, sz_ioff = bs.sz_ioff, sz_cnt = bs.sz_cnt, sz_start = bs.sz_start;
     Workspace *ws = nullptr;
-    const int64_t units_rows = std::max<int64_t>(1, ((int64_t)n + 4095) / 4096);
     const int64_t units_items = std::max<int64_t>(1, (max_items + kScanUnit - 1) / kScanUnit);
-    int rc = get_workspace(stream, std::max(units_rows, units_items), &ws);
+    int rc = get_workspace(stream, bpe_workspace_tiles(nbytes, n), &ws);
     if (rc) return rc;
-    rc = ensure_scratch(ws, 2 * sz_sym + sz_ioff + 2 * sz_cnt + sz_start + sz_pos);
+    rc = ensure_scratch(ws, bs.total);
     if (rc) return rc;
     uint8_t *sp = ws->d_scratch;
     uint16_t *symA = reinterpret_cast<uint16_t *>(sp);

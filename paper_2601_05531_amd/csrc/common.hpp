@@ -97,6 +97,8 @@ int get_workspace(hipStream_t stream, int64_t tiles, Workspace **out);
 int ensure_scratch(Workspace *ws, int64_t bytes);
 // Workspace of (current device, stream) if one exists.
 Workspace *find_workspace(hipStream_t stream);
+// Free the workspace of (current device, stream); the stream must be idle.
+void drop_workspace(hipStream_t stream);
 
 int device_cu_count();
 
@@ -124,6 +126,10 @@ struct BpeClass {
     uint32_t lds;    // dynamic LDS bytes per workgroup
 };
 int bpe_wave_classes(uint32_t table_lds_bytes, BpeClass *out, int max_out);
+
+// Scratch bytes and workspace tiles one BPE encode of (nbytes, n rows) needs.
+int64_t bpe_scratch_bytes(int64_t nbytes, int32_t n);
+int64_t bpe_workspace_tiles(int64_t nbytes, int32_t n);
 
 int launch_bpe_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets,
                       int32_t n, int32_t *d_ids, int64_t cap, int64_t *d_out_offsets, int8_t *d_mask,
