@@ -66,6 +66,13 @@ def encode_leg(steps: int, warmup: int):
     stream = torch.cuda.current_stream()
     sp = stream.cuda_stream
     nbytes = data.size
+    # tile sizes per k chosen by the autotuner on this batch (outside the timed region)
+    tuning = {}
+    for k in KS:
+        t, ms = dt.autotune(vocabs[k], d_in[0], d_offs, h_offsets=offs, add_cls_sep=True, layout=dt.PADDED,
+                            pad_to=plans[k][1], reps=3)
+        tuning[k] = {"tile_bytes": t["tile_bytes"], "blocks_per_cu": t["blocks_per_cu"], "median_ms": round(ms, 4)}
+    log("autotuned: %s" % tuning)
 
     def launch(step, j, k):
         x = d_in[(4 * step + j) % IN_SETS]
@@ -111,6 +118,7 @@ def encode_leg(steps: int, warmup: int):
         "value": tokens_per_step * steps / elapsed,
         "per_k_launch_ms": per_k_ms,
         "bytes_per_launch": bytes_k,
+        "tuning": tuning,
         "roofline": {
             "bound": "hbm",
             "achieved": round(achieved, 1),
@@ -249,6 +257,63 @@ def _stream_window_check(lens, woff, n_windows):
     return bool(np.array_equal(woff.cpu().numpy(), want))
 
 
+def small_leg(reps: int = 200):
+    """The small batch (64 x 16,384 i.i.d. bases, 1% N), PACKED ids for the
+    single-nucleotide and 6-mer vocabularies: one step = both encodes. Launch
+    bound (about a microsecond of HBM time each), so it is timed back to back
+    eagerly and as replays of two captured HIP graphs over the same buffers."""
+    import torch
+    import paper_2601_05531_amd as dt
+    import synth
+
+    data, offs = synth.workload_iid()
+    n = len(offs) - 1
+    d_in = torch.from_numpy(data).cuda()
+    d_off = torch.from_numpy(offs).cuda()
+    vs = [dt.Vocab(dt.SINGLE), dt.Vocab(dt.KMER, k=6)]
+    outs = []
+    tokens = 0
+    for v in vs:
+        total, _ = dt.plan(v, offs)
+        tokens += total
+        outs.append((torch.empty(total, dtype=torch.int32, device="cuda"),
+                     torch.empty(n + 1, dtype=torch.int64, device="cuda")))
+    opts = dt.make_opts()
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+
+    def eager():
+        for v, (ids, oo) in zip(vs, outs):
+            dt.dnatok_encode(v.handle, d_in.data_ptr(), data.size, d_off.data_ptr(), n, ids.data_ptr(), ids.numel(),
+                             oo.data_ptr(), None, opts, sp)
+
+    graphs = [dt.Graph(v, d_in, d_off, ids, oo) for v, (ids, oo) in zip(vs, outs)]
+
+    def replay():
+        for g in graphs:
+            g.launch(stream)
+
+    res = {}
+    for name, fn in (("eager", eager), ("graph", replay)):
+        for _ in range(10):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        us = a.elapsed_time(b) * 1e3 / reps
+        res[name] = {"us_per_step": round(us, 2), "tokens_per_s": tokens / (us * 1e-6)}
+    for g in graphs:
+        g.close()
+    log("small batch: eager %.1f us/step, graph %.1f us/step" % (res["eager"]["us_per_step"],
+                                                               res["graph"]["us_per_step"]))
+    return {"workload": "64 x 16384 i.i.d. bases (1%% N), single-nucleotide + 6-mer PACKED, %d tokens per step"
+                        % tokens, **res}
+
+
 BPE_TABLE = os.path.join(ROOT, "tests", "golden", "bpe4096_order5_64M.txt")
 
 
@@ -279,6 +344,9 @@ def bpe_leg(reps: int = 10):
     def fused():
         dt.dnatok_encode(v.handle, d_in.data_ptr(), nbytes, d_offs.data_ptr(), n, ids.data_ptr(), nbytes,
                          oo.data_ptr(), None, opts, sp)
+
+    tune, tune_ms = dt.autotune(v, d_in, d_offs, h_offsets=offs, reps=1)
+    log("bpe autotuned: %s (%.3f ms)" % (tune, tune_ms))
 
     fused()
     torch.cuda.synchronize()
@@ -326,6 +394,7 @@ def bpe_leg(reps: int = 10):
         "workload": "1024 sequences, log-uniform 500-20000 bases (%d bases), order-5 Markov, BPE 4096 merges "
                     "(oracle trainer, 64 Mbase), PACKED, no specials" % nbytes,
         "tokens": tokens,
+        "autotuned": {"bpe_item_bytes": tune["bpe_item_bytes"], "bpe_max_waves": tune["bpe_max_waves"]},
         "fused_ms": round(fused_ms, 4),
         "fused_tokens_per_s": tokens / (fused_ms * 1e-3),
         "fused_bases_per_s": nbytes / (fused_ms * 1e-3),
@@ -506,6 +575,7 @@ def main():
     ap.add_argument("--no-stream", action="store_true", help="skip the 2 GiB host-to-device stream leg")
     ap.add_argument("--no-bpe", action="store_true", help="skip the ragged BPE batch leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace leg")
+    ap.add_argument("--no-small", action="store_true", help="skip the small-batch eager/graph leg")
     ap.add_argument("--serve-requests", type=int, default=SERVE_REQUESTS)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -531,6 +601,9 @@ def main():
     stream = None
     if not args.no_stream:
         stream = stream_leg()
+    small = None
+    if not args.no_small:
+        small = small_leg()
     serve = None
     if not args.no_serve:
         serve = serve_leg(args.serve_requests)
@@ -561,12 +634,14 @@ def main():
                         "right-padded int32 ids + int8 mask, inputs resident in HBM",
             "tokens_per_step": enc["tokens_per_step"],
             "per_k_launch_ms": enc["per_k_launch_ms"],
+            "autotuned": enc["tuning"],
         },
         "roofline": enc["roofline"],
         "cpu_baseline": cpu,
         "stream": stream,
         "bpe": bpe,
         "serve": serve,
+        "small_batch": small,
     }
     print(json.dumps(line), flush=True)
 

@@ -281,6 +281,55 @@ int dnatok_stream_reset(dnatok_stream *s);
 
 int dnatok_stream_destroy(dnatok_stream *s);
 
+/* ---- tuning, autotuner and captured graphs ----------------------------------
+ *
+ * The paper attributes much of the remaining cost of batched encoding to
+ * launch overhead and memory layout (Discussion, "Performance
+ * Characteristics and Scaling Behavior"). These calls pick the tiling of a
+ * vocabulary's kernels by measurement and replay a fixed encode without
+ * per-launch host work. Tuning changes scheduling only: ids are the same for
+ * every setting.
+ */
+typedef struct dnatok_tuning {
+    int32_t tile_bytes;     /* SINGLE/LUT256/KMER: input bytes per tile, power of two 4096..65536 (0 = default) */
+    int32_t blocks_per_cu;  /* SINGLE/LUT256/KMER: workgroups per CU, 0 = as many as fit */
+    int32_t bpe_item_bytes; /* BPE: nominal item length S, power of two 1024..65536 (0 = 8192) */
+    int32_t bpe_max_waves;  /* BPE: most waves per workgroup of the length classes: 1, 2, 4 or 8 (0 = 8) */
+} dnatok_tuning;
+
+int dnatok_get_tuning(const dnatok_vocab *v, dnatok_tuning *out);
+
+/* Set (EINVAL for out-of-range fields); applies to calls made afterwards. */
+int dnatok_set_tuning(dnatok_vocab *v, const dnatok_tuning *t);
+
+/*
+ * Time every candidate tiling of v on this batch (the arguments of
+ * dnatok_encode; the outputs are overwritten) with HIP events on `stream`:
+ * one warm-up and `reps` timed launches each (median). The fastest setting
+ * is stored in v and returned in *best / *best_ms. Synchronizes `stream`;
+ * not allowed during graph capture (ESTATE). Errors as dnatok_encode.
+ */
+int dnatok_autotune(dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets, int32_t n,
+                    int32_t *d_ids, int64_t ids_capacity, int64_t *d_out_offsets, int8_t *d_mask,
+                    const dnatok_encode_opts *opts, void *stream, int32_t reps, dnatok_tuning *best,
+                    float *best_ms);
+
+typedef struct dnatok_graph dnatok_graph;
+
+/*
+ * Capture one dnatok_encode with exactly these buffers, sizes and options
+ * into an executable HIP graph (the encode is run once eagerly first, which
+ * also sizes the graph's private workspace). Each dnatok_graph_launch
+ * replays it on `stream` reading whatever the buffers hold at that point;
+ * replays of one graph must not overlap (order them on one stream or with
+ * events). The vocabulary and buffers must outlive the graph.
+ */
+int dnatok_graph_create(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets,
+                        int32_t n, int32_t *d_ids, int64_t ids_capacity, int64_t *d_out_offsets, int8_t *d_mask,
+                        const dnatok_encode_opts *opts, dnatok_graph **out);
+int dnatok_graph_launch(dnatok_graph *g, void *stream);
+int dnatok_graph_destroy(dnatok_graph *g);
+
 /* ---- serving loop -----------------------------------------------------------
  *
  * Online tokenization (Discussion, "When Does DNATok Matter?": the serving

@@ -80,6 +80,18 @@ class dnatok_stream_result(ctypes.Structure):
     ]
 
 
+class dnatok_tuning(ctypes.Structure):
+    _fields_ = [
+        ("tile_bytes", ctypes.c_int32),
+        ("blocks_per_cu", ctypes.c_int32),
+        ("bpe_item_bytes", ctypes.c_int32),
+        ("bpe_max_waves", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class dnatok_server_opts(ctypes.Structure):
     _fields_ = [
         ("budget_bytes", ctypes.c_int64),
@@ -147,11 +159,21 @@ def lib():
         L.dnatok_server_now.restype = ctypes.c_double
         L.dnatok_server_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.dnatok_server_destroy.argtypes = [vp]
+        L.dnatok_get_tuning.argtypes = [vp, ctypes.POINTER(dnatok_tuning)]
+        L.dnatok_set_tuning.argtypes = [vp, ctypes.POINTER(dnatok_tuning)]
+        L.dnatok_autotune.argtypes = [vp, vp, i64, vp, i32, vp, i64, vp, vp, ctypes.POINTER(dnatok_encode_opts),
+                                      vp, i32, ctypes.POINTER(dnatok_tuning), ctypes.POINTER(ctypes.c_float)]
+        L.dnatok_graph_create.argtypes = [vp, vp, i64, vp, i32, vp, i64, vp, vp, ctypes.POINTER(dnatok_encode_opts),
+                                          ctypes.POINTER(vp)]
+        L.dnatok_graph_launch.argtypes = [vp, vp]
+        L.dnatok_graph_destroy.argtypes = [vp]
         for name in ("dnatok_vocab_create", "dnatok_vocab_destroy", "dnatok_vocab_info", "dnatok_encode_plan",
                      "dnatok_encode", "dnatok_sync_status", "dnatok_decode", "dnatok_stream_create",
                      "dnatok_stream_push", "dnatok_stream_flush", "dnatok_stream_reset", "dnatok_stream_destroy",
                      "dnatok_server_create", "dnatok_server_submit", "dnatok_server_poll", "dnatok_server_wait",
-                     "dnatok_server_release", "dnatok_server_stats", "dnatok_server_destroy"):
+                     "dnatok_server_release", "dnatok_server_stats", "dnatok_server_destroy", "dnatok_get_tuning",
+                     "dnatok_set_tuning", "dnatok_autotune", "dnatok_graph_create", "dnatok_graph_launch",
+                     "dnatok_graph_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -510,6 +532,82 @@ class Server:
             dnatok_server_destroy(self.handle)
             self.handle = None
             self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- tuning, autotuner, captured graphs ----------------------------------------------
+
+def dnatok_get_tuning(vocab: int) -> dnatok_tuning:
+    t = dnatok_tuning()
+    _check(lib().dnatok_get_tuning(vocab, ctypes.byref(t)))
+    return t
+
+
+def dnatok_set_tuning(vocab: int, t: dnatok_tuning) -> int:
+    return _check(lib().dnatok_set_tuning(vocab, ctypes.byref(t)))
+
+
+def dnatok_autotune(vocab, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets, d_mask, opts, stream,
+                    reps=3):
+    t, ms = dnatok_tuning(), ctypes.c_float()
+    _check(lib().dnatok_autotune(vocab, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets, d_mask,
+                                 ctypes.byref(opts), stream, reps, ctypes.byref(t), ctypes.byref(ms)))
+    return t, ms.value
+
+
+def set_tuning(vocab: Vocab, tile_bytes=0, blocks_per_cu=0, bpe_item_bytes=0, bpe_max_waves=0):
+    dnatok_set_tuning(vocab.handle, dnatok_tuning(tile_bytes, blocks_per_cu, bpe_item_bytes, bpe_max_waves))
+
+
+def autotune(vocab: Vocab, d_bytes, d_offsets, h_offsets=None, add_cls_sep=False, layout=PACKED, pad_side=PAD_RIGHT,
+             pad_to=None, reps=3, stream=None):
+    """Time every candidate tiling on this batch and keep the fastest in the
+    vocabulary. Returns (tuning dict, median ms)."""
+    import torch
+    n = d_offsets.numel() - 1
+    if h_offsets is None:
+        h_offsets = d_offsets.cpu().numpy()
+    total, max_len = plan(vocab, h_offsets, add_cls_sep)
+    if layout == PADDED:
+        W = max_len if pad_to is None else int(pad_to)
+        cap = n * W
+    else:
+        W, cap = 0, total
+    ids = torch.empty(max(cap, 1), dtype=torch.int32, device=d_bytes.device)
+    oo = torch.empty(n + 1, dtype=torch.int64, device=d_bytes.device)
+    mask = torch.empty(max(cap, 1), dtype=torch.int8, device=d_bytes.device) if layout == PADDED else None
+    t, ms = dnatok_autotune(vocab.handle, _ptr(d_bytes), d_bytes.numel(), _ptr(d_offsets), n, _ptr(ids), ids.numel(),
+                            _ptr(oo), _ptr(mask), make_opts(add_cls_sep, layout, pad_side, W), _stream_ptr(stream),
+                            reps)
+    return t.as_dict(), ms
+
+
+class Graph:
+    """A captured dnatok_encode over fixed buffers (see dnatok_graph_create)."""
+
+    def __init__(self, vocab: Vocab, d_bytes, d_offsets, d_ids, d_out_offsets, d_mask=None, add_cls_sep=False,
+                 layout=PACKED, pad_side=PAD_RIGHT, pad_to=0):
+        n = d_offsets.numel() - 1
+        h = ctypes.c_void_p()
+        self._keep = (vocab, d_bytes, d_offsets, d_ids, d_out_offsets, d_mask)
+        _check(lib().dnatok_graph_create(vocab.handle, _ptr(d_bytes), d_bytes.numel(), _ptr(d_offsets), n,
+                                         _ptr(d_ids), d_ids.numel(), _ptr(d_out_offsets), _ptr(d_mask),
+                                         ctypes.byref(make_opts(add_cls_sep, layout, pad_side, pad_to)),
+                                         ctypes.byref(h)))
+        self.handle = h.value
+
+    def launch(self, stream=None):
+        _check(lib().dnatok_graph_launch(self.handle, _stream_ptr(stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().dnatok_graph_destroy(self.handle)
+            self.handle = None
 
     def __del__(self):
         try:

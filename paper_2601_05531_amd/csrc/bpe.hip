@@ -118,7 +118,6 @@ namespace {
 constexpr int NTM = 1024;             // k_bpe_block workgroup
 constexpr int NTE = 256;              // items / scan / emit workgroups
 constexpr int kMaxWaves = 8;          // waves per k_bpe_wave workgroup
-constexpr int32_t kItemBytes = 8192;  // nominal item length S
 constexpr int kScanPerThread = 16;
 constexpr int64_t kScanUnit = (int64_t)NTE * kScanPerThread;
 constexpr size_t kLdsBytes = 160 * 1024;
@@ -931,15 +930,17 @@ __global__ __launch_bounds__(NTE) void k_bpe_emit(EmitArgs a) {
 }  // namespace
 
 // Length classes of the wave kernel for a table of `tab` LDS bytes: waves
-// per workgroup w in {8, 4, 2, 1}, each wave holding up to np(w) symbols
+// per workgroup w in {8, 4, 2, 1} (those <= max_waves), each wave holding up
+// to np(w) symbols
 // where one workgroup fills the CU's LDS. Class w takes the items longer
 // than the previous class's capacity.
-int bpe_wave_classes(uint32_t tab, BpeClass *out, int max_out) {
+int bpe_wave_classes(uint32_t tab, int max_waves, BpeClass *out, int max_out) {
     int nc = 0;
     uint32_t prev = 0;
     const int waves[4] = {8, 4, 2, 1};
     for (int i = 0; i < 4 && nc < max_out; ++i) {
         const int w = waves[i];
+        if (w > max_waves) continue;
         if (kLdsBytes < kLdsReserve + tab) break;
         const size_t room = (kLdsBytes - kLdsReserve - tab) / (size_t)w;
         // largest multiple of 64 whose per-wave layout fits the room
@@ -963,10 +964,10 @@ namespace {
 struct BpeScratch {
     int64_t max_items, sz_sym, sz_ioff, sz_cnt, sz_start, sz_pos, total;
 };
-BpeScratch bpe_scratch(int64_t nbytes, int32_t n) {
+BpeScratch bpe_scratch(int64_t nbytes, int32_t n, int32_t S) {
     auto al = [](int64_t x) { return (x + 255) / 256 * 256; };
     BpeScratch b;
-    b.max_items = nbytes / kItemBytes + (int64_t)n + 1;
+    b.max_items = nbytes / S + (int64_t)n + 1;
     b.sz_sym = al(2 * (nbytes + 1));
     b.sz_ioff = al(8 * ((int64_t)n + 1));
     b.sz_cnt = al(4 * b.max_items);
@@ -977,11 +978,12 @@ BpeScratch bpe_scratch(int64_t nbytes, int32_t n) {
 }
 }  // namespace
 
-int64_t bpe_scratch_bytes(int64_t nbytes, int32_t n) { return bpe_scratch(nbytes, n).total; }
+int64_t bpe_scratch_bytes(int64_t nbytes, int32_t n, int32_t S) { return bpe_scratch(nbytes, n, S).total; }
 
-int64_t bpe_workspace_tiles(int64_t nbytes, int32_t n) {
+int64_t bpe_workspace_tiles(int64_t nbytes, int32_t n, int32_t S) {
     const int64_t units_rows = std::max<int64_t>(1, ((int64_t)n + 4095) / 4096);
-    const int64_t units_items = std::max<int64_t>(1, (bpe_scratch(nbytes, n).max_items + kScanUnit - 1) / kScanUnit);
+    const int64_t units_items =
+        std::max<int64_t>(1, (bpe_scratch(nbytes, n, S).max_items + kScanUnit - 1) / kScanUnit);
     return std::max(units_rows, units_items);
 }
 
@@ -990,12 +992,16 @@ int launch_bpe_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nby
                       const dnatok_encode_opts &o, hipStream_t stream) {
     const BpeTables &bt = v->bpe;
     const int32_t R = bt.n_merges;
-    const BpeScratch bs = bpe_scratch(nbytes, n);
+    const int32_t ti = v->tune_item.load(std::memory_order_relaxed);
+    const int32_t S = ti > 0 ? ti : kBpeItemBytesDefault;
+    const int32_t tw = v->tune_waves.load(std::memory_order_relaxed);
+    const int max_waves = tw > 0 ? tw : kMaxWaves;
+    const BpeScratch bs = bpe_scratch(nbytes, n, S);
     const int64_t max_items = bs.max_items;
     const int64_t sz_sym = bs.sz_sym, sz_ioff = bs.sz_ioff, sz_cnt = bs.sz_cnt, sz_start = bs.sz_start;
     Workspace *ws = nullptr;
     const int64_t units_items = std::max<int64_t>(1, (max_items + kScanUnit - 1) / kScanUnit);
-    int rc = get_workspace(stream, bpe_workspace_tiles(nbytes, n), &ws);
+    int rc = get_workspace(stream, bpe_workspace_tiles(nbytes, n, S), &ws);
     if (rc) return rc;
     rc = ensure_scratch(ws, bs.total);
     if (rc) return rc;
@@ -1017,11 +1023,11 @@ int launch_bpe_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nby
     const int cus = device_cu_count();
 
     // 1. item plan
-    rc = launch_rowscan(d_offsets, n, nbytes, item_off, kItemBytes, 0, stream);
+    rc = launch_rowscan(d_offsets, n, nbytes, item_off, S, 0, stream);
     if (rc) return rc;
 
     // 2. items
-    ItemArgs ia{d_bytes, nbytes, d_offsets, n, item_off, max_items, kItemBytes, item_start, item_len, item_cnt};
+    ItemArgs ia{d_bytes, nbytes, d_offsets, n, item_off, max_items, S, item_start, item_len, item_cnt};
     const int64_t g_items = std::max<int64_t>(1, std::min<int64_t>((max_items + 3) / 4, (int64_t)cus * 8));
     hipLaunchKernelGGL(k_bpe_items, dim3((unsigned)g_items), dim3(NTE), 0, stream, ia);
     DNATOK_HIP(hipGetLastError());
@@ -1029,7 +1035,7 @@ int launch_bpe_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nby
     // 3. wave classes
     const uint32_t tab = table_bytes(bt.slots, R);
     BpeClass cls[4];
-    const int ncls = bpe_wave_classes(tab, cls, 4);
+    const int ncls = bpe_wave_classes(tab, max_waves, cls, 4);
     int32_t covered = 0;
     for (int c = 0; c < ncls; ++c) {
         WaveArgs w;

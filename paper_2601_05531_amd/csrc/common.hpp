@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -56,6 +57,9 @@ struct BpeTables {
 }  // namespace dnatok
 
 struct dnatok_vocab {
+    // Scheduling knobs (dnatok_set_tuning / dnatok_autotune); 0 = default.
+    // They change how work is tiled, never the ids.
+    std::atomic<int32_t> tune_tile{0}, tune_blocks{0}, tune_item{0}, tune_waves{0};
     int32_t kind = 0;
     int32_t k = 1;
     int32_t pad_id = DNATOK_ID_PAD, cls_id = DNATOK_ID_CLS, sep_id = DNATOK_ID_SEP;
@@ -108,7 +112,9 @@ struct EncodeTuning {
     int64_t tile_bytes;  // bytes of input per tile (multiple of 16)
     int blocks_per_cu;   // 0 = as many as occupancy allows
 };
-EncodeTuning encode_tuning(bool kmer);
+EncodeTuning encode_tuning(const dnatok_vocab *v);
+constexpr int32_t kBpeItemBytesDefault = 8192;  // nominal BPE item length S
+constexpr int32_t kBpeItemBytesMin = 1024;
 
 int launch_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets,
                   int32_t n, int32_t *d_ids, int64_t cap, int64_t *d_out_offsets, int8_t *d_mask,
@@ -125,11 +131,12 @@ struct BpeClass {
     uint32_t np;     // symbols per wave
     uint32_t lds;    // dynamic LDS bytes per workgroup
 };
-int bpe_wave_classes(uint32_t table_lds_bytes, BpeClass *out, int max_out);
+int bpe_wave_classes(uint32_t table_lds_bytes, int max_waves, BpeClass *out, int max_out);
 
-// Scratch bytes and workspace tiles one BPE encode of (nbytes, n rows) needs.
-int64_t bpe_scratch_bytes(int64_t nbytes, int32_t n);
-int64_t bpe_workspace_tiles(int64_t nbytes, int32_t n);
+// Scratch bytes and workspace tiles one BPE encode of (nbytes, n rows) needs
+// with nominal item length S.
+int64_t bpe_scratch_bytes(int64_t nbytes, int32_t n, int32_t S);
+int64_t bpe_workspace_tiles(int64_t nbytes, int32_t n, int32_t S);
 
 int launch_bpe_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets,
                       int32_t n, int32_t *d_ids, int64_t cap, int64_t *d_out_offsets, int8_t *d_mask,

@@ -629,17 +629,12 @@ int launch_rowscan(const int64_t *d_offsets, int32_t n, int64_t nbytes, int64_t 
     return DNATOK_OK;
 }
 
-EncodeTuning encode_tuning(bool kmer) {
+EncodeTuning encode_tuning(const dnatok_vocab *v) {
+    const bool kmer = (v->kind == DNATOK_KMER);
     EncodeTuning t;
-    t.tile_bytes = kmer ? 32768 : 16384;
-    t.blocks_per_cu = 0;
-    const char *e = getenv(kmer ? "DNATOK_KMER_TILE_BYTES" : "DNATOK_LUT_TILE_BYTES");
-    if (e) {
-        long long v = atoll(e);
-        if (v >= 4096 && v <= 65536) t.tile_bytes = v;  // rounded up to a power of two
-    }
-    e = getenv("DNATOK_BLOCKS_PER_CU");
-    if (e) t.blocks_per_cu = atoi(e);
+    const int32_t tile = v->tune_tile.load(std::memory_order_relaxed);
+    t.tile_bytes = tile > 0 ? tile : (kmer ? 32768 : 16384);
+    t.blocks_per_cu = v->tune_blocks.load(std::memory_order_relaxed);
     return t;
 }
 
@@ -647,7 +642,7 @@ int launch_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes,
                   int32_t n, int32_t *d_ids, int64_t cap, int64_t *d_out_offsets, int8_t *d_mask,
                   const dnatok_encode_opts &o, hipStream_t stream) {
     const bool kmer = (v->kind == DNATOK_KMER);
-    const EncodeTuning tune = encode_tuning(kmer);
+    const EncodeTuning tune = encode_tuning(v);
     int U = 1;  // staging loads per thread: tiles are U * NT * 16 bytes
     while (U < 16 && (int64_t)U * NT * 16 < tune.tile_bytes) U <<= 1;
     const int64_t B = (int64_t)U * NT * 16;

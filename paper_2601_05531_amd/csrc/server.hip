@@ -368,8 +368,9 @@ int dnatok_server_create(const dnatok_server_opts *opts, dnatok_server **out) {
     if (o.max_batch_bytes < 1) return set_error(DNATOK_EINVAL, "max_batch_bytes must be >= 1");
     if (o.staging_bytes < o.max_batch_bytes) return set_error(DNATOK_EINVAL, "staging_bytes < max_batch_bytes");
     // per stream: BPE scratch and scan workspace for the largest batch
-    const int64_t scratch = bpe_scratch_bytes(o.max_batch_bytes, o.max_batch);
-    const int64_t tiles = bpe_workspace_tiles(o.max_batch_bytes, o.max_batch);
+    // (sized for the smallest BPE item length a vocabulary may be tuned to)
+    const int64_t scratch = bpe_scratch_bytes(o.max_batch_bytes, o.max_batch, kBpeItemBytesMin);
+    const int64_t tiles = bpe_workspace_tiles(o.max_batch_bytes, o.max_batch, kBpeItemBytesMin);
     const int64_t ws_bytes = 256 + 2 * 8 * std::max<int64_t>(tiles, 4096);
     const int64_t reserve = (int64_t)o.n_streams * (scratch + ws_bytes);
     const int64_t arena = (o.budget_bytes - reserve) / kAlign * kAlign;

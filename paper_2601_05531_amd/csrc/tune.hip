@@ -1,0 +1,193 @@
+// Per-vocabulary tuning, the autotuner and captured encode graphs.
+//
+// The paper's batch and length sweeps (Results, "Encoding Throughput";
+// Discussion, "Performance Characteristics and Scaling Behavior") show the
+// encode's speed depending on how work is cut into launches and tiles; here
+// the cut is chosen by timing candidates on the caller's own batch, and a
+// fixed encode can be replayed from a HIP graph without per-launch host work.
+#include <algorithm>
+#include <vector>
+
+#include "common.hpp"
+
+using namespace dnatok;
+
+namespace {
+
+bool pow2_in(int32_t x, int32_t lo, int32_t hi) { return x >= lo && x <= hi && (x & (x - 1)) == 0; }
+
+int check_tuning(const dnatok_tuning &t) {
+    if (t.tile_bytes != 0 && !pow2_in(t.tile_bytes, 4096, 65536))
+        return set_error(DNATOK_EINVAL, "tile_bytes must be 0 or a power of two in [4096, 65536]");
+    if (t.blocks_per_cu < 0 || t.blocks_per_cu > 64) return set_error(DNATOK_EINVAL, "blocks_per_cu out of range");
+    if (t.bpe_item_bytes != 0 && !pow2_in(t.bpe_item_bytes, kBpeItemBytesMin, 65536))
+        return set_error(DNATOK_EINVAL, "bpe_item_bytes must be 0 or a power of two in [1024, 65536]");
+    if (t.bpe_max_waves != 0 && t.bpe_max_waves != 1 && t.bpe_max_waves != 2 && t.bpe_max_waves != 4 &&
+        t.bpe_max_waves != 8)
+        return set_error(DNATOK_EINVAL, "bpe_max_waves must be 0, 1, 2, 4 or 8");
+    return DNATOK_OK;
+}
+
+void store(dnatok_vocab *v, const dnatok_tuning &t) {
+    v->tune_tile.store(t.tile_bytes, std::memory_order_relaxed);
+    v->tune_blocks.store(t.blocks_per_cu, std::memory_order_relaxed);
+    v->tune_item.store(t.bpe_item_bytes, std::memory_order_relaxed);
+    v->tune_waves.store(t.bpe_max_waves, std::memory_order_relaxed);
+}
+
+dnatok_tuning load(const dnatok_vocab *v) {
+    dnatok_tuning t;
+    t.tile_bytes = v->tune_tile.load(std::memory_order_relaxed);
+    t.blocks_per_cu = v->tune_blocks.load(std::memory_order_relaxed);
+    t.bpe_item_bytes = v->tune_item.load(std::memory_order_relaxed);
+    t.bpe_max_waves = v->tune_waves.load(std::memory_order_relaxed);
+    return t;
+}
+
+}  // namespace
+
+struct dnatok_graph {
+    hipStream_t stream = nullptr;  // capture stream; owns the graph's workspace
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+int dnatok_get_tuning(const dnatok_vocab *v, dnatok_tuning *out) {
+    if (!v || !out) return set_error(DNATOK_EINVAL, "null argument");
+    *out = load(v);
+    return DNATOK_OK;
+}
+
+int dnatok_set_tuning(dnatok_vocab *v, const dnatok_tuning *t) {
+    if (!v || !t) return set_error(DNATOK_EINVAL, "null argument");
+    int rc = check_tuning(*t);
+    if (rc) return rc;
+    store(v, *t);
+    return DNATOK_OK;
+}
+
+int dnatok_autotune(dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets, int32_t n,
+                    int32_t *d_ids, int64_t ids_capacity, int64_t *d_out_offsets, int8_t *d_mask,
+                    const dnatok_encode_opts *opts, void *stream, int32_t reps, dnatok_tuning *best,
+                    float *best_ms) {
+    if (!v) return set_error(DNATOK_EINVAL, "null vocabulary");
+    if (reps < 1 || reps > 100) return set_error(DNATOK_EINVAL, "reps must be 1..100");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+        return set_error(DNATOK_ESTATE, "autotune cannot run during graph capture");
+    std::vector<dnatok_tuning> cand;
+    if (v->kind == DNATOK_BPE) {
+        for (int32_t S : {2048, 4096, 8192, 16384, 32768})
+            for (int32_t w : {8, 4, 2, 1}) cand.push_back(dnatok_tuning{0, 0, S, w});
+    } else {
+        for (int32_t tile : {4096, 8192, 16384, 32768, 65536})
+            for (int32_t b : {0, 1, 2, 4}) cand.push_back(dnatok_tuning{tile, b, 0, 0});
+    }
+    const dnatok_tuning saved = load(v);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    DNATOK_HIP(hipEventCreate(&e0));
+    DNATOK_HIP(hipEventCreate(&e1));
+    float best_t = -1.0f;
+    dnatok_tuning best_c = saved;
+    int rc = DNATOK_OK;
+    for (const dnatok_tuning &c : cand) {
+        store(v, c);
+        std::vector<float> ts;
+        for (int r = 0; r <= reps && rc == DNATOK_OK; ++r) {
+            if (hipEventRecord(e0, st) != hipSuccess) rc = set_error(DNATOK_EDEVICE, "hipEventRecord failed");
+            if (rc == DNATOK_OK)
+                rc = dnatok_encode(v, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets, d_mask,
+                                   opts, stream);
+            if (rc == DNATOK_OK && hipEventRecord(e1, st) != hipSuccess)
+                rc = set_error(DNATOK_EDEVICE, "hipEventRecord failed");
+            if (rc == DNATOK_OK && hipEventSynchronize(e1) != hipSuccess)
+                rc = set_error(DNATOK_EDEVICE, "hipEventSynchronize failed");
+            float ms = 0.0f;
+            if (rc == DNATOK_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                rc = set_error(DNATOK_EDEVICE, "hipEventElapsedTime failed");
+            if (r > 0) ts.push_back(ms);  // the first launch warms up
+        }
+        if (rc != DNATOK_OK) break;
+        std::nth_element(ts.begin(), ts.begin() + ts.size() / 2, ts.end());
+        const float med = ts[ts.size() / 2];
+        if (best_t < 0.0f || med < best_t) {
+            best_t = med;
+            best_c = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != DNATOK_OK) {
+        store(v, saved);
+        return rc;
+    }
+    store(v, best_c);
+    if (best) *best = best_c;
+    if (best_ms) *best_ms = best_t;
+    return DNATOK_OK;
+}
+
+int dnatok_graph_create(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets,
+                        int32_t n, int32_t *d_ids, int64_t ids_capacity, int64_t *d_out_offsets, int8_t *d_mask,
+                        const dnatok_encode_opts *opts, dnatok_graph **out) {
+    if (!out) return set_error(DNATOK_EINVAL, "null output handle");
+    *out = nullptr;
+    auto g = new dnatok_graph();
+    auto fail = [&](int rc) {
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        if (g->stream) {
+            (void)hipStreamSynchronize(g->stream);
+            drop_workspace(g->stream);
+            (void)hipStreamDestroy(g->stream);
+        }
+        delete g;
+        return rc;
+    };
+    if (hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking) != hipSuccess)
+        return fail(set_error(DNATOK_EDEVICE, "hipStreamCreateWithFlags failed"));
+    // eager run: validates the call and sizes the workspace the graph will use
+    int rc = dnatok_encode(v, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets, d_mask, opts,
+                           g->stream);
+    if (rc) return fail(rc);
+    if (hipStreamSynchronize(g->stream) != hipSuccess)
+        return fail(set_error(DNATOK_EDEVICE, "hipStreamSynchronize failed"));
+    if (hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(set_error(DNATOK_EDEVICE, "hipStreamBeginCapture failed"));
+    rc = dnatok_encode(v, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets, d_mask, opts,
+                       g->stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(g->stream, &graph);
+    g->graph = graph;
+    if (rc) return fail(rc);
+    if (ec != hipSuccess || !graph) return fail(set_error(DNATOK_EDEVICE, "hipStreamEndCapture failed"));
+    if (hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess)
+        return fail(set_error(DNATOK_EDEVICE, "hipGraphInstantiate failed"));
+    *out = g;
+    return DNATOK_OK;
+}
+
+int dnatok_graph_launch(dnatok_graph *g, void *stream) {
+    if (!g || !g->exec) return set_error(DNATOK_EINVAL, "null graph");
+    DNATOK_HIP(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
+    return DNATOK_OK;
+}
+
+int dnatok_graph_destroy(dnatok_graph *g) {
+    if (!g) return DNATOK_OK;
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    (void)hipDeviceSynchronize();  // replays on other streams may still read the workspace
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->stream) {
+        drop_workspace(g->stream);
+        (void)hipStreamDestroy(g->stream);
+    }
+    delete g;
+    return DNATOK_OK;
+}
+
+}  // extern "C"
