@@ -183,6 +183,26 @@ int dnatok_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes,
                   const dnatok_encode_opts *opts, void *stream);
 
 /*
+ * Encode one ragged batch for several k-mer vocabularies (any k, 1..8 of
+ * them) in a single pass over its bytes: each tile is read and classified
+ * once and every vocabulary's ids (and mask) are written from it. The
+ * paper's throughput experiments sweep token settings over the same input
+ * (Results, "Encoding Throughput"); this serves such a batch with one read
+ * of the input instead of one per vocabulary. Arrays are host arrays of
+ * length n_vocabs: vocabs, d_ids (device pointers), ids_capacity,
+ * d_out_offsets (device pointers), d_mask (device pointers; entries may be
+ * NULL for PACKED) and opts, which must agree in add_cls_sep, layout and
+ * pad_side (pad_to and offset_base may differ). Each vocabulary's outputs
+ * are exactly those of dnatok_encode. A single vocabulary of any kind is
+ * passed through to dnatok_encode. Errors: as dnatok_encode; EVOCAB for a
+ * non-k-mer vocabulary among several.
+ */
+int dnatok_encode_multi(const dnatok_vocab *const *vocabs, int32_t n_vocabs, const uint8_t *d_bytes, int64_t nbytes,
+                        const int64_t *d_offsets, int32_t n, int32_t *const *d_ids, const int64_t *ids_capacity,
+                        int64_t *const *d_out_offsets, int8_t *const *d_mask, const dnatok_encode_opts *opts,
+                        void *stream);
+
+/*
  * Wait for `stream`, then return (and clear) the DNATOK_DERR_* flags the
  * device raised for calls on it since the last check. *flags may be NULL.
  */
@@ -314,19 +334,40 @@ int dnatok_autotune(dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, con
                     const dnatok_encode_opts *opts, void *stream, int32_t reps, dnatok_tuning *best,
                     float *best_ms);
 
+/* The autotuner for dnatok_encode_multi: the tiling is that of vocabs[0],
+ * which the multi-vocabulary pass uses; the fastest setting is stored there. */
+int dnatok_autotune_multi(dnatok_vocab *const *vocabs, int32_t n_vocabs, const uint8_t *d_bytes, int64_t nbytes,
+                          const int64_t *d_offsets, int32_t n, int32_t *const *d_ids, const int64_t *ids_capacity,
+                          int64_t *const *d_out_offsets, int8_t *const *d_mask, const dnatok_encode_opts *opts,
+                          void *stream, int32_t reps, dnatok_tuning *best, float *best_ms);
+
 typedef struct dnatok_graph dnatok_graph;
 
+/* The arguments of one dnatok_encode (minus the stream). */
+typedef struct dnatok_encode_call {
+    const dnatok_vocab *v;
+    const uint8_t *d_bytes;
+    int64_t nbytes;
+    const int64_t *d_offsets;
+    int32_t n;
+    int32_t reserved;
+    int32_t *d_ids;
+    int64_t ids_capacity;
+    int64_t *d_out_offsets;
+    int8_t *d_mask;
+    dnatok_encode_opts opts;
+} dnatok_encode_call;
+
 /*
- * Capture one dnatok_encode with exactly these buffers, sizes and options
- * into an executable HIP graph (the encode is run once eagerly first, which
- * also sizes the graph's private workspace). Each dnatok_graph_launch
- * replays it on `stream` reading whatever the buffers hold at that point;
- * replays of one graph must not overlap (order them on one stream or with
- * events). The vocabulary and buffers must outlive the graph.
+ * Capture n_calls encodes, in order, with exactly these buffers, sizes and
+ * options into one executable HIP graph (each encode is run once eagerly
+ * first, which also sizes the graph's private workspace). Each
+ * dnatok_graph_launch replays them all on `stream`, reading whatever the
+ * buffers hold at that point; replays of one graph must not overlap (order
+ * them on one stream or with events). Vocabularies and buffers must outlive
+ * the graph. Errors: as dnatok_encode for any call, EDEVICE.
  */
-int dnatok_graph_create(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets,
-                        int32_t n, int32_t *d_ids, int64_t ids_capacity, int64_t *d_out_offsets, int8_t *d_mask,
-                        const dnatok_encode_opts *opts, dnatok_graph **out);
+int dnatok_graph_create(const dnatok_encode_call *calls, int32_t n_calls, dnatok_graph **out);
 int dnatok_graph_launch(dnatok_graph *g, void *stream);
 int dnatok_graph_destroy(dnatok_graph *g);
 

@@ -92,6 +92,22 @@ class dnatok_tuning(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class dnatok_encode_call(ctypes.Structure):
+    _fields_ = [
+        ("v", ctypes.c_void_p),
+        ("d_bytes", ctypes.c_void_p),
+        ("nbytes", ctypes.c_int64),
+        ("d_offsets", ctypes.c_void_p),
+        ("n", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("d_ids", ctypes.c_void_p),
+        ("ids_capacity", ctypes.c_int64),
+        ("d_out_offsets", ctypes.c_void_p),
+        ("d_mask", ctypes.c_void_p),
+        ("opts", dnatok_encode_opts),
+    ]
+
+
 class dnatok_server_opts(ctypes.Structure):
     _fields_ = [
         ("budget_bytes", ctypes.c_int64),
@@ -143,6 +159,9 @@ def lib():
         L.dnatok_encode.argtypes = [vp, vp, i64, vp, i32, vp, i64, vp, vp,
                                     ctypes.POINTER(dnatok_encode_opts), vp]
         L.dnatok_sync_status.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32)]
+        L.dnatok_encode_multi.argtypes = [vp, i32, vp, i64, vp, i32, vp, vp, vp, vp, vp, vp]
+        L.dnatok_autotune_multi.argtypes = [vp, i32, vp, i64, vp, i32, vp, vp, vp, vp, vp, vp, i32,
+                                            ctypes.POINTER(dnatok_tuning), ctypes.POINTER(ctypes.c_float)]
         L.dnatok_decode.argtypes = [vp, vp, i64, vp, i32, vp, i64, vp, vp]
         L.dnatok_stream_create.argtypes = [vp, ctypes.POINTER(dnatok_stream_opts), vp, ctypes.POINTER(vp)]
         L.dnatok_stream_push.argtypes = [vp, vp, i64, vp, i32]
@@ -163,8 +182,7 @@ def lib():
         L.dnatok_set_tuning.argtypes = [vp, ctypes.POINTER(dnatok_tuning)]
         L.dnatok_autotune.argtypes = [vp, vp, i64, vp, i32, vp, i64, vp, vp, ctypes.POINTER(dnatok_encode_opts),
                                       vp, i32, ctypes.POINTER(dnatok_tuning), ctypes.POINTER(ctypes.c_float)]
-        L.dnatok_graph_create.argtypes = [vp, vp, i64, vp, i32, vp, i64, vp, vp, ctypes.POINTER(dnatok_encode_opts),
-                                          ctypes.POINTER(vp)]
+        L.dnatok_graph_create.argtypes = [ctypes.POINTER(dnatok_encode_call), i32, ctypes.POINTER(vp)]
         L.dnatok_graph_launch.argtypes = [vp, vp]
         L.dnatok_graph_destroy.argtypes = [vp]
         for name in ("dnatok_vocab_create", "dnatok_vocab_destroy", "dnatok_vocab_info", "dnatok_encode_plan",
@@ -173,7 +191,7 @@ def lib():
                      "dnatok_server_create", "dnatok_server_submit", "dnatok_server_poll", "dnatok_server_wait",
                      "dnatok_server_release", "dnatok_server_stats", "dnatok_server_destroy", "dnatok_get_tuning",
                      "dnatok_set_tuning", "dnatok_autotune", "dnatok_graph_create", "dnatok_graph_launch",
-                     "dnatok_graph_destroy"):
+                     "dnatok_graph_destroy", "dnatok_encode_multi", "dnatok_autotune_multi"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -588,17 +606,30 @@ def autotune(vocab: Vocab, d_bytes, d_offsets, h_offsets=None, add_cls_sep=False
 
 
 class Graph:
-    """A captured dnatok_encode over fixed buffers (see dnatok_graph_create)."""
+    """Captured dnatok_encode calls over fixed buffers (see dnatok_graph_create).
 
-    def __init__(self, vocab: Vocab, d_bytes, d_offsets, d_ids, d_out_offsets, d_mask=None, add_cls_sep=False,
-                 layout=PACKED, pad_side=PAD_RIGHT, pad_to=0):
-        n = d_offsets.numel() - 1
+    ``calls``: a list of dicts with keys vocab, d_bytes, d_offsets, d_ids,
+    d_out_offsets and optionally d_mask, add_cls_sep, layout, pad_side,
+    pad_to (tensors on the device)."""
+
+    def __init__(self, calls):
+        arr = (dnatok_encode_call * len(calls))()
+        self._keep = []
+        for c, d in zip(arr, calls):
+            c.v = d["vocab"].handle
+            c.d_bytes = _ptr(d["d_bytes"])
+            c.nbytes = d["d_bytes"].numel()
+            c.d_offsets = _ptr(d["d_offsets"])
+            c.n = d["d_offsets"].numel() - 1
+            c.d_ids = _ptr(d["d_ids"])
+            c.ids_capacity = d["d_ids"].numel()
+            c.d_out_offsets = _ptr(d["d_out_offsets"])
+            c.d_mask = _ptr(d.get("d_mask"))
+            c.opts = make_opts(d.get("add_cls_sep", False), d.get("layout", PACKED), d.get("pad_side", PAD_RIGHT),
+                               d.get("pad_to", 0))
+            self._keep.append(d)
         h = ctypes.c_void_p()
-        self._keep = (vocab, d_bytes, d_offsets, d_ids, d_out_offsets, d_mask)
-        _check(lib().dnatok_graph_create(vocab.handle, _ptr(d_bytes), d_bytes.numel(), _ptr(d_offsets), n,
-                                         _ptr(d_ids), d_ids.numel(), _ptr(d_out_offsets), _ptr(d_mask),
-                                         ctypes.byref(make_opts(add_cls_sep, layout, pad_side, pad_to)),
-                                         ctypes.byref(h)))
+        _check(lib().dnatok_graph_create(arr, len(calls), ctypes.byref(h)))
         self.handle = h.value
 
     def launch(self, stream=None):
@@ -614,3 +645,64 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+# ---- several k-mer vocabularies in one pass -------------------------------------------
+
+class MultiCall:
+    """Marshalled arguments of dnatok_encode_multi (host arrays kept alive)."""
+
+    def __init__(self, vocabs, d_bytes, d_offsets, outs, opts):
+        nv = len(vocabs)
+        self.nv = nv
+        self.vocabs = (ctypes.c_void_p * nv)(*[v.handle for v in vocabs])
+        self.ids = (ctypes.c_void_p * nv)(*[_ptr(o[0]) for o in outs])
+        self.caps = (ctypes.c_int64 * nv)(*[o[0].numel() for o in outs])
+        self.oofs = (ctypes.c_void_p * nv)(*[_ptr(o[1]) for o in outs])
+        self.masks = (ctypes.c_void_p * nv)(*[_ptr(o[2]) for o in outs])
+        self.opts = (dnatok_encode_opts * nv)(*opts)
+        self.d_bytes, self.nbytes = _ptr(d_bytes), d_bytes.numel()
+        self.d_offsets, self.n = _ptr(d_offsets), d_offsets.numel() - 1
+        self._keep = (vocabs, d_bytes, d_offsets, outs)
+
+    def args(self):
+        return (self.vocabs, self.nv, self.d_bytes, self.nbytes, self.d_offsets, self.n, self.ids, self.caps,
+                self.oofs, self.masks, self.opts)
+
+    def run(self, stream=None):
+        _check(lib().dnatok_encode_multi(*self.args(), _stream_ptr(stream)))
+
+    def autotune(self, reps=3, stream=None):
+        t, ms = dnatok_tuning(), ctypes.c_float()
+        _check(lib().dnatok_autotune_multi(*self.args(), _stream_ptr(stream), reps, ctypes.byref(t),
+                                           ctypes.byref(ms)))
+        return t.as_dict(), ms.value
+
+
+def encode_multi(vocabs, d_bytes, d_offsets, h_offsets=None, add_cls_sep=False, layout=PACKED, pad_side=PAD_RIGHT,
+                 stream=None):
+    """Encode one batch for several k-mer vocabularies in one pass. Returns a
+    list of (ids, out_offsets, mask) per vocabulary, as ``encode``."""
+    import torch
+    n = d_offsets.numel() - 1
+    if h_offsets is None:
+        h_offsets = d_offsets.cpu().numpy()
+    outs, opts, shapes = [], [], []
+    for v in vocabs:
+        total, max_len = plan(v, h_offsets, add_cls_sep)
+        W = max_len if layout == PADDED else 0
+        cap = n * W if layout == PADDED else total
+        ids = torch.empty(max(cap, 1), dtype=torch.int32, device=d_bytes.device)
+        oo = torch.empty(n + 1, dtype=torch.int64, device=d_bytes.device)
+        mask = torch.empty(max(cap, 1), dtype=torch.int8, device=d_bytes.device) if layout == PADDED else None
+        outs.append((ids, oo, mask))
+        opts.append(make_opts(add_cls_sep, layout, pad_side, W))
+        shapes.append((cap, W, total))
+    MultiCall(vocabs, d_bytes, d_offsets, outs, opts).run(stream)
+    res = []
+    for (ids, oo, mask), (cap, W, total) in zip(outs, shapes):
+        if layout == PADDED:
+            res.append((ids[:cap].view(n, W), oo, mask[:cap].view(n, W)))
+        else:
+            res.append((ids[:total], oo, None))
+    return res

@@ -276,12 +276,11 @@ int dnatok_encode_plan(const dnatok_vocab *v, const int64_t *h_offsets, int32_t 
     return DNATOK_OK;
 }
 
-int dnatok_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets, int32_t n,
-                  int32_t *d_ids, int64_t ids_capacity, int64_t *d_out_offsets, int8_t *d_mask,
-                  const dnatok_encode_opts *opts, void *stream) {
+// Checks one encode's arguments (everything dnatok_encode checks on the host).
+static int check_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets,
+                        int32_t n, int32_t *d_ids, int64_t ids_capacity, int64_t *d_out_offsets, int8_t *d_mask,
+                        const dnatok_encode_opts &o) {
     if (!v) return set_error(DNATOK_EINVAL, "null vocabulary");
-    dnatok_encode_opts o = {};
-    if (opts) o = *opts;
     if (n < 0 || nbytes < 0 || ids_capacity < 0) return set_error(DNATOK_EINVAL, "negative size");
     if (!d_offsets || !d_out_offsets) return set_error(DNATOK_EINVAL, "offsets and out_offsets are required");
     if (nbytes > 0 && !d_bytes) return set_error(DNATOK_EINVAL, "null bytes");
@@ -298,12 +297,46 @@ int dnatok_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes,
     int dev = 0;
     DNATOK_HIP(hipGetDevice(&dev));
     if (dev != v->device) return set_error(DNATOK_EINVAL, "vocabulary lives on device %d, current is %d", v->device, dev);
+    return DNATOK_OK;
+}
+
+int dnatok_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets, int32_t n,
+                  int32_t *d_ids, int64_t ids_capacity, int64_t *d_out_offsets, int8_t *d_mask,
+                  const dnatok_encode_opts *opts, void *stream) {
+    dnatok_encode_opts o = {};
+    if (opts) o = *opts;
+    int rc = check_encode(v, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets, d_mask, o);
+    if (rc) return rc;
     clear_error();
     if (v->kind == DNATOK_BPE)
         return launch_bpe_encode(v, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets, d_mask, o,
                                  static_cast<hipStream_t>(stream));
     return launch_encode(v, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets, d_mask, o,
                          static_cast<hipStream_t>(stream));
+}
+
+int dnatok_encode_multi(const dnatok_vocab *const *vocabs, int32_t n_vocabs, const uint8_t *d_bytes, int64_t nbytes,
+                        const int64_t *d_offsets, int32_t n, int32_t *const *d_ids, const int64_t *ids_capacity,
+                        int64_t *const *d_out_offsets, int8_t *const *d_mask, const dnatok_encode_opts *opts,
+                        void *stream) {
+    if (!vocabs || !d_ids || !ids_capacity || !d_out_offsets || !d_mask || !opts)
+        return set_error(DNATOK_EINVAL, "null argument array");
+    if (n_vocabs < 1 || n_vocabs > 8) return set_error(DNATOK_EINVAL, "n_vocabs must be 1..8");
+    for (int32_t i = 0; i < n_vocabs; ++i) {
+        int rc = check_encode(vocabs[i], d_bytes, nbytes, d_offsets, n, d_ids[i], ids_capacity[i], d_out_offsets[i],
+                              d_mask[i], opts[i]);
+        if (rc) return rc;
+        if (n_vocabs > 1 && vocabs[i]->kind != DNATOK_KMER)
+            return set_error(DNATOK_EVOCAB, "several vocabularies in one pass must all be k-mer vocabularies");
+        if (opts[i].add_cls_sep != opts[0].add_cls_sep || opts[i].layout != opts[0].layout ||
+            opts[i].pad_side != opts[0].pad_side)
+            return set_error(DNATOK_EINVAL, "options differ in more than pad_to and offset_base");
+    }
+    clear_error();
+    if (n_vocabs == 1) return dnatok_encode(vocabs[0], d_bytes, nbytes, d_offsets, n, d_ids[0], ids_capacity[0],
+                                            d_out_offsets[0], d_mask[0], &opts[0], stream);
+    return launch_encode_multi(vocabs, n_vocabs, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets,
+                               d_mask, opts, static_cast<hipStream_t>(stream));
 }
 
 int dnatok_sync_status(void *stream, uint32_t *flags) {

@@ -71,23 +71,57 @@ int build_bpe_tables(dnatok_vocab *v) {
     }
     v->max_token_bytes = mx;
 
-    uint32_t slots = 16;
-    while (slots < 2u * (uint32_t)(R > 0 ? R : 1)) slots <<= 1;
-    std::vector<uint16_t> slot(slots, kNoRank);
+    // cuckoo table at load <= 0.8; grown by 5% and rebuilt if an insertion
+    // walk does not settle
     std::vector<uint32_t> pair((size_t)(R > 0 ? R : 1), 0);
-    for (int32_t r = 0; r < R; ++r) {
-        uint32_t a = (uint32_t)v->h_merges[2 * r], b = (uint32_t)v->h_merges[2 * r + 1];
-        pair[r] = a | (b << 16);
-        uint32_t s = bpe_pair_hash(a, b) & (slots - 1);
-        while (slot[s] != kNoRank) s = (s + 1) & (slots - 1);
-        slot[s] = (uint16_t)r;
+    for (int32_t r = 0; r < R; ++r)
+        pair[r] = (uint32_t)v->h_merges[2 * r] | ((uint32_t)v->h_merges[2 * r + 1] << 16);
+    uint32_t nbk = std::max<uint32_t>(1, (uint32_t)((R * 5 + 7) / 8));
+    std::vector<uint32_t> bucket;
+    for (int attempt = 0;; ++attempt) {
+        if (attempt == 40) return set_error(DNATOK_EVOCAB, "could not build the pair table");
+        bucket.assign((size_t)nbk * 4, 0);
+        uint64_t rng = 0x2545F4914F6CDD1Dull + (uint64_t)attempt;
+        bool ok = true;
+        for (int32_t r = 0; r < R && ok; ++r) {
+            uint32_t key = pair[r], rank = (uint32_t)r;
+            uint32_t b1, b2;
+            bpe_buckets(key, nbk, &b1, &b2);
+            uint32_t cur = b1;
+            bool placed = false;
+            for (int kick = 0; kick < 500 && !placed; ++kick) {
+                for (uint32_t c : {cur, cur == b1 ? b2 : b1}) {
+                    for (int e = 0; e < 2 && !placed; ++e) {
+                        if (bucket[(size_t)c * 4 + 2 * e] == 0) {
+                            bucket[(size_t)c * 4 + 2 * e] = key;
+                            bucket[(size_t)c * 4 + 2 * e + 1] = rank;
+                            placed = true;
+                        }
+                    }
+                    if (placed) break;
+                }
+                if (placed) break;
+                // evict a random entry of the current bucket; move on to its other bucket
+                rng ^= rng << 13;
+                rng ^= rng >> 7;
+                rng ^= rng << 17;
+                const int e = (int)(rng & 1);
+                std::swap(key, bucket[(size_t)cur * 4 + 2 * e]);
+                std::swap(rank, bucket[(size_t)cur * 4 + 2 * e + 1]);
+                bpe_buckets(key, nbk, &b1, &b2);
+                cur = (cur == b1) ? b2 : b1;
+            }
+            ok = placed;
+        }
+        if (ok) break;
+        nbk = nbk + nbk / 20 + 1;
     }
-    t.slots = slots;
+    t.nbk = nbk;
 
     void *p = nullptr;
-    DNATOK_HIP(hipMalloc(&p, sizeof(uint16_t) * slots));
-    t.d_slot = static_cast<uint16_t *>(p);
-    DNATOK_HIP(hipMemcpy(t.d_slot, slot.data(), sizeof(uint16_t) * slots, hipMemcpyHostToDevice));
+    DNATOK_HIP(hipMalloc(&p, sizeof(uint32_t) * bucket.size()));
+    t.d_bucket = static_cast<uint32_t *>(p);
+    DNATOK_HIP(hipMemcpy(t.d_bucket, bucket.data(), sizeof(uint32_t) * bucket.size(), hipMemcpyHostToDevice));
     DNATOK_HIP(hipMalloc(&p, sizeof(uint32_t) * pair.size()));
     t.d_pair = static_cast<uint32_t *>(p);
     DNATOK_HIP(hipMemcpy(t.d_pair, pair.data(), sizeof(uint32_t) * pair.size(), hipMemcpyHostToDevice));
@@ -105,7 +139,7 @@ int build_bpe_tables(dnatok_vocab *v) {
 
 void free_bpe_tables(dnatok_vocab *v) {
     BpeTables &t = v->bpe;
-    if (t.d_slot) (void)hipFree(t.d_slot);
+    if (t.d_bucket) (void)hipFree(t.d_bucket);
     if (t.d_pair) (void)hipFree(t.d_pair);
     if (t.d_tok_len) (void)hipFree(t.d_tok_len);
     if (t.d_tok_off) (void)hipFree(t.d_tok_off);
@@ -143,35 +177,39 @@ __device__ __forceinline__ uint16_t symbol_of(uint8_t b) {
 }
 
 struct RankTab {
-    const uint16_t *slot;
+    const uint4 *bucket;
     const uint32_t *pair;
-    uint32_t mask;
+    uint32_t nbk;
 };
 
 // Rank of the pair (a, b), or kNoRank. Specials and N never merge.
 __device__ __forceinline__ uint32_t pair_rank(const RankTab &t, uint32_t a, uint32_t b) {
     if (a < 5 || a == 9 || b < 5 || b == 9) return kNoRank;
     const uint32_t key = a | (b << 16);
-    uint32_t s = bpe_pair_hash(a, b) & t.mask;
-    for (;;) {
-        const uint32_t r = t.slot[s];
-        if (r == kNoRank || t.pair[r] == key) return r;
-        s = (s + 1) & t.mask;
-    }
+    uint32_t b1, b2;
+    bpe_buckets(key, t.nbk, &b1, &b2);
+    const uint4 x = t.bucket[b1], y = t.bucket[b2];
+    uint32_t r = kNoRank;
+    r = (x.x == key) ? x.y : r;
+    r = (x.z == key) ? x.w : r;
+    r = (y.x == key) ? y.y : r;
+    r = (y.z == key) ? y.w : r;
+    return r;
 }
 
-// Table layout in LDS: 16-bit slots, then 32-bit pairs.
-__host__ __device__ inline uint32_t table_bytes(uint32_t slots, int32_t R) {
-    return al16(2u * slots) + al16(4u * (uint32_t)(R > 0 ? R : 1));
+// Table layout in LDS: buckets, then 32-bit pairs.
+__host__ __device__ inline uint32_t table_bytes(uint32_t nbk, int32_t R) {
+    return 16u * nbk + al16(4u * (uint32_t)(R > 0 ? R : 1));
 }
 
-__device__ void load_table(uint8_t *dyn, const uint16_t *g_slot, const uint32_t *g_pair, uint32_t slots, int32_t R,
+__device__ void load_table(uint8_t *dyn, const uint32_t *g_bucket, const uint32_t *g_pair, uint32_t nbk, int32_t R,
                            RankTab *t) {
-    uint16_t *slot = reinterpret_cast<uint16_t *>(dyn);
-    uint32_t *pair = reinterpret_cast<uint32_t *>(dyn + al16(2u * slots));
-    for (uint32_t s = threadIdx.x; s < slots; s += blockDim.x) slot[s] = g_slot[s];
+    uint4 *bucket = reinterpret_cast<uint4 *>(dyn);
+    uint32_t *pair = reinterpret_cast<uint32_t *>(dyn + 16u * nbk);
+    const uint4 *gb = reinterpret_cast<const uint4 *>(g_bucket);
+    for (uint32_t s = threadIdx.x; s < nbk; s += blockDim.x) bucket[s] = gb[s];
     for (int32_t r = threadIdx.x; r < R; r += blockDim.x) pair[r] = g_pair[r];
-    *t = RankTab{slot, pair, slots - 1};
+    *t = RankTab{bucket, pair, nbk};
 }
 
 // ---- 2. items ------------------------------------------------------------------
@@ -316,9 +354,9 @@ struct WaveArgs {
     int64_t max_items;
     uint16_t *tok;  // final symbols of item t at item_start[t]
     int32_t *item_cnt;
-    const uint16_t *slot;
+    const uint32_t *bucket;
     const uint32_t *pair;
-    uint32_t slots;
+    uint32_t nbk;
     int32_t R;
     int32_t lo, hi;  // this launch takes items with lo < length <= hi
     uint32_t np;     // positions per wave (multiple of 64, >= hi)
@@ -340,20 +378,86 @@ __host__ __device__ inline WaveLayout wave_layout(uint32_t np) {
     l.bmin = l.alive + al16(np / 8);
     l.cblk = l.bmin + al16(2u * nb);
     l.dirty = l.cblk + al16(2u * nb);
-    l.list = l.dirty + al16(4u * ((nb + 31) / 32));
+    l.list = l.dirty + al16(4u * ((nb + 31) / 32 + 1));
     l.bytes = l.list + 128u;
     return l;
 }
 __host__ __device__ inline uint32_t wave_lds_bytes(uint32_t np) { return wave_layout(np).bytes; }
 
+// Alive positions around p from one 128-bit window of the bitmap (words
+// w-1 .. w+2, w = p / 32): l = previous, q = next, q2 = the one after q.
+// Positions outside the window are found by scanning words (rare: a dead
+// run is shorter than the longest token). kNone where there is none.
+struct Neighbors {
+    uint32_t l, q, q2;
+};
+
+__device__ __forceinline__ uint32_t scan_up(const uint32_t *alive, uint32_t nw, uint32_t word) {
+    for (; word < nw; ++word) {
+        const uint32_t bits = alive[word];
+        if (bits) return (word << 5) + (uint32_t)__builtin_ctz(bits);
+    }
+    return kNone;
+}
+
+__device__ __forceinline__ uint32_t scan_down(const uint32_t *alive, int32_t word) {
+    for (; word >= 0; --word) {
+        const uint32_t bits = alive[word];
+        if (bits) return ((uint32_t)word << 5) + 31u - (uint32_t)__builtin_clz(bits);
+    }
+    return kNone;
+}
+
+// First set bit of the 128-bit (lo, hi) strictly above bit `rel`, or -1.
+__device__ __forceinline__ int32_t window_next(uint64_t lo, uint64_t hi, int32_t rel) {
+    if (rel < 63) {
+        const uint64_t m = lo & (~0ull << (rel + 1));
+        if (m) return __builtin_ctzll(m);
+    }
+    const int32_t rh = rel - 64;
+    const uint64_t m2 = rh < 0 ? hi : (rh < 63 ? hi & (~0ull << (rh + 1)) : 0ull);
+    return m2 ? 64 + __builtin_ctzll(m2) : -1;
+}
+
+__device__ __forceinline__ Neighbors neighbors(const uint32_t *alive, uint32_t nw, uint32_t p, bool want_q2) {
+    const uint32_t w = p >> 5;
+    const uint32_t a0 = w >= 1 ? alive[w - 1] : 0u;
+    const uint32_t a1 = alive[w];
+    const uint32_t a2 = w + 1 < nw ? alive[w + 1] : 0u;
+    const uint32_t a3 = w + 2 < nw ? alive[w + 2] : 0u;
+    const uint64_t lo = a0 | ((uint64_t)a1 << 32), hi = a2 | ((uint64_t)a3 << 32);
+    const int32_t base = 32 * ((int32_t)w - 1);  // position of window bit 0
+    const int32_t rel = 32 + (int32_t)(p & 31);
+    Neighbors nb;
+    const uint64_t below = lo & ((1ull << rel) - 1);
+    nb.l = below ? (uint32_t)(base + 63 - __clzll(below)) : scan_down(alive, (int32_t)w - 2);
+    const int32_t rq = window_next(lo, hi, rel);
+    nb.q = rq >= 0 ? (uint32_t)(base + rq) : scan_up(alive, nw, w + 3);
+    nb.q2 = kNone;
+    if (want_q2 && nb.q != kNone) {
+        if (rq >= 0) {
+            const int32_t r2 = window_next(lo, hi, rq);
+            nb.q2 = r2 >= 0 ? (uint32_t)(base + r2) : scan_up(alive, nw, w + 3);
+        } else {
+            // q itself lies beyond the window: continue from q
+            const uint32_t wq = nb.q >> 5;
+            const uint32_t bits = alive[wq] & ~((2u << (nb.q & 31)) - 1u);
+            nb.q2 = bits ? (wq << 5) + (uint32_t)__builtin_ctz(bits) : scan_up(alive, nw, wq + 1);
+        }
+    }
+    return nb;
+}
+
+constexpr int kK2Max = 16;  // level-2 blocks per lane (np <= 65536)
+
 __global__ __launch_bounds__(kMaxWaves * 64) void k_bpe_wave(WaveArgs a) {
     extern __shared__ __align__(16) uint8_t dyn[];
     RankTab tab;
-    load_table(dyn, a.slot, a.pair, a.slots, a.R, &tab);
+    load_table(dyn, a.bucket, a.pair, a.nbk, a.R, &tab);
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const WaveLayout lay = wave_layout(a.np);
-    uint8_t *wb = dyn + table_bytes(a.slots, a.R) + (threadIdx.x / 64) * a.wave_bytes;
+    uint8_t *wb = dyn + table_bytes(a.nbk, a.R) + (threadIdx.x / 64) * a.wave_bytes;
     uint16_t *sym = reinterpret_cast<uint16_t *>(wb);
     uint16_t *prk = reinterpret_cast<uint16_t *>(wb + lay.prk);
     uint32_t *alive = reinterpret_cast<uint32_t *>(wb + lay.alive);
@@ -373,27 +477,50 @@ __global__ __launch_bounds__(kMaxWaves * 64) void k_bpe_wave(WaveArgs a) {
         const int64_t c0 = a.item_start[t];
         const uint8_t *src = a.bytes + c0;
         const uint32_t nb = ((uint32_t)n + 63) / 64, nw = ((uint32_t)n + 31) / 32, k2 = (nb + 63) / 64;
+        const uint32_t ndw = (nb + 31) / 32 + 1;  // dirty words (one spare: a lane's bits may straddle two)
 
-        // symbols, alive bits, pair ranks, block minima
-        for (uint32_t p = lane; p < nb * 64; p += 64) sym[p] = p < (uint32_t)n ? symbol_of(src[p]) : 0;
+        // symbols (four per lane per step), alive bits, dirty bits
+        for (uint32_t p0 = 4 * lane; p0 < nb * 64; p0 += 256) {
+            uint32_t v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = p0 + u < (uint32_t)n ? symbol_of(src[p0 + u]) : 0u;
+            *reinterpret_cast<uint2 *>(sym + p0) = make_uint2(v[0] | (v[1] << 16), v[2] | (v[3] << 16));
+        }
         for (uint32_t w = lane; w < nb * 2; w += 64) {
             const int32_t f = n - 32 * (int32_t)w;
             alive[w] = f >= 32 ? ~0u : (f > 0 ? (1u << f) - 1u : 0u);
         }
-        for (uint32_t w = lane; w < (nb + 31) / 32; w += 64) dirty[w] = 0;
+        for (uint32_t w = lane; w < ndw; w += 64) dirty[w] = 0;
         wave_sync();
-        for (uint32_t i = 0; i < nb; ++i) {
-            const uint32_t p = i * 64 + lane;
-            const uint32_t r = (p + 1 < (uint32_t)n) ? pair_rank(tab, sym[p], sym[p + 1]) : kNoRank;
-            prk[p] = (uint16_t)r;
-            const uint32_t m = dev::wave_min_all_u32(r);
-            if (lane == 0) bmin[i] = (uint16_t)m;
+        // pair ranks and block minima, four blocks at a time
+        for (uint32_t i = 0; i < nb; i += 4) {
+            uint32_t r[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t p = (i + u) * 64 + lane;
+                const bool has = i + u < nb && p + 1 < (uint32_t)n;
+                const uint32_t pn = has ? p + 1 : p;
+                const uint32_t x = (i + u < nb) ? sym[p] : 0u, y = (i + u < nb) ? sym[pn] : 0u;
+                r[u] = has ? pair_rank(tab, x, y) : kNoRank;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (i + u < nb) {
+                    prk[(i + u) * 64 + lane] = (uint16_t)r[u];
+                    const uint32_t m = dev::wave_min_all_u32(r[u]);
+                    if (lane == 0) bmin[i + u] = (uint16_t)m;
+                }
+            }
         }
         wave_sync();
+        // level 2: this lane's blocks lane*k2 .. lane*k2 + k2 - 1, minima in registers
+        const uint32_t b0 = (uint32_t)lane * k2;
+        uint32_t bm[kK2Max];
         uint32_t l2 = kNoRank;
-        for (uint32_t k = 0; k < k2; ++k) {
-            const uint32_t b = lane * k2 + k;
-            if (b < nb) l2 = min(l2, (uint32_t)bmin[b]);
+#pragma unroll
+        for (int k = 0; k < kK2Max; ++k) {
+            bm[k] = ((uint32_t)k < k2 && b0 + k < nb) ? (uint32_t)bmin[b0 + k] : kNoRank;
+            l2 = min(l2, bm[k]);
         }
 
         // Each round refreshes every block it visits and leaves no pair of
@@ -408,13 +535,11 @@ __global__ __launch_bounds__(kMaxWaves * 64) void k_bpe_wave(WaveArgs a) {
             const uint32_t pr = tab.pair[rs];
             const uint32_t L = pr & 0xFFFF, NEW = 10 + rs;
             const bool chain = L == (pr >> 16);
-            // blocks holding rank rs, in order
+            // blocks holding rank rs, in order; they are all refreshed after the round
             uint32_t cm = 0;
             if (l2 == rs) {
-                for (uint32_t k = 0; k < k2; ++k) {
-                    const uint32_t b = lane * k2 + k;
-                    if (b < nb && bmin[b] == rs) cm |= 1u << k;
-                }
+#pragma unroll
+                for (int k = 0; k < kK2Max; ++k) cm |= (uint32_t)(bm[k] == rs) << k;
             }
             const uint32_t cc = (uint32_t)__popc(cm);
             const uint32_t cinc = dev::wave_incl_sum_u32(cc);
@@ -422,13 +547,11 @@ __global__ __launch_bounds__(kMaxWaves * 64) void k_bpe_wave(WaveArgs a) {
             {
                 uint32_t o = cinc - cc, m = cm;
                 while (m) {
-                    const uint32_t k = (uint32_t)__builtin_ctz(m);
-                    const uint32_t b = lane * k2 + k;
-                    cblk[o++] = (uint16_t)b;
-                    atomicOr(&dirty[b >> 5], 1u << (b & 31));
+                    cblk[o++] = (uint16_t)(b0 + (uint32_t)__builtin_ctz(m));
                     m &= m - 1;
                 }
             }
+            uint32_t own_dirty = cm;
             wave_sync();
             uint32_t carry_q = kNone;
             int32_t carry_off = 0;
@@ -456,7 +579,9 @@ __global__ __launch_bounds__(kMaxWaves * 64) void k_bpe_wave(WaveArgs a) {
                 // which occurrences merge: all, or for (X, X) every other one of a run
                 const bool valid = (uint32_t)lane < nc;
                 const uint32_t p = valid ? list[lane] : 0;
-                const uint32_t q = valid ? next_alive(alive, nw, p) : kNone;
+                Neighbors nbr{kNone, kNone, kNone};
+                if (valid) nbr = neighbors(alive, nw, p, true);
+                const uint32_t q = nbr.q;
                 // lane 0 compares with the last occurrence of the previous group
                 const uint32_t q_up = dev::wave_from_prev_u32(q, carry_q);
                 const bool adj = chain && valid && q_up == p;
@@ -472,18 +597,15 @@ __global__ __launch_bounds__(kMaxWaves * 64) void k_bpe_wave(WaveArgs a) {
                 const uint32_t rq = ms ? q : kNone;
                 const uint32_t rq1 = dev::wave_from_prev_u32(rq, kNone);
                 const uint32_t rq2 = dev::wave_from_prev_u32(rq1, kNone);
-                uint32_t l = kNone, rk_l = kNoRank, rk_r = kNoRank;
-                bool left = false;
+                const uint32_t l = nbr.l, q2 = nbr.q2;
+                uint32_t rk_l = kNoRank, rk_r = kNoRank;
+                const bool left = ms && l != kNone && rq1 != l && rq2 != l;
                 if (ms) {
-                    const uint32_t q2 = next_alive(alive, nw, q);
-                    if (q2 != kNone) {
-                        // an occurrence right after a merge merges too
-                        const uint32_t s2 = (prk[q2] == rs) ? NEW : sym[q2];
-                        rk_r = pair_rank(tab, NEW, s2);
-                    }
-                    l = prev_alive(alive, p);
-                    left = l != kNone && rq1 != l && rq2 != l;
-                    if (left) rk_l = pair_rank(tab, sym[l], NEW);
+                    // an occurrence right after a merge merges too
+                    const uint32_t s2 = q2 != kNone ? ((prk[q2] == rs) ? NEW : (uint32_t)sym[q2]) : 0u;
+                    const uint32_t sl = left ? (uint32_t)sym[l] : 0u;
+                    if (q2 != kNone) rk_r = pair_rank(tab, NEW, s2);
+                    if (left) rk_l = pair_rank(tab, sl, NEW);
                 }
                 wave_sync();
                 if (ms) {
@@ -491,34 +613,32 @@ __global__ __launch_bounds__(kMaxWaves * 64) void k_bpe_wave(WaveArgs a) {
                     prk[p] = (uint16_t)rk_r;
                     prk[q] = kNoRank;
                     atomicAnd(&alive[q >> 5], ~(1u << (q & 31)));
-                    atomicOr(&dirty[(p >> 6) >> 5], 1u << ((p >> 6) & 31));
-                    atomicOr(&dirty[(q >> 6) >> 5], 1u << ((q >> 6) & 31));
+                    // p's block is a visited block; q's and l's may be neighbours
+                    if ((q >> 6) != (p >> 6)) atomicOr(&dirty[(q >> 6) >> 5], 1u << ((q >> 6) & 31));
                     if (left) {
                         prk[l] = (uint16_t)rk_l;
-                        atomicOr(&dirty[(l >> 6) >> 5], 1u << ((l >> 6) & 31));
+                        if ((l >> 6) != (p >> 6)) atomicOr(&dirty[(l >> 6) >> 5], 1u << ((l >> 6) & 31));
                     }
                 }
                 wave_sync();
                 base += m;
             }
-            // refresh the minima of changed blocks
-            bool touched = false;
-            for (uint32_t k = 0; k < k2; ++k) {
-                const uint32_t b = lane * k2 + k;
-                if (b < nb && ((dirty[b >> 5] >> (b & 31)) & 1u)) {
-                    bmin[b] = (uint16_t)block_min(prk, b);
-                    touched = true;
-                }
+            // refresh the minima of this lane's changed blocks
+            {
+                const uint32_t w0 = b0 >> 5;
+                const uint64_t dw = b0 < nb ? ((uint64_t)dirty[w0] | ((uint64_t)dirty[w0 + 1] << 32)) : 0ull;
+                own_dirty |= (uint32_t)(dw >> (b0 & 31)) & ((k2 >= 32) ? ~0u : ((1u << k2) - 1u));
+            }
+            if (own_dirty) {
+#pragma unroll
+                for (int k = 0; k < kK2Max; ++k)
+                    if ((own_dirty >> k) & 1u) bm[k] = block_min(prk, b0 + k);
+                l2 = kNoRank;
+#pragma unroll
+                for (int k = 0; k < kK2Max; ++k) l2 = min(l2, bm[k]);
             }
             wave_sync();
-            for (uint32_t w = lane; w < (nb + 31) / 32; w += 64) dirty[w] = 0;
-            if (touched) {
-                l2 = kNoRank;
-                for (uint32_t k = 0; k < k2; ++k) {
-                    const uint32_t b = lane * k2 + k;
-                    if (b < nb) l2 = min(l2, (uint32_t)bmin[b]);
-                }
-            }
+            for (uint32_t w = lane; w < ndw; w += 64) dirty[w] = 0;
             wave_sync();
         }
 
@@ -725,9 +845,9 @@ struct BlockArgs {
     uint16_t *symA;  // [nbytes]: final symbols of every item at its start
     uint16_t *symB;  // [nbytes]: second buffer
     int32_t *item_cnt;
-    const uint16_t *slot;
+    const uint32_t *bucket;
     const uint32_t *pair;
-    uint32_t slots;
+    uint32_t nbk;
     int32_t R;
     int32_t lo;  // this launch takes items longer than lo
     uint32_t *hdr;
@@ -740,8 +860,8 @@ __global__ __launch_bounds__(NTM) void k_bpe_block(BlockArgs a) {
     __shared__ int32_t s_rstar;
     __shared__ int64_t s_ticket;
     RankTab tab;
-    load_table(dyn, a.slot, a.pair, a.slots, a.R, &tab);
-    int32_t *hist = reinterpret_cast<int32_t *>(dyn + table_bytes(a.slots, a.R));
+    load_table(dyn, a.bucket, a.pair, a.nbk, a.R, &tab);
+    int32_t *hist = reinterpret_cast<int32_t *>(dyn + table_bytes(a.nbk, a.R));
     const int tid = threadIdx.x;
     const int64_t total = min(*a.n_items_at, a.max_items);
     __syncthreads();
@@ -1033,7 +1153,7 @@ int launch_bpe_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nby
     DNATOK_HIP(hipGetLastError());
 
     // 3. wave classes
-    const uint32_t tab = table_bytes(bt.slots, R);
+    const uint32_t tab = table_bytes(bt.nbk, R);
     BpeClass cls[4];
     const int ncls = bpe_wave_classes(tab, max_waves, cls, 4);
     int32_t covered = 0;
@@ -1046,9 +1166,9 @@ int launch_bpe_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nby
         w.max_items = max_items;
         w.tok = symA;
         w.item_cnt = item_cnt;
-        w.slot = bt.d_slot;
+        w.bucket = bt.d_bucket;
         w.pair = bt.d_pair;
-        w.slots = bt.slots;
+        w.nbk = bt.nbk;
         w.R = R;
         w.lo = cls[c].lo;
         w.hi = cls[c].hi;
@@ -1075,9 +1195,9 @@ int launch_bpe_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nby
         b.symA = symA;
         b.symB = symB;
         b.item_cnt = item_cnt;
-        b.slot = bt.d_slot;
+        b.bucket = bt.d_bucket;
         b.pair = bt.d_pair;
-        b.slots = bt.slots;
+        b.nbk = bt.nbk;
         b.R = R;
         b.lo = covered;
         b.hdr = ws->d_hdr;

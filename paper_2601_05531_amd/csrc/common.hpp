@@ -29,16 +29,33 @@ void clear_error();
 
 // ---- vocabulary ----------------------------------------------------------------
 
-// Pair -> rank lookup shared by the host (table build) and the device: open
-// addressing with linear probing over a power-of-two table of 16-bit ranks
-// (0xFFFF = empty); a hit is confirmed against the packed merge pair
-// left | right << 16 of that rank.
-__host__ __device__ inline uint32_t bpe_pair_hash(uint32_t a, uint32_t b) {
-    uint32_t h = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u) * 0x85EBCA77u;
+// Pair -> rank lookup shared by the host (table build) and the device: a
+// two-choice cuckoo table of 16-byte buckets, each holding two entries
+// (key, rank) with key = left | right << 16 (never 0: left >= 5). A pair is
+// in one of its two buckets, so a lookup is two independent 16-byte reads.
+__host__ __device__ inline uint32_t bpe_hash1(uint32_t key) {
+    uint32_t h = key * 0x9E3779B1u;
     h ^= h >> 15;
-    h *= 0x2C1B3C6Du;
+    h *= 0x85EBCA77u;
     h ^= h >> 13;
     return h;
+}
+__host__ __device__ inline uint32_t bpe_hash2(uint32_t key) {
+    uint32_t h = (key ^ 0x5BD1E995u) * 0xC2B2AE35u;
+    h ^= h >> 16;
+    h *= 0x27D4EB2Fu;
+    h ^= h >> 15;
+    return h;
+}
+// Bucket of hash h among nbk buckets, and the two buckets of a key.
+__host__ __device__ inline uint32_t bpe_bucket(uint32_t h, uint32_t nbk) {
+    return (uint32_t)(((uint64_t)h * nbk) >> 32);
+}
+__host__ __device__ inline void bpe_buckets(uint32_t key, uint32_t nbk, uint32_t *b1, uint32_t *b2) {
+    *b1 = bpe_bucket(bpe_hash1(key), nbk);
+    uint32_t c = bpe_bucket(bpe_hash2(key), nbk);
+    if (c == *b1) c = (*b1 + 1 == nbk) ? 0 : *b1 + 1;
+    *b2 = c;
 }
 
 constexpr int32_t kBpeMaxMerges = 8192;  // ranks and ids fit 16 bits; tables live in LDS
@@ -46,8 +63,8 @@ constexpr uint16_t kNoRank = 0xFFFF;
 
 struct BpeTables {
     int32_t n_merges = 0;
-    uint32_t slots = 0;             // power of two >= 2 * n_merges
-    uint16_t *d_slot = nullptr;     // [slots] rank or kNoRank
+    uint32_t nbk = 0;               // cuckoo buckets
+    uint32_t *d_bucket = nullptr;   // [nbk][4]: key0, rank0, key1, rank1 (key 0 = empty)
     uint32_t *d_pair = nullptr;     // [R] left | right << 16
     int32_t *d_tok_len = nullptr;   // decoded length per id, [vocab]
     int64_t *d_tok_off = nullptr;   // offset of each id's bases in d_tok_chars, [vocab]
@@ -119,6 +136,14 @@ constexpr int32_t kBpeItemBytesMin = 1024;
 int launch_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets,
                   int32_t n, int32_t *d_ids, int64_t cap, int64_t *d_out_offsets, int8_t *d_mask,
                   const dnatok_encode_opts &o, hipStream_t stream);
+
+// One pass over the input writing the same batch for several vocabularies of
+// one kind (SINGLE/LUT256: one; KMER: up to 8, any k), options alike but for
+// pad_to and offset_base.
+int launch_encode_multi(const dnatok_vocab *const *vs, int nv, const uint8_t *d_bytes, int64_t nbytes,
+                        const int64_t *d_offsets, int32_t n, int32_t *const *d_ids, const int64_t *caps,
+                        int64_t *const *d_out_offsets, int8_t *const *d_masks, const dnatok_encode_opts *os,
+                        hipStream_t stream);
 
 // out[i] = sum over rows r < i of ceil(L_r / divisor) + 2 * cls (out[n] = total).
 int launch_rowscan(const int64_t *d_offsets, int32_t n, int64_t nbytes, int64_t *d_out, int32_t divisor, int32_t cls,

@@ -41,6 +41,7 @@ constexpr int NT = 256;
 constexpr int kRowsPerThread = 16;                   // row scan: rows per thread per pass
 constexpr int64_t kUnitRows = (int64_t)NT * kRowsPerThread;
 constexpr int32_t kFuseMaxRows = 16384;              // PADDED: fold the row scan into the cell launch
+constexpr int kMaxMultiVocabs = 8;                    // vocabularies one cell launch can write
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 
@@ -234,29 +235,37 @@ __global__ __launch_bounds__(NT) void k_rowscan(RowScanArgs a) {
 
 // ---- cell kernel -------------------------------------------------------------------
 
+// One vocabulary's output of a cell launch (several k-mer vocabularies can
+// share one pass over the input).
+struct VocabOut {
+    int32_t k;
+    int32_t al;               // element misalignment of ids within 16 bytes
+    int32_t *ids;
+    int64_t cap;
+    const int64_t *out_offs;  // PACKED: row starts (written by the row scan)
+    int8_t *mask;
+    const int32_t *lut;
+    int32_t pad_id, cls_id, sep_id;
+    int64_t W;
+    int64_t base;
+};
+
 struct CellArgs {
     const uint8_t *abase;  // input base aligned down to 16 bytes
     int64_t shift;         // d_bytes - abase
     int64_t nbytes;
     const int64_t *offs;
     int32_t n;
-    int32_t k;
-    int32_t *ids;
-    int64_t cap;
-    const int64_t *out_offs;  // PACKED: row starts (written by the row scan)
-    int8_t *mask;
-    const int32_t *lut;
+    int32_t nv;            // vocabularies written by this launch
     int32_t cls;
     int32_t padded;
     int32_t left;
-    int32_t pad_id, cls_id, sep_id;
-    int64_t W;
-    int64_t base;
     int64_t tileB;
     int64_t ntiles;
-    int32_t fused_scan;  // the last block runs the row scan instead of tiles
+    int32_t fused_scan;  // the last block runs the row scans instead of tiles
     uint32_t *err_hdr;
-    RowScanArgs scan;
+    VocabOut vo[kMaxMultiVocabs];
+    RowScanArgs scan[kMaxMultiVocabs];
 };
 
 // Per-row facts a tile needs for its owned cells (row chunk of up to NT rows).
@@ -318,25 +327,26 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
 
     const int tid = threadIdx.x;
     if (a.fused_scan && blockIdx.x == gridDim.x - 1) {
-        rowscan_single_block(a.scan, s_tmp, a.err_hdr);
+        for (int vi = 0; vi < a.nv; ++vi) {
+            rowscan_single_block(a.scan[vi], s_tmp, a.err_hdr);
+            __syncthreads();
+        }
         return;
     }
     const int64_t G = gridDim.x - (a.fused_scan ? 1 : 0);
     if (!KMER)
-        for (int i = tid; i < 256; i += NT) lut_s[i] = a.lut[i];
+        for (int i = tid; i < 256; i += NT) lut_s[i] = a.vo[0].lut[i];
     if (tid == 0) s_err = 0;
     const int64_t B = a.tileB;  // == U * NT * 16
     constexpr int64_t nchunks = (int64_t)U * NT + 1;
     uint64_t *win64 = reinterpret_cast<uint64_t *>(dyn);                 // KMER: nchunks
     uint32_t *val32 = reinterpret_cast<uint32_t *>(win64 + nchunks);     // KMER: nchunks
     uint8_t *raw = dyn;
-    const int32_t k = KMER ? a.k : 1;
-    const int64_t al = (int64_t)((reinterpret_cast<uintptr_t>(a.ids) >> 2) & 3);
     const int64_t off_first = (a.n > 0) ? a.offs[0] : 0;
     const int64_t off_last = (a.n > 0) ? a.offs[a.n] : 0;
     uint32_t err = 0;
 
-    auto load_row = [&](int64_t i) {
+    auto load_row = [&](int64_t i, int32_t k) {
         Row r;
         int64_t o0 = a.offs[i], o1 = a.offs[i + 1];
         o0 = o0 < 0 ? 0 : (o0 > a.nbytes ? a.nbytes : o0);
@@ -425,20 +435,24 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
         __syncthreads();
         const int64_t ia = s_ia, ib = s_ib;
 
-        // Write pass, one chunk of up to NT rows at a time.
+        // Write pass per vocabulary, one chunk of up to NT rows at a time.
+        for (int vi = 0; vi < a.nv; ++vi) {
+        const VocabOut &o = a.vo[vi];
+        const int32_t k = KMER ? o.k : 1;
+        const int64_t al = o.al;
         for (int64_t cb = ia; cb < ib; cb += NT) {
             const int64_t i = cb + tid;
             const int nrows = (int)((ib - cb) < NT ? (ib - cb) : NT);
             int64_t gcnt = 0;
             if (i < ib) {
-                const Row r = load_row(i);
+                const Row r = load_row(i, k);
                 int64_t clo = 0, chi = 0;
-                if (!(a.padded && r.len > a.W)) {
-                    clo = cells_before(r, P0, k, a.cls, a.padded, a.left, a.W);
-                    chi = cells_before(r, P1, k, a.cls, a.padded, a.left, a.W);
+                if (!(a.padded && r.len > o.W)) {
+                    clo = cells_before(r, P0, k, a.cls, a.padded, a.left, o.W);
+                    chi = cells_before(r, P1, k, a.cls, a.padded, a.left, o.W);
                 }
                 const int64_t ncell = chi - clo;
-                const int64_t lead = (a.padded && a.left) ? a.W - r.len : 0;
+                const int64_t lead = (a.padded && a.left) ? o.W - r.len : 0;
                 const int64_t tt0 = clo - lead;  // token index of the first owned cell
                 SegInfo sg;
                 sg.ncell = (int32_t)ncell;
@@ -448,7 +462,7 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
                 sg.cc_sep = a.cls ? clamp_rel(r.len - 1 - tt0, ncell) : -1;
                 sg.cc_tail = (KMER && r.nb > 0 && (r.end - r.off) % k) ? clamp_rel(a.cls + r.nb - 1 - tt0, ncell) : -1;
                 sg.base_idx = (r.off - P0) + (tt0 - a.cls) * k;
-                sg.dlo = a.padded ? i * a.W + clo : (a.out_offs[i] - a.base) + clo;
+                sg.dlo = a.padded ? i * o.W + clo : (o.out_offs[i] - o.base) + clo;
                 sg.gpre = 0;
                 seg[tid] = sg;
                 if (ncell > 0) gcnt = ((sg.dlo + al + ncell - 1) >> 2) - ((sg.dlo + al) >> 2) + 1;
@@ -483,10 +497,10 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
                 }
                 const int64_t eb = (gb + qi) * 4 - al;
                 const int32_t cc0 = ccb + 4 * (int32_t)(qi - seg_lo);
-                int32_t *dst = a.ids + eb;
+                int32_t *dst = o.ids + eb;
                 // Fast path: four body tokens, none of them a short final frame.
                 const bool fast = cc0 >= sg.b0 && cc0 + 3 < sg.b1 && (uint32_t)(sg.cc_tail - cc0) > 3u &&
-                                  (a.padded || (eb >= 0 && eb + 3 < a.cap));
+                                  (a.padded || (eb >= 0 && eb + 3 < o.cap));
                 if (fast) {
                     const uint32_t idx0 = (uint32_t)sg.base_idx + (uint32_t)cc0 * (uint32_t)k;
                     int32_t vv[4];
@@ -499,7 +513,7 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
                     i32x4 x = {vv[0], vv[1], vv[2], vv[3]};
                     __builtin_nontemporal_store(x, reinterpret_cast<i32x4 *>(dst));
                     if (a.padded) {
-                        int8_t *md = a.mask + eb;
+                        int8_t *md = o.mask + eb;
                         if ((reinterpret_cast<uintptr_t>(md) & 3) == 0)
                             __builtin_nontemporal_store(0x01010101u, reinterpret_cast<uint32_t *>(md));
                         else
@@ -515,12 +529,12 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
                 for (int rr = 0; rr < 4; ++rr) {
                     const int32_t cc = cc0 + rr;
                     in[rr] = (cc >= 0 && cc < sg.ncell);
-                    if (in[rr] && !a.padded && (eb + rr < 0 || eb + rr >= a.cap)) {
+                    if (in[rr] && !a.padded && (eb + rr < 0 || eb + rr >= o.cap)) {
                         in[rr] = false;
                         err |= DNATOK_DERR_CAPACITY;
                     }
                     all_in = all_in && in[rr];
-                    int32_t val = a.pad_id;
+                    int32_t val = o.pad_id;
                     uint32_t m = 0;
                     if (in[rr]) {
                         if (cc >= sg.b0 && cc < sg.b1) {
@@ -529,10 +543,10 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
                             if (KMER) val = (cc == sg.cc_tail) ? DNATOK_ID_UNK : kmer_at(win64, val32, idx, k);
                             else val = lut_s[raw[idx]];
                         } else if (cc == sg.cc_cls) {
-                            val = a.cls_id;
+                            val = o.cls_id;
                             m = 1;
                         } else if (cc == sg.cc_sep) {
-                            val = a.sep_id;
+                            val = o.sep_id;
                             m = 1;
                         }
                     }
@@ -542,7 +556,7 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
                 if (all_in) {
                     *reinterpret_cast<int4 *>(dst) = make_int4(vv[0], vv[1], vv[2], vv[3]);
                     if (a.padded) {
-                        int8_t *md = a.mask + eb;
+                        int8_t *md = o.mask + eb;
                         if ((reinterpret_cast<uintptr_t>(md) & 3) == 0) {
                             *reinterpret_cast<uint32_t *>(md) = mk;
                         } else {
@@ -555,11 +569,12 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
                     for (int rr = 0; rr < 4; ++rr) {
                         if (!in[rr]) continue;
                         dst[rr] = vv[rr];
-                        if (a.padded) a.mask[eb + rr] = (int8_t)((mk >> (8 * rr)) & 1);
+                        if (a.padded) o.mask[eb + rr] = (int8_t)((mk >> (8 * rr)) & 1);
                     }
                 }
             }
             __syncthreads();
+        }
         }
     }
     if (err) atomicOr(&s_err, err);
@@ -638,9 +653,13 @@ EncodeTuning encode_tuning(const dnatok_vocab *v) {
     return t;
 }
 
-int launch_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets,
-                  int32_t n, int32_t *d_ids, int64_t cap, int64_t *d_out_offsets, int8_t *d_mask,
-                  const dnatok_encode_opts &o, hipStream_t stream) {
+int launch_encode_multi(const dnatok_vocab *const *vs, int nv, const uint8_t *d_bytes, int64_t nbytes,
+                        const int64_t *d_offsets, int32_t n, int32_t *const *d_ids, const int64_t *caps,
+                        int64_t *const *d_out_offsets, int8_t *const *d_masks, const dnatok_encode_opts *os,
+                        hipStream_t stream) {
+    if (nv < 1 || nv > kMaxMultiVocabs) return set_error(DNATOK_EINVAL, "1 to %d vocabularies", kMaxMultiVocabs);
+    const dnatok_vocab *v = vs[0];
+    const dnatok_encode_opts &o = os[0];
     const bool kmer = (v->kind == DNATOK_KMER);
     const EncodeTuning tune = encode_tuning(v);
     int U = 1;  // staging loads per thread: tiles are U * NT * 16 bytes
@@ -655,56 +674,62 @@ int launch_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes,
     a.nbytes = nbytes;
     a.offs = d_offsets;
     a.n = n;
-    a.k = kmer ? v->k : 1;
-    a.ids = d_ids;
-    a.cap = cap;
-    a.out_offs = d_out_offsets;
-    a.mask = d_mask;
-    a.lut = v->d_lut;
+    a.nv = nv;
     a.cls = o.add_cls_sep ? 1 : 0;
     a.padded = (o.layout == DNATOK_PADDED) ? 1 : 0;
     a.left = (o.pad_side == DNATOK_PAD_LEFT) ? 1 : 0;
-    a.pad_id = v->pad_id;
-    a.cls_id = v->cls_id;
-    a.sep_id = v->sep_id;
-    a.W = a.padded ? o.pad_to : 0;
-    a.base = o.offset_base;
     a.tileB = B;
     // the last tile also owns the end position (anchors of trailing empty rows)
     a.ntiles = (nbytes + a.shift + B - 1) / B;
     if (a.ntiles < 1) a.ntiles = 1;
-
-    RowScanArgs &s = a.scan;
-    s.offs = d_offsets;
-    s.n = n;
-    s.nbytes = nbytes;
-    s.out_offs = d_out_offsets;
-    s.k = a.k;
-    s.kmer = kmer ? 1 : 0;
-    s.cls = a.cls;
-    s.padded = a.padded;
-    s.W = a.W;
-    s.base = a.base;
-    s.nunits = ((int64_t)n + kUnitRows - 1) / kUnitRows;
-    if (s.nunits < 1) s.nunits = 1;
+    const int64_t nunits = std::max<int64_t>(1, ((int64_t)n + kUnitRows - 1) / kUnitRows);
 
     Workspace *ws = nullptr;
-    int rc = get_workspace(stream, s.nunits, &ws);
+    int rc = get_workspace(stream, nunits, &ws);
     if (rc) return rc;
     a.err_hdr = ws->d_hdr;
     a.fused_scan = (a.padded && n <= kFuseMaxRows) ? 1 : 0;
-    if (!a.fused_scan) {
-        s.q.hdr = ws->d_hdr;
-        s.q.status0 = ws->d_status;
-        s.q.status1 = ws->d_status + ws->cap;
-        if (s.nunits > ws->high_water) ws->high_water = s.nunits;
-        s.q.clear_n = ws->high_water;
-        int per_cu = 0;
-        DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rowscan, NT, 0));
-        int64_t g = (int64_t)device_cu_count() * (per_cu > 0 ? per_cu : 1);
-        if (g > s.nunits) g = s.nunits;
-        hipLaunchKernelGGL(k_rowscan, dim3((unsigned)g), dim3(NT), 0, stream, s);
-        DNATOK_HIP(hipGetLastError());
+    for (int vi = 0; vi < nv; ++vi) {
+        const dnatok_vocab *w = vs[vi];
+        VocabOut &out = a.vo[vi];
+        out.k = kmer ? w->k : 1;
+        out.al = (int32_t)((reinterpret_cast<uintptr_t>(d_ids[vi]) >> 2) & 3);
+        out.ids = d_ids[vi];
+        out.cap = caps[vi];
+        out.out_offs = d_out_offsets[vi];
+        out.mask = d_masks[vi];
+        out.lut = w->d_lut;
+        out.pad_id = w->pad_id;
+        out.cls_id = w->cls_id;
+        out.sep_id = w->sep_id;
+        out.W = a.padded ? os[vi].pad_to : 0;
+        out.base = os[vi].offset_base;
+
+        RowScanArgs &sc = a.scan[vi];
+        sc.offs = d_offsets;
+        sc.n = n;
+        sc.nbytes = nbytes;
+        sc.out_offs = d_out_offsets[vi];
+        sc.k = out.k;
+        sc.kmer = kmer ? 1 : 0;
+        sc.cls = a.cls;
+        sc.padded = a.padded;
+        sc.W = out.W;
+        sc.base = out.base;
+        sc.nunits = nunits;
+        if (!a.fused_scan) {
+            sc.q.hdr = ws->d_hdr;
+            sc.q.status0 = ws->d_status;
+            sc.q.status1 = ws->d_status + ws->cap;
+            if (sc.nunits > ws->high_water) ws->high_water = sc.nunits;
+            sc.q.clear_n = ws->high_water;
+            int per_cu = 0;
+            DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rowscan, NT, 0));
+            int64_t g = (int64_t)device_cu_count() * (per_cu > 0 ? per_cu : 1);
+            if (g > sc.nunits) g = sc.nunits;
+            hipLaunchKernelGGL(k_rowscan, dim3((unsigned)g), dim3(NT), 0, stream, sc);
+            DNATOK_HIP(hipGetLastError());
+        }
     }
 
     const size_t dyn = kmer ? (size_t)nchunks * 12 : (size_t)nchunks * 16;
@@ -720,6 +745,13 @@ int launch_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes,
     int64_t grid = (a.ntiles + per_block - 1) / per_block;
     if (a.fused_scan) grid += 1;
     return kmer ? launch_cells<true>(a, U, grid, dyn, stream) : launch_cells<false>(a, U, grid, dyn, stream);
+}
+
+int launch_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets,
+                  int32_t n, int32_t *d_ids, int64_t cap, int64_t *d_out_offsets, int8_t *d_mask,
+                  const dnatok_encode_opts &o, hipStream_t stream) {
+    return launch_encode_multi(&v, 1, d_bytes, nbytes, d_offsets, n, &d_ids, &cap, &d_out_offsets, &d_mask, &o,
+                               stream);
 }
 
 }  // namespace dnatok

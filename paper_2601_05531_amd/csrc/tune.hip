@@ -68,13 +68,16 @@ int dnatok_set_tuning(dnatok_vocab *v, const dnatok_tuning *t) {
     return DNATOK_OK;
 }
 
-int dnatok_autotune(dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets, int32_t n,
-                    int32_t *d_ids, int64_t ids_capacity, int64_t *d_out_offsets, int8_t *d_mask,
-                    const dnatok_encode_opts *opts, void *stream, int32_t reps, dnatok_tuning *best,
-                    float *best_ms) {
+}  // extern "C"
+
+namespace {
+
+// Times every candidate tiling of v with `run` (one encode on `st`): one
+// warm-up and `reps` timed launches each, median; keeps the fastest in v.
+template <class Run>
+int autotune_loop(dnatok_vocab *v, hipStream_t st, int32_t reps, Run run, dnatok_tuning *best, float *best_ms) {
     if (!v) return set_error(DNATOK_EINVAL, "null vocabulary");
     if (reps < 1 || reps > 100) return set_error(DNATOK_EINVAL, "reps must be 1..100");
-    hipStream_t st = static_cast<hipStream_t>(stream);
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
         return set_error(DNATOK_ESTATE, "autotune cannot run during graph capture");
@@ -98,9 +101,7 @@ int dnatok_autotune(dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, con
         std::vector<float> ts;
         for (int r = 0; r <= reps && rc == DNATOK_OK; ++r) {
             if (hipEventRecord(e0, st) != hipSuccess) rc = set_error(DNATOK_EDEVICE, "hipEventRecord failed");
-            if (rc == DNATOK_OK)
-                rc = dnatok_encode(v, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets, d_mask,
-                                   opts, stream);
+            if (rc == DNATOK_OK) rc = run();
             if (rc == DNATOK_OK && hipEventRecord(e1, st) != hipSuccess)
                 rc = set_error(DNATOK_EDEVICE, "hipEventRecord failed");
             if (rc == DNATOK_OK && hipEventSynchronize(e1) != hipSuccess)
@@ -130,10 +131,34 @@ int dnatok_autotune(dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, con
     return DNATOK_OK;
 }
 
-int dnatok_graph_create(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets,
-                        int32_t n, int32_t *d_ids, int64_t ids_capacity, int64_t *d_out_offsets, int8_t *d_mask,
-                        const dnatok_encode_opts *opts, dnatok_graph **out) {
-    if (!out) return set_error(DNATOK_EINVAL, "null output handle");
+}  // namespace
+
+extern "C" {
+
+int dnatok_autotune(dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets, int32_t n,
+                    int32_t *d_ids, int64_t ids_capacity, int64_t *d_out_offsets, int8_t *d_mask,
+                    const dnatok_encode_opts *opts, void *stream, int32_t reps, dnatok_tuning *best,
+                    float *best_ms) {
+    return autotune_loop(v, static_cast<hipStream_t>(stream), reps, [&] {
+        return dnatok_encode(v, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets, d_mask, opts,
+                             stream);
+    }, best, best_ms);
+}
+
+int dnatok_autotune_multi(dnatok_vocab *const *vocabs, int32_t n_vocabs, const uint8_t *d_bytes, int64_t nbytes,
+                          const int64_t *d_offsets, int32_t n, int32_t *const *d_ids, const int64_t *ids_capacity,
+                          int64_t *const *d_out_offsets, int8_t *const *d_mask, const dnatok_encode_opts *opts,
+                          void *stream, int32_t reps, dnatok_tuning *best, float *best_ms) {
+    if (!vocabs || n_vocabs < 1) return set_error(DNATOK_EINVAL, "no vocabularies");
+    return autotune_loop(vocabs[0], static_cast<hipStream_t>(stream), reps, [&] {
+        return dnatok_encode_multi(vocabs, n_vocabs, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity,
+                                   d_out_offsets, d_mask, opts, stream);
+    }, best, best_ms);
+}
+
+int dnatok_graph_create(const dnatok_encode_call *calls, int32_t n_calls, dnatok_graph **out) {
+    if (!out || (!calls && n_calls > 0)) return set_error(DNATOK_EINVAL, "null argument");
+    if (n_calls < 1 || n_calls > 1024) return set_error(DNATOK_EINVAL, "n_calls must be 1..1024");
     *out = nullptr;
     auto g = new dnatok_graph();
     auto fail = [&](int rc) {
@@ -147,18 +172,23 @@ int dnatok_graph_create(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t n
         delete g;
         return rc;
     };
+    auto run = [&](const dnatok_encode_call &c) {
+        return dnatok_encode(c.v, c.d_bytes, c.nbytes, c.d_offsets, c.n, c.d_ids, c.ids_capacity, c.d_out_offsets,
+                             c.d_mask, &c.opts, g->stream);
+    };
     if (hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking) != hipSuccess)
         return fail(set_error(DNATOK_EDEVICE, "hipStreamCreateWithFlags failed"));
-    // eager run: validates the call and sizes the workspace the graph will use
-    int rc = dnatok_encode(v, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets, d_mask, opts,
-                           g->stream);
-    if (rc) return fail(rc);
+    // eager run: validates the calls and sizes the workspace the graph will use
+    for (int32_t i = 0; i < n_calls; ++i) {
+        const int rc = run(calls[i]);
+        if (rc) return fail(rc);
+    }
     if (hipStreamSynchronize(g->stream) != hipSuccess)
         return fail(set_error(DNATOK_EDEVICE, "hipStreamSynchronize failed"));
     if (hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return fail(set_error(DNATOK_EDEVICE, "hipStreamBeginCapture failed"));
-    rc = dnatok_encode(v, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets, d_mask, opts,
-                       g->stream);
+    int rc = DNATOK_OK;
+    for (int32_t i = 0; i < n_calls && rc == DNATOK_OK; ++i) rc = run(calls[i]);
     hipGraph_t graph = nullptr;
     const hipError_t ec = hipStreamEndCapture(g->stream, &graph);
     g->graph = graph;

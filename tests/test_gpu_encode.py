@@ -298,3 +298,61 @@ def test_encode_decode_roundtrip_acgt():
         torch.cuda.synchronize()
         assert np.array_equal(dec_off.cpu().numpy(), offs)
         assert np.array_equal(out.cpu().numpy()[:offs[-1]], data)
+
+
+# ---------------------------------------------------------------- several k-mer vocabularies in one pass
+
+def _check_multi(vs, ks, data, offs, cls, layout, side):
+    torch = _torch()
+    print("multi ks=%s n=%d layout=%d side=%d cls=%d" % (ks, len(offs) - 1, layout, side, cls), flush=True)
+    res = dt.encode_multi(vs, _dev(data), _dev(offs), h_offsets=offs, add_cls_sep=cls, layout=layout, pad_side=side)
+    torch.cuda.synchronize()
+    assert dt.sync_status() == 0
+    for k, (ids, oo, mask) in zip(ks, res):
+        want_ids, want_off = _oracle(dt.KMER, data, offs, k, cls=cls)
+        assert np.array_equal(oo.cpu().numpy(), want_off), k
+        if layout == dt.PADDED:
+            W = ids.shape[1]
+            w_ids, w_mask = oracle.pad(want_ids, want_off, W, side, 0)
+            assert np.array_equal(ids.cpu().numpy(), w_ids), k
+            assert np.array_equal(mask.cpu().numpy(), w_mask), k
+        else:
+            assert np.array_equal(ids.cpu().numpy(), want_ids), k
+
+
+def test_multi_vocab_fuzz_all_layouts():
+    data, offs = _fuzz_batch(501, 2500, 130)
+    ks = [1, 2, 3, 4, 5, 6, 7, 8]
+    vs = [_vocab(dt.KMER, k) for k in ks]
+    _check_multi(vs, ks, data, offs, True, dt.PACKED, dt.PAD_RIGHT)
+    _check_multi(vs, ks, data, offs, True, dt.PADDED, dt.PAD_RIGHT)
+    _check_multi(vs, ks, data, offs, False, dt.PADDED, dt.PAD_LEFT)
+
+
+def test_multi_vocab_markov_full_size(markov_batch):
+    data, offs = markov_batch
+    ks = [3, 4, 5, 6]
+    _check_multi([_vocab(dt.KMER, k) for k in ks], ks, data, offs, True, dt.PADDED, dt.PAD_RIGHT)
+
+
+def test_multi_vocab_many_rows_unfused_scan():
+    # more rows than the PADDED launch folds its row scans into
+    data, offs = _fuzz_batch(502, 20000, 40)
+    ks = [3, 6]
+    _check_multi([_vocab(dt.KMER, k) for k in ks], ks, data, offs, True, dt.PADDED, dt.PAD_RIGHT)
+
+
+def test_multi_vocab_errors():
+    torch = _torch()
+    data, offs = _fuzz_batch(503, 10, 50)
+    bpe = dt.Vocab(dt.BPE, merges=np.zeros((0, 2), np.int32))
+    with pytest.raises(dt.DnatokError) as e:
+        dt.encode_multi([_vocab(dt.KMER, 3), bpe], _dev(data), _dev(offs), h_offsets=offs)
+    assert e.value.code == dt.EVOCAB
+    vs = [_vocab(dt.KMER, 3), _vocab(dt.KMER, 4)]
+    outs = [(torch.empty(1000, dtype=torch.int32, device="cuda"), torch.empty(11, dtype=torch.int64, device="cuda"),
+             None) for _ in vs]
+    opts = [dt.make_opts(True), dt.make_opts(False)]
+    with pytest.raises(dt.DnatokError) as e:
+        dt.MultiCall(vs, _dev(data), _dev(offs), outs, opts).run()
+    assert e.value.code == dt.EINVAL

@@ -104,8 +104,8 @@ def test_graph_replays_follow_buffer_contents(kind):
     ids = torch.zeros(cap, dtype=torch.int32, device="cuda")
     oo = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
     mask = torch.zeros(cap, dtype=torch.int8, device="cuda") if padded else None
-    g = dt.Graph(v, d_in, d_off, ids, oo, mask, add_cls_sep=True, layout=dt.PADDED if padded else dt.PACKED,
-                 pad_to=W if padded else 0)
+    g = dt.Graph([dict(vocab=v, d_bytes=d_in, d_offsets=d_off, d_ids=ids, d_out_offsets=oo, d_mask=mask,
+                       add_cls_sep=True, layout=dt.PADDED if padded else dt.PACKED, pad_to=W if padded else 0)])
     other = _dev(datas[2][:L * 8])
     other_off = _dev(synth.offsets_from_lengths([L] * 8))
     for rep in range(5):
@@ -124,4 +124,30 @@ def test_graph_replays_follow_buffer_contents(kind):
             assert np.array_equal(mask.cpu().numpy(), w_mask.reshape(-1))
         else:
             assert np.array_equal(ids.cpu().numpy()[:len(want_ids)], want_ids)
+    g.close()
+
+
+def test_one_graph_of_several_encodes():
+    torch = _torch()
+    data, offs = synth.workload_iid()
+    n = len(offs) - 1
+    d_in, d_off = _dev(data), _dev(offs)
+    calls, wants = [], []
+    for kind, k in ((dt.SINGLE, 1), (dt.KMER, 6), (dt.KMER, 3)):
+        v = dt.Vocab(kind, k=k)
+        want_ids, want_off = oracle.encode(kind, data, offs, k=k)
+        wants.append((want_ids, want_off))
+        calls.append(dict(vocab=v, d_bytes=d_in, d_offsets=d_off,
+                          d_ids=torch.zeros(len(want_ids), dtype=torch.int32, device="cuda"),
+                          d_out_offsets=torch.zeros(n + 1, dtype=torch.int64, device="cuda")))
+    g = dt.Graph(calls)
+    for rep in range(3):
+        for c in calls:
+            c["d_ids"].zero_()
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        for c, (want_ids, want_off) in zip(calls, wants):
+            assert np.array_equal(c["d_ids"].cpu().numpy(), want_ids)
+            assert np.array_equal(c["d_out_offsets"].cpu().numpy(), want_off)
     g.close()
