@@ -42,7 +42,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def encode_leg(steps: int, warmup: int):
+def encode_leg(steps: int, warmup: int, tuning=None, per_vocab: bool = True):
     import torch
     import paper_2601_05531_amd as dt
     import synth
@@ -74,8 +74,13 @@ def encode_leg(steps: int, warmup: int):
     vlist = [vocabs[k] for k in KS]
     calls = [dt.MultiCall(vlist, d_in[s], d_offs, [outs[s % SETS][k] for k in KS], [opts[k] for k in KS])
              for s in range(IN_SETS)]
-    tune_multi, tune_ms = calls[0].autotune(reps=3)
-    log("autotuned (one pass, k=3..6): %s %.4f ms" % (tune_multi, tune_ms))
+    if tuning is None:
+        tune_multi, tune_ms = calls[0].autotune(reps=3)
+        log("autotuned (one pass, k=3..6): %s %.4f ms" % (tune_multi, tune_ms))
+    else:
+        dt.set_tuning(vocabs[KS[0]], tile_bytes=tuning[0], blocks_per_cu=tuning[1])
+        tune_multi = dt.dnatok_get_tuning(vocabs[KS[0]].handle).as_dict()
+        log("tiling set: %s" % tune_multi)
     for s in range(warmup):
         calls[s % IN_SETS].run(stream)
     torch.cuda.synchronize()
@@ -101,6 +106,33 @@ def encode_leg(steps: int, warmup: int):
     achieved = bytes_launch / (launch_ms * 1e-3) / 1e9
     for k in KS:  # oracle-free invariant on the last output set: sum(mask) == tokens
         assert int(outs[(steps - 1) % SETS][k][2].sum().item()) == plans[k][0]
+
+    res = {
+        "tokens_per_step": tokens_per_step,
+        "ms_per_step": elapsed / steps * 1e3,
+        "value": tokens_per_step * steps / elapsed,
+        "launch_ms": launch_ms,
+        "bytes_per_launch": bytes_launch,
+        "tuning": tune_multi,
+        "per_vocab": None,
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(),
+            "kernel": "k_cells<KMER> writing k = 3, 4, 5, 6 in one pass",
+            "per_launch_bytes": "1 B per input byte (read once) + 16 B per row of offsets + per vocabulary "
+                                "5 B per cell (4 B id + 1 B mask over n x pad_to) = %d B" % bytes_launch,
+        },
+        "data": data,
+        "offs": offs,
+    }
+    log("encode (one pass, k=3..6): %.3e tokens/s, %.4f ms/step (launch %.4f ms, %.0f GB/s)" % (
+        res["value"], res["ms_per_step"], launch_ms, achieved))
+    if not per_vocab:
+        return res
 
     # Reference: the same step as four single-vocabulary launches, each tiled
     # by the autotuner for its own k.
@@ -137,38 +169,41 @@ def encode_leg(steps: int, warmup: int):
                 for j, k in enumerate(KS)}
     bytes_k = {k: nbytes + 16 * (n + 1) + 5 * n * plans[k][1] for k in KS}
     achieved_k = sum(bytes_k.values()) / (sum(per_k_ms.values()) * 1e-3) / 1e9
-    res = {
-        "tokens_per_step": tokens_per_step,
-        "ms_per_step": elapsed / steps * 1e3,
-        "value": tokens_per_step * steps / elapsed,
-        "launch_ms": launch_ms,
-        "bytes_per_launch": bytes_launch,
-        "tuning": tune_multi,
-        "per_vocab": {
-            "value": tokens_per_step * steps / (u1 - u0),
-            "ms_per_step": (u1 - u0) / steps * 1e3,
-            "per_k_launch_ms": per_k_ms,
-            "autotuned": tuning,
-            "achieved_GBps": round(achieved_k, 1),
-        },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
-            "kernel": "k_cells<KMER> writing k = 3, 4, 5, 6 in one pass",
-            "per_launch_bytes": "1 B per input byte (read once) + 16 B per row of offsets + per vocabulary "
-                                "5 B per cell (4 B id + 1 B mask over n x pad_to) = %d B" % bytes_launch,
-        },
-        "data": data,
-        "offs": offs,
+    res["per_vocab"] = {
+        "value": tokens_per_step * steps / (u1 - u0),
+        "ms_per_step": (u1 - u0) / steps * 1e3,
+        "per_k_launch_ms": per_k_ms,
+        "autotuned": tuning,
+        "achieved_GBps": round(achieved_k, 1),
     }
-    log("encode (one pass, k=3..6): %.3e tokens/s, %.4f ms/step (launch %.4f ms, %.0f GB/s)" % (
-        res["value"], res["ms_per_step"], launch_ms, achieved))
     log("encode (four launches): %.3e tokens/s, per-launch ms %s" % (res["per_vocab"]["value"], per_k_ms))
     return res
+
+
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_cells_multi_k_batch_traffic.md")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the one-pass encode from the committed counter
+    summary (FETCH_SIZE / WRITE_SIZE calibrated by a copy of known size), or
+    None when the summary is missing or the kernel source changed since."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if ":" in line and line.startswith("    "):
+            key, val = line.strip().split(":", 1)
+            fields[key.strip()] = val.strip()
+    try:
+        src = os.path.join(ROOT, fields["kernel_source"])
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields["kernel_source_sha256"]:
+            return None
+        return int(fields["traffic_bytes_per_launch"])
+    except (KeyError, OSError, ValueError):
+        return None
 
 
 def copy_leg(sizes=(45 << 20, 1 << 30), reps: int = 20):
@@ -611,6 +646,9 @@ def main():
     ap.add_argument("--no-bpe", action="store_true", help="skip the ragged BPE batch leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace leg")
     ap.add_argument("--no-small", action="store_true", help="skip the small-batch eager/graph leg")
+    ap.add_argument("--no-per-vocab", action="store_true", help="skip the four single-vocabulary launches")
+    ap.add_argument("--tuning", type=str, default=None,
+                    help="TILE,BLOCKS: fixed tiling of the one-pass encode instead of the autotuner's")
     ap.add_argument("--serve-requests", type=int, default=SERVE_REQUESTS)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -625,7 +663,8 @@ def main():
     import paper_2601_05531_amd as dt
     dt.lib()
 
-    enc = encode_leg(args.steps, args.warmup)
+    tuning = tuple(int(x) for x in args.tuning.split(",")) if args.tuning else None
+    enc = encode_leg(args.steps, args.warmup, tuning=tuning, per_vocab=not args.no_per_vocab)
     copy = None
     if not args.no_copy:
         copy = copy_leg()
