@@ -42,6 +42,7 @@ constexpr int kRowsPerThread = 16;                   // row scan: rows per threa
 constexpr int64_t kUnitRows = (int64_t)NT * kRowsPerThread;
 constexpr int32_t kFuseMaxRows = 16384;              // PADDED: fold the row scan into the cell launch
 constexpr int kMaxMultiVocabs = 8;                    // vocabularies one cell launch can write
+constexpr int32_t kFusePackedRows = 2 * NT;            // PACKED, one vocabulary: every block scans the rows itself
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 
@@ -243,6 +244,7 @@ struct VocabOut {
     int32_t *ids;
     int64_t cap;
     const int64_t *out_offs;  // PACKED: row starts (written by the row scan)
+    int64_t *out_offs_w;      // the same array, written by a fused packed scan
     int8_t *mask;
     const int32_t *lut;
     int32_t pad_id, cls_id, sep_id;
@@ -263,6 +265,8 @@ struct CellArgs {
     int64_t tileB;
     int64_t ntiles;
     int32_t fused_scan;  // the last block runs the row scans instead of tiles
+    int32_t fused_packed;   // PACKED, <= kFusePackedRows rows: each block scans the row lengths into LDS
+    int32_t prefix_off;     // byte offset of that scan in the dynamic LDS
     uint32_t *err_hdr;
     VocabOut vo[kMaxMultiVocabs];
     RowScanArgs scan[kMaxMultiVocabs];
@@ -345,6 +349,44 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
     const int64_t off_first = (a.n > 0) ? a.offs[0] : 0;
     const int64_t off_last = (a.n > 0) ? a.offs[a.n] : 0;
     uint32_t err = 0;
+    int64_t *s_prefix = reinterpret_cast<int64_t *>(dyn + a.prefix_off);
+    if (a.fused_packed) {
+        // Small PACKED batch: every block forms the row starts itself (two
+        // rows per thread) instead of waiting for a separate row-scan launch;
+        // block 0 also publishes them as the output offsets.
+        const VocabOut &o = a.vo[0];
+        const int32_t kk = KMER ? o.k : 1;
+        int64_t len2[2];
+        int64_t mine = 0;
+        uint32_t e2 = 0;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int64_t i = 2 * (int64_t)tid + j;
+            len2[j] = 0;
+            if (i < a.n) {
+                int64_t o0 = a.offs[i], o1 = a.offs[i + 1];
+                if (o0 < 0 || o1 < o0 || o1 > a.nbytes) e2 |= DNATOK_DERR_OFFSETS;
+                o0 = o0 < 0 ? 0 : (o0 > a.nbytes ? a.nbytes : o0);
+                o1 = o1 < o0 ? o0 : (o1 > a.nbytes ? a.nbytes : o1);
+                len2[j] = body_tokens(o1 - o0, kk, KMER) + 2 * a.cls;
+            }
+            mine += len2[j];
+        }
+        int64_t total;
+        int64_t run = dev::block_excl_scan<NT>(mine, s_tmp, &total);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int64_t i = 2 * (int64_t)tid + j;
+            if (i < a.n) {
+                s_prefix[i] = run;
+                if (blockIdx.x == 0) o.out_offs_w[i] = o.base + run;
+            }
+            run += len2[j];
+        }
+        if (blockIdx.x == 0 && tid == 0) o.out_offs_w[a.n] = o.base + total;
+        if (blockIdx.x == 0) err |= e2;
+        __syncthreads();
+    }
 
     auto load_row = [&](int64_t i, int32_t k) {
         Row r;
@@ -462,7 +504,7 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
                 sg.cc_sep = a.cls ? clamp_rel(r.len - 1 - tt0, ncell) : -1;
                 sg.cc_tail = (KMER && r.nb > 0 && (r.end - r.off) % k) ? clamp_rel(a.cls + r.nb - 1 - tt0, ncell) : -1;
                 sg.base_idx = (r.off - P0) + (tt0 - a.cls) * k;
-                sg.dlo = a.padded ? i * o.W + clo : (o.out_offs[i] - o.base) + clo;
+                sg.dlo = a.padded ? i * o.W + clo : (a.fused_packed ? s_prefix[i] : o.out_offs[i] - o.base) + clo;
                 sg.gpre = 0;
                 seg[tid] = sg;
                 if (ncell > 0) gcnt = ((sg.dlo + al + ncell - 1) >> 2) - ((sg.dlo + al) >> 2) + 1;
@@ -689,6 +731,7 @@ int launch_encode_multi(const dnatok_vocab *const *vs, int nv, const uint8_t *d_
     if (rc) return rc;
     a.err_hdr = ws->d_hdr;
     a.fused_scan = (a.padded && n <= kFuseMaxRows) ? 1 : 0;
+    a.fused_packed = (!a.padded && nv == 1 && n <= kFusePackedRows) ? 1 : 0;
     for (int vi = 0; vi < nv; ++vi) {
         const dnatok_vocab *w = vs[vi];
         VocabOut &out = a.vo[vi];
@@ -697,6 +740,7 @@ int launch_encode_multi(const dnatok_vocab *const *vs, int nv, const uint8_t *d_
         out.ids = d_ids[vi];
         out.cap = caps[vi];
         out.out_offs = d_out_offsets[vi];
+        out.out_offs_w = d_out_offsets[vi];
         out.mask = d_masks[vi];
         out.lut = w->d_lut;
         out.pad_id = w->pad_id;
@@ -717,7 +761,7 @@ int launch_encode_multi(const dnatok_vocab *const *vs, int nv, const uint8_t *d_
         sc.W = out.W;
         sc.base = out.base;
         sc.nunits = nunits;
-        if (!a.fused_scan) {
+        if (!a.fused_scan && !a.fused_packed) {
             sc.q.hdr = ws->d_hdr;
             sc.q.status0 = ws->d_status;
             sc.q.status1 = ws->d_status + ws->cap;
@@ -732,7 +776,9 @@ int launch_encode_multi(const dnatok_vocab *const *vs, int nv, const uint8_t *d_
         }
     }
 
-    const size_t dyn = kmer ? (size_t)nchunks * 12 : (size_t)nchunks * 16;
+    const size_t dyn_tile = ((kmer ? (size_t)nchunks * 12 : (size_t)nchunks * 16) + 15) / 16 * 16;
+    a.prefix_off = (int32_t)dyn_tile;
+    const size_t dyn = dyn_tile + (a.fused_packed ? 8 * (size_t)(n + 1) : 0);
     int per_cu = 0;
     rc = kmer ? blocks_per_cu<true>(U, dyn, &per_cu) : blocks_per_cu<false>(U, dyn, &per_cu);
     if (rc) return rc;

@@ -356,3 +356,14 @@ def test_multi_vocab_errors():
     with pytest.raises(dt.DnatokError) as e:
         dt.MultiCall(vs, _dev(data), _dev(offs), outs, opts).run()
     assert e.value.code == dt.EINVAL
+
+
+@pytest.mark.parametrize("k", [1, 3, 6])
+def test_small_packed_batches_scan_in_the_cell_launch(k):
+    # up to 512 rows PACKED: the row starts are formed inside the cell launch
+    for n_rows, seed in ((1, 1), (37, 2), (512, 3)):
+        data, offs = _fuzz_batch(600 + seed * 10 + k, n_rows, 3000)
+        v = _vocab(dt.KMER, k) if k > 1 else _vocab(dt.SINGLE)
+        kind = dt.KMER if k > 1 else dt.SINGLE
+        for shift, cls in ((0, True), (3, False)):
+            check_packed(v, data, offs, cls, k=k, byte_shift=shift)
