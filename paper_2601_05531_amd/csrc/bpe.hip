@@ -225,6 +225,10 @@ struct ItemArgs {
     int64_t *item_start;
     int32_t *item_len;
     int32_t *item_cnt;
+    int32_t ncls;         // length classes of the wave kernel
+    int32_t cls_hi[4];    // class c takes lengths in (cls_hi[c-1], cls_hi[c]]
+    uint32_t *qctl;       // [counts 4, tickets 4, done]
+    int32_t *queue;       // [4][max_items] item indices per class
 };
 
 // Item j >= 1 of row [off, end) may start only just after a barrier found
@@ -278,9 +282,17 @@ __global__ __launch_bounds__(NTE) void k_bpe_items(ItemArgs a) {
             c0 = c1 = 0;
         }
         if (lane == 0) {
+            const int32_t len = (int32_t)(c1 > c0 ? c1 - c0 : 0);
             a.item_start[t] = c0;
-            a.item_len[t] = (int32_t)(c1 > c0 ? c1 - c0 : 0);
+            a.item_len[t] = len;
             a.item_cnt[t] = 0;
+            // queue of its length class (longer items go to the workgroup kernel)
+            int c = 0;
+            while (c < a.ncls && len > a.cls_hi[c]) ++c;
+            if (len > 0 && c < a.ncls) {
+                const uint32_t pos = atomicAdd(a.qctl + c, 1u);
+                a.queue[(int64_t)c * a.max_items + pos] = (int32_t)t;
+            }
         }
     }
 }
@@ -350,7 +362,6 @@ struct WaveArgs {
     const uint8_t *bytes;
     const int64_t *item_start;
     const int32_t *item_len;
-    const int64_t *n_items_at;  // item_off + n
     int64_t max_items;
     uint16_t *tok;  // final symbols of item t at item_start[t]
     int32_t *item_cnt;
@@ -358,10 +369,16 @@ struct WaveArgs {
     const uint32_t *pair;
     uint32_t nbk;
     int32_t R;
-    int32_t lo, hi;  // this launch takes items with lo < length <= hi
-    uint32_t np;     // positions per wave (multiple of 64, >= hi)
-    uint32_t wave_bytes;
-    uint32_t *hdr;  // [ticket, done]
+    // phases, longest items first: phase m runs mode_waves[m] waves per
+    // workgroup, each holding up to mode_np[m] symbols, on queue mode_class[m]
+    int32_t nmodes;
+    int32_t mode_waves[4];
+    uint32_t mode_np[4];
+    uint32_t mode_wave_bytes[4];
+    int32_t mode_class[4];
+    uint32_t *qctl;  // [counts 4, tickets 4, done]
+    const int32_t *queue;
+    uint32_t *hdr;   // error word at hdr + 3
 };
 
 // Per-wave LDS, each part 16-byte aligned: sym[np], prk[np] (16-bit),
@@ -450,14 +467,10 @@ __device__ __forceinline__ Neighbors neighbors(const uint32_t *alive, uint32_t n
 
 constexpr int kK2Max = 16;  // level-2 blocks per lane (np <= 65536)
 
-__global__ __launch_bounds__(kMaxWaves * 64) void k_bpe_wave(WaveArgs a) {
-    extern __shared__ __align__(16) uint8_t dyn[];
-    RankTab tab;
-    load_table(dyn, a.bucket, a.pair, a.nbk, a.R, &tab);
-    __syncthreads();
+// One item, by one wave, in the LDS region at wb laid out for np symbols.
+__device__ __forceinline__ void wave_item(const WaveArgs &a, const RankTab &tab, uint8_t *wb, uint32_t np, int64_t t) {
     const int lane = threadIdx.x & 63;
-    const WaveLayout lay = wave_layout(a.np);
-    uint8_t *wb = dyn + table_bytes(a.nbk, a.R) + (threadIdx.x / 64) * a.wave_bytes;
+    const WaveLayout lay = wave_layout(np);
     uint16_t *sym = reinterpret_cast<uint16_t *>(wb);
     uint16_t *prk = reinterpret_cast<uint16_t *>(wb + lay.prk);
     uint32_t *alive = reinterpret_cast<uint32_t *>(wb + lay.alive);
@@ -465,203 +478,220 @@ __global__ __launch_bounds__(kMaxWaves * 64) void k_bpe_wave(WaveArgs a) {
     uint16_t *cblk = reinterpret_cast<uint16_t *>(wb + lay.cblk);
     uint32_t *dirty = reinterpret_cast<uint32_t *>(wb + lay.dirty);
     uint16_t *list = reinterpret_cast<uint16_t *>(wb + lay.list);
-    const int64_t total = min(*a.n_items_at, a.max_items);
+    const int32_t n = a.item_len[t];
+    const int64_t c0 = a.item_start[t];
+    const uint8_t *src = a.bytes + c0;
+    const uint32_t nb = ((uint32_t)n + 63) / 64, nw = ((uint32_t)n + 31) / 32, k2 = (nb + 63) / 64;
+    const uint32_t ndw = (nb + 31) / 32 + 1;  // dirty words (one spare: a lane's bits may straddle two)
 
-    for (;;) {
-        uint32_t tk = 0;
-        if (lane == 0) tk = atomicAdd(a.hdr + 0, 1u);
-        const int64_t t = (int64_t)dev::wave_read_u32(tk, 0);
-        if (t >= total) break;
-        const int32_t n = a.item_len[t];
-        if (n <= a.lo || n > a.hi) continue;
-        const int64_t c0 = a.item_start[t];
-        const uint8_t *src = a.bytes + c0;
-        const uint32_t nb = ((uint32_t)n + 63) / 64, nw = ((uint32_t)n + 31) / 32, k2 = (nb + 63) / 64;
-        const uint32_t ndw = (nb + 31) / 32 + 1;  // dirty words (one spare: a lane's bits may straddle two)
-
-        // symbols (four per lane per step), alive bits, dirty bits
-        for (uint32_t p0 = 4 * lane; p0 < nb * 64; p0 += 256) {
-            uint32_t v[4];
+    // symbols (four per lane per step), alive bits, dirty bits
+    for (uint32_t p0 = 4 * lane; p0 < nb * 64; p0 += 256) {
+        uint32_t v[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = p0 + u < (uint32_t)n ? symbol_of(src[p0 + u]) : 0u;
-            *reinterpret_cast<uint2 *>(sym + p0) = make_uint2(v[0] | (v[1] << 16), v[2] | (v[3] << 16));
+        for (int u = 0; u < 4; ++u) v[u] = p0 + u < (uint32_t)n ? symbol_of(src[p0 + u]) : 0u;
+        *reinterpret_cast<uint2 *>(sym + p0) = make_uint2(v[0] | (v[1] << 16), v[2] | (v[3] << 16));
+    }
+    for (uint32_t w = lane; w < nb * 2; w += 64) {
+        const int32_t f = n - 32 * (int32_t)w;
+        alive[w] = f >= 32 ? ~0u : (f > 0 ? (1u << f) - 1u : 0u);
+    }
+    for (uint32_t w = lane; w < ndw; w += 64) dirty[w] = 0;
+    wave_sync();
+    // pair ranks and block minima, four blocks at a time
+    for (uint32_t i = 0; i < nb; i += 4) {
+        uint32_t r[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t p = (i + u) * 64 + lane;
+            const bool has = i + u < nb && p + 1 < (uint32_t)n;
+            const uint32_t pn = has ? p + 1 : p;
+            const uint32_t x = (i + u < nb) ? sym[p] : 0u, y = (i + u < nb) ? sym[pn] : 0u;
+            r[u] = has ? pair_rank(tab, x, y) : kNoRank;
         }
-        for (uint32_t w = lane; w < nb * 2; w += 64) {
-            const int32_t f = n - 32 * (int32_t)w;
-            alive[w] = f >= 32 ? ~0u : (f > 0 ? (1u << f) - 1u : 0u);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (i + u < nb) {
+                prk[(i + u) * 64 + lane] = (uint16_t)r[u];
+                const uint32_t m = dev::wave_min_all_u32(r[u]);
+                if (lane == 0) bmin[i + u] = (uint16_t)m;
+            }
         }
+    }
+    wave_sync();
+    // level 2: this lane's blocks lane*k2 .. lane*k2 + k2 - 1, minima in registers
+    const uint32_t b0 = (uint32_t)lane * k2;
+    uint32_t bm[kK2Max];
+    uint32_t l2 = kNoRank;
+#pragma unroll
+    for (int k = 0; k < kK2Max; ++k) {
+        bm[k] = ((uint32_t)k < k2 && b0 + k < nb) ? (uint32_t)bmin[b0 + k] : kNoRank;
+        l2 = min(l2, bm[k]);
+    }
+
+    // Each round refreshes every block it visits and leaves no pair of
+    // rank rs behind, so rs strictly increases: at most R rounds.
+    for (int32_t round = 0;; ++round) {
+        const uint32_t rs = dev::wave_min_all_u32(l2);
+        if (rs == kNoRank) break;
+        if (round > a.R) {
+            if (lane == 0) dev::raise_error(a.hdr, DNATOK_DERR_INTERNAL);
+            break;
+        }
+        const uint32_t pr = tab.pair[rs];
+        const uint32_t L = pr & 0xFFFF, NEW = 10 + rs;
+        const bool chain = L == (pr >> 16);
+        // blocks holding rank rs, in order; they are all refreshed after the round
+        uint32_t cm = 0;
+        if (l2 == rs) {
+#pragma unroll
+            for (int k = 0; k < kK2Max; ++k) cm |= (uint32_t)(bm[k] == rs) << k;
+        }
+        const uint32_t cc = (uint32_t)__popc(cm);
+        const uint32_t cinc = dev::wave_incl_sum_u32(cc);
+        const uint32_t ncb = dev::wave_read_u32(cinc, 63);
+        {
+            uint32_t o = cinc - cc, m = cm;
+            while (m) {
+                cblk[o++] = (uint16_t)(b0 + (uint32_t)__builtin_ctz(m));
+                m &= m - 1;
+            }
+        }
+        uint32_t own_dirty = cm;
+        wave_sync();
+        uint32_t carry_q = kNone;
+        int32_t carry_off = 0;
+        for (uint32_t base = 0; base < ncb;) {
+            // gather up to 64 occurrences from the next blocks
+            const uint32_t j = base + lane;
+            uint64_t mm = 0;
+            uint32_t b = 0;
+            if (j < ncb) {
+                b = cblk[j];
+                mm = block_match(prk, b, rs);
+            }
+            const uint32_t c = (uint32_t)__popcll(mm);
+            const uint32_t inc = dev::wave_incl_sum_u32(c);
+            const uint32_t m = (uint32_t)__popcll(__ballot(j < ncb && inc <= 64));
+            if ((uint32_t)lane < m) {
+                uint32_t o = inc - c;
+                while (mm) {
+                    list[o++] = (uint16_t)(b * 64 + (uint32_t)__builtin_ctzll(mm));
+                    mm &= mm - 1;
+                }
+            }
+            const uint32_t nc = dev::wave_read_u32(inc, m - 1);
+            wave_sync();
+            // which occurrences merge: all, or for (X, X) every other one of a run
+            const bool valid = (uint32_t)lane < nc;
+            const uint32_t p = valid ? list[lane] : 0;
+            Neighbors nbr{kNone, kNone, kNone};
+            if (valid) nbr = neighbors(alive, nw, p, true);
+            const uint32_t q = nbr.q;
+            // lane 0 compares with the last occurrence of the previous group
+            const uint32_t q_up = dev::wave_from_prev_u32(q, carry_q);
+            const bool adj = chain && valid && q_up == p;
+            const uint64_t starts = __ballot(valid && !adj);
+            const uint64_t below = starts & (lane == 63 ? ~0ull : ((2ull << lane) - 1));
+            const int32_t off = below ? lane - (63 - __clzll(below)) : carry_off + 1 + lane;
+            const bool ms = valid && (!chain || (off & 1) == 0);
+            if (nc > 0) {
+                carry_q = dev::wave_read_u32(q, nc - 1);
+                carry_off = (int32_t)dev::wave_read_u32((uint32_t)off, nc - 1);
+            }
+            // right elements of the merges one and two occurrences back
+            const uint32_t rq = ms ? q : kNone;
+            const uint32_t rq1 = dev::wave_from_prev_u32(rq, kNone);
+            const uint32_t rq2 = dev::wave_from_prev_u32(rq1, kNone);
+            const uint32_t l = nbr.l, q2 = nbr.q2;
+            uint32_t rk_l = kNoRank, rk_r = kNoRank;
+            const bool left = ms && l != kNone && rq1 != l && rq2 != l;
+            if (ms) {
+                // an occurrence right after a merge merges too
+                const uint32_t s2 = q2 != kNone ? ((prk[q2] == rs) ? NEW : (uint32_t)sym[q2]) : 0u;
+                const uint32_t sl = left ? (uint32_t)sym[l] : 0u;
+                if (q2 != kNone) rk_r = pair_rank(tab, NEW, s2);
+                if (left) rk_l = pair_rank(tab, sl, NEW);
+            }
+            wave_sync();
+            if (ms) {
+                sym[p] = (uint16_t)NEW;
+                prk[p] = (uint16_t)rk_r;
+                prk[q] = kNoRank;
+                atomicAnd(&alive[q >> 5], ~(1u << (q & 31)));
+                // p's block is a visited block; q's and l's may be neighbours
+                if ((q >> 6) != (p >> 6)) atomicOr(&dirty[(q >> 6) >> 5], 1u << ((q >> 6) & 31));
+                if (left) {
+                    prk[l] = (uint16_t)rk_l;
+                    if ((l >> 6) != (p >> 6)) atomicOr(&dirty[(l >> 6) >> 5], 1u << ((l >> 6) & 31));
+                }
+            }
+            wave_sync();
+            base += m;
+        }
+        // refresh the minima of this lane's changed blocks
+        {
+            const uint32_t w0 = b0 >> 5;
+            const uint64_t dw = b0 < nb ? ((uint64_t)dirty[w0] | ((uint64_t)dirty[w0 + 1] << 32)) : 0ull;
+            own_dirty |= (uint32_t)(dw >> (b0 & 31)) & ((k2 >= 32) ? ~0u : ((1u << k2) - 1u));
+        }
+        if (own_dirty) {
+#pragma unroll
+            for (int k = 0; k < kK2Max; ++k)
+                if ((own_dirty >> k) & 1u) bm[k] = block_min(prk, b0 + k);
+            l2 = kNoRank;
+#pragma unroll
+            for (int k = 0; k < kK2Max; ++k) l2 = min(l2, bm[k]);
+        }
+        wave_sync();
         for (uint32_t w = lane; w < ndw; w += 64) dirty[w] = 0;
         wave_sync();
-        // pair ranks and block minima, four blocks at a time
-        for (uint32_t i = 0; i < nb; i += 4) {
-            uint32_t r[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint32_t p = (i + u) * 64 + lane;
-                const bool has = i + u < nb && p + 1 < (uint32_t)n;
-                const uint32_t pn = has ? p + 1 : p;
-                const uint32_t x = (i + u < nb) ? sym[p] : 0u, y = (i + u < nb) ? sym[pn] : 0u;
-                r[u] = has ? pair_rank(tab, x, y) : kNoRank;
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (i + u < nb) {
-                    prk[(i + u) * 64 + lane] = (uint16_t)r[u];
-                    const uint32_t m = dev::wave_min_all_u32(r[u]);
-                    if (lane == 0) bmin[i + u] = (uint16_t)m;
-                }
-            }
-        }
-        wave_sync();
-        // level 2: this lane's blocks lane*k2 .. lane*k2 + k2 - 1, minima in registers
-        const uint32_t b0 = (uint32_t)lane * k2;
-        uint32_t bm[kK2Max];
-        uint32_t l2 = kNoRank;
-#pragma unroll
-        for (int k = 0; k < kK2Max; ++k) {
-            bm[k] = ((uint32_t)k < k2 && b0 + k < nb) ? (uint32_t)bmin[b0 + k] : kNoRank;
-            l2 = min(l2, bm[k]);
-        }
-
-        // Each round refreshes every block it visits and leaves no pair of
-        // rank rs behind, so rs strictly increases: at most R rounds.
-        for (int32_t round = 0;; ++round) {
-            const uint32_t rs = dev::wave_min_all_u32(l2);
-            if (rs == kNoRank) break;
-            if (round > a.R) {
-                if (lane == 0) dev::raise_error(a.hdr, DNATOK_DERR_INTERNAL);
-                break;
-            }
-            const uint32_t pr = tab.pair[rs];
-            const uint32_t L = pr & 0xFFFF, NEW = 10 + rs;
-            const bool chain = L == (pr >> 16);
-            // blocks holding rank rs, in order; they are all refreshed after the round
-            uint32_t cm = 0;
-            if (l2 == rs) {
-#pragma unroll
-                for (int k = 0; k < kK2Max; ++k) cm |= (uint32_t)(bm[k] == rs) << k;
-            }
-            const uint32_t cc = (uint32_t)__popc(cm);
-            const uint32_t cinc = dev::wave_incl_sum_u32(cc);
-            const uint32_t ncb = dev::wave_read_u32(cinc, 63);
-            {
-                uint32_t o = cinc - cc, m = cm;
-                while (m) {
-                    cblk[o++] = (uint16_t)(b0 + (uint32_t)__builtin_ctz(m));
-                    m &= m - 1;
-                }
-            }
-            uint32_t own_dirty = cm;
-            wave_sync();
-            uint32_t carry_q = kNone;
-            int32_t carry_off = 0;
-            for (uint32_t base = 0; base < ncb;) {
-                // gather up to 64 occurrences from the next blocks
-                const uint32_t j = base + lane;
-                uint64_t mm = 0;
-                uint32_t b = 0;
-                if (j < ncb) {
-                    b = cblk[j];
-                    mm = block_match(prk, b, rs);
-                }
-                const uint32_t c = (uint32_t)__popcll(mm);
-                const uint32_t inc = dev::wave_incl_sum_u32(c);
-                const uint32_t m = (uint32_t)__popcll(__ballot(j < ncb && inc <= 64));
-                if ((uint32_t)lane < m) {
-                    uint32_t o = inc - c;
-                    while (mm) {
-                        list[o++] = (uint16_t)(b * 64 + (uint32_t)__builtin_ctzll(mm));
-                        mm &= mm - 1;
-                    }
-                }
-                const uint32_t nc = dev::wave_read_u32(inc, m - 1);
-                wave_sync();
-                // which occurrences merge: all, or for (X, X) every other one of a run
-                const bool valid = (uint32_t)lane < nc;
-                const uint32_t p = valid ? list[lane] : 0;
-                Neighbors nbr{kNone, kNone, kNone};
-                if (valid) nbr = neighbors(alive, nw, p, true);
-                const uint32_t q = nbr.q;
-                // lane 0 compares with the last occurrence of the previous group
-                const uint32_t q_up = dev::wave_from_prev_u32(q, carry_q);
-                const bool adj = chain && valid && q_up == p;
-                const uint64_t starts = __ballot(valid && !adj);
-                const uint64_t below = starts & (lane == 63 ? ~0ull : ((2ull << lane) - 1));
-                const int32_t off = below ? lane - (63 - __clzll(below)) : carry_off + 1 + lane;
-                const bool ms = valid && (!chain || (off & 1) == 0);
-                if (nc > 0) {
-                    carry_q = dev::wave_read_u32(q, nc - 1);
-                    carry_off = (int32_t)dev::wave_read_u32((uint32_t)off, nc - 1);
-                }
-                // right elements of the merges one and two occurrences back
-                const uint32_t rq = ms ? q : kNone;
-                const uint32_t rq1 = dev::wave_from_prev_u32(rq, kNone);
-                const uint32_t rq2 = dev::wave_from_prev_u32(rq1, kNone);
-                const uint32_t l = nbr.l, q2 = nbr.q2;
-                uint32_t rk_l = kNoRank, rk_r = kNoRank;
-                const bool left = ms && l != kNone && rq1 != l && rq2 != l;
-                if (ms) {
-                    // an occurrence right after a merge merges too
-                    const uint32_t s2 = q2 != kNone ? ((prk[q2] == rs) ? NEW : (uint32_t)sym[q2]) : 0u;
-                    const uint32_t sl = left ? (uint32_t)sym[l] : 0u;
-                    if (q2 != kNone) rk_r = pair_rank(tab, NEW, s2);
-                    if (left) rk_l = pair_rank(tab, sl, NEW);
-                }
-                wave_sync();
-                if (ms) {
-                    sym[p] = (uint16_t)NEW;
-                    prk[p] = (uint16_t)rk_r;
-                    prk[q] = kNoRank;
-                    atomicAnd(&alive[q >> 5], ~(1u << (q & 31)));
-                    // p's block is a visited block; q's and l's may be neighbours
-                    if ((q >> 6) != (p >> 6)) atomicOr(&dirty[(q >> 6) >> 5], 1u << ((q >> 6) & 31));
-                    if (left) {
-                        prk[l] = (uint16_t)rk_l;
-                        if ((l >> 6) != (p >> 6)) atomicOr(&dirty[(l >> 6) >> 5], 1u << ((l >> 6) & 31));
-                    }
-                }
-                wave_sync();
-                base += m;
-            }
-            // refresh the minima of this lane's changed blocks
-            {
-                const uint32_t w0 = b0 >> 5;
-                const uint64_t dw = b0 < nb ? ((uint64_t)dirty[w0] | ((uint64_t)dirty[w0 + 1] << 32)) : 0ull;
-                own_dirty |= (uint32_t)(dw >> (b0 & 31)) & ((k2 >= 32) ? ~0u : ((1u << k2) - 1u));
-            }
-            if (own_dirty) {
-#pragma unroll
-                for (int k = 0; k < kK2Max; ++k)
-                    if ((own_dirty >> k) & 1u) bm[k] = block_min(prk, b0 + k);
-                l2 = kNoRank;
-#pragma unroll
-                for (int k = 0; k < kK2Max; ++k) l2 = min(l2, bm[k]);
-            }
-            wave_sync();
-            for (uint32_t w = lane; w < ndw; w += 64) dirty[w] = 0;
-            wave_sync();
-        }
-
-        // surviving symbols in order
-        uint32_t cnt = 0;
-        uint16_t *out = a.tok + c0;
-        for (uint32_t base = 0; base < nb * 64; base += 64) {
-            const uint32_t p = base + lane;
-            const bool on = (alive[p >> 5] >> (p & 31)) & 1u;
-            const uint64_t mk = __ballot(on);
-            if (on) out[cnt + (uint32_t)__popcll(mk & ((1ull << lane) - 1))] = sym[p];
-            cnt += (uint32_t)__popcll(mk);
-        }
-        if (lane == 0) a.item_cnt[t] = (int32_t)cnt;
-        wave_sync();
     }
-    if (lane == 0) {
-        // the last wave to finish resets the ticket for the next launch
-        const uint32_t total_waves = gridDim.x * (blockDim.x / 64);
-        if (atomicAdd(a.hdr + 1, 1u) == total_waves - 1) {
-            dev::st_relaxed32(a.hdr + 0, 0u);
-            dev::st_relaxed32(a.hdr + 1, 0u);
+
+    // surviving symbols in order
+    uint32_t cnt = 0;
+    uint16_t *out = a.tok + c0;
+    for (uint32_t base = 0; base < nb * 64; base += 64) {
+        const uint32_t p = base + lane;
+        const bool on = (alive[p >> 5] >> (p & 31)) & 1u;
+        const uint64_t mk = __ballot(on);
+        if (on) out[cnt + (uint32_t)__popcll(mk & ((1ull << lane) - 1))] = sym[p];
+        cnt += (uint32_t)__popcll(mk);
+    }
+    if (lane == 0) a.item_cnt[t] = (int32_t)cnt;
+    wave_sync();
+}
+
+// Persistent BPE over all length classes in one launch: every workgroup
+// takes the longest class first (one wave with the whole LDS), then shorter
+// classes with more waves sharing it, pulling items from each class's queue;
+// a workgroup barrier separates the phases because the LDS is re-divided.
+__global__ __launch_bounds__(kMaxWaves * 64) void k_bpe_wave(WaveArgs a) {
+    extern __shared__ __align__(16) uint8_t dyn[];
+    RankTab tab;
+    load_table(dyn, a.bucket, a.pair, a.nbk, a.R, &tab);
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x / 64;
+    uint8_t *pool = dyn + table_bytes(a.nbk, a.R);
+    for (int m = 0; m < a.nmodes; ++m) {
+        if (wave < a.mode_waves[m]) {
+            const int c = a.mode_class[m];
+            const uint32_t count = a.qctl[c];
+            uint8_t *wb = pool + (size_t)wave * a.mode_wave_bytes[m];
+            for (;;) {
+                uint32_t tk = 0;
+                if (lane == 0) tk = atomicAdd(a.qctl + 4 + c, 1u);
+                tk = dev::wave_read_u32(tk, 0);
+                if (tk >= count) break;
+                wave_item(a, tab, wb, a.mode_np[m], (int64_t)a.queue[(int64_t)c * a.max_items + tk]);
+            }
         }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        // the last workgroup to finish empties the queues for the next launch
+        if (atomicAdd(a.qctl + 8, 1u) == gridDim.x - 1)
+            for (int i = 0; i < 9; ++i) dev::st_relaxed32(a.qctl + i, 0u);
     }
 }
 
@@ -1080,9 +1110,9 @@ int bpe_wave_classes(uint32_t tab, int max_waves, BpeClass *out, int max_out) {
 
 namespace {
 // Scratch of one BPE encode: symA, symB (uint16 per byte), item offsets,
-// counts, lengths, starts and positions.
+// counts, lengths, starts, positions and the four length-class queues.
 struct BpeScratch {
-    int64_t max_items, sz_sym, sz_ioff, sz_cnt, sz_start, sz_pos, total;
+    int64_t max_items, sz_sym, sz_ioff, sz_cnt, sz_start, sz_pos, sz_queue, total;
 };
 BpeScratch bpe_scratch(int64_t nbytes, int32_t n, int32_t S) {
     auto al = [](int64_t x) { return (x + 255) / 256 * 256; };
@@ -1093,7 +1123,8 @@ BpeScratch bpe_scratch(int64_t nbytes, int32_t n, int32_t S) {
     b.sz_cnt = al(4 * b.max_items);
     b.sz_start = al(8 * b.max_items);
     b.sz_pos = al(8 * (b.max_items + 1));
-    b.total = 2 * b.sz_sym + b.sz_ioff + 2 * b.sz_cnt + b.sz_start + b.sz_pos;
+    b.sz_queue = al(4 * 4 * b.max_items);
+    b.total = 2 * b.sz_sym + b.sz_ioff + 2 * b.sz_cnt + b.sz_start + b.sz_pos + b.sz_queue;
     return b;
 }
 }  // namespace
@@ -1139,6 +1170,8 @@ int launch_bpe_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nby
     int64_t *item_start = reinterpret_cast<int64_t *>(sp);
     sp += sz_start;
     int64_t *item_pos = reinterpret_cast<int64_t *>(sp);
+    sp += bs.sz_pos;
+    int32_t *queue = reinterpret_cast<int32_t *>(sp);
     if (units_items > ws->high_water) ws->high_water = units_items;
     const int cus = device_cu_count();
 
@@ -1147,22 +1180,24 @@ int launch_bpe_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nby
     if (rc) return rc;
 
     // 2. items
-    ItemArgs ia{d_bytes, nbytes, d_offsets, n, item_off, max_items, S, item_start, item_len, item_cnt};
+    const uint32_t tab = table_bytes(bt.nbk, R);
+    BpeClass cls[4];
+    const int ncls = bpe_wave_classes(tab, max_waves, cls, 4);
+    uint32_t *qctl = ws->d_hdr + HDR_BPE_QUEUES;  // self-resetting queue counters
+    ItemArgs ia{d_bytes, nbytes, d_offsets, n, item_off, max_items, S, item_start, item_len, item_cnt,
+                ncls, {0, 0, 0, 0}, qctl, queue};
+    for (int c = 0; c < ncls; ++c) ia.cls_hi[c] = cls[c].hi;
     const int64_t g_items = std::max<int64_t>(1, std::min<int64_t>((max_items + 3) / 4, (int64_t)cus * 8));
     hipLaunchKernelGGL(k_bpe_items, dim3((unsigned)g_items), dim3(NTE), 0, stream, ia);
     DNATOK_HIP(hipGetLastError());
 
-    // 3. wave classes
-    const uint32_t tab = table_bytes(bt.nbk, R);
-    BpeClass cls[4];
-    const int ncls = bpe_wave_classes(tab, max_waves, cls, 4);
+    // 3. all length classes in one persistent launch, longest first
     int32_t covered = 0;
-    for (int c = 0; c < ncls; ++c) {
+    if (ncls > 0) {
         WaveArgs w;
         w.bytes = d_bytes;
         w.item_start = item_start;
         w.item_len = item_len;
-        w.n_items_at = item_off + n;
         w.max_items = max_items;
         w.tok = symA;
         w.item_cnt = item_cnt;
@@ -1170,18 +1205,26 @@ int launch_bpe_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nby
         w.pair = bt.d_pair;
         w.nbk = bt.nbk;
         w.R = R;
-        w.lo = cls[c].lo;
-        w.hi = cls[c].hi;
-        w.np = cls[c].np;
-        w.wave_bytes = wave_lds_bytes(cls[c].np);
+        w.nmodes = ncls;
+        uint32_t lds = 0;
+        int wmax = 1;
+        for (int m = 0; m < ncls; ++m) {
+            const BpeClass &c = cls[ncls - 1 - m];
+            w.mode_waves[m] = c.waves;
+            w.mode_np[m] = c.np;
+            w.mode_wave_bytes[m] = wave_lds_bytes(c.np);
+            w.mode_class[m] = ncls - 1 - m;
+            lds = std::max(lds, c.lds);
+            wmax = std::max(wmax, c.waves);
+        }
+        w.qctl = qctl;
+        w.queue = queue;
         w.hdr = ws->d_hdr;
         DNATOK_HIP(hipFuncSetAttribute((const void *)k_bpe_wave, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)cls[c].lds));
-        const int per_cu = std::max<int>(1, (int)((kLdsBytes - kLdsReserve) / cls[c].lds));
-        hipLaunchKernelGGL(k_bpe_wave, dim3((unsigned)(cus * per_cu)), dim3(64 * cls[c].waves), cls[c].lds, stream,
-                           w);
+                                       (int)lds));
+        hipLaunchKernelGGL(k_bpe_wave, dim3((unsigned)cus), dim3(64 * wmax), lds, stream, w);
         DNATOK_HIP(hipGetLastError());
-        covered = cls[c].hi;
+        covered = cls[ncls - 1].hi;
     }
 
     // 4. longer items

@@ -98,7 +98,9 @@ namespace dnatok {
 // the parity, and every launch zeroes the status array of the other parity for
 // the next one, so no memset is ever enqueued between launches (graph capture
 // friendly). One workspace exists per (device, stream).
-enum HdrSlot { HDR_TICKET = 0, HDR_DONE = 1, HDR_PARITY = 2, HDR_ERR = 3, HDR_WORDS = 4 };
+// Words 8..16 hold the BPE length-class queue counters (counts 4, tickets 4,
+// done), zero between launches.
+enum HdrSlot { HDR_TICKET = 0, HDR_DONE = 1, HDR_PARITY = 2, HDR_ERR = 3, HDR_WORDS = 4, HDR_BPE_QUEUES = 8 };
 
 struct Workspace {
     int device = 0;
