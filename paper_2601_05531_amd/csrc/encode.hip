@@ -53,17 +53,29 @@ __device__ __forceinline__ int64_t body_tokens(int64_t L, int32_t k, bool kmer) 
     return span < 0x7FFFFFFF ? (int64_t)((uint32_t)span / (uint32_t)k) : span / k;
 }
 
+// x / k for k >= 1 with kinv = floor((2^32 - 1) / k): the high product is
+// floor(x / k) or one less (x < 2^32), and one step corrects it. Quotients
+// of 2^31 or more take the plain division.
+__device__ __forceinline__ int64_t div_k(int64_t x, int32_t k, uint32_t kinv) {
+    if (x < 0x7FFFFFFF) {
+        const uint32_t ux = (uint32_t)x;
+        uint32_t q = __umulhi(ux, kinv);
+        if (ux - q * (uint32_t)k >= (uint32_t)k) ++q;
+        return (int64_t)q;
+    }
+    return x / k;
+}
+
 struct Row {
     int64_t off, end, nb, len;
 };
 
 // Tokens of the row whose anchor byte is < X.
-__device__ __forceinline__ int64_t tokens_before(const Row &r, int64_t X, int32_t k, int32_t cls) {
+__device__ __forceinline__ int64_t tokens_before(const Row &r, int64_t X, int32_t k, uint32_t kinv, int32_t cls) {
     int64_t c = 0;
     if (X > r.off) {
         // body anchors off + j*k < X  <=>  j < ceil((X - off) / k)
-        const int64_t span = X - r.off + k - 1;
-        c += (X >= r.end) ? r.nb : (span < 0x7FFFFFFF ? (int64_t)((uint32_t)span / (uint32_t)k) : span / k);
+        c += (X >= r.end) ? r.nb : div_k(X - r.off + k - 1, k, kinv);
         if (cls) c += 1;  // CLS anchored at off
     }
     if (cls) {
@@ -74,9 +86,9 @@ __device__ __forceinline__ int64_t tokens_before(const Row &r, int64_t X, int32_
 }
 
 // Cells (tokens plus pads) of the row whose anchor is < X.
-__device__ __forceinline__ int64_t cells_before(const Row &r, int64_t X, int32_t k, int32_t cls, int32_t padded,
-                                                int32_t left, int64_t W) {
-    int64_t c = tokens_before(r, X, k, cls);
+__device__ __forceinline__ int64_t cells_before(const Row &r, int64_t X, int32_t k, uint32_t kinv, int32_t cls,
+                                                int32_t padded, int32_t left, int64_t W) {
+    int64_t c = tokens_before(r, X, k, kinv, cls);
     if (!padded) return c;
     int64_t pads = W - r.len;
     if (left) {
@@ -124,6 +136,45 @@ __device__ __forceinline__ int32_t kmer_at(const uint64_t *win64, const uint32_t
     return ok ? (int32_t)(5 + digits) : DNATOK_ID_UNK;
 }
 
+// Per-vocabulary constants of kmer4_at: the shift that brings k-mer r of a
+// 32-base window to the bottom, the validity bits it needs, the digit mask.
+struct Kmer4 {
+    uint32_t sh[4];
+    uint32_t vm[4];
+    uint32_t dm;
+};
+
+__device__ __forceinline__ Kmer4 kmer4_consts(int32_t k) {
+    Kmer4 c;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        c.sh[r] = 64u - 2u * (uint32_t)(k * (r + 1));
+        c.vm[r] = ((1u << k) - 1u) << (32 - k * (r + 1));
+    }
+    c.dm = (1u << (2 * k)) - 1u;
+    return c;
+}
+
+// Ids of the four consecutive k-mers (k <= 8) starting at tile byte idx0.
+// Their 4k bases lie within the 32 bases from idx0 on: window w = idx0 / 16
+// shifted left by o = idx0 % 16 bases, with the first o bases of chunk w + 2
+// (the low half of window w + 1) shifted in below; validity bits likewise.
+__device__ __forceinline__ i32x4 kmer4_at(const uint64_t *win64, const uint32_t *val32, uint32_t idx0,
+                                          const Kmer4 &c) {
+    const uint32_t w = idx0 >> 4, o = idx0 & 15;
+    const uint64_t w0 = win64[w], w1 = win64[w + 1];
+    const uint32_t v0 = val32[w], v1 = val32[w + 1];
+    const uint64_t X = (w0 << (2 * o)) | (((uint64_t)(uint32_t)w1 << (2 * o)) >> 32);
+    const uint32_t nV = ~(uint32_t)((((uint64_t)v0 << 32) | (uint64_t)(v1 << 16)) << o >> 32);
+    i32x4 r;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int32_t id = 5 + (int32_t)((uint32_t)(X >> c.sh[q]) & c.dm);
+        r[q] = (nV & c.vm[q]) == 0 ? id : DNATOK_ID_UNK;
+    }
+    return r;
+}
+
 // A relative cell index, or -1 when it lies before the segment (single
 // cells: CLS, SEP, short final frame).
 __device__ __forceinline__ int32_t clamp_rel(int64_t v, int64_t hi) {
@@ -142,6 +193,7 @@ struct RowScanArgs {
     int64_t nbytes;
     int64_t *out_offs;
     int32_t k;
+    uint32_t kinv;  // floor((2^32 - 1) / k)
     int32_t kmer;
     int32_t cls;
     int32_t padded;
@@ -159,6 +211,14 @@ __device__ __forceinline__ int64_t rowscan_unit(const RowScanArgs &a, int64_t ro
                                                 Prefix prefix) {
     const int tid = threadIdx.x;
     const int64_t i0 = row0 + (int64_t)tid * kRowsPerThread;
+    // all of this thread's offsets first, from indices clamped to the batch,
+    // so the loads go out together instead of one per row behind its test
+    int64_t off[kRowsPerThread + 1];
+#pragma unroll
+    for (int j = 0; j <= kRowsPerThread; ++j) {
+        const int64_t i = i0 + j;
+        off[j] = a.offs[i < a.n ? i : a.n];
+    }
     int64_t len[kRowsPerThread];
     int64_t mine = 0;
 #pragma unroll
@@ -166,11 +226,11 @@ __device__ __forceinline__ int64_t rowscan_unit(const RowScanArgs &a, int64_t ro
         const int64_t i = i0 + j;
         len[j] = 0;
         if (i < a.n) {
-            int64_t o0 = a.offs[i], o1 = a.offs[i + 1];
+            int64_t o0 = off[j], o1 = off[j + 1];
             if (o0 < 0 || o1 < o0 || o1 > a.nbytes) err |= DNATOK_DERR_OFFSETS;
             o0 = o0 < 0 ? 0 : (o0 > a.nbytes ? a.nbytes : o0);
             o1 = o1 < o0 ? o0 : (o1 > a.nbytes ? a.nbytes : o1);
-            len[j] = body_tokens(o1 - o0, a.k, a.kmer) + 2 * a.cls;
+            len[j] = (a.kmer ? div_k(o1 - o0 + a.k - 1, a.k, a.kinv) : o1 - o0) + 2 * a.cls;
             if (a.padded && len[j] > a.W) err |= DNATOK_DERR_ROW_WIDTH;
         }
         mine += len[j];
@@ -240,6 +300,7 @@ __global__ __launch_bounds__(NT) void k_rowscan(RowScanArgs a) {
 // share one pass over the input).
 struct VocabOut {
     int32_t k;
+    uint32_t kinv;            // floor((2^32 - 1) / k)
     int32_t al;               // element misalignment of ids within 16 bytes
     int32_t *ids;
     int64_t cap;
@@ -273,6 +334,18 @@ struct CellArgs {
 };
 
 // Per-row facts a tile needs for its owned cells (row chunk of up to NT rows).
+// Per-vocabulary facts the segment pass reads with a per-thread vocabulary
+// index (kept in LDS: kernel arguments are read with uniform indices only).
+struct VocabLds {
+    int32_t k;
+    uint32_t kinv;
+    int32_t al;
+    int32_t pad_;
+    int64_t W;
+    int64_t base;
+    const int64_t *out_offs;
+};
+
 struct SegInfo {
     int64_t dlo;       // destination element of the first owned cell
     int64_t gpre;      // first 4-element store group of this segment in the chunk's group list
@@ -293,54 +366,81 @@ __device__ __forceinline__ uint4 load_chunk(const CellArgs &a, int64_t q0) {
     return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-// Put the 16-byte chunks of tile t that this thread stages in flight:
-// chunk u * NT + tid for u < U, plus (thread 0) the halo chunk U * NT that
-// holds the first bytes of the next tile. Tiles whose chunks all lie inside
-// the input take branch-free vector loads; only the first and last tile
-// check bytes one by one.
-template <int U>
-__device__ __forceinline__ void fetch_tile(const CellArgs &a, int64_t t, uint4 (&v)[U], uint4 &halo) {
-    const int tid = threadIdx.x;
-    constexpr int64_t nchunks = (int64_t)U * NT + 1;
-    const bool interior = (t * a.tileB >= a.shift) && (t * a.tileB + nchunks * 16 <= a.shift + a.nbytes);
-    if (interior) {
-        const u32x4 *src = reinterpret_cast<const u32x4 *>(a.abase + t * a.tileB);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const u32x4 x = __builtin_nontemporal_load(src + (int64_t)u * NT + tid);
-            v[u] = make_uint4(x[0], x[1], x[2], x[3]);
-        }
-        if (tid == 0) {
-            const u32x4 x = __builtin_nontemporal_load(src + (int64_t)U * NT);
-            halo = make_uint4(x[0], x[1], x[2], x[3]);
-        }
-    } else {
-        for (int u = 0; u < U; ++u) v[u] = load_chunk(a, t * a.tileB + 16 * ((int64_t)u * NT + tid));
-        if (tid == 0) halo = load_chunk(a, t * a.tileB + 16 * (int64_t)U * NT);
-    }
+// Workgroups are dispatched to the 8 XCDs in turn, so walk order L (tile
+// walker bid takes L = bid, bid + G, ...) runs on XCD L % 8. Give each XCD a
+// contiguous share of the tiles: neighbouring tiles, which share cache lines
+// at their edges, then go through the same L2. A bijection on [0, ntiles).
+__device__ __forceinline__ int64_t xcd_tile(int64_t L, int64_t ntiles) {
+    const int64_t x = L & 7, j = L >> 3, q = ntiles >> 3, r = ntiles & 7;
+    return x * q + (x < r ? x : r) + j;
 }
 
-template <bool KMER, int U>
+// Whether every chunk of tile t, halo included, lies inside the input.
+template <int U>
+__device__ __forceinline__ bool tile_interior(const CellArgs &a, int64_t t) {
+    constexpr int64_t nchunks = (int64_t)U * NT + 1;
+    return (t * a.tileB >= a.shift) && (t * a.tileB + nchunks * 16 <= a.shift + a.nbytes);
+}
+
+// Put the 16-byte chunks of interior tile t that this thread stages in
+// flight: chunk u * NT + tid for u < U, and the halo chunk U * NT holding the
+// first bytes of the next tile (every thread loads it, one transaction per
+// wave, so no value depends on the thread and nothing has to be merged).
+template <int U>
+__device__ __forceinline__ void fetch_tile(const CellArgs &a, int64_t t, uint4 (&v)[U], uint4 &halo, int tid) {
+    const u32x4 *src = reinterpret_cast<const u32x4 *>(a.abase + t * a.tileB);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const u32x4 x = __builtin_nontemporal_load(src + (int64_t)u * NT + tid);
+        v[u] = make_uint4(x[0], x[1], x[2], x[3]);
+    }
+    const u32x4 x = __builtin_nontemporal_load(src + (int64_t)U * NT);
+    halo = make_uint4(x[0], x[1], x[2], x[3]);
+}
+
+// PF: blocks walk several tiles and the next tile's loads are issued while
+// the current one is written (its registers stay live through the writes).
+template <bool KMER, int U, bool PF>
 __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
     extern __shared__ __align__(16) uint8_t dyn[];
     __shared__ int32_t lut_s[256];
     __shared__ SegInfo seg[NT];
+    __shared__ VocabLds vtab[kMaxMultiVocabs];
+    __shared__ int64_t s_vg[kMaxMultiVocabs + 1];
+    __shared__ int64_t s_po[dev::kWave + 1];  // offs[s_w0 ..] as probed by the row search
+    __shared__ int64_t s_w0, s_w1;
     __shared__ int64_t s_tmp[NT / dev::kWave + 1];
     __shared__ int64_t s_ia, s_ib;
     __shared__ uint32_t s_err;
 
     const int tid = threadIdx.x;
-    if (a.fused_scan && blockIdx.x == gridDim.x - 1) {
-        for (int vi = 0; vi < a.nv; ++vi) {
-            rowscan_single_block(a.scan[vi], s_tmp, a.err_hdr);
-            __syncthreads();
-        }
+    // Fused PADDED row scans: the last nv blocks, one vocabulary each. They
+    // start as the first tile walkers retire, so no walker waits for a slot.
+    const int nscan = a.fused_scan ? a.nv : 0;
+    const int64_t G = (int64_t)gridDim.x - nscan;  // tile walkers
+    if ((int64_t)blockIdx.x >= G) {
+        rowscan_single_block(a.scan[blockIdx.x - G], s_tmp, a.err_hdr);
         return;
     }
-    const int64_t G = gridDim.x - (a.fused_scan ? 1 : 0);
+    const int64_t bid = blockIdx.x;
     if (!KMER)
         for (int i = tid; i < 256; i += NT) lut_s[i] = a.vo[0].lut[i];
     if (tid == 0) s_err = 0;
+    for (int vi = 0; vi < a.nv; ++vi)
+        if (tid == vi) {
+            VocabLds e;
+            e.k = a.vo[vi].k;
+            e.kinv = a.vo[vi].kinv;
+            e.al = a.vo[vi].al;
+            e.pad_ = 0;
+            e.W = a.vo[vi].W;
+            e.base = a.vo[vi].base;
+            e.out_offs = a.vo[vi].out_offs;
+            vtab[vi] = e;
+        }
+    // rows per chunk: NT / nv rounded down to a power of two
+    int R = NT;
+    while (R * a.nv > NT) R >>= 1;
     const int64_t B = a.tileB;  // == U * NT * 16
     constexpr int64_t nchunks = (int64_t)U * NT + 1;
     uint64_t *win64 = reinterpret_cast<uint64_t *>(dyn);                 // KMER: nchunks
@@ -379,37 +479,68 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
             const int64_t i = 2 * (int64_t)tid + j;
             if (i < a.n) {
                 s_prefix[i] = run;
-                if (blockIdx.x == 0) o.out_offs_w[i] = o.base + run;
+                if (bid == 0) o.out_offs_w[i] = o.base + run;
             }
             run += len2[j];
         }
-        if (blockIdx.x == 0 && tid == 0) o.out_offs_w[a.n] = o.base + total;
-        if (blockIdx.x == 0) err |= e2;
+        if (bid == 0 && tid == 0) o.out_offs_w[a.n] = o.base + total;
+        if (bid == 0) err |= e2;
         __syncthreads();
     }
 
-    auto load_row = [&](int64_t i, int32_t k) {
+    auto make_row = [&](int64_t o0, int64_t o1, int32_t k, uint32_t kinv) {
         Row r;
-        int64_t o0 = a.offs[i], o1 = a.offs[i + 1];
-        o0 = o0 < 0 ? 0 : (o0 > a.nbytes ? a.nbytes : o0);
-        o1 = o1 < o0 ? o0 : (o1 > a.nbytes ? a.nbytes : o1);
         r.off = o0;
         r.end = o1;
-        r.nb = body_tokens(o1 - o0, k, KMER);
+        r.nb = KMER ? div_k(o1 - o0 + k - 1, k, kinv) : o1 - o0;
         r.len = r.nb + 2 * a.cls;
         return r;
     };
 
     uint4 v[U];
     uint4 halo = make_uint4(0, 0, 0, 0);
-    int64_t t = blockIdx.x;
-    if (t < a.ntiles) fetch_tile<U>(a, t, v, halo);
-    for (; t < a.ntiles; t += G) {
+    // v and halo hold tile t's chunks when pf is set; first and last tiles
+    // (not interior) are read byte by byte when staged
+    bool pf = false;
+    if (PF && bid < a.ntiles) {
+        const int64_t t0 = xcd_tile(bid, a.ntiles);
+        pf = tile_interior<U>(a, t0);
+        if (pf) fetch_tile<U>(a, t0, v, halo, tid);
+    }
+    for (int64_t L = bid; L < a.ntiles; L += G) {
+        const int64_t t = xcd_tile(L, a.ntiles);
+        // The staging addresses are recomputed per tile from a copy of the
+        // thread index the compiler cannot see through: hoisted out of the
+        // loop they would hold some 5 registers per chunk through the writes.
+        int stid = tid;
+        asm volatile("" : "+v"(stid));
         const int64_t P0 = t * B - a.shift;
         const int64_t P1 = (t == a.ntiles - 1) ? INT64_MAX : P0 + B;
 
-        // Stage this tile from registers into LDS, then put the next tile's
-        // loads in flight while this one is written.
+        // Wave 0 puts the row search's probe in flight before the tile's own
+        // loads, so one wait covers both: 64 rows around the row the byte
+        // position would fall in if rows were equally long, and the offsets
+        // bounding them (indices clamped to the batch).
+        int64_t w0 = 0, w1 = 0, po0 = 0, po1 = 0;
+        if (tid < dev::kWave) {
+            const int64_t n = a.n;
+            int64_t guess = 0;
+            if (off_last > off_first && P0 > off_first)
+                guess = (int64_t)((double)(P0 - off_first) / (double)(off_last - off_first) * (double)n);
+            w0 = guess - dev::kWave / 2;
+            if (w0 + dev::kWave > n) w0 = n - dev::kWave;
+            if (w0 < 0) w0 = 0;
+            w1 = (w0 + dev::kWave < n) ? w0 + dev::kWave : n;  // probe rows [w0, w1)
+            const int64_t q = w0 + tid;
+            po0 = a.offs[q < n ? q : n];
+            po1 = a.offs[q + 1 < n ? q + 1 : n];
+        }
+        if (!PF) {
+            pf = tile_interior<U>(a, t);
+            if (pf) fetch_tile<U>(a, t, v, halo, stid);
+        }
+
+        // Stage this tile into LDS (from the registers its prefetch filled).
         auto stage = [&](int64_t m, uint4 x) {
             if (KMER) {
                 // chunk m's digits are the high half of window m and the low
@@ -428,14 +559,23 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
                 reinterpret_cast<uint4 *>(raw)[m] = x;
             }
         };
+        if (pf) {
+            // one chunk at a time: interleaving the classification of all U
+            // chunks buys nothing and costs registers through the whole kernel
 #pragma unroll
-        for (int u = 0; u < U; ++u) stage((int64_t)u * NT + tid, v[u]);
-        if (tid == 0) stage(nchunks - 1, halo);
-        if (t + G < a.ntiles) fetch_tile<U>(a, t + G, v, halo);
+            for (int u = 0; u < U; ++u) {
+                stage((int64_t)u * NT + stid, v[u]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (stid == 0) stage(nchunks - 1, halo);
+        } else {
+            for (int u = 0; u < U; ++u)
+                stage((int64_t)u * NT + stid, load_chunk(a, t * B + 16 * ((int64_t)u * NT + stid)));
+            if (stid == 0) stage(nchunks - 1, load_chunk(a, t * B + 16 * (int64_t)U * NT));
+        }
 
-        // Wave 0: rows with an anchor in [P0, P1) are [ia, ib). The first
-        // probe window is centred on the row the byte position would fall in
-        // if rows were equally long; a miss falls back to a 64-way search.
+        // Wave 0: rows with an anchor in [P0, P1) are [ia, ib), from the
+        // probed window when it brackets them, else by a 64-way search.
         if (tid < dev::kWave) {
             auto pa = [&](int64_t i) {
                 const int64_t o0 = a.offs[i], o1 = a.offs[i + 1];
@@ -443,16 +583,9 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
             };
             auto pb = [&](int64_t i) { return a.offs[i] >= P1; };
             const int64_t n = a.n;
-            int64_t guess = 0;
-            if (off_last > off_first && P0 > off_first)
-                guess = (int64_t)((double)(P0 - off_first) / (double)(off_last - off_first) * (double)n);
-            int64_t w0 = guess - dev::kWave / 2;
-            if (w0 + dev::kWave > n) w0 = n - dev::kWave;
-            if (w0 < 0) w0 = 0;
-            const int64_t w1 = (w0 + dev::kWave < n) ? w0 + dev::kWave : n;  // probe [w0, w1)
             const int64_t q = w0 + tid;
             const bool live = q < w1;
-            const uint64_t ba = __ballot(live ? pa(q) : true);
+            const uint64_t ba = __ballot(live ? (((po1 > po0) ? po1 - 1 : po0) >= P0) : true);
             int64_t ia;
             if (w0 > 0 && (ba & 1ull)) ia = dev::wave_lower_bound(0, w0, pa);  // answer left of the window
             else ia = ba ? w0 + __builtin_ctzll(ba) : w1;  // inside, or w1 == n
@@ -460,7 +593,7 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
             int64_t ib = n;
             if (P1 != INT64_MAX) {
                 // pb is monotone too and its answer is >= ia; reuse the window when it brackets it
-                const uint64_t bb = __ballot(live && q >= ia ? pb(q) : (q >= ia));
+                const uint64_t bb = __ballot(live && q >= ia ? (po0 >= P1) : (q >= ia));
                 const int64_t lo = ia > w0 ? ia : w0;
                 if (lo < w1 && ia >= w0 && bb) {
                     const int64_t cand = w0 + __builtin_ctzll(bb);
@@ -469,32 +602,72 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
                     ib = dev::wave_lower_bound(ia, n, pb);
                 }
             }
+            s_po[tid] = po0;
+            if (tid == dev::kWave - 1) s_po[dev::kWave] = po1;
             if (tid == 0) {
                 s_ia = ia;
                 s_ib = ib;
+                s_w0 = w0;
+                s_w1 = w1;
             }
         }
         __syncthreads();
         const int64_t ia = s_ia, ib = s_ib;
 
-        // Write pass per vocabulary, one chunk of up to NT rows at a time.
-        for (int vi = 0; vi < a.nv; ++vi) {
-        const VocabOut &o = a.vo[vi];
-        const int32_t k = KMER ? o.k : 1;
-        const int64_t al = o.al;
-        for (int64_t cb = ia; cb < ib; cb += NT) {
-            const int64_t i = cb + tid;
-            const int nrows = (int)((ib - cb) < NT ? (ib - cb) : NT);
+        // Rows are taken in chunks of R rows, R = NT / nv rounded down to a
+        // power of two, so every (vocabulary, row) pair of a chunk has a
+        // thread: one segment pass and one block scan serve all vocabularies.
+        // A chunk's byte offsets are read once, before any of its stores: a
+        // vector load waits for all of the wave's earlier stores as well, so
+        // a load between write passes would drain the write stream. The next
+        // tile's loads go out after the first chunk's offsets and overlap this
+        // tile's writes.
+        const int pv = tid / R, pr = tid % R;  // this thread's (vocabulary, row-in-chunk) pair
+        int64_t ro0 = 0, ro1 = 0;  // clamped byte range of row cb + pr
+        const int64_t pw0 = s_w0, pw1 = s_w1;
+        auto load_offs = [&](int64_t cb) {
+            const int64_t i = cb + pr;
+            if (pv < a.nv && i < ib) {
+                int64_t o0, o1;
+                if (i >= pw0 && i < pw1) {  // probed by the row search
+                    o0 = s_po[i - pw0];
+                    o1 = s_po[i - pw0 + 1];
+                } else {
+                    o0 = a.offs[i];
+                    o1 = a.offs[i + 1];
+                }
+                o0 = o0 < 0 ? 0 : (o0 > a.nbytes ? a.nbytes : o0);
+                o1 = o1 < o0 ? o0 : (o1 > a.nbytes ? a.nbytes : o1);
+                ro0 = o0;
+                ro1 = o1;
+            }
+        };
+        load_offs(ia);
+        if (PF) {
+            pf = L + G < a.ntiles;
+            if (pf) {
+                const int64_t tn = xcd_tile(L + G, a.ntiles);  // this block's next tile
+                pf = tile_interior<U>(a, tn);
+                if (pf) fetch_tile<U>(a, tn, v, halo, stid);
+            }
+        }
+        for (int64_t cb = ia; cb < ib; cb += R) {
+            if (cb != ia) load_offs(cb);
+            const int nrc = (int)((ib - cb) < R ? (ib - cb) : R);  // rows in this chunk
             int64_t gcnt = 0;
-            if (i < ib) {
-                const Row r = load_row(i, k);
+            if (pv < a.nv && pr < nrc) {
+                // segment of row i for vocabulary pv
+                const int64_t i = cb + pr;
+                const VocabLds &vl = vtab[pv];
+                const int32_t k = KMER ? vl.k : 1;
+                const Row r = make_row(ro0, ro1, k, vl.kinv);
                 int64_t clo = 0, chi = 0;
-                if (!(a.padded && r.len > o.W)) {
-                    clo = cells_before(r, P0, k, a.cls, a.padded, a.left, o.W);
-                    chi = cells_before(r, P1, k, a.cls, a.padded, a.left, o.W);
+                if (!(a.padded && r.len > vl.W)) {
+                    clo = cells_before(r, P0, k, vl.kinv, a.cls, a.padded, a.left, vl.W);
+                    chi = cells_before(r, P1, k, vl.kinv, a.cls, a.padded, a.left, vl.W);
                 }
                 const int64_t ncell = chi - clo;
-                const int64_t lead = (a.padded && a.left) ? o.W - r.len : 0;
+                const int64_t lead = (a.padded && a.left) ? vl.W - r.len : 0;
                 const int64_t tt0 = clo - lead;  // token index of the first owned cell
                 SegInfo sg;
                 sg.ncell = (int32_t)ncell;
@@ -502,121 +675,143 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
                 sg.b1 = clamp_cells(a.cls + r.nb - tt0, ncell);
                 sg.cc_cls = a.cls ? clamp_rel(-tt0, ncell) : -1;
                 sg.cc_sep = a.cls ? clamp_rel(r.len - 1 - tt0, ncell) : -1;
-                sg.cc_tail = (KMER && r.nb > 0 && (r.end - r.off) % k) ? clamp_rel(a.cls + r.nb - 1 - tt0, ncell) : -1;
+                sg.cc_tail = (KMER && r.nb > 0 && r.nb * k != r.end - r.off) ? clamp_rel(a.cls + r.nb - 1 - tt0, ncell) : -1;
                 sg.base_idx = (r.off - P0) + (tt0 - a.cls) * k;
-                sg.dlo = a.padded ? i * o.W + clo : (a.fused_packed ? s_prefix[i] : o.out_offs[i] - o.base) + clo;
-                sg.gpre = 0;
+                sg.dlo = a.padded ? i * vl.W + clo : (a.fused_packed ? s_prefix[i] : vl.out_offs[i] - vl.base) + clo;
                 seg[tid] = sg;
-                if (ncell > 0) gcnt = ((sg.dlo + al + ncell - 1) >> 2) - ((sg.dlo + al) >> 2) + 1;
+                if (ncell > 0) gcnt = ((sg.dlo + vl.al + ncell - 1) >> 2) - ((sg.dlo + vl.al) >> 2) + 1;
             }
+            // groups of all pairs, vocabulary-major; vocabulary v's are [s_vg[v], s_vg[v + 1])
             int64_t G4;
             const int64_t gpre = dev::block_excl_scan<NT>(gcnt, s_tmp, &G4);
-            if (i < ib) seg[tid].gpre = gpre;
+            if (pv < a.nv && pr < nrc) seg[tid].gpre = gpre;
+            if (pv < a.nv && pr == 0) s_vg[pv] = gpre;
+            if (tid == 0) s_vg[a.nv] = G4;
             __syncthreads();
 
-            // Groups walk segments in order: cache the current segment's facts
-            // in registers and reload them only when a group crosses into
-            // another segment.
-            int s = -1;
-            int64_t seg_lo = 0, seg_hi = -1;  // groups [seg_lo, seg_hi) belong to segment s
-            SegInfo sg{};
-            int64_t gb = 0;      // aligned group index of the segment's first group, minus gpre
-            int32_t ccb = 0;     // relative cell of the first element of group qi = ccb + 4 * (qi - seg_lo)
-            for (int64_t qi = tid; qi < G4; qi += NT) {
-                if (qi < seg_lo || qi >= seg_hi) {
-                    int lo = 0, hi = nrows - 1;
-                    while (lo < hi) {  // last segment with gpre <= qi
-                        int mid = (lo + hi + 1) >> 1;
-                        if (seg[mid].gpre <= qi) lo = mid;
-                        else hi = mid - 1;
-                    }
-                    s = lo;
-                    sg = seg[s];
-                    seg_lo = sg.gpre;
-                    seg_hi = (s + 1 < nrows) ? seg[s + 1].gpre : G4;
-                    gb = ((sg.dlo + al) >> 2) - sg.gpre;
-                    ccb = (int32_t)((((sg.dlo + al) >> 2) * 4 - al) - sg.dlo);
-                }
-                const int64_t eb = (gb + qi) * 4 - al;
-                const int32_t cc0 = ccb + 4 * (int32_t)(qi - seg_lo);
-                int32_t *dst = o.ids + eb;
-                // Fast path: four body tokens, none of them a short final frame.
-                const bool fast = cc0 >= sg.b0 && cc0 + 3 < sg.b1 && (uint32_t)(sg.cc_tail - cc0) > 3u &&
-                                  (a.padded || (eb >= 0 && eb + 3 < o.cap));
-                if (fast) {
-                    const uint32_t idx0 = (uint32_t)sg.base_idx + (uint32_t)cc0 * (uint32_t)k;
-                    int32_t vv[4];
-#pragma unroll
-                    for (int rr = 0; rr < 4; ++rr) {
-                        const uint32_t idx = idx0 + (uint32_t)(rr * k);
-                        if (KMER) vv[rr] = kmer_at(win64, val32, idx, k);
-                        else vv[rr] = lut_s[raw[idx]];
-                    }
-                    i32x4 x = {vv[0], vv[1], vv[2], vv[3]};
-                    __builtin_nontemporal_store(x, reinterpret_cast<i32x4 *>(dst));
-                    if (a.padded) {
-                        int8_t *md = o.mask + eb;
-                        if ((reinterpret_cast<uintptr_t>(md) & 3) == 0)
-                            __builtin_nontemporal_store(0x01010101u, reinterpret_cast<uint32_t *>(md));
-                        else
-                            for (int rr = 0; rr < 4; ++rr) md[rr] = 1;
-                    }
-                    continue;
-                }
-                int32_t vv[4];
-                uint32_t mk = 0;
-                bool in[4];
-                bool all_in = true;
-#pragma unroll
-                for (int rr = 0; rr < 4; ++rr) {
-                    const int32_t cc = cc0 + rr;
-                    in[rr] = (cc >= 0 && cc < sg.ncell);
-                    if (in[rr] && !a.padded && (eb + rr < 0 || eb + rr >= o.cap)) {
-                        in[rr] = false;
-                        err |= DNATOK_DERR_CAPACITY;
-                    }
-                    all_in = all_in && in[rr];
-                    int32_t val = o.pad_id;
-                    uint32_t m = 0;
-                    if (in[rr]) {
-                        if (cc >= sg.b0 && cc < sg.b1) {
-                            m = 1;
-                            const uint32_t idx = (uint32_t)sg.base_idx + (uint32_t)cc * (uint32_t)k;
-                            if (KMER) val = (cc == sg.cc_tail) ? DNATOK_ID_UNK : kmer_at(win64, val32, idx, k);
-                            else val = lut_s[raw[idx]];
-                        } else if (cc == sg.cc_cls) {
-                            val = o.cls_id;
-                            m = 1;
-                        } else if (cc == sg.cc_sep) {
-                            val = o.sep_id;
-                            m = 1;
+            // Each wave goes on to the next vocabulary as soon as it is done
+            // with this one: no barrier until the chunk ends.
+            for (int vi = 0; vi < a.nv; ++vi) {
+                const VocabOut &o = a.vo[vi];
+                const int32_t k = KMER ? o.k : 1;
+                const int64_t al = o.al;
+                int32_t *const ids_v = o.ids;
+                int8_t *const mask_v = o.mask;
+                const int64_t cap_v = o.cap;
+                // mask + element e is 4-byte aligned for every group start e = 4g - al
+                const bool mask4 = ((reinterpret_cast<uintptr_t>(mask_v) - (uintptr_t)al) & 3) == 0;
+                const bool k4 = k <= 8;
+                const Kmer4 kc = kmer4_consts(k4 ? k : 8);
+                const int64_t q0 = s_vg[vi], q1 = s_vg[vi + 1];
+                const int sbase = vi * R;
+                // Groups walk segments in order: cache the current segment's facts
+                // in registers and reload them only when a group crosses into
+                // another segment.
+                int64_t seg_lo = 0, seg_hi = -1;  // groups [seg_lo, seg_hi) belong to the cached segment
+                SegInfo sg{};
+                int64_t geb = 0;     // first element of group qi = geb + 4 * qi
+                int32_t ccb = 0;     // relative cell of the first element of group qi = ccb + 4 * (qi - seg_lo)
+                int32_t f_lo = 0, f_hi = -1;  // groups starting at a relative cell in [f_lo, f_hi] are four body tokens
+                // group qi is written by thread qi % NT, across vocabularies
+                for (int64_t qi = q0 + ((tid - q0) & (NT - 1)); qi < q1; qi += NT) {
+                    if (qi < seg_lo || qi >= seg_hi) {
+                        int lo = sbase, hi = sbase + nrc - 1;
+                        while (lo < hi) {  // last segment with gpre <= qi
+                            int mid = (lo + hi + 1) >> 1;
+                            if (seg[mid].gpre <= qi) lo = mid;
+                            else hi = mid - 1;
                         }
+                        sg = seg[lo];
+                        seg_lo = sg.gpre;
+                        seg_hi = (lo + 1 < sbase + nrc) ? seg[lo + 1].gpre : q1;
+                        const int64_t g0 = (sg.dlo + al) >> 2;  // aligned group holding the first owned cell
+                        geb = (g0 - sg.gpre) * 4 - al;
+                        ccb = (int32_t)((g0 * 4 - al) - sg.dlo);
+                        // the short final frame (if owned here) is the last body cell
+                        const int32_t fe = (sg.cc_tail >= sg.b0 && sg.cc_tail < sg.b1) ? sg.cc_tail : sg.b1;
+                        f_lo = sg.b0;
+                        f_hi = fe - 4;
                     }
-                    vv[rr] = val;
-                    mk |= m << (8 * rr);
-                }
-                if (all_in) {
-                    *reinterpret_cast<int4 *>(dst) = make_int4(vv[0], vv[1], vv[2], vv[3]);
-                    if (a.padded) {
-                        int8_t *md = o.mask + eb;
-                        if ((reinterpret_cast<uintptr_t>(md) & 3) == 0) {
-                            *reinterpret_cast<uint32_t *>(md) = mk;
+                    const int64_t eb = geb + 4 * qi;
+                    const int32_t cc0 = ccb + 4 * (int32_t)(qi - seg_lo);
+                    int32_t *dst = ids_v + eb;
+                    const bool fast = cc0 >= f_lo && cc0 <= f_hi && (a.padded || (eb >= 0 && eb + 3 < cap_v));
+                    if (fast) {
+                        const uint32_t idx0 = (uint32_t)sg.base_idx + (uint32_t)cc0 * (uint32_t)k;
+                        i32x4 x;
+                        if (KMER && k4) {
+                            x = kmer4_at(win64, val32, idx0, kc);
                         } else {
-#pragma unroll
-                            for (int rr = 0; rr < 4; ++rr) md[rr] = (int8_t)((mk >> (8 * rr)) & 1);
+    #pragma unroll
+                            for (int rr = 0; rr < 4; ++rr) {
+                                const uint32_t idx = idx0 + (uint32_t)(rr * k);
+                                x[rr] = KMER ? kmer_at(win64, val32, idx, k) : lut_s[raw[idx]];
+                            }
                         }
+                        __builtin_nontemporal_store(x, reinterpret_cast<i32x4 *>(dst));
+                        if (a.padded) {
+                            int8_t *md = mask_v + eb;
+                            if (mask4)
+                                __builtin_nontemporal_store(0x01010101u, reinterpret_cast<uint32_t *>(md));
+                            else
+                                for (int rr = 0; rr < 4; ++rr) md[rr] = 1;
+                        }
+                        continue;
                     }
-                } else {
-#pragma unroll
+                    int32_t vv[4];
+                    uint32_t mk = 0;
+                    bool in[4];
+                    bool all_in = true;
+    #pragma unroll
                     for (int rr = 0; rr < 4; ++rr) {
-                        if (!in[rr]) continue;
-                        dst[rr] = vv[rr];
-                        if (a.padded) o.mask[eb + rr] = (int8_t)((mk >> (8 * rr)) & 1);
+                        const int32_t cc = cc0 + rr;
+                        in[rr] = (cc >= 0 && cc < sg.ncell);
+                        if (in[rr] && !a.padded && (eb + rr < 0 || eb + rr >= cap_v)) {
+                            in[rr] = false;
+                            err |= DNATOK_DERR_CAPACITY;
+                        }
+                        all_in = all_in && in[rr];
+                        int32_t val = o.pad_id;
+                        uint32_t m = 0;
+                        if (in[rr]) {
+                            if (cc >= sg.b0 && cc < sg.b1) {
+                                m = 1;
+                                const uint32_t idx = (uint32_t)sg.base_idx + (uint32_t)cc * (uint32_t)k;
+                                if (KMER) val = (cc == sg.cc_tail) ? DNATOK_ID_UNK : kmer_at(win64, val32, idx, k);
+                                else val = lut_s[raw[idx]];
+                            } else if (cc == sg.cc_cls) {
+                                val = o.cls_id;
+                                m = 1;
+                            } else if (cc == sg.cc_sep) {
+                                val = o.sep_id;
+                                m = 1;
+                            }
+                        }
+                        vv[rr] = val;
+                        mk |= m << (8 * rr);
+                    }
+                    if (all_in) {
+                        *reinterpret_cast<int4 *>(dst) = make_int4(vv[0], vv[1], vv[2], vv[3]);
+                        if (a.padded) {
+                            int8_t *md = mask_v + eb;
+                            if (mask4) {
+                                *reinterpret_cast<uint32_t *>(md) = mk;
+                            } else {
+    #pragma unroll
+                                for (int rr = 0; rr < 4; ++rr) md[rr] = (int8_t)((mk >> (8 * rr)) & 1);
+                            }
+                        }
+                    } else {
+    #pragma unroll
+                        for (int rr = 0; rr < 4; ++rr) {
+                            if (!in[rr]) continue;
+                            dst[rr] = vv[rr];
+                            if (a.padded) mask_v[eb + rr] = (int8_t)((mk >> (8 * rr)) & 1);
+                        }
                     }
                 }
             }
             __syncthreads();
-        }
         }
     }
     if (err) atomicOr(&s_err, err);
@@ -624,29 +819,29 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
     if (tid == 0 && s_err) dev::raise_error(a.err_hdr, s_err);
 }
 
-template <bool KMER>
+template <bool KMER, bool PF>
 int launch_cells(const CellArgs &a, int U, int64_t grid, size_t dyn, hipStream_t stream) {
     switch (U) {
-    case 1: hipLaunchKernelGGL((k_cells<KMER, 1>), dim3((unsigned)grid), dim3(NT), dyn, stream, a); break;
-    case 2: hipLaunchKernelGGL((k_cells<KMER, 2>), dim3((unsigned)grid), dim3(NT), dyn, stream, a); break;
-    case 4: hipLaunchKernelGGL((k_cells<KMER, 4>), dim3((unsigned)grid), dim3(NT), dyn, stream, a); break;
-    case 8: hipLaunchKernelGGL((k_cells<KMER, 8>), dim3((unsigned)grid), dim3(NT), dyn, stream, a); break;
-    case 16: hipLaunchKernelGGL((k_cells<KMER, 16>), dim3((unsigned)grid), dim3(NT), dyn, stream, a); break;
+    case 1: hipLaunchKernelGGL((k_cells<KMER, 1, PF>), dim3((unsigned)grid), dim3(NT), dyn, stream, a); break;
+    case 2: hipLaunchKernelGGL((k_cells<KMER, 2, PF>), dim3((unsigned)grid), dim3(NT), dyn, stream, a); break;
+    case 4: hipLaunchKernelGGL((k_cells<KMER, 4, PF>), dim3((unsigned)grid), dim3(NT), dyn, stream, a); break;
+    case 8: hipLaunchKernelGGL((k_cells<KMER, 8, PF>), dim3((unsigned)grid), dim3(NT), dyn, stream, a); break;
+    case 16: hipLaunchKernelGGL((k_cells<KMER, 16, PF>), dim3((unsigned)grid), dim3(NT), dyn, stream, a); break;
     default: return set_error(DNATOK_EINVAL, "unsupported staging depth %d", U);
     }
     DNATOK_HIP(hipGetLastError());
     return DNATOK_OK;
 }
 
-template <bool KMER>
+template <bool KMER, bool PF>
 int blocks_per_cu(int U, size_t dyn, int *out) {
     *out = 1;
     switch (U) {
-    case 1: DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_cells<KMER, 1>, NT, dyn)); break;
-    case 2: DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_cells<KMER, 2>, NT, dyn)); break;
-    case 4: DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_cells<KMER, 4>, NT, dyn)); break;
-    case 8: DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_cells<KMER, 8>, NT, dyn)); break;
-    case 16: DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_cells<KMER, 16>, NT, dyn)); break;
+    case 1: DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_cells<KMER, 1, PF>, NT, dyn)); break;
+    case 2: DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_cells<KMER, 2, PF>, NT, dyn)); break;
+    case 4: DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_cells<KMER, 4, PF>, NT, dyn)); break;
+    case 8: DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_cells<KMER, 8, PF>, NT, dyn)); break;
+    case 16: DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_cells<KMER, 16, PF>, NT, dyn)); break;
     default: break;
     }
     return DNATOK_OK;
@@ -662,6 +857,7 @@ int launch_rowscan(const int64_t *d_offsets, int32_t n, int64_t nbytes, int64_t 
     s.nbytes = nbytes;
     s.out_offs = d_out;
     s.k = divisor;
+    s.kinv = 0xFFFFFFFFu / (uint32_t)(divisor > 0 ? divisor : 1);
     s.kmer = 1;
     s.cls = cls;
     s.padded = 0;
@@ -736,6 +932,7 @@ int launch_encode_multi(const dnatok_vocab *const *vs, int nv, const uint8_t *d_
         const dnatok_vocab *w = vs[vi];
         VocabOut &out = a.vo[vi];
         out.k = kmer ? w->k : 1;
+        out.kinv = 0xFFFFFFFFu / (uint32_t)out.k;
         out.al = (int32_t)((reinterpret_cast<uintptr_t>(d_ids[vi]) >> 2) & 3);
         out.ids = d_ids[vi];
         out.cap = caps[vi];
@@ -755,6 +952,7 @@ int launch_encode_multi(const dnatok_vocab *const *vs, int nv, const uint8_t *d_
         sc.nbytes = nbytes;
         sc.out_offs = d_out_offsets[vi];
         sc.k = out.k;
+        sc.kinv = out.kinv;
         sc.kmer = kmer ? 1 : 0;
         sc.cls = a.cls;
         sc.padded = a.padded;
@@ -779,18 +977,27 @@ int launch_encode_multi(const dnatok_vocab *const *vs, int nv, const uint8_t *d_
     const size_t dyn_tile = ((kmer ? (size_t)nchunks * 12 : (size_t)nchunks * 16) + 15) / 16 * 16;
     a.prefix_off = (int32_t)dyn_tile;
     const size_t dyn = dyn_tile + (a.fused_packed ? 8 * (size_t)(n + 1) : 0);
-    int per_cu = 0;
-    rc = kmer ? blocks_per_cu<true>(U, dyn, &per_cu) : blocks_per_cu<false>(U, dyn, &per_cu);
-    if (rc) return rc;
-    if (per_cu < 1) per_cu = 1;
-    if (tune.blocks_per_cu > 0 && tune.blocks_per_cu < per_cu) per_cu = tune.blocks_per_cu;
-    // As many blocks as fit, then evened out so every block walks the same
-    // number of tiles (no straggler round).
-    const int64_t gmax = (int64_t)device_cu_count() * per_cu;
-    const int64_t per_block = (a.ntiles + gmax - 1) / gmax;
+    // As many tile walkers as fit, then evened out so every walker takes the
+    // same number of tiles (no straggler round). Walkers with more than one
+    // tile use the prefetching kernel, whose occupancy may be lower.
+    int64_t per_block = 1;
+    for (int pass = 0; pass < 2; ++pass) {
+        const bool pfk = pass == 1;
+        int per_cu = 0;
+        rc = kmer ? (pfk ? blocks_per_cu<true, true>(U, dyn, &per_cu) : blocks_per_cu<true, false>(U, dyn, &per_cu))
+                  : (pfk ? blocks_per_cu<false, true>(U, dyn, &per_cu) : blocks_per_cu<false, false>(U, dyn, &per_cu));
+        if (rc) return rc;
+        if (per_cu < 1) per_cu = 1;
+        if (tune.blocks_per_cu > 0 && tune.blocks_per_cu < per_cu) per_cu = tune.blocks_per_cu;
+        const int64_t gmax = (int64_t)device_cu_count() * per_cu;
+        per_block = (a.ntiles + gmax - 1) / gmax;
+        if (per_block == 1) break;  // one tile each: no prefetch
+    }
+    const bool pf = per_block > 1;
     int64_t grid = (a.ntiles + per_block - 1) / per_block;
-    if (a.fused_scan) grid += 1;
-    return kmer ? launch_cells<true>(a, U, grid, dyn, stream) : launch_cells<false>(a, U, grid, dyn, stream);
+    if (a.fused_scan) grid += nv;
+    if (kmer) return pf ? launch_cells<true, true>(a, U, grid, dyn, stream) : launch_cells<true, false>(a, U, grid, dyn, stream);
+    return pf ? launch_cells<false, true>(a, U, grid, dyn, stream) : launch_cells<false, false>(a, U, grid, dyn, stream);
 }
 
 int launch_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets,
