@@ -328,6 +328,7 @@ struct CellArgs {
     int32_t fused_scan;  // the last block runs the row scans instead of tiles
     int32_t fused_packed;   // PACKED, <= kFusePackedRows rows: each block scans the row lengths into LDS
     int32_t prefix_off;     // byte offset of that scan in the dynamic LDS
+    int32_t lut_off;        // byte offset of the 256-entry table in the dynamic LDS (SINGLE, LUT256)
     uint32_t *err_hdr;
     VocabOut vo[kMaxMultiVocabs];
     RowScanArgs scan[kMaxMultiVocabs];
@@ -343,17 +344,59 @@ struct VocabLds {
     int32_t pad_;
     int64_t W;
     int64_t base;
+    int64_t cap;
     const int64_t *out_offs;
 };
 
 struct SegInfo {
-    int64_t dlo;       // destination element of the first owned cell
-    int64_t gpre;      // first 4-element store group of this segment in the chunk's group list
-    int64_t base_idx;  // tile-relative byte index of the body token at relative cell 0
-    int32_t ncell;     // owned cells
-    int32_t b0, b1;    // relative cells holding body tokens
+    int64_t dlo;        // destination element of the first owned cell
+    int64_t epre;       // first edge group of this segment in the chunk's edge list
+    uint32_t base_idx;  // tile-relative byte index (mod 2^32) of the body token at relative cell 0
+    int32_t ncell;      // owned cells
+    int32_t b0, b1;     // relative cells holding body tokens
     int32_t cc_cls, cc_sep, cc_tail;  // relative cells of CLS, SEP and a short final k-mer (-1 if none)
+    int32_t ipre;       // first interior group of this segment in the chunk's interior list
 };
+
+// The aligned 4-element store groups of a segment whose first owned cell
+// goes to element dlo (ids are 16-byte aligned at element -al): groups
+// [gfirst, glast] touch it; [gA, gB) hold four body tokens, none of them the
+// short final frame, and (PACKED) lie inside the capacity. The rest are its
+// edge groups: [gfirst, gA) and [gB, glast].
+struct SegGroups {
+    int64_t gfirst, glast, gA, gB;
+};
+
+__device__ __forceinline__ SegGroups seg_groups(int64_t dlo, int64_t al, int32_t ncell, int32_t b0, int32_t b1,
+                                                int32_t cc_tail, bool padded, int64_t cap) {
+    SegGroups g;
+    if (ncell <= 0) {
+        g.gfirst = 0;
+        g.glast = -1;
+        g.gA = 0;
+        g.gB = 0;
+        return g;
+    }
+    g.gfirst = (dlo + al) >> 2;
+    g.glast = (dlo + al + ncell - 1) >> 2;
+    const int32_t fe = (cc_tail >= b0 && cc_tail < b1) ? cc_tail : b1;  // end of the full frames
+    int64_t gA = (dlo + al + b0 + 3) >> 2;
+    int64_t gB = (dlo + al + fe) >> 2;
+    if (!padded) {
+        const int64_t lo = (al + 3) >> 2, hi = (cap + al) >> 2;  // element 4g - al in [0, cap - 3]
+        gA = gA > lo ? gA : lo;
+        gB = gB < hi ? gB : hi;
+    }
+    if (gB < gA) gB = gA;
+    g.gA = gA;
+    g.gB = gB;
+    return g;
+}
+
+__device__ __forceinline__ int32_t rfl(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t rfl64(int64_t v) {
+    return (int64_t)(((uint64_t)(uint32_t)rfl((int32_t)(v >> 32)) << 32) | (uint32_t)rfl((int32_t)v));
+}
 
 __device__ __forceinline__ uint4 load_chunk(const CellArgs &a, int64_t q0) {
     if (q0 >= a.shift && q0 + 16 <= a.shift + a.nbytes)
@@ -403,12 +446,13 @@ __device__ __forceinline__ void fetch_tile(const CellArgs &a, int64_t t, uint4 (
 template <bool KMER, int U, bool PF>
 __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
     extern __shared__ __align__(16) uint8_t dyn[];
-    __shared__ int32_t lut_s[256];
     __shared__ SegInfo seg[NT];
     __shared__ VocabLds vtab[kMaxMultiVocabs];
     __shared__ int64_t s_vg[kMaxMultiVocabs + 1];
     __shared__ int64_t s_po[dev::kWave + 1];  // offs[s_w0 ..] as probed by the row search
     __shared__ int64_t s_w0, s_w1;
+    __shared__ int32_t s_clist[NT], s_cpre[NT];  // segments holding interior groups, and their first one
+    __shared__ int64_t s_itot;
     __shared__ int64_t s_tmp[NT / dev::kWave + 1];
     __shared__ int64_t s_ia, s_ib;
     __shared__ uint32_t s_err;
@@ -423,6 +467,7 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
         return;
     }
     const int64_t bid = blockIdx.x;
+    int32_t *lut_s = reinterpret_cast<int32_t *>(dyn + a.lut_off);
     if (!KMER)
         for (int i = tid; i < 256; i += NT) lut_s[i] = a.vo[0].lut[i];
     if (tid == 0) s_err = 0;
@@ -435,6 +480,7 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
             e.pad_ = 0;
             e.W = a.vo[vi].W;
             e.base = a.vo[vi].base;
+            e.cap = a.vo[vi].cap;
             e.out_offs = a.vo[vi].out_offs;
             vtab[vi] = e;
         }
@@ -654,7 +700,7 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
         for (int64_t cb = ia; cb < ib; cb += R) {
             if (cb != ia) load_offs(cb);
             const int nrc = (int)((ib - cb) < R ? (ib - cb) : R);  // rows in this chunk
-            int64_t gcnt = 0;
+            int64_t nint = 0, nedge = 0;  // this pair's interior and edge groups
             if (pv < a.nv && pr < nrc) {
                 // segment of row i for vocabulary pv
                 const int64_t i = cb + pr;
@@ -676,21 +722,115 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
                 sg.cc_cls = a.cls ? clamp_rel(-tt0, ncell) : -1;
                 sg.cc_sep = a.cls ? clamp_rel(r.len - 1 - tt0, ncell) : -1;
                 sg.cc_tail = (KMER && r.nb > 0 && r.nb * k != r.end - r.off) ? clamp_rel(a.cls + r.nb - 1 - tt0, ncell) : -1;
-                sg.base_idx = (r.off - P0) + (tt0 - a.cls) * k;
+                sg.base_idx = (uint32_t)((r.off - P0) + (tt0 - a.cls) * k);
                 sg.dlo = a.padded ? i * vl.W + clo : (a.fused_packed ? s_prefix[i] : vl.out_offs[i] - vl.base) + clo;
+                const SegGroups gg =
+                    seg_groups(sg.dlo, vl.al, sg.ncell, sg.b0, sg.b1, sg.cc_tail, a.padded != 0, vl.cap);
+                nint = gg.gB - gg.gA;
+                nedge = (gg.gA - gg.gfirst) + (gg.glast + 1 - gg.gB);
                 seg[tid] = sg;
-                if (ncell > 0) gcnt = ((sg.dlo + vl.al + ncell - 1) >> 2) - ((sg.dlo + vl.al) >> 2) + 1;
             }
-            // groups of all pairs, vocabulary-major; vocabulary v's are [s_vg[v], s_vg[v + 1])
-            int64_t G4;
-            const int64_t gpre = dev::block_excl_scan<NT>(gcnt, s_tmp, &G4);
-            if (pv < a.nv && pr < nrc) seg[tid].gpre = gpre;
-            if (pv < a.nv && pr == 0) s_vg[pv] = gpre;
-            if (tid == 0) s_vg[a.nv] = G4;
+            // Interior groups (with the count of segments holding any in the
+            // top bits) and edge groups of all pairs, vocabulary-major.
+            int64_t itot, etot;
+            const int64_t ipk = dev::block_excl_scan<NT>(((int64_t)(nint > 0) << 52) | nint, s_tmp, &itot);
+            const int64_t epre = dev::block_excl_scan<NT>(nedge, s_tmp, &etot);
+            if (pv < a.nv && pr < nrc) {
+                seg[tid].ipre = (int32_t)(ipk & ((1ll << 52) - 1));
+                seg[tid].epre = epre;
+                if (nint > 0) {
+                    s_clist[ipk >> 52] = tid;
+                    s_cpre[ipk >> 52] = (int32_t)(ipk & ((1ll << 52) - 1));
+                }
+            }
+            if (pv < a.nv && pr == 0) s_vg[pv] = epre;  // vocabulary v's edges are [s_vg[v], s_vg[v + 1])
+            if (tid == 0) {
+                s_vg[a.nv] = etot;
+                s_itot = itot;
+            }
             __syncthreads();
 
-            // Each wave goes on to the next vocabulary as soon as it is done
-            // with this one: no barrier until the chunk ends.
+            // Interior groups: each wave takes a contiguous share of them,
+            // segment by segment, with the segment's and its vocabulary's
+            // facts uniform across the wave and two groups per lane in flight.
+            {
+                constexpr int NW = NT / dev::kWave;
+                const int64_t itv = s_itot;
+                const int32_t T = (int32_t)(itv & ((1ll << 52) - 1));
+                const int nz = (int)(itv >> 52);
+                const int wv = tid / dev::kWave, lane = tid & (dev::kWave - 1);
+                const int32_t x0 = (int32_t)((int64_t)T * wv / NW), x1 = (int32_t)((int64_t)T * (wv + 1) / NW);
+                if (x0 < x1) {
+                    // listed segments starting at or before x0, minus one
+                    int cnt = 0;
+#pragma unroll
+                    for (int r4 = 0; r4 < NT / dev::kWave; ++r4) {
+                        const int cl = r4 * dev::kWave + lane;
+                        cnt += __popcll(__ballot(cl < nz && s_cpre[cl] <= x0));
+                    }
+                    int c = cnt - 1;
+                    int32_t x = x0;
+                    while (x < x1) {
+                        const int sidx = rfl(s_clist[c]);
+                        const int vi = rfl(sidx / R);
+                        const VocabOut &o = a.vo[vi];
+                        const int32_t k = KMER ? o.k : 1;
+                        const int64_t al = o.al;
+                        const SegInfo &sr = seg[sidx];
+                        const int64_t dlo = rfl64(sr.dlo);
+                        const uint32_t bidx = (uint32_t)rfl((int32_t)sr.base_idx);
+                        const int32_t ipre = rfl(sr.ipre);
+                        const SegGroups gg = seg_groups(dlo, al, rfl(sr.ncell), rfl(sr.b0), rfl(sr.b1), rfl(sr.cc_tail),
+                                                        a.padded != 0, o.cap);
+                        const int32_t n = (int32_t)(gg.gB - gg.gA);
+                        const int32_t j0 = x - ipre;
+                        const int32_t j1 = (x1 < ipre + n ? x1 : ipre + n) - ipre;
+                        const int32_t cA = (int32_t)(4 * gg.gA - al - dlo);  // relative cell of group gA's first element
+                        i32x4 *d4 = reinterpret_cast<i32x4 *>(o.ids + (4 * gg.gA - al));
+                        int8_t *m1 = o.mask + (4 * gg.gA - al);
+                        const bool mask4 = ((reinterpret_cast<uintptr_t>(o.mask) - (uintptr_t)al) & 3) == 0;
+                        const bool k4 = k <= 8;
+                        const Kmer4 kc = kmer4_consts(k4 ? k : 8);
+                        auto ids_of = [&](int32_t j) {
+                            const uint32_t idx0 = bidx + (uint32_t)(cA + 4 * j) * (uint32_t)k;
+                            i32x4 y;
+                            if (KMER && k4) {
+                                y = kmer4_at(win64, val32, idx0, kc);
+                            } else {
+#pragma unroll
+                                for (int rr = 0; rr < 4; ++rr) {
+                                    const uint32_t idx = idx0 + (uint32_t)(rr * k);
+                                    y[rr] = KMER ? kmer_at(win64, val32, idx, k) : lut_s[raw[idx]];
+                                }
+                            }
+                            return y;
+                        };
+                        auto put = [&](int32_t j, i32x4 y) {
+                            __builtin_nontemporal_store(y, d4 + j);
+                            if (a.padded) {
+                                if (mask4)
+                                    __builtin_nontemporal_store(0x01010101u, reinterpret_cast<uint32_t *>(m1 + 4 * j));
+                                else
+                                    for (int rr = 0; rr < 4; ++rr) m1[4 * j + rr] = 1;
+                            }
+                        };
+                        for (int32_t j = j0 + lane; j < j1; j += 2 * dev::kWave) {
+                            const int32_t jb = j + dev::kWave;
+                            const bool hb = jb < j1;
+                            const i32x4 ya = ids_of(j);
+                            const i32x4 yb = ids_of(hb ? jb : j);
+                            put(j, ya);
+                            if (hb) put(jb, yb);
+                        }
+                        x = ipre + j1;
+                        ++c;
+                    }
+                }
+            }
+
+            // Edge groups (CLS, SEP, short final frames, pads, ragged ends,
+            // capacity overruns) cell by cell, vocabulary by vocabulary with
+            // no barrier between them: edge q is written by thread q % NT.
             for (int vi = 0; vi < a.nv; ++vi) {
                 const VocabOut &o = a.vo[vi];
                 const int32_t k = KMER ? o.k : 1;
@@ -698,71 +838,39 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
                 int32_t *const ids_v = o.ids;
                 int8_t *const mask_v = o.mask;
                 const int64_t cap_v = o.cap;
-                // mask + element e is 4-byte aligned for every group start e = 4g - al
                 const bool mask4 = ((reinterpret_cast<uintptr_t>(mask_v) - (uintptr_t)al) & 3) == 0;
-                const bool k4 = k <= 8;
-                const Kmer4 kc = kmer4_consts(k4 ? k : 8);
                 const int64_t q0 = s_vg[vi], q1 = s_vg[vi + 1];
                 const int sbase = vi * R;
-                // Groups walk segments in order: cache the current segment's facts
-                // in registers and reload them only when a group crosses into
-                // another segment.
-                int64_t seg_lo = 0, seg_hi = -1;  // groups [seg_lo, seg_hi) belong to the cached segment
+                // cached segment: edges [seg_lo, seg_hi), head edges h of them
+                int64_t seg_lo = 0, seg_hi = -1, gfirst = 0, gB = 0, h = 0;
                 SegInfo sg{};
-                int64_t geb = 0;     // first element of group qi = geb + 4 * qi
-                int32_t ccb = 0;     // relative cell of the first element of group qi = ccb + 4 * (qi - seg_lo)
-                int32_t f_lo = 0, f_hi = -1;  // groups starting at a relative cell in [f_lo, f_hi] are four body tokens
-                // group qi is written by thread qi % NT, across vocabularies
-                for (int64_t qi = q0 + ((tid - q0) & (NT - 1)); qi < q1; qi += NT) {
-                    if (qi < seg_lo || qi >= seg_hi) {
+                for (int64_t qe = q0 + ((tid - q0) & (NT - 1)); qe < q1; qe += NT) {
+                    if (qe < seg_lo || qe >= seg_hi) {
                         int lo = sbase, hi = sbase + nrc - 1;
-                        while (lo < hi) {  // last segment with gpre <= qi
+                        while (lo < hi) {  // last segment with epre <= qe
                             int mid = (lo + hi + 1) >> 1;
-                            if (seg[mid].gpre <= qi) lo = mid;
+                            if (seg[mid].epre <= qe) lo = mid;
                             else hi = mid - 1;
                         }
                         sg = seg[lo];
-                        seg_lo = sg.gpre;
-                        seg_hi = (lo + 1 < sbase + nrc) ? seg[lo + 1].gpre : q1;
-                        const int64_t g0 = (sg.dlo + al) >> 2;  // aligned group holding the first owned cell
-                        geb = (g0 - sg.gpre) * 4 - al;
-                        ccb = (int32_t)((g0 * 4 - al) - sg.dlo);
-                        // the short final frame (if owned here) is the last body cell
-                        const int32_t fe = (sg.cc_tail >= sg.b0 && sg.cc_tail < sg.b1) ? sg.cc_tail : sg.b1;
-                        f_lo = sg.b0;
-                        f_hi = fe - 4;
+                        seg_lo = sg.epre;
+                        seg_hi = (lo + 1 < sbase + nrc) ? seg[lo + 1].epre : q1;
+                        const SegGroups gg =
+                            seg_groups(sg.dlo, al, sg.ncell, sg.b0, sg.b1, sg.cc_tail, a.padded != 0, cap_v);
+                        gfirst = gg.gfirst;
+                        gB = gg.gB;
+                        h = gg.gA - gg.gfirst;
                     }
-                    const int64_t eb = geb + 4 * qi;
-                    const int32_t cc0 = ccb + 4 * (int32_t)(qi - seg_lo);
+                    const int64_t le = qe - seg_lo;
+                    const int64_t gq = le < h ? gfirst + le : gB + (le - h);
+                    const int64_t eb = 4 * gq - al;
+                    const int32_t cc0 = (int32_t)(eb - sg.dlo);
                     int32_t *dst = ids_v + eb;
-                    const bool fast = cc0 >= f_lo && cc0 <= f_hi && (a.padded || (eb >= 0 && eb + 3 < cap_v));
-                    if (fast) {
-                        const uint32_t idx0 = (uint32_t)sg.base_idx + (uint32_t)cc0 * (uint32_t)k;
-                        i32x4 x;
-                        if (KMER && k4) {
-                            x = kmer4_at(win64, val32, idx0, kc);
-                        } else {
-    #pragma unroll
-                            for (int rr = 0; rr < 4; ++rr) {
-                                const uint32_t idx = idx0 + (uint32_t)(rr * k);
-                                x[rr] = KMER ? kmer_at(win64, val32, idx, k) : lut_s[raw[idx]];
-                            }
-                        }
-                        __builtin_nontemporal_store(x, reinterpret_cast<i32x4 *>(dst));
-                        if (a.padded) {
-                            int8_t *md = mask_v + eb;
-                            if (mask4)
-                                __builtin_nontemporal_store(0x01010101u, reinterpret_cast<uint32_t *>(md));
-                            else
-                                for (int rr = 0; rr < 4; ++rr) md[rr] = 1;
-                        }
-                        continue;
-                    }
                     int32_t vv[4];
                     uint32_t mk = 0;
                     bool in[4];
                     bool all_in = true;
-    #pragma unroll
+#pragma unroll
                     for (int rr = 0; rr < 4; ++rr) {
                         const int32_t cc = cc0 + rr;
                         in[rr] = (cc >= 0 && cc < sg.ncell);
@@ -776,7 +884,7 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
                         if (in[rr]) {
                             if (cc >= sg.b0 && cc < sg.b1) {
                                 m = 1;
-                                const uint32_t idx = (uint32_t)sg.base_idx + (uint32_t)cc * (uint32_t)k;
+                                const uint32_t idx = sg.base_idx + (uint32_t)cc * (uint32_t)k;
                                 if (KMER) val = (cc == sg.cc_tail) ? DNATOK_ID_UNK : kmer_at(win64, val32, idx, k);
                                 else val = lut_s[raw[idx]];
                             } else if (cc == sg.cc_cls) {
@@ -797,12 +905,12 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
                             if (mask4) {
                                 *reinterpret_cast<uint32_t *>(md) = mk;
                             } else {
-    #pragma unroll
+#pragma unroll
                                 for (int rr = 0; rr < 4; ++rr) md[rr] = (int8_t)((mk >> (8 * rr)) & 1);
                             }
                         }
                     } else {
-    #pragma unroll
+#pragma unroll
                         for (int rr = 0; rr < 4; ++rr) {
                             if (!in[rr]) continue;
                             dst[rr] = vv[rr];
@@ -975,8 +1083,9 @@ int launch_encode_multi(const dnatok_vocab *const *vs, int nv, const uint8_t *d_
     }
 
     const size_t dyn_tile = ((kmer ? (size_t)nchunks * 12 : (size_t)nchunks * 16) + 15) / 16 * 16;
-    a.prefix_off = (int32_t)dyn_tile;
-    const size_t dyn = dyn_tile + (a.fused_packed ? 8 * (size_t)(n + 1) : 0);
+    a.lut_off = (int32_t)dyn_tile;
+    a.prefix_off = (int32_t)(dyn_tile + (kmer ? 0 : 1024));
+    const size_t dyn = (size_t)a.prefix_off + (a.fused_packed ? 8 * (size_t)(n + 1) : 0);
     // As many tile walkers as fit, then evened out so every walker takes the
     // same number of tiles (no straggler round). Walkers with more than one
     // tile use the prefetching kernel, whose occupancy may be lower.

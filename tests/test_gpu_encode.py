@@ -342,6 +342,21 @@ def test_multi_vocab_many_rows_unfused_scan():
     _check_multi([_vocab(dt.KMER, k) for k in ks], ks, data, offs, True, dt.PADDED, dt.PAD_RIGHT)
 
 
+@pytest.mark.parametrize("ks", [(6,), (3, 4, 5, 6)])
+def test_walkers_with_several_tiles_prefetch(ks):
+    # 4 KiB tiles and one tile walker per CU: every walker takes several tiles
+    # (the tile count is not a multiple of the 8 XCDs) and puts the next one's
+    # loads in flight while writing the current one
+    data, offs = synth.workload_markov_batch(600, 5000, seed=synth.substream(95, len(ks)))
+    ragged = synth.offsets_from_lengths(np.random.default_rng(96).integers(0, 12000, 250))
+    ragged = ragged[ragged <= len(data)]
+    vs = [_vocab(dt.KMER, k) for k in ks]
+    dt.set_tuning(vs[0], tile_bytes=4096, blocks_per_cu=1)
+    _check_multi(vs, list(ks), data, offs, True, dt.PADDED, dt.PAD_RIGHT)
+    _check_multi(vs, list(ks), data, offs, False, dt.PACKED, dt.PAD_RIGHT)
+    _check_multi(vs, list(ks), data[:ragged[-1]], ragged, True, dt.PADDED, dt.PAD_LEFT)
+
+
 def test_multi_vocab_errors():
     torch = _torch()
     data, offs = _fuzz_batch(503, 10, 50)
