@@ -387,7 +387,7 @@ def small_leg(reps: int = 200):
 BPE_TABLE = os.path.join(ROOT, "tests", "golden", "bpe4096_order5_64M.txt")
 
 
-def bpe_leg(reps: int = 10):
+def bpe_leg(reps: int = 10, tuning=None, per_seq_leg: bool = True):
     """Ragged BPE batch: 1,024 sequences, lengths log-uniform in [500, 20000]
     bases, fresh walk of the order-5 Markov chain the 4096-merge table was
     trained on; PACKED ids, no specials. The fused form encodes the whole
@@ -415,8 +415,13 @@ def bpe_leg(reps: int = 10):
         dt.dnatok_encode(v.handle, d_in.data_ptr(), nbytes, d_offs.data_ptr(), n, ids.data_ptr(), nbytes,
                          oo.data_ptr(), None, opts, sp)
 
-    tune, tune_ms = dt.autotune(v, d_in, d_offs, h_offsets=offs, reps=1)
-    log("bpe autotuned: %s (%.3f ms)" % (tune, tune_ms))
+    if tuning is None:
+        tune, tune_ms = dt.autotune(v, d_in, d_offs, h_offsets=offs, reps=1)
+        log("bpe autotuned: %s (%.3f ms)" % (tune, tune_ms))
+    else:
+        dt.set_tuning(v, bpe_item_bytes=tuning[0], bpe_max_waves=tuning[1])
+        tune = dt.dnatok_get_tuning(v.handle).as_dict()
+        log("bpe tiling set: %s" % tune)
 
     fused()
     torch.cuda.synchronize()
@@ -432,6 +437,20 @@ def bpe_leg(reps: int = 10):
         evs.append((a, b))
     torch.cuda.synchronize()
     fused_ms = float(np.median([a.elapsed_time(b) for a, b in evs]))
+
+    out = {
+        "workload": "1024 sequences, log-uniform 500-20000 bases (%d bases), order-5 Markov, BPE 4096 merges "
+                    "(oracle trainer, 64 Mbase), PACKED, no specials" % nbytes,
+        "tokens": tokens,
+        ("autotuned" if tuning is None else "tiling"): {"bpe_item_bytes": tune["bpe_item_bytes"],
+                                                        "bpe_max_waves": tune["bpe_max_waves"]},
+        "fused_ms": round(fused_ms, 4),
+        "fused_tokens_per_s": tokens / (fused_ms * 1e-3),
+        "fused_bases_per_s": nbytes / (fused_ms * 1e-3),
+    }
+    if not per_seq_leg:
+        log("bpe: fused %.3f ms (%.3e tokens/s)" % (fused_ms, out["fused_tokens_per_s"]))
+        return out, data, offs, merges
 
     # one call per sequence, each writing its ids where the fused call put them
     lens = np.diff(offs)
@@ -460,19 +479,12 @@ def bpe_leg(reps: int = 10):
         torch.cuda.synchronize()
         times.append(a.elapsed_time(b))
     per_ms = float(min(times))
-    out = {
-        "workload": "1024 sequences, log-uniform 500-20000 bases (%d bases), order-5 Markov, BPE 4096 merges "
-                    "(oracle trainer, 64 Mbase), PACKED, no specials" % nbytes,
-        "tokens": tokens,
-        "autotuned": {"bpe_item_bytes": tune["bpe_item_bytes"], "bpe_max_waves": tune["bpe_max_waves"]},
-        "fused_ms": round(fused_ms, 4),
-        "fused_tokens_per_s": tokens / (fused_ms * 1e-3),
-        "fused_bases_per_s": nbytes / (fused_ms * 1e-3),
+    out.update({
         "per_sequence_ms": round(per_ms, 3),
         "per_sequence_tokens_per_s": tokens / (per_ms * 1e-3),
         "fused_speedup": round(per_ms / fused_ms, 2),
         "per_sequence_ids_identical": same,
-    }
+    })
     log("bpe: fused %.3f ms (%.3e tokens/s), per-sequence %.3f ms, identical=%s" % (
         fused_ms, out["fused_tokens_per_s"], per_ms, same))
     return out, data, offs, merges
@@ -649,6 +661,10 @@ def main():
     ap.add_argument("--no-per-vocab", action="store_true", help="skip the four single-vocabulary launches")
     ap.add_argument("--tuning", type=str, default=None,
                     help="TILE,BLOCKS: fixed tiling of the one-pass encode instead of the autotuner's")
+    ap.add_argument("--bpe-tuning", type=str, default=None,
+                    help="ITEM_BYTES,WAVES: fixed BPE tiling instead of the autotuner's")
+    ap.add_argument("--no-bpe-per-seq", action="store_true",
+                    help="time only the fused BPE call (skip the one-call-per-sequence comparison)")
     ap.add_argument("--serve-requests", type=int, default=SERVE_REQUESTS)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -681,7 +697,8 @@ def main():
         serve = serve_leg(args.serve_requests)
     bpe = bpe_in = None
     if not args.no_bpe:
-        bpe, b_data, b_offs, merges = bpe_leg()
+        bt = tuple(int(x) for x in args.bpe_tuning.split(",")) if args.bpe_tuning else None
+        bpe, b_data, b_offs, merges = bpe_leg(tuning=bt, per_seq_leg=not args.no_bpe_per_seq)
         bpe_in = (b_data, b_offs, merges)
     cpu = None
     if not args.no_cpu:

@@ -18,18 +18,26 @@
 //    (right) anchor. A tile therefore owns one contiguous run of cells per
 //    row it touches and its work is bounded by B whatever the row lengths.
 //    Cell positions follow from out_offsets (PACKED) or row * width
-//    (PADDED), so tiles never wait on each other: blocks walk a static
-//    grid-stride tile sequence with no atomics at all.
-//  * Each tile is staged into LDS once with coalesced 16-byte loads; the
-//    next tile's loads are issued before the current tile is written.
-//    k-mer tiles are classified on the way in: 2-bit base digits packed
-//    most-significant-first (16 bases per word) plus one validity bit per
-//    base, so a k-mer id is two funnel shifts and a mask compare.
-//    Single-base tiles keep raw bytes, with the 256-entry table in LDS.
-//  * Stores go out as aligned 16-byte groups of four ids (plus one 4-byte
-//    mask word in PADDED layout); ragged group edges use scalar stores.
-//  * PADDED layout with a modest row count fuses the row scan into one
-//    extra block of the cell kernel: a single launch.
+//    (PADDED), so tiles never wait on each other: tile walkers take an
+//    evened-out static share of the tiles, each XCD a contiguous range,
+//    with no atomics at all (one ticket counter for the whole device is far
+//    slower than any imbalance it would fix on this chip).
+//  * Each tile is staged into LDS once with coalesced 16-byte loads, issued
+//    together with the row-search probe so one wait covers both; walkers
+//    with several tiles issue the next tile's loads before writing the
+//    current one. k-mer tiles are classified on the way in: 2-bit base
+//    digits packed most-significant-first (16 bases per word) plus one
+//    validity bit per base. Single-base tiles keep raw bytes, with the
+//    256-entry table in LDS.
+//  * One pass over the rows of a chunk gives every (vocabulary, row) segment
+//    of the tile; one block scan splits their aligned 16-byte store groups
+//    into interior groups (four body tokens) and edge groups (specials,
+//    pads, tails, ragged ends). Each wave writes a contiguous share of the
+//    interior groups with the segment's facts uniform across it: four
+//    k-mer ids from one 32-base window read, one 16-byte id store and one
+//    4-byte mask word. Edge groups go cell by cell.
+//  * PADDED layout with a modest row count folds the row scans into the
+//    cell launch: its last nv blocks scan one vocabulary each.
 #include "common.hpp"
 #include "device.hpp"
 
@@ -787,7 +795,7 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
                         const int32_t j1 = (x1 < ipre + n ? x1 : ipre + n) - ipre;
                         const int32_t cA = (int32_t)(4 * gg.gA - al - dlo);  // relative cell of group gA's first element
                         i32x4 *d4 = reinterpret_cast<i32x4 *>(o.ids + (4 * gg.gA - al));
-                        int8_t *m1 = o.mask + (4 * gg.gA - al);
+                        int8_t *m1 = a.padded ? o.mask + (4 * gg.gA - al) : nullptr;  // PACKED has no mask
                         const bool mask4 = ((reinterpret_cast<uintptr_t>(o.mask) - (uintptr_t)al) & 3) == 0;
                         const bool k4 = k <= 8;
                         const Kmer4 kc = kmer4_consts(k4 ? k : 8);

@@ -121,6 +121,15 @@ def test_fuzz_kmer_all_shapes(k):
     check_padded(v, data, offs, False, dt.PAD_LEFT, k=k)
 
 
+@pytest.mark.parametrize("k", [1, 3, 8])
+def test_wide_padding_rows_are_mostly_pads(k):
+    # short rows in a wide matrix: almost every store group of a row is pads
+    data, offs = _fuzz_batch(2000 + k, 700, 130)
+    v = _vocab(dt.KMER, k) if k > 1 else _vocab(dt.SINGLE)
+    check_padded(v, data, offs, True, dt.PAD_RIGHT, k=k, pad_extra=3001)
+    check_padded(v, data, offs, False, dt.PAD_LEFT, k=k, pad_extra=2999)
+
+
 def test_fuzz_single_and_lut256():
     data, offs = _fuzz_batch(77, 3000, 130)
     for shift in (0, 3, 8):
