@@ -760,7 +760,7 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
 
             // Interior groups: each wave takes a contiguous share of them,
             // segment by segment, with the segment's and its vocabulary's
-            // facts uniform across the wave and two groups per lane in flight.
+            // facts uniform across the wave and four groups per lane in flight.
             {
                 constexpr int NW = NT / dev::kWave;
                 const int64_t itv = s_itot;
@@ -822,13 +822,17 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
                                     for (int rr = 0; rr < 4; ++rr) m1[4 * j + rr] = 1;
                             }
                         };
-                        for (int32_t j = j0 + lane; j < j1; j += 2 * dev::kWave) {
-                            const int32_t jb = j + dev::kWave;
-                            const bool hb = jb < j1;
+                        for (int32_t j = j0 + lane; j < j1; j += 4 * dev::kWave) {
+                            const int32_t jb = j + dev::kWave, jc = j + 2 * dev::kWave, jd = j + 3 * dev::kWave;
+                            const bool hb = jb < j1, hc = jc < j1, hd = jd < j1;
                             const i32x4 ya = ids_of(j);
                             const i32x4 yb = ids_of(hb ? jb : j);
+                            const i32x4 yc = ids_of(hc ? jc : j);
+                            const i32x4 yd = ids_of(hd ? jd : j);
                             put(j, ya);
                             if (hb) put(jb, yb);
+                            if (hc) put(jc, yc);
+                            if (hd) put(jd, yd);
                         }
                         x = ipre + j1;
                         ++c;
