@@ -459,7 +459,7 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
     __shared__ int64_t s_vg[kMaxMultiVocabs + 1];
     __shared__ int64_t s_po[dev::kWave + 1];  // offs[s_w0 ..] as probed by the row search
     __shared__ int64_t s_w0, s_w1;
-    __shared__ int32_t s_clist[NT], s_cpre[NT];  // segments holding interior groups, and their first one
+    __shared__ int32_t s_ipre[NT];  // first interior group of each (vocabulary, row) pair, in pair order
     __shared__ int64_t s_itot;
     __shared__ int64_t s_tmp[NT / dev::kWave + 1];
     __shared__ int64_t s_ia, s_ib;
@@ -553,11 +553,37 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
 
     uint4 v[U];
     uint4 halo = make_uint4(0, 0, 0, 0);
+    // Row-search probe of the tile starting at byte P0: 64 rows around the
+    // row that byte would fall in if rows were equally long, [w0, w1), and
+    // (wave 0) the offsets bounding them, indices clamped to the batch.
+    auto probe_window = [&](int64_t P0, int64_t &w0, int64_t &w1) {
+        const int64_t n = a.n;
+        int64_t guess = 0;
+        if (off_last > off_first && P0 > off_first)
+            guess = (int64_t)((double)(P0 - off_first) / (double)(off_last - off_first) * (double)n);
+        w0 = guess - dev::kWave / 2;
+        if (w0 + dev::kWave > n) w0 = n - dev::kWave;
+        if (w0 < 0) w0 = 0;
+        w1 = (w0 + dev::kWave < n) ? w0 + dev::kWave : n;
+    };
+    int64_t po0 = 0, po1 = 0;  // wave 0: offs[w0 + lane], offs[w0 + lane + 1] of the next probe
+    auto probe_load = [&](int64_t P0) {
+        if (tid < dev::kWave) {
+            int64_t w0, w1;
+            probe_window(P0, w0, w1);
+            const int64_t q = w0 + tid;
+            po0 = a.offs[q < a.n ? q : a.n];
+            po1 = a.offs[q + 1 < a.n ? q + 1 : a.n];
+        }
+    };
     // v and halo hold tile t's chunks when pf is set; first and last tiles
-    // (not interior) are read byte by byte when staged
-    bool pf = false;
+    // (not interior) are read byte by byte when staged. With PF the next
+    // tile's probe is put in flight with its bytes (probed).
+    bool pf = false, probed = false;
     if (PF && bid < a.ntiles) {
         const int64_t t0 = xcd_tile(bid, a.ntiles);
+        probe_load(t0 * B - a.shift);
+        probed = true;
         pf = tile_interior<U>(a, t0);
         if (pf) fetch_tile<U>(a, t0, v, halo, tid);
     }
@@ -572,23 +598,12 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
         const int64_t P1 = (t == a.ntiles - 1) ? INT64_MAX : P0 + B;
 
         // Wave 0 puts the row search's probe in flight before the tile's own
-        // loads, so one wait covers both: 64 rows around the row the byte
-        // position would fall in if rows were equally long, and the offsets
-        // bounding them (indices clamped to the batch).
-        int64_t w0 = 0, w1 = 0, po0 = 0, po1 = 0;
-        if (tid < dev::kWave) {
-            const int64_t n = a.n;
-            int64_t guess = 0;
-            if (off_last > off_first && P0 > off_first)
-                guess = (int64_t)((double)(P0 - off_first) / (double)(off_last - off_first) * (double)n);
-            w0 = guess - dev::kWave / 2;
-            if (w0 + dev::kWave > n) w0 = n - dev::kWave;
-            if (w0 < 0) w0 = 0;
-            w1 = (w0 + dev::kWave < n) ? w0 + dev::kWave : n;  // probe rows [w0, w1)
-            const int64_t q = w0 + tid;
-            po0 = a.offs[q < n ? q : n];
-            po1 = a.offs[q + 1 < n ? q + 1 : n];
-        }
+        // loads (unless it went out with the prefetch), so one wait covers
+        // both.
+        int64_t w0 = 0, w1 = 0;
+        probe_window(P0, w0, w1);
+        if (!probed) probe_load(P0);
+        probed = false;
         if (!PF) {
             pf = tile_interior<U>(a, t);
             if (pf) fetch_tile<U>(a, t, v, halo, stid);
@@ -701,6 +716,8 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
             pf = L + G < a.ntiles;
             if (pf) {
                 const int64_t tn = xcd_tile(L + G, a.ntiles);  // this block's next tile
+                probe_load(tn * B - a.shift);  // the search has moved this tile's probe to LDS
+                probed = true;
                 pf = tile_interior<U>(a, tn);
                 if (pf) fetch_tile<U>(a, tn, v, halo, stid);
             }
@@ -738,23 +755,22 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
                 nedge = (gg.gA - gg.gfirst) + (gg.glast + 1 - gg.gB);
                 seg[tid] = sg;
             }
-            // Interior groups (with the count of segments holding any in the
-            // top bits) and edge groups of all pairs, vocabulary-major.
-            int64_t itot, etot;
-            const int64_t ipk = dev::block_excl_scan<NT>(((int64_t)(nint > 0) << 52) | nint, s_tmp, &itot);
-            const int64_t epre = dev::block_excl_scan<NT>(nedge, s_tmp, &etot);
+            // Interior groups (bits 40 up: fewer than 2^20 in a chunk) and
+            // edge groups (low 40 bits) of all pairs, vocabulary-major, in
+            // one scan.
+            constexpr int64_t kEdgeMask = (1ll << 40) - 1;
+            int64_t tot;
+            const int64_t pk = dev::block_excl_scan<NT>((nint << 40) | nedge, s_tmp, &tot);
+            const int64_t epre = pk & kEdgeMask;
+            s_ipre[tid] = (int32_t)(pk >> 40);
             if (pv < a.nv && pr < nrc) {
-                seg[tid].ipre = (int32_t)(ipk & ((1ll << 52) - 1));
+                seg[tid].ipre = (int32_t)(pk >> 40);
                 seg[tid].epre = epre;
-                if (nint > 0) {
-                    s_clist[ipk >> 52] = tid;
-                    s_cpre[ipk >> 52] = (int32_t)(ipk & ((1ll << 52) - 1));
-                }
             }
             if (pv < a.nv && pr == 0) s_vg[pv] = epre;  // vocabulary v's edges are [s_vg[v], s_vg[v + 1])
             if (tid == 0) {
-                s_vg[a.nv] = etot;
-                s_itot = itot;
+                s_vg[a.nv] = tot & kEdgeMask;
+                s_itot = tot >> 40;
             }
             __syncthreads();
 
@@ -763,23 +779,22 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
             // facts uniform across the wave and four groups per lane in flight.
             {
                 constexpr int NW = NT / dev::kWave;
-                const int64_t itv = s_itot;
-                const int32_t T = (int32_t)(itv & ((1ll << 52) - 1));
-                const int nz = (int)(itv >> 52);
+                const int32_t T = (int32_t)s_itot;
                 const int wv = tid / dev::kWave, lane = tid & (dev::kWave - 1);
                 const int32_t x0 = (int32_t)((int64_t)T * wv / NW), x1 = (int32_t)((int64_t)T * (wv + 1) / NW);
-                if (x0 < x1) {
-                    // listed segments starting at or before x0, minus one
+                // the pair holding interior group x: the last one whose first
+                // interior group is <= x (it holds at least one)
+                auto pair_of = [&](int32_t x) {
                     int cnt = 0;
 #pragma unroll
-                    for (int r4 = 0; r4 < NT / dev::kWave; ++r4) {
-                        const int cl = r4 * dev::kWave + lane;
-                        cnt += __popcll(__ballot(cl < nz && s_cpre[cl] <= x0));
-                    }
-                    int c = cnt - 1;
+                    for (int r4 = 0; r4 < NT / dev::kWave; ++r4)
+                        cnt += __popcll(__ballot(s_ipre[r4 * dev::kWave + lane] <= x));
+                    return cnt - 1;
+                };
+                if (x0 < x1) {
                     int32_t x = x0;
                     while (x < x1) {
-                        const int sidx = rfl(s_clist[c]);
+                        const int sidx = rfl(pair_of(x));
                         const int vi = rfl(sidx / R);
                         const VocabOut &o = a.vo[vi];
                         const int32_t k = KMER ? o.k : 1;
@@ -835,7 +850,6 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
                             if (hd) put(jd, yd);
                         }
                         x = ipre + j1;
-                        ++c;
                     }
                 }
             }
