@@ -307,27 +307,6 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// Next / previous alive position strictly after / before x, or kNone.
-__device__ __forceinline__ uint32_t next_alive(const uint32_t *alive, uint32_t nw, uint32_t x) {
-    uint32_t w = x >> 5;
-    uint32_t bits = alive[w] & ~((2u << (x & 31)) - 1u);
-    while (!bits) {
-        if (++w >= nw) return kNone;
-        bits = alive[w];
-    }
-    return (w << 5) + (uint32_t)__builtin_ctz(bits);
-}
-
-__device__ __forceinline__ uint32_t prev_alive(const uint32_t *alive, uint32_t x) {
-    uint32_t w = x >> 5;
-    uint32_t bits = alive[w] & ((1u << (x & 31)) - 1u);
-    while (!bits) {
-        if (w == 0) return kNone;
-        bits = alive[--w];
-    }
-    return (w << 5) + 31u - (uint32_t)__builtin_clz(bits);
-}
-
 // Minimum of the 64 pair ranks of block b (16-byte LDS reads).
 __device__ __forceinline__ uint32_t block_min(const uint16_t *prk, uint32_t b) {
     const uint4 *src = reinterpret_cast<const uint4 *>(prk + (size_t)b * 64);
