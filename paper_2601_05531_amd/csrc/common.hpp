@@ -131,7 +131,7 @@ struct EncodeTuning {
     int64_t tile_bytes;  // bytes of input per tile (multiple of 16)
     int blocks_per_cu;   // 0 = as many as occupancy allows
 };
-EncodeTuning encode_tuning(const dnatok_vocab *v);
+EncodeTuning encode_tuning(const dnatok_vocab *v, int64_t nbytes);
 constexpr int32_t kBpeItemBytesDefault = 8192;  // nominal BPE item length S
 constexpr int32_t kBpeItemBytesMin = 1024;
 

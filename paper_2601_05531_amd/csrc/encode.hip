@@ -1016,11 +1016,21 @@ int launch_rowscan(const int64_t *d_offsets, int32_t n, int64_t nbytes, int64_t 
     return DNATOK_OK;
 }
 
-EncodeTuning encode_tuning(const dnatok_vocab *v) {
+EncodeTuning encode_tuning(const dnatok_vocab *v, int64_t nbytes) {
     const bool kmer = (v->kind == DNATOK_KMER);
     EncodeTuning t;
     const int32_t tile = v->tune_tile.load(std::memory_order_relaxed);
-    t.tile_bytes = tile > 0 ? tile : (kmer ? 32768 : 16384);
+    if (tile > 0) {
+        t.tile_bytes = tile;
+    } else {
+        // Untuned: 32 KiB (k-mer) or 16 KiB tiles, halved down to 4 KiB while
+        // the batch would give fewer than two tiles per CU (a 1 Mbase batch
+        // would otherwise run on a fraction of the chip).
+        int64_t want = kmer ? 32768 : 16384;
+        const int64_t target = nbytes / (2 * (int64_t)device_cu_count());
+        while (want > 4096 && want > target) want >>= 1;
+        t.tile_bytes = want;
+    }
     t.blocks_per_cu = v->tune_blocks.load(std::memory_order_relaxed);
     return t;
 }
@@ -1033,7 +1043,7 @@ int launch_encode_multi(const dnatok_vocab *const *vs, int nv, const uint8_t *d_
     const dnatok_vocab *v = vs[0];
     const dnatok_encode_opts &o = os[0];
     const bool kmer = (v->kind == DNATOK_KMER);
-    const EncodeTuning tune = encode_tuning(v);
+    const EncodeTuning tune = encode_tuning(v, nbytes);
     int U = 1;  // staging loads per thread: tiles are U * NT * 16 bytes
     while (U < 16 && (int64_t)U * NT * 16 < tune.tile_bytes) U <<= 1;
     const int64_t B = (int64_t)U * NT * 16;
