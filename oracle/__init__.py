@@ -49,6 +49,10 @@ def _load():
         lib.oracle_encode.restype = i64
         lib.oracle_encode.argtypes = [ctypes.c_int, ctypes.c_int, vp, i32, i32, vp, i32,
                                       vp, vp, i32, ctypes.c_int, vp, i64, vp]
+        lib.oracle_revcomp.restype = ctypes.c_int
+        lib.oracle_revcomp.argtypes = [vp, vp, i32, vp]
+        lib.oracle_encode_overlap.restype = i64
+        lib.oracle_encode_overlap.argtypes = [ctypes.c_int, vp, vp, i32, ctypes.c_int, vp, i64, vp]
         lib.oracle_pad.restype = ctypes.c_int
         lib.oracle_pad.argtypes = [vp, vp, i32, i64, ctypes.c_int, i32, vp, vp]
         lib.oracle_decode.restype = i64
@@ -85,6 +89,44 @@ def encode(kind: int, data, offsets, k: int = 1, lut=None, merges=None, add_cls_
     if total < 0:
         raise ValueError("oracle_encode failed (%d)" % total)
     return ids[:total].copy(), out_off
+
+
+def revcomp(data, offsets):
+    """Reverse complement of every row (A<->T, C<->G, case kept, other bytes
+    unchanged; rows stay at their offsets). Returns uint8[len(data)]."""
+    data = _c(data, np.uint8)
+    offsets = _c(offsets, np.int64)
+    out = data.copy()
+    if _load().oracle_revcomp(_ptr(data), _ptr(offsets), len(offsets) - 1, _ptr(out)) != 0:
+        raise ValueError("offsets decrease")
+    return out
+
+
+def encode_overlap(data, offsets, k: int, add_cls_sep: bool = False):
+    """PACKED encode with overlapping k-mers (stride 1). Returns (ids, out_offsets)."""
+    data = _c(data, np.uint8)
+    offsets = _c(offsets, np.int64)
+    n = len(offsets) - 1
+    cap = int(offsets[-1] - offsets[0]) + 2 * n + 1 if n > 0 else 1
+    ids = np.empty(cap, dtype=np.int32)
+    out_off = np.empty(n + 1, dtype=np.int64)
+    total = _load().oracle_encode_overlap(k, _ptr(data), _ptr(offsets), n, int(add_cls_sep), _ptr(ids), cap,
+                                          _ptr(out_off))
+    if total < 0:
+        raise ValueError("oracle_encode_overlap failed (%d)" % total)
+    return ids[:total].copy(), out_off
+
+
+def embed(table, ids):
+    """Embedding lookup, the paper's embed_tokens applied to identifiers (Design,
+    the embedder mapping B x T identifiers to B x T x D activations): row r
+    of the result is row ids[r] of ``table`` (any dtype, copied bit for bit).
+    ``ids`` may have any shape; the result has shape ids.shape + (D,)."""
+    table = np.asarray(table)
+    ids = np.asarray(ids, dtype=np.int64)
+    if ids.size and (ids.min() < 0 or ids.max() >= table.shape[0]):
+        raise ValueError("id outside the table")
+    return table[ids]
 
 
 def pad(ids, out_offsets, width: int, side: int = RIGHT, pad_id: int = PAD):

@@ -8,7 +8,10 @@ the two pin each other:
   pair (the per-occurrence form of ranked-merge BPE), where ``oracle.c``
   replaces every occurrence of the lowest-rank pair per round (Sennrich et
   al.'s form). For well-formed merge tables both give one segmentation;
-* the BPE trainer recounts all pairs from scratch every step.
+* the BPE trainer recounts all pairs from scratch every step;
+* the reverse complement goes through ``str.translate`` and slicing, the
+  overlapping k-mers through string slices, the embedding lookup through a
+  loop over rows.
 """
 from __future__ import annotations
 
@@ -116,3 +119,38 @@ def expand(tok: int, merges) -> str:
         a, b = merges[tok - 10]
         return expand(int(a), merges) + expand(int(b), merges)
     raise ValueError(tok)
+
+
+_COMP = str.maketrans("ACGTacgt", "TGCAtgca")
+
+
+def revcomp_text(text: str) -> str:
+    """Reverse complement of one row (A<->T, C<->G, case kept, others kept)."""
+    return text.translate(_COMP)[::-1]
+
+
+def kmer_body_text(text: str, k: int):
+    """Non-overlapping k-mer body of one row (frames from base 0, stride k)."""
+    out = []
+    for s in range(0, len(text), k):
+        w = text[s:s + k]
+        ok = len(w) == k and all(ch in "ACGTacgt" for ch in w)
+        out.append(kmer_id(w) if ok else 1)
+    return out
+
+
+def overlap_body_text(text: str, k: int):
+    """Overlapping k-mer body of one row: one window per start s <= L - k;
+    a non-empty row shorter than k is one UNK."""
+    if 0 < len(text) < k:
+        return [1]
+    out = []
+    for s in range(len(text) - k + 1):
+        w = text[s:s + k]
+        out.append(kmer_id(w) if all(ch in "ACGTacgt" for ch in w) else 1)
+    return out
+
+
+def embed_rows(table_rows, ids):
+    """List of table rows picked by ids, one by one."""
+    return [table_rows[i] for i in ids]

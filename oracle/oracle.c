@@ -47,6 +47,19 @@
  *   the row, LEFT right-aligns them (the paper's left padding); the int8 mask
  *   is 1 on tokens (CLS/SEP included) and 0 on pads.
  *
+ *   Reverse complement (the augmentation the paper's discussion of data
+ *   augmentation names as the natural one to run on the GPU): each row is
+ *   read back to front with A<->T and C<->G swapped (case kept); N, n and
+ *   every other byte stay as they are. An encode of the reverse complement
+ *   is the encode of that row.
+ *
+ *   Overlapping k-mers (stride 1, the older scheme the introduction
+ *   describes): a window starts at every base s with s + k <= L, giving
+ *   L - k + 1 tokens, each with the k-mer id rule above (UNK if the window
+ *   holds a byte other than ACGT in either case). A non-empty row shorter
+ *   than k gives one UNK, as a short final frame does for non-overlapping
+ *   k-mers; an empty row gives none.
+ *
  *   Decode (the inverse table the paper lists as future work): base, k-mer
  *   and merge ids -> their uppercase bases (merges expanded recursively);
  *   N -> "N"; UNK -> "N" repeated over the width it stands for (k for KMER,
@@ -213,6 +226,73 @@ int64_t oracle_encode(int kind, int k, const int32_t *lut, int32_t cls_id, int32
     free(tmp);
     free(rt.sorted);
     return status < 0 ? status : total;
+}
+
+/*
+ * Reverse complement of every row: out[offsets[i] + t] is the complement of
+ * bytes[offsets[i + 1] - 1 - t]. Returns 0, or -2 on decreasing offsets.
+ */
+int oracle_revcomp(const uint8_t *bytes, const int64_t *offsets, int32_t n, uint8_t *out) {
+    for (int32_t i = 0; i < n; ++i) {
+        int64_t lo = offsets[i], hi = offsets[i + 1];
+        if (hi < lo) return -2;
+        for (int64_t t = 0; t < hi - lo; ++t) {
+            uint8_t b = bytes[hi - 1 - t];
+            uint8_t c = b;
+            switch (b) {
+            case 'A': c = 'T'; break;
+            case 'T': c = 'A'; break;
+            case 'C': c = 'G'; break;
+            case 'G': c = 'C'; break;
+            case 'a': c = 't'; break;
+            case 't': c = 'a'; break;
+            case 'c': c = 'g'; break;
+            case 'g': c = 'c'; break;
+            default: break;
+            }
+            out[lo + t] = c;
+        }
+    }
+    return 0;
+}
+
+/*
+ * PACKED encode with overlapping k-mers (stride 1). Same contract as
+ * oracle_encode for the KMER kind.
+ */
+int64_t oracle_encode_overlap(int k, const uint8_t *bytes, const int64_t *offsets, int32_t n, int add_cls_sep,
+                              int32_t *out_ids, int64_t ids_cap, int64_t *out_offsets) {
+    if (k < 1 || k > 15) return -2;
+    int64_t total = 0;
+    out_offsets[0] = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const uint8_t *row = bytes + offsets[i];
+        int64_t L = offsets[i + 1] - offsets[i];
+        if (L < 0) return -2;
+        int64_t nb = (L >= k) ? L - k + 1 : (L > 0 ? 1 : 0);
+        int64_t len = nb + (add_cls_sep ? 2 : 0);
+        if (total + len > ids_cap) return -1;
+        int64_t w = total;
+        if (add_cls_sep) out_ids[w++] = CLS;
+        if (L > 0 && L < k) {
+            out_ids[w++] = UNK;
+        } else {
+            for (int64_t s = 0; s + k <= L; ++s) {
+                int32_t id = 0;
+                int ok = 1;
+                for (int j = 0; j < k; ++j) {
+                    int d = base_digit(row[s + j]);
+                    if (d < 0) { ok = 0; break; }
+                    id = id * 4 + d;
+                }
+                out_ids[w++] = ok ? 5 + id : UNK;
+            }
+        }
+        if (add_cls_sep) out_ids[w++] = SEP;
+        total += len;
+        out_offsets[i + 1] = total;
+    }
+    return total;
 }
 
 /*

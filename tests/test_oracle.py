@@ -341,3 +341,125 @@ def test_bpe4096_table_is_the_trainers_output():
     assert stored.shape == (4096, 2)
     assert oracle.bpe_check(stored) == 0
     assert np.array_equal(make_bpe4096.make(), stored)
+
+
+# ---------------------------------------------------------------- reverse complement
+
+def test_revcomp_golden():
+    for row in _golden("revcomp_overlap.txt"):
+        if row[0] != "rc":
+            continue
+        data, offs = _rows([row[1]])
+        assert bytes(oracle.revcomp(data, offs)).decode("latin-1") == row[2]
+
+
+def test_revcomp_involution_and_bruteforce():
+    rng = np.random.default_rng(11)
+    strings = ["".join(chr(int(b)) for b in rng.integers(0, 256, int(L))) for L in rng.integers(0, 60, 30)]
+    strings += ["ACGTNacgtn", "", "A"]
+    data, offs = _rows(strings)
+    rc = oracle.revcomp(data, offs)
+    assert np.array_equal(oracle.revcomp(rc, offs), data)
+    for i, s in enumerate(strings):
+        assert bytes(rc[offs[i]:offs[i + 1]]).decode("latin-1") == brute.revcomp_text(s)
+
+
+@pytest.mark.parametrize("k", [1, 3, 6])
+def test_revcomp_kmer_closed_form(k):
+    # On ACGT rows with L a multiple of k, token j of the reverse complement
+    # is token nb-1-j of the row with its digits complemented (3 - d) and
+    # read in reverse order.
+    rng = np.random.default_rng(k)
+    strings = ["".join(rng.choice(list("ACGTacgt"), size=k * int(m))) for m in rng.integers(0, 20, 12)]
+    data, offs = _rows(strings)
+    fwd, foff = oracle.encode(oracle.KMER, data, offs, k=k)
+    rev, roff = oracle.encode(oracle.KMER, oracle.revcomp(data, offs), offs, k=k)
+    assert np.array_equal(foff, roff)
+    for i in range(len(strings)):
+        f = fwd[foff[i]:foff[i + 1]]
+        r = rev[roff[i]:roff[i + 1]]
+        for j in range(len(f)):
+            v = int(f[len(f) - 1 - j]) - 5
+            digits = [(v >> (2 * (k - 1 - t))) & 3 for t in range(k)]
+            want = 5 + sum((3 - d) * 4 ** t for t, d in enumerate(digits))
+            assert int(r[j]) == want
+
+
+# ---------------------------------------------------------------- overlapping k-mers
+
+def test_overlap_golden():
+    for row in _golden("revcomp_overlap.txt"):
+        if row[0] != "ov":
+            continue
+        ids, out_off = oracle.encode_overlap(*_rows([row[2]]), k=int(row[1]))
+        assert ids.tolist() == [int(x) for x in row[3].split()]
+
+
+@pytest.mark.parametrize("k", [1, 2, 4, 6, 8])
+def test_overlap_lengths_and_bruteforce(k):
+    rng = np.random.default_rng(20 + k)
+    alphabet = list("ACGTacgtNn#")
+    strings = ["".join(rng.choice(alphabet, size=int(L), p=[.115] * 8 + [.04, .04, .0]))
+               for L in rng.integers(0, 40, 40)] + ["", "A" * (k - 1), "C" * k]
+    for cls in (False, True):
+        ids, out_off = oracle.encode_overlap(*_rows(strings), k=k, add_cls_sep=cls)
+        for i, s in enumerate(strings):
+            L = len(s)
+            nb = L - k + 1 if L >= k else (1 if L else 0)
+            assert out_off[i + 1] - out_off[i] == nb + 2 * cls
+            want = brute.overlap_body_text(s, k)
+            if cls:
+                want = [2] + want + [3]
+            assert ids[out_off[i]:out_off[i + 1]].tolist() == want
+
+
+@pytest.mark.parametrize("k", [2, 3, 6])
+def test_overlap_contains_the_frames_and_rolls(k):
+    # Every non-overlapping frame is the overlapping window at s = j*k, and
+    # consecutive valid windows satisfy id' - 5 = ((id - 5) * 4 + d) mod 4^k.
+    rng = np.random.default_rng(30 + k)
+    strings = ["".join(rng.choice(list("ACGTN"), size=int(L), p=[.24] * 4 + [.04])) for L in rng.integers(k, 90, 25)]
+    data, offs = _rows(strings)
+    ov, ooff = oracle.encode_overlap(data, offs, k=k)
+    fr, foff = oracle.encode(oracle.KMER, data, offs, k=k)
+    for i, s in enumerate(strings):
+        o = ov[ooff[i]:ooff[i + 1]]
+        f = fr[foff[i]:foff[i + 1]]
+        for j in range(len(s) // k):
+            assert o[j * k] == f[j]
+        for t in range(len(o) - 1):
+            if o[t] != 1 and o[t + 1] != 1:
+                d = "ACGT".index(s[t + k])
+                assert int(o[t + 1]) - 5 == ((int(o[t]) - 5) * 4 + d) % 4 ** k
+
+
+# ---------------------------------------------------------------- embedding lookup
+
+def test_embed_matches_torch_embedding():
+    import torch
+    rng = np.random.default_rng(5)
+    strings = ["".join(rng.choice(list("ACGTNacgt#"), size=int(L))) for L in rng.integers(0, 50, 20)]
+    data, offs = _rows(strings)
+    for kind, k, V in ((oracle.SINGLE, 1, 11), (oracle.KMER, 3, 69)):
+        ids, out_off = oracle.encode(kind, data, offs, k=k, add_cls_sep=True)
+        W = int(np.diff(out_off).max())
+        pids, _ = oracle.pad(ids, out_off, W, oracle.LEFT)
+        table = rng.standard_normal((V, 16)).astype(np.float32)
+        got = oracle.embed(table, pids)
+        want = torch.nn.functional.embedding(torch.from_numpy(pids.astype(np.int64)), torch.from_numpy(table))
+        assert got.shape == (len(strings), W, 16)
+        assert np.array_equal(got, want.numpy())
+        rows = brute.embed_rows([list(r) for r in table], ids.tolist())
+        assert np.array_equal(oracle.embed(table, ids), np.array(rows, dtype=np.float32).reshape(-1, 16))
+
+
+def test_embed_identity_table_recovers_ids_and_rejects_range():
+    data, offs = _rows(["ACGTNacgtn#", "GATTACA"])
+    ids, _ = oracle.encode(oracle.SINGLE, data, offs, add_cls_sep=True)
+    table = np.repeat(np.arange(10, dtype=np.int32)[:, None], 3, axis=1)
+    out = oracle.embed(table, ids)
+    assert np.array_equal(out[:, 0], ids) and np.array_equal(out[:, 2], ids)
+    with pytest.raises(ValueError):
+        oracle.embed(table, np.array([10]))
+    with pytest.raises(ValueError):
+        oracle.embed(table, np.array([-1]))
