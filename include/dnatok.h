@@ -55,6 +55,7 @@ extern "C" {
 #define DNATOK_DERR_CAPACITY 2u  /* PACKED output exceeds ids_capacity (excess not written) */
 #define DNATOK_DERR_ROW_WIDTH 4u /* PADDED row longer than pad_to (excess not written) */
 #define DNATOK_DERR_INTERNAL 8u  /* a bounded device loop hit its limit (a library fault): output invalid */
+#define DNATOK_DERR_IDS 16u      /* dnatok_embed_ids: an id outside the table (its row is written as zeros) */
 
 /* ---- ids and enums --------------------------------------------------------- */
 #define DNATOK_ID_PAD 0
@@ -111,14 +112,26 @@ typedef struct dnatok_vocab_desc {
  *  pad_to       PADDED row width W (> 0). The paper pads and never truncates,
  *               so W must be at least the longest row (dnatok_encode_plan
  *               returns it).
+ *  variant      0, or an OR of DNATOK_VARIANT_* flags (SINGLE, LUT256 and
+ *               KMER only; BPE gives EVOCAB):
+ *               REVCOMP encodes each row's reverse complement (the row read
+ *               back to front with A<->T and C<->G swapped, case kept, N and
+ *               other bytes unchanged; the paper's discussion names reverse
+ *               complementation as the augmentation to run on the GPU);
+ *               OVERLAP (KMER only, else EINVAL) writes stride-1 k-mers, the
+ *               overlapping scheme of the paper's introduction: L - k + 1
+ *               windows, one UNK for a non-empty row shorter than k.
  *  offset_base  added to every value written to d_out_offsets (lets chunked
  *               callers write one global offsets array).
  */
+#define DNATOK_VARIANT_REVCOMP 1
+#define DNATOK_VARIANT_OVERLAP 2
+
 typedef struct dnatok_encode_opts {
     int32_t add_cls_sep;
     int32_t layout;
     int32_t pad_side;
-    int32_t reserved;
+    int32_t variant;
     int64_t pad_to;
     int64_t offset_base;
 } dnatok_encode_opts;
@@ -201,6 +214,42 @@ int dnatok_encode_multi(const dnatok_vocab *const *vocabs, int32_t n_vocabs, con
                         const int64_t *d_offsets, int32_t n, int32_t *const *d_ids, const int64_t *ids_capacity,
                         int64_t *const *d_out_offsets, int8_t *const *d_mask, const dnatok_encode_opts *opts,
                         void *stream);
+
+/*
+ * Encode fused with the embedding lookup: the ids dnatok_encode would write
+ * (any layout and variant; SINGLE, LUT256 and KMER) are looked up in an
+ * embedding table on the device and the table rows are written out, the
+ * ids never leaving the kernel (paper: Design, the embedder embed_tokens
+ * mapping B x T identifiers to B x T x D activations, called by the
+ * EmbedFromStrings algorithm on the device-resident ids).
+ *  d_table        device table of n_rows rows of row_bytes bytes each (any
+ *                 element type: rows are copied bit for bit), caller-owned.
+ *                 n_rows must be at least the vocabulary size (EINVAL).
+ *  d_out          device output of out_rows rows of row_bytes: row c is the
+ *                 table row of output cell c (PACKED: token c; PADDED: cell
+ *                 c of the n x pad_to matrix, pads looking up the pad id).
+ *  d_out_offsets  device int64[n + 1], as for dnatok_encode.
+ *  d_ids          optional (NULL): also write the ids, as dnatok_encode
+ *                 would, with room for out_rows ids.
+ *  d_mask         PADDED: optional int8[n x pad_to] mask, as dnatok_encode.
+ * row_bytes is 1 .. 2^20; 16-byte aligned table, output and row_bytes take
+ * the fastest copy. Asynchronous on `stream`. Errors: EINVAL, ETOOSMALL
+ * (PADDED and out_rows < n * pad_to), EVOCAB (BPE: encode first, then
+ * dnatok_embed_ids); device-side errors raise DNATOK_DERR_* as for encode.
+ */
+int dnatok_embed(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets, int32_t n,
+                 const void *d_table, int64_t n_rows, int64_t row_bytes, void *d_out, int64_t out_rows,
+                 int64_t *d_out_offsets, int32_t *d_ids, int8_t *d_mask, const dnatok_encode_opts *opts,
+                 void *stream);
+
+/*
+ * Embedding lookup of given ids (the embedder of the paper's Design section
+ * applied to an id tensor, e.g. BPE output): row i of d_out (n_ids rows of
+ * row_bytes) is row d_ids[i] of the table. An id outside [0, n_rows) writes
+ * a zero row and raises DNATOK_DERR_IDS. Asynchronous. Errors: EINVAL.
+ */
+int dnatok_embed_ids(const int32_t *d_ids, int64_t n_ids, const void *d_table, int64_t n_rows, int64_t row_bytes,
+                     void *d_out, void *stream);
 
 /*
  * Wait for `stream`, then return (and clear) the DNATOK_DERR_* flags the

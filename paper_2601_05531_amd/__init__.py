@@ -20,7 +20,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdnatok.so")
 
 OK, EINVAL, EVOCAB, ENOMEM, EBUDGET, EDEVICE, ESTATE, ETOOSMALL = 0, -1, -2, -3, -4, -5, -6, -7
-DERR_OFFSETS, DERR_CAPACITY, DERR_ROW_WIDTH, DERR_INTERNAL = 1, 2, 4, 8
+DERR_OFFSETS, DERR_CAPACITY, DERR_ROW_WIDTH, DERR_INTERNAL, DERR_IDS = 1, 2, 4, 8, 16
+VARIANT_REVCOMP, VARIANT_OVERLAP = 1, 2
 SINGLE, LUT256, KMER, BPE = 0, 1, 2, 3
 PACKED, PADDED = 0, 1
 PAD_RIGHT, PAD_LEFT = 0, 1
@@ -51,7 +52,7 @@ class dnatok_encode_opts(ctypes.Structure):
         ("add_cls_sep", ctypes.c_int32),
         ("layout", ctypes.c_int32),
         ("pad_side", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("variant", ctypes.c_int32),
         ("pad_to", ctypes.c_int64),
         ("offset_base", ctypes.c_int64),
     ]
@@ -185,13 +186,17 @@ def lib():
         L.dnatok_graph_create.argtypes = [ctypes.POINTER(dnatok_encode_call), i32, ctypes.POINTER(vp)]
         L.dnatok_graph_launch.argtypes = [vp, vp]
         L.dnatok_graph_destroy.argtypes = [vp]
+        L.dnatok_embed.argtypes = [vp, vp, i64, vp, i32, vp, i64, i64, vp, i64, vp, vp, vp,
+                                   ctypes.POINTER(dnatok_encode_opts), vp]
+        L.dnatok_embed_ids.argtypes = [vp, i64, vp, i64, i64, vp, vp]
         for name in ("dnatok_vocab_create", "dnatok_vocab_destroy", "dnatok_vocab_info", "dnatok_encode_plan",
                      "dnatok_encode", "dnatok_sync_status", "dnatok_decode", "dnatok_stream_create",
                      "dnatok_stream_push", "dnatok_stream_flush", "dnatok_stream_reset", "dnatok_stream_destroy",
                      "dnatok_server_create", "dnatok_server_submit", "dnatok_server_poll", "dnatok_server_wait",
                      "dnatok_server_release", "dnatok_server_stats", "dnatok_server_destroy", "dnatok_get_tuning",
                      "dnatok_set_tuning", "dnatok_autotune", "dnatok_graph_create", "dnatok_graph_launch",
-                     "dnatok_graph_destroy", "dnatok_encode_multi", "dnatok_autotune_multi"):
+                     "dnatok_graph_destroy", "dnatok_encode_multi", "dnatok_autotune_multi", "dnatok_embed",
+                     "dnatok_embed_ids"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -241,6 +246,16 @@ def dnatok_encode(handle, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_
                   stream) -> int:
     return _check(lib().dnatok_encode(handle, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets,
                                       d_mask, ctypes.byref(opts), stream))
+
+
+def dnatok_embed(handle, d_bytes, nbytes, d_offsets, n, d_table, n_rows, row_bytes, d_out, out_rows, d_out_offsets,
+                 d_ids, d_mask, opts, stream) -> int:
+    return _check(lib().dnatok_embed(handle, d_bytes, nbytes, d_offsets, n, d_table, n_rows, row_bytes, d_out,
+                                     out_rows, d_out_offsets, d_ids, d_mask, ctypes.byref(opts), stream))
+
+
+def dnatok_embed_ids(d_ids, n_ids, d_table, n_rows, row_bytes, d_out, stream) -> int:
+    return _check(lib().dnatok_embed_ids(d_ids, n_ids, d_table, n_rows, row_bytes, d_out, stream))
 
 
 def dnatok_sync_status(stream) -> int:
@@ -322,32 +337,34 @@ class Vocab:
             pass
 
 
-def make_opts(add_cls_sep=False, layout=PACKED, pad_side=PAD_RIGHT, pad_to=0, offset_base=0):
+def make_opts(add_cls_sep=False, layout=PACKED, pad_side=PAD_RIGHT, pad_to=0, offset_base=0, variant=0):
     o = dnatok_encode_opts()
     o.add_cls_sep, o.layout, o.pad_side, o.pad_to, o.offset_base = int(add_cls_sep), layout, pad_side, pad_to, offset_base
+    o.variant = variant
     return o
 
 
-def plan(vocab: Vocab, h_offsets, add_cls_sep=False):
+def plan(vocab: Vocab, h_offsets, add_cls_sep=False, variant=0):
     h_offsets = np.ascontiguousarray(h_offsets, dtype=np.int64)
-    return dnatok_encode_plan(vocab.handle, h_offsets, len(h_offsets) - 1, make_opts(add_cls_sep))
+    return dnatok_encode_plan(vocab.handle, h_offsets, len(h_offsets) - 1, make_opts(add_cls_sep, variant=variant))
 
 
 def encode(vocab: Vocab, d_bytes, d_offsets, h_offsets=None, add_cls_sep=False, layout=PACKED,
-           pad_side=PAD_RIGHT, pad_to=None, out=None, stream=None):
+           pad_side=PAD_RIGHT, pad_to=None, out=None, stream=None, variant=0):
     """Encode a ragged batch held in device tensors.
 
     ``d_bytes``: uint8 cuda tensor; ``d_offsets``: int64 cuda tensor [n+1];
     ``h_offsets``: the same offsets on the host (numpy) for output sizing
     (copied from the device when omitted). Returns ``(ids, out_offsets, mask)``
     (``mask`` is None for PACKED). ``out`` may pass preallocated
-    ``(ids, out_offsets, mask)``.
+    ``(ids, out_offsets, mask)``. ``variant``: 0 or an OR of VARIANT_REVCOMP
+    and VARIANT_OVERLAP.
     """
     import torch
     n = d_offsets.numel() - 1
     if h_offsets is None:
         h_offsets = d_offsets.cpu().numpy()
-    total, max_len = plan(vocab, h_offsets, add_cls_sep)
+    total, max_len = plan(vocab, h_offsets, add_cls_sep, variant)
     dev = d_bytes.device
     if layout == PADDED:
         if pad_to is None:
@@ -367,7 +384,7 @@ def encode(vocab: Vocab, d_bytes, d_offsets, h_offsets=None, add_cls_sep=False, 
         mask = torch.empty(max(cap, 1), dtype=torch.int8, device=dev) if layout == PADDED else None
     else:
         ids, out_off, mask = out
-    opts = make_opts(add_cls_sep, layout, pad_side, W)
+    opts = make_opts(add_cls_sep, layout, pad_side, W, variant=variant)
     dnatok_encode(vocab.handle, _ptr(d_bytes), d_bytes.numel(), _ptr(d_offsets), n, _ptr(ids), ids.numel(),
                   _ptr(out_off), _ptr(mask), opts, _stream_ptr(stream))
     if layout == PADDED:
@@ -377,6 +394,56 @@ def encode(vocab: Vocab, d_bytes, d_offsets, h_offsets=None, add_cls_sep=False, 
         # total is known once the device has encoded (a synchronising read)
         total = int(out_off[n].item())
     return ids[:total], out_off, None
+
+
+def embed(vocab: Vocab, d_bytes, d_offsets, table, h_offsets=None, add_cls_sep=False, layout=PACKED,
+          pad_side=PAD_RIGHT, pad_to=None, variant=0, want_ids=False, want_mask=True, out=None, stream=None):
+    """Encode fused with the embedding lookup (``dnatok_embed``).
+
+    ``table``: a 2-D cuda tensor [n_rows, D] of any dtype (rows are copied bit
+    for bit). Returns ``(emb, out_offsets, ids, mask)``: ``emb`` is
+    [total, D] (PACKED) or [n, W, D] (PADDED) in the table's dtype; ``ids``
+    and ``mask`` are None unless asked for (``mask``: PADDED only). ``out``
+    may pass a preallocated ``emb`` buffer of at least that many rows.
+    """
+    import torch
+    n = d_offsets.numel() - 1
+    if h_offsets is None:
+        h_offsets = d_offsets.cpu().numpy()
+    total, max_len = plan(vocab, h_offsets, add_cls_sep, variant)
+    dev = d_bytes.device
+    if layout == PADDED:
+        W = max_len if pad_to is None else max(int(pad_to), max_len)
+        rows = n * W
+    else:
+        W, rows = 0, total
+    row_bytes = table.stride(0) * table.element_size()
+    assert table.dim() == 2 and table.is_contiguous()
+    emb = out if out is not None else torch.empty((max(rows, 1), table.shape[1]), dtype=table.dtype, device=dev)
+    out_off = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    ids = torch.empty(max(rows, 1), dtype=torch.int32, device=dev) if want_ids else None
+    mask = torch.empty(max(rows, 1), dtype=torch.int8, device=dev) if (want_mask and layout == PADDED) else None
+    opts = make_opts(add_cls_sep, layout, pad_side, W, variant=variant)
+    dnatok_embed(vocab.handle, _ptr(d_bytes), d_bytes.numel(), _ptr(d_offsets), n, _ptr(table), table.shape[0],
+                 row_bytes, _ptr(emb), emb.shape[0], _ptr(out_off), _ptr(ids), _ptr(mask), opts, _stream_ptr(stream))
+    if layout == PADDED:
+        shape = (n, W)
+        return (emb[:rows].view(n, W, table.shape[1]), out_off,
+                ids[:rows].view(shape) if ids is not None else None,
+                mask[:rows].view(shape) if mask is not None else None)
+    return emb[:rows], out_off, (ids[:rows] if ids is not None else None), None
+
+
+def embed_ids(d_ids, table, stream=None):
+    """Embedding lookup of an int32 cuda id tensor (``dnatok_embed_ids``):
+    returns ``table[ids]`` computed on the device, shape ids.shape + (D,)."""
+    import torch
+    assert table.dim() == 2 and table.is_contiguous() and d_ids.dtype == torch.int32
+    ids = d_ids.contiguous()
+    out = torch.empty((max(ids.numel(), 1), table.shape[1]), dtype=table.dtype, device=ids.device)
+    dnatok_embed_ids(_ptr(ids), ids.numel(), _ptr(table), table.shape[0], table.stride(0) * table.element_size(),
+                     _ptr(out), _stream_ptr(stream))
+    return out[:ids.numel()].view(tuple(ids.shape) + (table.shape[1],))
 
 
 def decode(vocab: Vocab, d_ids, d_offsets, out_capacity=None, stream=None):

@@ -263,11 +263,13 @@ int dnatok_encode_plan(const dnatok_vocab *v, const int64_t *h_offsets, int32_t 
     if (!v || n < 0 || (!h_offsets && n > 0)) return set_error(DNATOK_EINVAL, "bad argument");
     const int64_t sp = (opts && opts->add_cls_sep) ? 2 : 0;
     const int64_t k = (v->kind == DNATOK_KMER) ? v->k : 1;
+    const bool overlap = opts && (opts->variant & DNATOK_VARIANT_OVERLAP) && v->kind == DNATOK_KMER;
     int64_t tot = 0, mx = 0;
     for (int32_t i = 0; i < n; ++i) {
         int64_t L = h_offsets[i + 1] - h_offsets[i];
         if (L < 0) return set_error(DNATOK_EINVAL, "offsets decrease at row %d", i);
-        int64_t len = (L + k - 1) / k + sp;
+        int64_t body = overlap ? (L >= k ? L - k + 1 : (L > 0 ? 1 : 0)) : (L + k - 1) / k;
+        int64_t len = body + sp;
         tot += len;
         mx = std::max(mx, len);
     }
@@ -276,28 +278,45 @@ int dnatok_encode_plan(const dnatok_vocab *v, const int64_t *h_offsets, int32_t 
     return DNATOK_OK;
 }
 
-// Checks one encode's arguments (everything dnatok_encode checks on the host).
-static int check_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets,
-                        int32_t n, int32_t *d_ids, int64_t ids_capacity, int64_t *d_out_offsets, int8_t *d_mask,
-                        const dnatok_encode_opts &o) {
+// Checks an encode's inputs and options (everything but the id and mask
+// outputs).
+static int check_inputs(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets,
+                        int32_t n, int64_t *d_out_offsets, const dnatok_encode_opts &o) {
     if (!v) return set_error(DNATOK_EINVAL, "null vocabulary");
-    if (n < 0 || nbytes < 0 || ids_capacity < 0) return set_error(DNATOK_EINVAL, "negative size");
+    if (n < 0 || nbytes < 0) return set_error(DNATOK_EINVAL, "negative size");
     if (!d_offsets || !d_out_offsets) return set_error(DNATOK_EINVAL, "offsets and out_offsets are required");
     if (nbytes > 0 && !d_bytes) return set_error(DNATOK_EINVAL, "null bytes");
-    if (ids_capacity > 0 && !d_ids) return set_error(DNATOK_EINVAL, "null ids");
-    if ((reinterpret_cast<uintptr_t>(d_ids) & 3) != 0) return set_error(DNATOK_EINVAL, "ids must be 4-byte aligned");
     if (o.layout != DNATOK_PACKED && o.layout != DNATOK_PADDED) return set_error(DNATOK_EINVAL, "bad layout");
     if (o.pad_side != DNATOK_PAD_RIGHT && o.pad_side != DNATOK_PAD_LEFT) return set_error(DNATOK_EINVAL, "bad pad side");
-    if (o.layout == DNATOK_PADDED) {
-        if (o.pad_to <= 0) return set_error(DNATOK_EINVAL, "PADDED needs pad_to > 0");
-        if (!d_mask) return set_error(DNATOK_EINVAL, "PADDED needs a mask buffer");
-        if ((int64_t)n > 0 && o.pad_to > ids_capacity / (int64_t)n)
-            return set_error(DNATOK_ETOOSMALL, "ids_capacity %lld < n * pad_to", (long long)ids_capacity);
-    }
+    if (o.layout == DNATOK_PADDED && o.pad_to <= 0) return set_error(DNATOK_EINVAL, "PADDED needs pad_to > 0");
+    if (o.variant & ~(DNATOK_VARIANT_REVCOMP | DNATOK_VARIANT_OVERLAP)) return set_error(DNATOK_EINVAL, "unknown variant flags");
+    if (o.variant && v->kind == DNATOK_BPE) return set_error(DNATOK_EVOCAB, "encode variants need SINGLE, LUT256 or KMER");
+    if ((o.variant & DNATOK_VARIANT_OVERLAP) && v->kind != DNATOK_KMER)
+        return set_error(DNATOK_EINVAL, "overlapping windows need a k-mer vocabulary");
     int dev = 0;
     DNATOK_HIP(hipGetDevice(&dev));
     if (dev != v->device) return set_error(DNATOK_EINVAL, "vocabulary lives on device %d, current is %d", v->device, dev);
     return DNATOK_OK;
+}
+
+// Capacity of a PADDED output of `cap` cells against n x pad_to.
+static int check_padded_cap(int32_t n, int64_t cap, const dnatok_encode_opts &o, const char *what) {
+    if (o.layout == DNATOK_PADDED && (int64_t)n > 0 && o.pad_to > cap / (int64_t)n)
+        return set_error(DNATOK_ETOOSMALL, "%s %lld < n * pad_to", what, (long long)cap);
+    return DNATOK_OK;
+}
+
+// Checks one encode's arguments (everything dnatok_encode checks on the host).
+static int check_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets,
+                        int32_t n, int32_t *d_ids, int64_t ids_capacity, int64_t *d_out_offsets, int8_t *d_mask,
+                        const dnatok_encode_opts &o) {
+    int rc = check_inputs(v, d_bytes, nbytes, d_offsets, n, d_out_offsets, o);
+    if (rc) return rc;
+    if (ids_capacity < 0) return set_error(DNATOK_EINVAL, "negative size");
+    if (ids_capacity > 0 && !d_ids) return set_error(DNATOK_EINVAL, "null ids");
+    if ((reinterpret_cast<uintptr_t>(d_ids) & 3) != 0) return set_error(DNATOK_EINVAL, "ids must be 4-byte aligned");
+    if (o.layout == DNATOK_PADDED && !d_mask) return set_error(DNATOK_EINVAL, "PADDED needs a mask buffer");
+    return check_padded_cap(n, ids_capacity, o, "ids_capacity");
 }
 
 int dnatok_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets, int32_t n,
@@ -311,6 +330,9 @@ int dnatok_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes,
     if (v->kind == DNATOK_BPE)
         return launch_bpe_encode(v, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets, d_mask, o,
                                  static_cast<hipStream_t>(stream));
+    if (o.variant)
+        return launch_encode_variant(v, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets, d_mask, o,
+                                     static_cast<hipStream_t>(stream));
     return launch_encode(v, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets, d_mask, o,
                          static_cast<hipStream_t>(stream));
 }
@@ -328,6 +350,8 @@ int dnatok_encode_multi(const dnatok_vocab *const *vocabs, int32_t n_vocabs, con
         if (rc) return rc;
         if (n_vocabs > 1 && vocabs[i]->kind != DNATOK_KMER)
             return set_error(DNATOK_EVOCAB, "several vocabularies in one pass must all be k-mer vocabularies");
+        if (n_vocabs > 1 && opts[i].variant)
+            return set_error(DNATOK_EINVAL, "encode variants take one vocabulary per call");
         if (opts[i].add_cls_sep != opts[0].add_cls_sep || opts[i].layout != opts[0].layout ||
             opts[i].pad_side != opts[0].pad_side)
             return set_error(DNATOK_EINVAL, "options differ in more than pad_to and offset_base");
@@ -337,6 +361,48 @@ int dnatok_encode_multi(const dnatok_vocab *const *vocabs, int32_t n_vocabs, con
                                             d_out_offsets[0], d_mask[0], &opts[0], stream);
     return launch_encode_multi(vocabs, n_vocabs, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets,
                                d_mask, opts, static_cast<hipStream_t>(stream));
+}
+
+static int check_table(const void *d_table, int64_t n_rows, int64_t row_bytes, const void *d_out, int64_t out_rows) {
+    if (row_bytes < 1 || row_bytes > (1 << 20)) return set_error(DNATOK_EINVAL, "row_bytes must be 1 .. 2^20");
+    if (n_rows < 1 || !d_table) return set_error(DNATOK_EINVAL, "an embedding table is required");
+    if (out_rows < 0) return set_error(DNATOK_EINVAL, "negative size");
+    if (out_rows > 0 && !d_out) return set_error(DNATOK_EINVAL, "null output");
+    return DNATOK_OK;
+}
+
+int dnatok_embed(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets, int32_t n,
+                 const void *d_table, int64_t n_rows, int64_t row_bytes, void *d_out, int64_t out_rows,
+                 int64_t *d_out_offsets, int32_t *d_ids, int8_t *d_mask, const dnatok_encode_opts *opts,
+                 void *stream) {
+    dnatok_encode_opts o = {};
+    if (opts) o = *opts;
+    if (!v) return set_error(DNATOK_EINVAL, "null vocabulary");
+    if (v->kind == DNATOK_BPE) return set_error(DNATOK_EVOCAB, "BPE: encode, then dnatok_embed_ids");
+    int rc = check_table(d_table, n_rows, row_bytes, d_out, out_rows);
+    if (rc) return rc;
+    if (n_rows < v->vocab_size)
+        return set_error(DNATOK_EINVAL, "table has %lld rows, the vocabulary %d ids", (long long)n_rows, v->vocab_size);
+    rc = check_inputs(v, d_bytes, nbytes, d_offsets, n, d_out_offsets, o);
+    if (rc) return rc;
+    if ((reinterpret_cast<uintptr_t>(d_ids) & 3) != 0) return set_error(DNATOK_EINVAL, "ids must be 4-byte aligned");
+    rc = check_padded_cap(n, out_rows, o, "out_rows");
+    if (rc) return rc;
+    clear_error();
+    return launch_embed(v, d_bytes, nbytes, d_offsets, n, d_table, n_rows, row_bytes, d_out, out_rows, d_out_offsets,
+                        d_ids, d_mask, o, static_cast<hipStream_t>(stream));
+}
+
+int dnatok_embed_ids(const int32_t *d_ids, int64_t n_ids, const void *d_table, int64_t n_rows, int64_t row_bytes,
+                     void *d_out, void *stream) {
+    if (n_ids < 0) return set_error(DNATOK_EINVAL, "negative size");
+    if (n_ids > 0 && !d_ids) return set_error(DNATOK_EINVAL, "null ids");
+    if ((reinterpret_cast<uintptr_t>(d_ids) & 3) != 0) return set_error(DNATOK_EINVAL, "ids must be 4-byte aligned");
+    int rc = check_table(d_table, n_rows, row_bytes, d_out, n_ids);
+    if (rc) return rc;
+    clear_error();
+    if (n_ids == 0) return DNATOK_OK;
+    return launch_embed_ids(d_ids, n_ids, d_table, n_rows, row_bytes, d_out, static_cast<hipStream_t>(stream));
 }
 
 int dnatok_sync_status(void *stream, uint32_t *flags) {

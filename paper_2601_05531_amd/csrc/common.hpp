@@ -147,6 +147,26 @@ int launch_encode_multi(const dnatok_vocab *const *vs, int nv, const uint8_t *d_
                         int64_t *const *d_out_offsets, int8_t *const *d_masks, const dnatok_encode_opts *os,
                         hipStream_t stream);
 
+// Row scan of the closed-form token counts: out[i] = base + the sum over
+// rows r < i of len_r, len = body + 2 * cls with body = L (kmer = 0),
+// ceil(L / k) (frames) or L - k + 1, one for 0 < L < k (overlap). Raises
+// DNATOK_DERR_OFFSETS for bad offsets and, PADDED, DNATOK_DERR_ROW_WIDTH
+// for a row longer than W.
+struct RowScanSpec {
+    const int64_t *offs;
+    int32_t n;
+    int64_t nbytes;
+    int64_t *out;
+    int32_t k;
+    int32_t kmer;
+    int32_t overlap;
+    int32_t cls;
+    int32_t padded;
+    int64_t W;
+    int64_t base;
+};
+int launch_rowscan_spec(const RowScanSpec &sp, hipStream_t stream);
+
 // out[i] = sum over rows r < i of ceil(L_r / divisor) + 2 * cls (out[n] = total).
 int launch_rowscan(const int64_t *d_offsets, int32_t n, int64_t nbytes, int64_t *d_out, int32_t divisor, int32_t cls,
                    hipStream_t stream);
@@ -168,6 +188,19 @@ int64_t bpe_workspace_tiles(int64_t nbytes, int32_t n, int32_t S);
 int launch_bpe_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets,
                       int32_t n, int32_t *d_ids, int64_t cap, int64_t *d_out_offsets, int8_t *d_mask,
                       const dnatok_encode_opts &o, hipStream_t stream);
+
+// Output-parallel kernels (cellwise.hip): encode variants (reverse
+// complement, overlapping k-mers), the fused encode + embedding lookup, and
+// the lookup of given ids.
+int launch_encode_variant(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets,
+                          int32_t n, int32_t *d_ids, int64_t cap, int64_t *d_out_offsets, int8_t *d_mask,
+                          const dnatok_encode_opts &o, hipStream_t stream);
+int launch_embed(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets, int32_t n,
+                 const void *d_table, int64_t n_rows, int64_t row_bytes, void *d_out, int64_t out_rows,
+                 int64_t *d_out_offsets, int32_t *d_ids, int8_t *d_mask, const dnatok_encode_opts &o,
+                 hipStream_t stream);
+int launch_embed_ids(const int32_t *d_ids, int64_t n_ids, const void *d_table, int64_t n_rows, int64_t row_bytes,
+                     void *d_out, hipStream_t stream);
 
 int launch_decode(const dnatok_vocab *v, const int32_t *d_ids, int64_t n_ids, const int64_t *d_offsets,
                   int32_t n, uint8_t *d_out, int64_t out_capacity, int64_t *d_out_offsets, hipStream_t stream);

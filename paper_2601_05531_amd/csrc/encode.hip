@@ -203,6 +203,7 @@ struct RowScanArgs {
     int32_t k;
     uint32_t kinv;  // floor((2^32 - 1) / k)
     int32_t kmer;
+    int32_t overlap;  // k-mer windows of stride 1: L - k + 1 (one for 0 < L < k)
     int32_t cls;
     int32_t padded;
     int64_t W;
@@ -238,7 +239,10 @@ __device__ __forceinline__ int64_t rowscan_unit(const RowScanArgs &a, int64_t ro
             if (o0 < 0 || o1 < o0 || o1 > a.nbytes) err |= DNATOK_DERR_OFFSETS;
             o0 = o0 < 0 ? 0 : (o0 > a.nbytes ? a.nbytes : o0);
             o1 = o1 < o0 ? o0 : (o1 > a.nbytes ? a.nbytes : o1);
-            len[j] = (a.kmer ? div_k(o1 - o0 + a.k - 1, a.k, a.kinv) : o1 - o0) + 2 * a.cls;
+            const int64_t L = o1 - o0;
+            int64_t nb = L;
+            if (a.kmer) nb = a.overlap ? (L >= a.k ? L - a.k + 1 : (L > 0 ? 1 : 0)) : div_k(L + a.k - 1, a.k, a.kinv);
+            len[j] = nb + 2 * a.cls;
             if (a.padded && len[j] > a.W) err |= DNATOK_DERR_ROW_WIDTH;
         }
         mine += len[j];
@@ -983,21 +987,21 @@ int blocks_per_cu(int U, size_t dyn, int *out) {
 
 }  // namespace
 
-int launch_rowscan(const int64_t *d_offsets, int32_t n, int64_t nbytes, int64_t *d_out, int32_t divisor, int32_t cls,
-                   hipStream_t stream) {
+int launch_rowscan_spec(const RowScanSpec &sp, hipStream_t stream) {
     RowScanArgs s;
-    s.offs = d_offsets;
-    s.n = n;
-    s.nbytes = nbytes;
-    s.out_offs = d_out;
-    s.k = divisor;
-    s.kinv = 0xFFFFFFFFu / (uint32_t)(divisor > 0 ? divisor : 1);
-    s.kmer = 1;
-    s.cls = cls;
-    s.padded = 0;
-    s.W = 0;
-    s.base = 0;
-    s.nunits = ((int64_t)n + kUnitRows - 1) / kUnitRows;
+    s.offs = sp.offs;
+    s.n = sp.n;
+    s.nbytes = sp.nbytes;
+    s.out_offs = sp.out;
+    s.k = sp.k > 0 ? sp.k : 1;
+    s.kinv = 0xFFFFFFFFu / (uint32_t)s.k;
+    s.kmer = sp.kmer;
+    s.overlap = sp.overlap;
+    s.cls = sp.cls;
+    s.padded = sp.padded;
+    s.W = sp.W;
+    s.base = sp.base;
+    s.nunits = ((int64_t)sp.n + kUnitRows - 1) / kUnitRows;
     if (s.nunits < 1) s.nunits = 1;
     Workspace *ws = nullptr;
     int rc = get_workspace(stream, s.nunits, &ws);
@@ -1014,6 +1018,23 @@ int launch_rowscan(const int64_t *d_offsets, int32_t n, int64_t nbytes, int64_t 
     hipLaunchKernelGGL(k_rowscan, dim3((unsigned)g), dim3(NT), 0, stream, s);
     DNATOK_HIP(hipGetLastError());
     return DNATOK_OK;
+}
+
+int launch_rowscan(const int64_t *d_offsets, int32_t n, int64_t nbytes, int64_t *d_out, int32_t divisor, int32_t cls,
+                   hipStream_t stream) {
+    RowScanSpec sp;
+    sp.offs = d_offsets;
+    sp.n = n;
+    sp.nbytes = nbytes;
+    sp.out = d_out;
+    sp.k = divisor;
+    sp.kmer = 1;
+    sp.overlap = 0;
+    sp.cls = cls;
+    sp.padded = 0;
+    sp.W = 0;
+    sp.base = 0;
+    return launch_rowscan_spec(sp, stream);
 }
 
 EncodeTuning encode_tuning(const dnatok_vocab *v, int64_t nbytes) {
@@ -1098,6 +1119,7 @@ int launch_encode_multi(const dnatok_vocab *const *vs, int nv, const uint8_t *d_
         sc.k = out.k;
         sc.kinv = out.kinv;
         sc.kmer = kmer ? 1 : 0;
+        sc.overlap = 0;
         sc.cls = a.cls;
         sc.padded = a.padded;
         sc.W = out.W;

@@ -1,0 +1,285 @@
+"""GPU parity of the output-parallel paths: encode variants (reverse
+complement, overlapping k-mers), the encode fused with the embedding lookup,
+and the lookup of given ids. The HIP library (through its C-ABI) against the
+CPU oracle, element by element; embedding rows are compared byte for byte."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2601_05531_amd as dt
+import synth
+
+pytestmark = pytest.mark.gpu
+
+RC, OV = dt.VARIANT_REVCOMP, dt.VARIANT_OVERLAP
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    return torch
+
+
+def _dev(a):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _ragged(seed, n=400, hi=3000.0):
+    """Rows of a decorated order-3 genome (soft-masking, N runs, invalid
+    bytes) with log-uniform lengths plus empty rows and rows of 1..16 bases."""
+    lens = synth.loguniform_int(synth.substream(70, seed), n, 1, hi)
+    lens[::37] = 0
+    lens[5::41] = np.arange(1, len(lens[5::41]) + 1) % 17
+    data = synth.genome(synth.substream(70, 1000 + seed), synth.substream(70, 2000 + seed), 3, int(lens.sum()))
+    return data, synth.offsets_from_lengths(lens)
+
+
+def _want(kind, data, offs, k, variant, cls, lut=None, cls_id=2, sep_id=3):
+    d = oracle.revcomp(data, offs) if variant & RC else data
+    if variant & OV:
+        return oracle.encode_overlap(d, offs, k, add_cls_sep=cls)
+    return oracle.encode(kind, d, offs, k=k, lut=lut, add_cls_sep=cls, cls_id=cls_id, sep_id=sep_id)
+
+
+LUT_IDS = dict(pad_id=0, cls_id=5, sep_id=6)
+
+
+def _vocab(kind, k):
+    if kind == dt.LUT256:
+        return dt.Vocab(dt.LUT256, lut256=oracle.fallback_lut(), **LUT_IDS)
+    return dt.Vocab(kind, k=k)
+
+
+def _oracle_ids(kind, data, offs, k, variant, cls):
+    if kind == dt.LUT256:
+        return _want(kind, data, offs, k, variant, cls, lut=oracle.fallback_lut(), cls_id=LUT_IDS["cls_id"],
+                     sep_id=LUT_IDS["sep_id"])
+    return _want(kind, data, offs, k, variant, cls)
+
+
+# ---------------------------------------------------------------- encode variants
+
+VARIANT_CASES = [
+    (dt.SINGLE, 1, RC), (dt.LUT256, 1, RC),
+    (dt.KMER, 1, RC), (dt.KMER, 3, RC), (dt.KMER, 6, RC), (dt.KMER, 8, RC), (dt.KMER, 15, RC),
+    (dt.KMER, 1, OV), (dt.KMER, 2, OV), (dt.KMER, 6, OV), (dt.KMER, 15, OV),
+    (dt.KMER, 6, RC | OV),
+]
+
+
+@pytest.mark.parametrize("kind,k,variant", VARIANT_CASES)
+@pytest.mark.parametrize("cls", [False, True])
+def test_variant_packed(kind, k, variant, cls):
+    torch = _torch()
+    data, offs = _ragged(k * 10 + variant)
+    print("variant packed kind=%d k=%d variant=%d cls=%d n=%d nbytes=%d" % (kind, k, variant, cls, len(offs) - 1,
+                                                                          len(data)), flush=True)
+    want_ids, want_off = _oracle_ids(kind, data, offs, k, variant, cls)
+    v = _vocab(kind, k)
+    ids, out_off, _ = dt.encode(v, _dev(data), _dev(offs), h_offsets=offs, add_cls_sep=cls, variant=variant)
+    torch.cuda.synchronize()
+    assert dt.sync_status() == 0
+    assert np.array_equal(out_off.cpu().numpy(), want_off)
+    got = ids.cpu().numpy()
+    bad = np.nonzero(got != want_ids)[0]
+    assert got.shape == want_ids.shape and bad.size == 0, bad[:5]
+
+
+@pytest.mark.parametrize("kind,k,variant,side,extra", [
+    (dt.SINGLE, 1, RC, dt.PAD_RIGHT, 0), (dt.LUT256, 1, RC, dt.PAD_LEFT, 3),
+    (dt.KMER, 4, OV, dt.PAD_RIGHT, 1500), (dt.KMER, 6, RC | OV, dt.PAD_LEFT, 0),
+    (dt.KMER, 5, RC, dt.PAD_LEFT, 7),
+])
+def test_variant_padded(kind, k, variant, side, extra):
+    torch = _torch()
+    data, offs = _ragged(100 + k)
+    print("variant padded kind=%d k=%d variant=%d side=%d extra=%d" % (kind, k, variant, side, extra), flush=True)
+    want_ids, want_off = _oracle_ids(kind, data, offs, k, variant, True)
+    W = int(np.diff(want_off).max()) + extra
+    pad_id = LUT_IDS["pad_id"] if kind == dt.LUT256 else 0
+    w_ids, w_mask = oracle.pad(want_ids, want_off, W, side, pad_id)
+    v = _vocab(kind, k)
+    ids, out_off, mask = dt.encode(v, _dev(data), _dev(offs), h_offsets=offs, add_cls_sep=True, layout=dt.PADDED,
+                                   pad_side=side, pad_to=W, variant=variant)
+    torch.cuda.synchronize()
+    assert dt.sync_status() == 0
+    assert np.array_equal(out_off.cpu().numpy(), want_off)
+    assert np.array_equal(ids.cpu().numpy(), w_ids)
+    assert np.array_equal(mask.cpu().numpy(), w_mask)
+
+
+def test_variant_rejections():
+    _torch()
+    data, offs = _ragged(1, n=4)
+    d, o = _dev(data), _dev(offs)
+    with pytest.raises(dt.DnatokError):
+        dt.encode(dt.Vocab(dt.SINGLE), d, o, h_offsets=offs, variant=OV)
+    with pytest.raises(dt.DnatokError):
+        dt.encode(dt.Vocab(dt.BPE, merges=np.zeros((0, 2), np.int32)), d, o, h_offsets=offs, variant=RC)
+    with pytest.raises(dt.DnatokError):
+        dt.encode(dt.Vocab(dt.KMER, k=3), d, o, h_offsets=offs, variant=4)
+
+
+# ---------------------------------------------------------------- fused encode + embedding lookup
+
+def _table(seed, V, D, dtype):
+    """A random table and its rows as bytes (uint8 [V, row_bytes])."""
+    torch = _torch()
+    g = torch.Generator().manual_seed(seed)
+    if dtype in (torch.int8, torch.uint8):
+        t = torch.randint(-100, 100, (V, D), generator=g).to(dtype)
+    else:
+        t = torch.randn(V, D, generator=g).to(dtype)
+    return t.to("cuda"), t.view(torch.uint8).numpy().reshape(V, -1)
+
+
+def _emb_bytes(emb):
+    torch = _torch()
+    return emb.contiguous().view(torch.uint8).cpu().numpy().reshape(emb.shape[:-1] + (-1,))
+
+
+EMBED_CASES = [
+    # kind, k, variant, D, dtype name
+    (dt.SINGLE, 1, 0, 128, "bfloat16"),    # 256-byte rows: 16-byte units
+    (dt.KMER, 6, 0, 33, "float32"),        # 132-byte rows: 4-byte units
+    (dt.KMER, 3, RC, 4, "float16"),        # 8-byte rows
+    (dt.KMER, 2, OV, 1, "bfloat16"),       # 2-byte rows
+    (dt.LUT256, 1, 0, 3, "int8"),          # 3-byte rows: byte units
+]
+
+
+@pytest.mark.parametrize("kind,k,variant,D,dtn", EMBED_CASES)
+@pytest.mark.parametrize("layout,side", [(dt.PACKED, dt.PAD_RIGHT), (dt.PADDED, dt.PAD_LEFT),
+                                         (dt.PADDED, dt.PAD_RIGHT)])
+def test_embed_parity(kind, k, variant, D, dtn, layout, side):
+    torch = _torch()
+    data, offs = _ragged(200 + k + D, n=150, hi=2000.0)
+    print("embed kind=%d k=%d variant=%d D=%d %s layout=%d side=%d" % (kind, k, variant, D, dtn, layout, side),
+          flush=True)
+    v = _vocab(kind, k)
+    table, rows = _table(k * 1000 + D, v.vocab_size + 3, D, getattr(torch, dtn))
+    want_ids, want_off = _oracle_ids(kind, data, offs, k, variant, True)
+    emb, out_off, ids, mask = dt.embed(v, _dev(data), _dev(offs), table, h_offsets=offs, add_cls_sep=True,
+                                       layout=layout, pad_side=side, variant=variant, want_ids=True)
+    torch.cuda.synchronize()
+    assert dt.sync_status() == 0
+    assert np.array_equal(out_off.cpu().numpy(), want_off)
+    if layout == dt.PADDED:
+        W = int(np.diff(want_off).max())
+        pad_id = LUT_IDS["pad_id"] if kind == dt.LUT256 else 0
+        want_ids, w_mask = oracle.pad(want_ids, want_off, W, side, pad_id)
+        assert np.array_equal(mask.cpu().numpy(), w_mask)
+    assert np.array_equal(ids.cpu().numpy(), want_ids)
+    got = _emb_bytes(emb)
+    want = oracle.embed(rows, want_ids)
+    assert got.shape == want.shape
+    bad = np.nonzero((got != want).any(axis=-1).reshape(-1))[0]
+    assert bad.size == 0, bad[:5]
+
+
+def test_embed_misaligned_output_and_guard_rows():
+    # an output view starting 2 bytes in (2-byte units), and a PACKED capacity
+    # short by 5 rows: DERR_CAPACITY raised, rows past the capacity untouched
+    torch = _torch()
+    data, offs = _ragged(300, n=60)
+    v = dt.Vocab(dt.KMER, k=4)
+    table, rows = _table(7, v.vocab_size, 8, torch.bfloat16)
+    want_ids, want_off = _want(dt.KMER, data, offs, 4, 0, False)
+    total = int(want_off[-1])
+    raw = torch.full(((total + 1) * 16 + 2,), 0xAB, dtype=torch.uint8, device="cuda")
+    out = raw[2:2 + total * 16]
+    out_off = torch.empty(len(offs), dtype=torch.int64, device="cuda")
+    opts = dt.make_opts()
+    d_data, d_offs = _dev(data), _dev(offs)  # kept alive until the launch has run
+    dt.dnatok_embed(v.handle, dt._ptr(d_data), len(data), dt._ptr(d_offs), len(offs) - 1, dt._ptr(table),
+                    table.shape[0], 16, dt._ptr(out), total - 5, dt._ptr(out_off), None, None, opts,
+                    torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert dt.sync_status() == dt.DERR_CAPACITY
+    got = out.cpu().numpy().reshape(total, 16)
+    want = oracle.embed(rows, want_ids)
+    assert np.array_equal(got[:total - 5], want[:total - 5])
+    assert (got[total - 5:] == 0xAB).all()
+    r = raw.cpu().numpy()
+    assert (r[:2] == 0xAB).all() and (r[2 + total * 16:] == 0xAB).all()
+
+
+def test_embed_rejections():
+    torch = _torch()
+    data, offs = _ragged(2, n=4)
+    v = dt.Vocab(dt.KMER, k=3)
+    small = torch.zeros((v.vocab_size - 1, 4), dtype=torch.float32, device="cuda")
+    with pytest.raises(dt.DnatokError):
+        dt.embed(v, _dev(data), _dev(offs), small, h_offsets=offs)
+    b = dt.Vocab(dt.BPE, merges=np.zeros((0, 2), np.int32))
+    with pytest.raises(dt.DnatokError):
+        dt.embed(b, _dev(data), _dev(offs), torch.zeros((16, 4), device="cuda"), h_offsets=offs)
+
+
+# ---------------------------------------------------------------- lookup of given ids
+
+def test_embed_ids_bpe_and_out_of_range():
+    torch = _torch()
+    corpus = synth.genome(synth.substream(71, 0), synth.substream(71, 1), 3, 100_000)
+    merges = oracle.bpe_train(corpus, 200)
+    data, offs = _ragged(400, n=120)
+    v = dt.Vocab(dt.BPE, merges=merges)
+    ids, out_off, _ = dt.encode(v, _dev(data), _dev(offs), h_offsets=offs, add_cls_sep=True)
+    table, rows = _table(9, v.vocab_size, 64, torch.bfloat16)
+    emb = dt.embed_ids(ids, table)
+    torch.cuda.synchronize()
+    assert dt.sync_status() == 0
+    want_ids, _ = oracle.encode(oracle.BPE, data, offs, merges=merges, add_cls_sep=True)
+    assert np.array_equal(_emb_bytes(emb), oracle.embed(rows, want_ids))
+    # ids outside the table: zero rows and DERR_IDS
+    bad = torch.tensor([0, -1, v.vocab_size, 5, 2 ** 31 - 1], dtype=torch.int32, device="cuda")
+    emb = dt.embed_ids(bad, table)
+    torch.cuda.synchronize()
+    assert dt.sync_status() == dt.DERR_IDS
+    got = _emb_bytes(emb)
+    assert np.array_equal(got[0], rows[0]) and np.array_equal(got[3], rows[5])
+    assert (got[[1, 2, 4]] == 0).all()
+
+
+# ---------------------------------------------------------------- full-size batch, sampled rows
+
+def test_embed_full_batch_sampled_rows():
+    # the 4096 x 8192 batch, single-nucleotide ids with CLS/SEP, left-padded,
+    # D = 128 bf16 (the paper's embedding width): 8.6 GB of output. Sampled
+    # rows are compared with the oracle run on those rows alone.
+    torch = _torch()
+    data, offs = synth.workload_markov_batch()
+    v = dt.Vocab(dt.SINGLE)
+    table, rows = _table(11, 11, 128, torch.bfloat16)
+    print("embed full batch n=%d nbytes=%d" % (len(offs) - 1, len(data)), flush=True)
+    emb, out_off, _, mask = dt.embed(v, _dev(data), _dev(offs), table, h_offsets=offs, add_cls_sep=True,
+                                     layout=dt.PADDED, pad_side=dt.PAD_LEFT)
+    torch.cuda.synchronize()
+    assert dt.sync_status() == 0
+    rng = np.random.default_rng(5)
+    sample = np.concatenate([[0, len(offs) - 2], rng.choice(len(offs) - 1, 10, replace=False)])
+    for r in sample:
+        row = data[offs[r]:offs[r + 1]]
+        ids, _ = oracle.encode(oracle.SINGLE, row, np.array([0, len(row)]), add_cls_sep=True)
+        assert np.array_equal(_emb_bytes(emb[r]), oracle.embed(rows, ids))
+        assert (mask[r].cpu().numpy() == 1).all()
+    del emb
+
+
+def test_overlap_full_batch_sampled_rows():
+    torch = _torch()
+    data, offs = synth.workload_markov_batch()
+    v = dt.Vocab(dt.KMER, k=6)
+    print("overlap full batch", flush=True)
+    ids, out_off, mask = dt.encode(v, _dev(data), _dev(offs), h_offsets=offs, add_cls_sep=True, layout=dt.PADDED,
+                                   variant=OV | RC)
+    torch.cuda.synchronize()
+    assert dt.sync_status() == 0
+    assert ids.shape == (4096, 8192 - 6 + 1 + 2)
+    rng = np.random.default_rng(6)
+    for r in np.concatenate([[0, 4095], rng.choice(4096, 10, replace=False)]):
+        row = data[offs[r]:offs[r + 1]]
+        o = np.array([0, len(row)])
+        want, _ = oracle.encode_overlap(oracle.revcomp(row, o), o, 6, add_cls_sep=True)
+        assert np.array_equal(ids[r].cpu().numpy(), want)
