@@ -398,6 +398,83 @@ def small_leg(reps: int = 200):
                         % tokens, **res}
 
 
+def cellwise_leg(data, offs, reps: int = 10):
+    """Output-parallel paths on the batched workload (4096 x 8192 bases, CLS/SEP,
+    PADDED with the int8 mask). The encode fused with the embedding lookup
+    writes D = 128 bf16 rows (the paper's embedding width) per cell: the
+    single-nucleotide table has 11 rows (the paper's vocabulary size), the
+    6-mer table 4101; the paper left-pads, so these do too. The encode
+    variants write ids: reverse-complement 6-mer frames and overlapping
+    (stride 1) 6-mers of the reverse complement. Each call is a row scan plus
+    one cell launch; the time per call covers both. Algorithmic bytes: input
+    1 B per base plus offsets, output ids or rows plus the mask, and the table
+    once."""
+    import torch
+    import paper_2601_05531_amd as dt
+
+    n = len(offs) - 1
+    d_in = torch.from_numpy(data).cuda()
+    d_off = torch.from_numpy(offs).cuda()
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+    in_bytes = data.size + 8 * (n + 1)
+    cases = (("embed_single_d128_bf16", dt.SINGLE, 1, 0, 11),
+             ("embed_6mer_d128_bf16", dt.KMER, 6, 0, 4101),
+             ("revcomp_6mer_ids", dt.KMER, 6, dt.VARIANT_REVCOMP, 0),
+             ("revcomp_overlap_6mer_ids", dt.KMER, 6, dt.VARIANT_REVCOMP | dt.VARIANT_OVERLAP, 0))
+    out = {}
+    for name, kind, k, variant, V in cases:
+        v = dt.Vocab(kind, k=k)
+        _, W = dt.plan(v, offs, add_cls_sep=True, variant=variant)
+        cells = n * W
+        opts = dt.make_opts(True, dt.PADDED, dt.PAD_LEFT if V else dt.PAD_RIGHT, W, variant=variant)
+        oo = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+        mask = torch.empty(cells, dtype=torch.int8, device="cuda")
+        if V:
+            g = torch.Generator(device="cuda").manual_seed(42)
+            table = torch.randn((V, 128), generator=g, device="cuda").to(torch.bfloat16)
+            emb = torch.empty((cells, 128), dtype=torch.bfloat16, device="cuda")
+            out_bytes = cells * 256 + cells + V * 256
+
+            def call():
+                dt.dnatok_embed(v.handle, d_in.data_ptr(), data.size, d_off.data_ptr(), n, table.data_ptr(), V, 256,
+                                emb.data_ptr(), cells, oo.data_ptr(), None, mask.data_ptr(), opts, sp)
+        else:
+            ids = torch.empty(cells, dtype=torch.int32, device="cuda")
+            out_bytes = cells * 5
+
+            def call():
+                dt.dnatok_encode(v.handle, d_in.data_ptr(), data.size, d_off.data_ptr(), n, ids.data_ptr(), cells,
+                                 oo.data_ptr(), mask.data_ptr(), opts, sp)
+        for _ in range(3):
+            call()
+        torch.cuda.synchronize()
+        assert dt.sync_status() == 0
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            call()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        alg = in_bytes + out_bytes + 8 * (n + 1)
+        gbps = alg / (ms * 1e-3) / 1e9
+        out[name] = {"ms": round(ms, 4), "cells": cells, "cells_per_s": cells / (ms * 1e-3),
+                     "algorithmic_bytes": alg, "GBps": round(gbps, 1), "frac_hbm_peak": round(gbps / HBM_PEAK_GBS, 3)}
+        log("%s: %.3f ms, %.3e cells/s, %.0f GB/s (%.2f of peak)" % (name, ms, cells / (ms * 1e-3), gbps,
+                                                                     gbps / HBM_PEAK_GBS))
+        del call
+        if V:
+            del emb, table
+        else:
+            del ids
+        v.close()
+        torch.cuda.empty_cache()
+    out["workload"] = ("4096 x 8192 bases (order-3 Markov, soft-masked, N runs, invalid bytes), CLS/SEP, PADDED "
+                       "with int8 mask; embeddings D = 128 bf16 left-padded, variants right-padded")
+    return out
+
+
 BPE_TABLE = os.path.join(ROOT, "tests", "golden", "bpe4096_order5_64M.txt")
 
 
@@ -672,6 +749,8 @@ def main():
     ap.add_argument("--no-bpe", action="store_true", help="skip the ragged BPE batch leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace leg")
     ap.add_argument("--no-small", action="store_true", help="skip the small-batch eager/graph leg")
+    ap.add_argument("--no-cellwise", action="store_true",
+                    help="skip the embedding-lookup and encode-variant leg")
     ap.add_argument("--no-per-vocab", action="store_true", help="skip the four single-vocabulary launches")
     ap.add_argument("--tuning", type=str, default=None,
                     help="TILE,BLOCKS: fixed tiling of the one-pass encode instead of the autotuner's")
@@ -706,6 +785,9 @@ def main():
     small = None
     if not args.no_small:
         small = small_leg()
+    cellwise = None
+    if not args.no_cellwise:
+        cellwise = cellwise_leg(enc["data"], enc["offs"])
     serve = None
     if not args.no_serve:
         serve = serve_leg(args.serve_requests)
@@ -746,6 +828,7 @@ def main():
         "bpe": bpe,
         "serve": serve,
         "small_batch": small,
+        "embed_and_variants": cellwise,
     }
     print(json.dumps(line), flush=True)
 

@@ -14,12 +14,19 @@
 // bf16, against about one input byte), or one id per base for stride-1
 // windows. Work is therefore cut by output cells rather than input tiles:
 //  * A block takes chunks of NT * CPT consecutive cells (cells = tokens plus
-//    pads). Each thread works out the ids of CPT cells, NT apart so that id
-//    and mask stores stay coalesced: the row a cell falls in (PADDED: cell /
-//    W with a 32-bit reciprocal; PACKED: the chunk's first and last rows by
-//    one-wave 64-way searches over the row starts the row scan wrote, then a
-//    binary search between them), the token it holds (pad, CLS, SEP or a
-//    body token), and the body token from the row's bytes.
+//    pads); each thread takes CPT consecutive cells of the chunk, so its ids
+//    go out as one 16-byte store and its mask bytes as one word. The thread
+//    finds the row of its first cell (PADDED: cell / W with a 32-bit
+//    reciprocal; PACKED: the chunk's first and last rows by one-wave 64-way
+//    searches over the row starts the row scan wrote, then a binary search
+//    between them) and steps to the next row only at a row end. It places
+//    every cell first (pad, CLS, SEP or body token, and the bytes a body
+//    token reads), then issues all of its reads at once: a k-mer reads the
+//    three (k <= 8) or five dwords that hold it and classifies them with
+//    the same 16-byte classifier the tile kernel uses; reverse complement
+//    reverses and complements the digits in registers (the bytes are never
+//    rewritten), and for table kinds it reads a table already mapped
+//    through the complement.
 //  * With an embedding table the chunk's ids go to LDS and the block copies
 //    the table rows out in UB-byte units (UB = 16 whenever the row size and
 //    pointers allow): lane l of a wave moves unit l, so a wave writes 1 KiB
@@ -37,7 +44,7 @@ namespace dnatok {
 namespace {
 
 constexpr int NT = 256;
-constexpr int CPT = 4;                       // cells per thread per chunk
+constexpr int CPT = 4;                       // cells per thread per chunk (a multiple of 4)
 constexpr int64_t kChunk = (int64_t)NT * CPT;
 constexpr int kCopyUnroll = 4;               // table units loaded before they are stored
 
@@ -60,6 +67,7 @@ struct CwArgs {
     int32_t cls, padded, left;
     int64_t W;
     uint32_t winv;           // floor((2^32 - 1) / W) when W < 2^31, else 0
+    uint32_t kinv;           // floor((2^32 - 1) / k)
     int32_t pad_id, cls_id, sep_id;
     const int32_t *lut;
     int32_t *ids;            // optional for EMBED
@@ -107,10 +115,10 @@ __device__ __forceinline__ uint32_t udiv(uint32_t x, uint32_t d, uint32_t dinv) 
     return q;
 }
 
-// Base digit A/a=0 C/c=1 G/g=2 T/t=3, or -1 for any other byte.
-__device__ __forceinline__ int32_t base_digit(uint32_t b) {
-    const uint32_t f = b | 0x20u;  // only 'A' and 'a' fold to 'a', and so on
-    return f == 'a' ? 0 : f == 'c' ? 1 : f == 'g' ? 2 : f == 't' ? 3 : -1;
+// x / d for x >= 0, d >= 1, with the 32-bit path when both fit.
+__device__ __forceinline__ int64_t div_any(int64_t x, int64_t d, uint32_t dinv) {
+    if (dinv && x < ((int64_t)1 << 32)) return udiv((uint32_t)x, (uint32_t)d, dinv);
+    return x / d;
 }
 
 // Watson-Crick complement of a byte, case kept; other bytes unchanged.
@@ -142,7 +150,7 @@ __device__ __forceinline__ RowFacts row_facts(const CwArgs &a, int64_t r) {
     int64_t nb;
     if (a.lut_kind) nb = L;
     else if (a.overlap) nb = L >= a.k ? L - a.k + 1 : (L > 0 ? 1 : 0);
-    else nb = (L + a.k - 1) / a.k;
+    else nb = div_any(L + a.k - 1, a.k, a.kinv);
     f.o0 = o0;
     f.o1 = o1;
     f.nb = nb;
@@ -150,45 +158,54 @@ __device__ __forceinline__ RowFacts row_facts(const CwArgs &a, int64_t r) {
     return f;
 }
 
-// Id of body token j of a row (reverse complement: of the row read back to
-// front with bases complemented).
-__device__ __forceinline__ int32_t body_id(const CwArgs &a, const int32_t *s_lut, const RowFacts &f, int64_t j) {
-    if (a.lut_kind) {
-        const int64_t pos = a.revcomp ? f.o1 - 1 - j : f.o0 + j;
-        uint32_t b = a.bytes[pos];
-        if (a.revcomp) b = complement(b);
-        return s_lut[b];
+// The 16 bytes from p on, for a k-mer at p (k <= 8 needs three dwords,
+// k <= 15 five). Dword addresses are clamped to the dword that holds the
+// k-mer's last byte, so every read stays within the dwords the k-mer
+// occupies; bytes past the k-mer are don't-cares.
+template <bool K8>
+__device__ __forceinline__ uint4 window16(const uint8_t *p, int32_t k) {
+    constexpr int ND = K8 ? 3 : 5;
+    const uintptr_t addr = reinterpret_cast<uintptr_t>(p);
+    const uint32_t sh = (uint32_t)(addr & 3);
+    const uint8_t *first = p - sh;
+    const uint8_t *last = p + (k - 1) - ((addr + (uintptr_t)(k - 1)) & 3);
+    uint32_t w[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        if (i < ND) {
+            const uint8_t *q = first + 4 * i;
+            w[i] = *reinterpret_cast<const uint32_t *>(q < last ? q : last);
+        } else {
+            w[i] = 0;
+        }
     }
-    const int64_t s = j * a.stride;
-    if (s + a.k > f.o1 - f.o0) return DNATOK_ID_UNK;  // short final frame, or a row shorter than k
-    int32_t acc = 0;
-    bool ok = true;
-    for (int t = 0; t < a.k; ++t) {
-        const int64_t pos = a.revcomp ? f.o1 - 1 - (s + t) : f.o0 + s + t;
-        int32_t d = base_digit(a.bytes[pos]);
-        ok = ok && d >= 0;
-        if (a.revcomp) d = 3 - d;
-        acc = acc * 4 + (d & 3);
-    }
-    return ok ? 5 + acc : DNATOK_ID_UNK;
+    uint4 r;
+    r.x = __builtin_amdgcn_alignbyte(w[1], w[0], sh);
+    r.y = __builtin_amdgcn_alignbyte(w[2], w[1], sh);
+    r.z = __builtin_amdgcn_alignbyte(w[3], w[2], sh);
+    r.w = __builtin_amdgcn_alignbyte(w[4], w[3], sh);
+    return r;
 }
 
-// Id of position p of a row's span (PADDED: 0 <= p < W; PACKED: p < len).
-__device__ __forceinline__ int32_t cell_id(const CwArgs &a, const int32_t *s_lut, const RowFacts &f, int64_t p,
-                                           bool &tok) {
-    int64_t q = p;
-    if (a.padded && a.left) q = p - (a.W - f.len);
-    tok = q >= 0 && q < f.len;
-    if (!tok) return a.pad_id;
-    if (a.cls) {
-        if (q == 0) return a.cls_id;
-        if (q == f.len - 1) return a.sep_id;
-        return body_id(a, s_lut, f, q - 1);
+// Id of the k-mer whose bytes (in memory order) open window v; reverse
+// complement: of those bytes taken back to front, each complemented.
+__device__ __forceinline__ int32_t kmer_id(uint4 v, int32_t k, int32_t revcomp) {
+    uint32_t code, valid;
+    dev::classify16(v, code, valid);
+    const uint32_t km = (1u << k) - 1u;
+    if ((valid >> (32 - k)) != km) return DNATOK_ID_UNK;
+    uint32_t x = code >> (32 - 2 * k);
+    if (revcomp) {
+        // digits in reverse order (bit reversal, then each 2-bit digit's
+        // bits swapped back), each complemented (3 - d = d ^ 3)
+        uint32_t y = __builtin_bitreverse32(x);
+        y = ((y >> 1) & 0x55555555u) | ((y & 0x55555555u) << 1);
+        x = (y >> (32 - 2 * k)) ^ ((1u << (2 * k)) - 1u);
     }
-    return body_id(a, s_lut, f, q);
+    return (int32_t)(5 + x);
 }
 
-// Row of a PACKED cell: the first r with out_offs[r + 1] - base > cell.
+// Row of a PACKED cell: the first r in [lo, hi] with out_offs[r + 1] - base > cell.
 __device__ __forceinline__ int64_t packed_row(const CwArgs &a, int64_t lo, int64_t hi, int64_t cell) {
     while (lo < hi) {
         const int64_t mid = (lo + hi) >> 1;
@@ -198,13 +215,93 @@ __device__ __forceinline__ int64_t packed_row(const CwArgs &a, int64_t lo, int64
     return lo;
 }
 
-template <int MODE, int UB>
+// Ids of the cells cb .. cb + CPT - 1 (those below cend) and whether each
+// holds a token (not a pad). First every cell is placed (row, token kind,
+// and for a body token the bytes it reads; other cells point their reads
+// at the offsets array, which always holds a readable word), then all
+// reads are issued, then the ids are formed. Rows change within a thread's
+// cells only at row ends.
+template <bool K8>
+__device__ __forceinline__ void thread_cells(const CwArgs &a, const int32_t *s_lut, int64_t cb, int64_t cend,
+                                             const int64_t *s_rows, int32_t (&id)[CPT], bool (&tok)[CPT]) {
+    int64_t row, p;
+    if (a.padded) {
+        row = div_any(cb, a.W, a.winv);
+        p = cb - row * a.W;
+    } else {
+        row = packed_row(a, s_rows[0], s_rows[1], cb);
+        p = cb - (a.out_offs[row] - a.base);
+    }
+    RowFacts f = row_facts(a, row);
+    const uint8_t *dummy = reinterpret_cast<const uint8_t *>(a.offs);
+    const uint8_t *src[CPT];
+    int32_t fixed[CPT], kk[CPT];
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+        src[i] = dummy;
+        fixed[i] = a.pad_id;
+        kk[i] = 1;
+        tok[i] = false;
+        if (cb + i < cend) {
+            if (p == (a.padded ? a.W : f.len)) {
+                // the next row (PACKED: the next non-empty one; one exists,
+                // since this cell is below the total)
+                p = 0;
+                do {
+                    ++row;
+                    f = row_facts(a, row);
+                } while (!a.padded && f.len == 0);
+            }
+            int64_t q = p;
+            if (a.padded && a.left) q = p - (a.W - f.len);
+            tok[i] = q >= 0 && q < f.len;
+            if (tok[i]) {
+                if (a.cls && q == 0) {
+                    fixed[i] = a.cls_id;
+                } else if (a.cls && q == f.len - 1) {
+                    fixed[i] = a.sep_id;
+                } else {
+                    const int64_t j = q - a.cls;
+                    if (a.lut_kind) {
+                        src[i] = a.bytes + (a.revcomp ? f.o1 - 1 - j : f.o0 + j);
+                        fixed[i] = -1;
+                    } else {
+                        const int64_t s0 = j * a.stride;
+                        if (s0 + a.k > f.o1 - f.o0) {
+                            fixed[i] = DNATOK_ID_UNK;  // short final frame, or a row shorter than k
+                        } else {
+                            src[i] = a.bytes + (a.revcomp ? f.o1 - s0 - a.k : f.o0 + s0);
+                            fixed[i] = -1;
+                            kk[i] = a.k;
+                        }
+                    }
+                }
+            }
+            ++p;
+        }
+    }
+    if (a.lut_kind) {
+        uint32_t b[CPT];
+#pragma unroll
+        for (int i = 0; i < CPT; ++i) b[i] = *src[i];
+#pragma unroll
+        for (int i = 0; i < CPT; ++i) id[i] = fixed[i] >= 0 ? fixed[i] : s_lut[b[i]];
+    } else {
+        uint4 win[CPT];
+#pragma unroll
+        for (int i = 0; i < CPT; ++i) win[i] = window16<K8>(src[i], kk[i]);
+#pragma unroll
+        for (int i = 0; i < CPT; ++i) id[i] = fixed[i] >= 0 ? fixed[i] : kmer_id(win[i], a.k, a.revcomp);
+    }
+}
+
+template <int MODE, int UB, bool K8>
 __global__ __launch_bounds__(NT) void k_cellwise(CwArgs a) {
     __shared__ int32_t s_lut[256];
     __shared__ int32_t s_id[kChunk];
     __shared__ int64_t s_rows[2];
     const int tid = threadIdx.x;
-    if (MODE != CW_GATHER) s_lut[tid] = a.lut[tid];
+    if (MODE != CW_GATHER) s_lut[tid] = a.lut[a.revcomp ? complement((uint32_t)tid) : (uint32_t)tid];
     int64_t total = a.ncells;
     if (total < 0) total = a.out_offs[a.n] - a.base;
     const int64_t limit = total < a.cap ? total : a.cap;
@@ -213,68 +310,73 @@ __global__ __launch_bounds__(NT) void k_cellwise(CwArgs a) {
     __syncthreads();
 
     for (int64_t c0 = (int64_t)blockIdx.x * kChunk; c0 < limit; c0 += (int64_t)gridDim.x * kChunk) {
-        const int64_t ncell = limit - c0 < kChunk ? limit - c0 : kChunk;
+        const int64_t cend = limit - c0 < kChunk ? limit : c0 + kChunk;
         if (MODE != CW_GATHER && !a.padded) {
             // the chunk's first and last rows, one wave each
             const int w = tid / dev::kWave;
             if (w < 2) {
-                const int64_t key = w == 0 ? c0 : c0 + ncell - 1;
+                const int64_t key = w == 0 ? c0 : cend - 1;
                 const int64_t r = dev::wave_lower_bound(0, a.n, [&](int64_t q) { return a.out_offs[q + 1] - a.base > key; });
                 if ((tid & (dev::kWave - 1)) == 0) s_rows[w] = r;
             }
             __syncthreads();
         }
-        // row and position of this thread's first cell (PADDED)
-        int64_t prow = 0, pp = 0;
-        if (MODE != CW_GATHER && a.padded) {
-            const int64_t c = c0 + tid;
-            prow = c / a.W;
-            pp = c - prow * a.W;
-        }
+        // this thread's CPT consecutive cells
+        const int64_t cb = c0 + (int64_t)tid * CPT;
+        int32_t id[CPT];
+        bool tok[CPT];
 #pragma unroll
         for (int i = 0; i < CPT; ++i) {
-            const int64_t d = (int64_t)tid + (int64_t)i * NT;
-            const int64_t c = c0 + d;
-            int32_t id = 0;
-            if (d < ncell) {
-                if (MODE == CW_GATHER) {
-                    id = a.ids_in[c];
-                    if (id < 0 || id >= a.n_rows) {
+            id[i] = 0;
+            tok[i] = false;
+        }
+        if (MODE == CW_GATHER) {
+#pragma unroll
+            for (int i = 0; i < CPT; ++i) {
+                if (cb + i < cend) {
+                    id[i] = a.ids_in[cb + i];
+                    if (id[i] < 0 || id[i] >= a.n_rows) {
                         err |= DNATOK_DERR_IDS;
-                        id = -1;
+                        id[i] = -1;
                     }
-                } else {
-                    bool tok;
-                    if (a.padded) {
-                        const RowFacts f = row_facts(a, prow);
-                        id = cell_id(a, s_lut, f, pp, tok);
-                        if (a.mask) a.mask[c] = tok ? 1 : 0;
-                    } else {
-                        const int64_t r = packed_row(a, s_rows[0], s_rows[1], c);
-                        const RowFacts f = row_facts(a, r);
-                        id = cell_id(a, s_lut, f, c - (a.out_offs[r] - a.base), tok);
-                    }
-                    if (a.ids) a.ids[c] = id;
                 }
             }
-            if (MODE != CW_ENCODE) s_id[d] = id;
-            if (MODE != CW_GATHER && a.padded && i + 1 < CPT) {
-                // advance to the cell NT further on
-                pp += NT;
-                if (a.winv) {
-                    const uint32_t q = udiv((uint32_t)pp, (uint32_t)a.W, a.winv);
-                    prow += q;
-                    pp -= (int64_t)q * a.W;
-                } else if (pp >= a.W) {
-                    pp -= a.W;  // W >= 2^31 > NT: one row at most
-                    ++prow;
+        } else if (cb < cend) {
+            thread_cells<K8>(a, s_lut, cb, cend, s_rows, id, tok);
+        }
+        if (MODE != CW_GATHER && cb < cend) {
+            const bool full = cb + CPT <= cend;
+            if (a.ids) {
+                if (full && ((reinterpret_cast<uintptr_t>(a.ids + cb) & 15) == 0)) {
+#pragma unroll
+                    for (int g = 0; g < CPT; g += 4)
+                        *reinterpret_cast<int4 *>(a.ids + cb + g) = make_int4(id[g], id[g + 1], id[g + 2], id[g + 3]);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < CPT; ++i)
+                        if (cb + i < cend) a.ids[cb + i] = id[i];
+                }
+            }
+            if (a.mask) {
+                if (full && ((reinterpret_cast<uintptr_t>(a.mask + cb) & 3) == 0)) {
+#pragma unroll
+                    for (int g = 0; g < CPT; g += 4)
+                        *reinterpret_cast<uint32_t *>(a.mask + cb + g) = (uint32_t)tok[g] | (uint32_t)tok[g + 1] << 8 |
+                                                                         (uint32_t)tok[g + 2] << 16 |
+                                                                         (uint32_t)tok[g + 3] << 24;
+                } else {
+#pragma unroll
+                    for (int i = 0; i < CPT; ++i)
+                        if (cb + i < cend) a.mask[cb + i] = tok[i] ? 1 : 0;
                 }
             }
         }
         if (MODE != CW_ENCODE) {
+#pragma unroll
+            for (int i = 0; i < CPT; ++i) s_id[tid * CPT + i] = id[i];
             typedef typename Unit<UB>::T V;
             __syncthreads();
-            const uint32_t units = (uint32_t)ncell * a.ru;
+            const uint32_t units = (uint32_t)(cend - c0) * a.ru;
             uint8_t *ob = a.emb + c0 * a.row_bytes;
             for (uint32_t u0 = tid; u0 < units; u0 += NT * kCopyUnroll) {
                 V v[kCopyUnroll];
@@ -284,8 +386,8 @@ __global__ __launch_bounds__(NT) void k_cellwise(CwArgs a) {
                     const uint32_t u = u0 + t * NT;
                     cell[t] = udiv(u, a.ru, a.ruinv);
                     part[t] = u - cell[t] * a.ru;
-                    const int32_t id = u < units ? s_id[cell[t]] : -1;
-                    if (id >= 0) v[t] = *reinterpret_cast<const V *>(a.table + (int64_t)id * a.row_bytes + part[t] * UB);
+                    const int32_t rid = u < units ? s_id[cell[t]] : -1;
+                    if (rid >= 0) v[t] = *reinterpret_cast<const V *>(a.table + (int64_t)rid * a.row_bytes + part[t] * UB);
                     else v[t] = V{};
                 }
 #pragma unroll
@@ -295,23 +397,32 @@ __global__ __launch_bounds__(NT) void k_cellwise(CwArgs a) {
                         __builtin_nontemporal_store(v[t], reinterpret_cast<V *>(ob + (int64_t)cell[t] * a.row_bytes + part[t] * UB));
                 }
             }
+            __syncthreads();
+        } else if (!a.padded) {
+            __syncthreads();  // s_rows is rewritten for the next chunk
         }
-        __syncthreads();
     }
     if (err) dev::raise_error(a.err_hdr, err);
 }
 
-template <int MODE, int UB>
+template <int MODE, int UB, bool K8>
 int launch_cw(const CwArgs &a, int64_t max_cells, hipStream_t stream) {
     int per_cu = 0;
-    DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cellwise<MODE, UB>, NT, 0));
+    DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cellwise<MODE, UB, K8>, NT, 0));
     int64_t g = (int64_t)device_cu_count() * (per_cu > 0 ? per_cu : 1);
     const int64_t chunks = (max_cells + kChunk - 1) / kChunk;
     if (g > chunks) g = chunks;
     if (g < 1) g = 1;
-    hipLaunchKernelGGL((k_cellwise<MODE, UB>), dim3((unsigned)g), dim3(NT), 0, stream, a);
+    hipLaunchKernelGGL((k_cellwise<MODE, UB, K8>), dim3((unsigned)g), dim3(NT), 0, stream, a);
     DNATOK_HIP(hipGetLastError());
     return DNATOK_OK;
+}
+
+// k-mers of up to 8 bases read three dwords per token, longer ones five.
+template <int MODE, int UB>
+int launch_cw_k(const CwArgs &a, int64_t max_cells, hipStream_t stream) {
+    if (a.lut_kind || a.k <= 8) return launch_cw<MODE, UB, true>(a, max_cells, stream);
+    return launch_cw<MODE, UB, false>(a, max_cells, stream);
 }
 
 template <int MODE>
@@ -324,11 +435,11 @@ int launch_cw_units(CwArgs &a, int64_t max_cells, hipStream_t stream) {
     a.ru = (uint32_t)(a.row_bytes / ub);
     a.ruinv = 0xFFFFFFFFu / a.ru;
     switch (ub) {
-    case 16: return launch_cw<MODE, 16>(a, max_cells, stream);
-    case 8: return launch_cw<MODE, 8>(a, max_cells, stream);
-    case 4: return launch_cw<MODE, 4>(a, max_cells, stream);
-    case 2: return launch_cw<MODE, 2>(a, max_cells, stream);
-    default: return launch_cw<MODE, 1>(a, max_cells, stream);
+    case 16: return launch_cw_k<MODE, 16>(a, max_cells, stream);
+    case 8: return launch_cw_k<MODE, 8>(a, max_cells, stream);
+    case 4: return launch_cw_k<MODE, 4>(a, max_cells, stream);
+    case 2: return launch_cw_k<MODE, 2>(a, max_cells, stream);
+    default: return launch_cw_k<MODE, 1>(a, max_cells, stream);
     }
 }
 
@@ -349,6 +460,7 @@ int setup_encode(CwArgs &a, const dnatok_vocab *v, const uint8_t *d_bytes, int64
     a.k = kmer ? v->k : 1;
     a.overlap = (o.variant & DNATOK_VARIANT_OVERLAP) ? 1 : 0;
     a.stride = a.overlap ? 1 : a.k;
+    a.kinv = 0xFFFFFFFFu / (uint32_t)a.k;
     a.revcomp = (o.variant & DNATOK_VARIANT_REVCOMP) ? 1 : 0;
     a.cls = o.add_cls_sep ? 1 : 0;
     a.padded = o.layout == DNATOK_PADDED ? 1 : 0;
@@ -396,7 +508,7 @@ int launch_encode_variant(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t
     a.mask = a.padded ? d_mask : nullptr;
     a.cap = cap;
     if (max_cells < 0 || max_cells > cap) max_cells = cap;
-    return launch_cw<CW_ENCODE, 16>(a, max_cells, stream);
+    return launch_cw_k<CW_ENCODE, 16>(a, max_cells, stream);
 }
 
 int launch_embed(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets, int32_t n,

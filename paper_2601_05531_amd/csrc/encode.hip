@@ -111,27 +111,6 @@ __device__ __forceinline__ int64_t cells_before(const Row &r, int64_t X, int32_t
     return c;
 }
 
-// 16 bytes -> 16 two-bit base digits (most significant first) and 16
-// validity bits (bit 31 = first byte) for the A/C/G/T/a/c/g/t test. Per 4
-// bytes: fold case, read the digit off bits 1-2 (a->0 c->1 g->2 t->3), look
-// the canonical letter of that digit up with a byte permute, and compare;
-// multiplies gather the 2-bit digits and the validity bits.
-__device__ __forceinline__ void classify16(uint4 v, uint32_t &code, uint32_t &valid) {
-    const uint32_t x[4] = {v.x, v.y, v.z, v.w};
-    code = 0;
-    valid = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const uint32_t f = x[q] | 0x20202020u;  // only A/a map to a (likewise c, g, t)
-        const uint32_t d = ((f >> 1) ^ (f >> 2)) & 0x03030303u;
-        const uint32_t canon = __builtin_amdgcn_perm(0u, 0x74676361u, d);  // "acgt"[d] per byte
-        const uint32_t z = f ^ canon;
-        const uint32_t bad = (((z & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | z) & 0x80808080u;  // byte != letter
-        code |= ((d * 0x40100401u) >> 24) << (24 - 8 * q);
-        valid |= ((((bad ^ 0x80808080u) >> 7) * 0x80402010u) >> 28) << (28 - 4 * q);
-    }
-}
-
 // Id of the k-mer whose first base is tile byte idx. win64[m] holds the
 // digits of chunks m and m+1 (32 bases, first base in the top bits) and
 // val32[m] their validity bits, so any k-mer (k <= 15) starting in chunk m
@@ -619,7 +598,7 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
                 // chunk m's digits are the high half of window m and the low
                 // half of window m-1 (likewise its validity bits)
                 uint32_t c, vb;
-                classify16(x, c, vb);
+                dev::classify16(x, c, vb);
                 uint32_t *w32 = reinterpret_cast<uint32_t *>(win64);
                 uint16_t *v16 = reinterpret_cast<uint16_t *>(val32);
                 w32[2 * m + 1] = c;
