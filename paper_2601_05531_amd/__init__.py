@@ -677,7 +677,7 @@ class Graph:
 
     ``calls``: a list of dicts with keys vocab, d_bytes, d_offsets, d_ids,
     d_out_offsets and optionally d_mask, add_cls_sep, layout, pad_side,
-    pad_to (tensors on the device)."""
+    pad_to, variant (tensors on the device)."""
 
     def __init__(self, calls):
         arr = (dnatok_encode_call * len(calls))()
@@ -693,7 +693,7 @@ class Graph:
             c.d_out_offsets = _ptr(d["d_out_offsets"])
             c.d_mask = _ptr(d.get("d_mask"))
             c.opts = make_opts(d.get("add_cls_sep", False), d.get("layout", PACKED), d.get("pad_side", PAD_RIGHT),
-                               d.get("pad_to", 0))
+                               d.get("pad_to", 0), variant=d.get("variant", 0))
             self._keep.append(d)
         h = ctypes.c_void_p()
         _check(lib().dnatok_graph_create(arr, len(calls), ctypes.byref(h)))

@@ -38,12 +38,16 @@
 // and the written offsets agree.
 #include "common.hpp"
 #include "device.hpp"
+#include "rowscan.hpp"
 
 namespace dnatok {
 
 namespace {
 
 constexpr int NT = 256;
+static_assert(NT == kScanNT, "the fused row scan runs with the cell kernel's block size");
+constexpr int32_t kFuseMaxRows = 16384;      // PADDED: the first block scans the rows instead of a separate launch
+constexpr int kGridPerSlot = 4;              // blocks launched per resident block slot
 constexpr int CPT = 4;                       // cells per thread per chunk (a multiple of 4)
 constexpr int64_t kChunk = (int64_t)NT * CPT;
 constexpr int kCopyUnroll = 4;               // table units loaded before they are stored
@@ -79,6 +83,8 @@ struct CwArgs {
     uint8_t *emb;
     uint32_t ru, ruinv;      // units per table row and floor((2^32 - 1) / ru)
     uint32_t *err_hdr;
+    int32_t fused_scan;      // PADDED, few rows: block 0 writes out_offsets (the others take cells)
+    RowScanArgs scan;
 };
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -233,6 +239,73 @@ __device__ __forceinline__ void thread_cells(const CwArgs &a, const int32_t *s_l
         p = cb - (a.out_offs[row] - a.base);
     }
     RowFacts f = row_facts(a, row);
+    // Fast path: the CPT cells are body tokens of this row whose windows
+    // lie within 32 bytes (any overlapping k, frames of k <= 8, table
+    // kinds): one 32-byte read, two classifications, then shifts per cell.
+    {
+        const int32_t kw = a.lut_kind ? 1 : a.k;
+        const int32_t st = a.lut_kind ? 1 : a.stride;
+        const int32_t spanb = (CPT - 1) * st + kw;
+        int64_t q0 = p;
+        if (a.padded && a.left) q0 = p - (a.W - f.len);
+        const int64_t j0 = q0 - a.cls;
+        const int64_t s0 = j0 * st;
+        if (spanb <= 32 && cb + CPT <= cend && p + CPT <= (a.padded ? a.W : f.len) && q0 >= a.cls &&
+            q0 + CPT <= f.len - a.cls && s0 + spanb <= f.o1 - f.o0) {
+            const int64_t lo = a.revcomp ? f.o1 - s0 - spanb : f.o0 + s0;
+            const uint8_t *pl = a.bytes + lo;
+            const uintptr_t addr = reinterpret_cast<uintptr_t>(pl);
+            const uint32_t sh = (uint32_t)(addr & 3);
+            const uint8_t *first = pl - sh;
+            const uint8_t *last = pl + (spanb - 1) - ((addr + (uintptr_t)(spanb - 1)) & 3);
+            uint32_t w[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const uint8_t *q = first + 4 * i;
+                w[i] = *reinterpret_cast<const uint32_t *>(q < last ? q : last);
+            }
+            if (a.lut_kind) {
+                const uint32_t b4 = __builtin_amdgcn_alignbyte(w[1], w[0], sh);
+#pragma unroll
+                for (int i = 0; i < CPT; ++i) {
+                    const int t = a.revcomp ? CPT - 1 - i : i;
+                    id[i] = s_lut[(b4 >> (8 * t)) & 255u];
+                    tok[i] = true;
+                }
+                return;
+            }
+            uint4 v0, v1;
+            v0.x = __builtin_amdgcn_alignbyte(w[1], w[0], sh);
+            v0.y = __builtin_amdgcn_alignbyte(w[2], w[1], sh);
+            v0.z = __builtin_amdgcn_alignbyte(w[3], w[2], sh);
+            v0.w = __builtin_amdgcn_alignbyte(w[4], w[3], sh);
+            v1.x = __builtin_amdgcn_alignbyte(w[5], w[4], sh);
+            v1.y = __builtin_amdgcn_alignbyte(w[6], w[5], sh);
+            v1.z = __builtin_amdgcn_alignbyte(w[7], w[6], sh);
+            v1.w = __builtin_amdgcn_alignbyte(w[8], w[7], sh);
+            uint32_t c0, c1, va0, va1;
+            dev::classify16(v0, c0, va0);
+            dev::classify16(v1, c1, va1);
+            const uint64_t code = ((uint64_t)c0 << 32) | c1;  // 32 digits, first byte on top
+            const uint32_t valid = va0 | (va1 >> 16);         // 32 validity bits, first byte on top
+            const int32_t k = a.k;
+            const uint32_t km = (1u << k) - 1u;
+#pragma unroll
+            for (int i = 0; i < CPT; ++i) {
+                const int32_t off = (a.revcomp ? CPT - 1 - i : i) * st;  // window of cell i within the 32 bytes
+                uint32_t x = (uint32_t)((code << (2 * off)) >> (64 - 2 * k));
+                const bool ok = ((valid << off) >> (32 - k)) == km;
+                if (a.revcomp) {
+                    uint32_t y = __builtin_bitreverse32(x);
+                    y = ((y >> 1) & 0x55555555u) | ((y & 0x55555555u) << 1);
+                    x = (y >> (32 - 2 * k)) ^ ((1u << (2 * k)) - 1u);
+                }
+                id[i] = ok ? (int32_t)(5 + x) : DNATOK_ID_UNK;
+                tok[i] = true;
+            }
+            return;
+        }
+    }
     const uint8_t *dummy = reinterpret_cast<const uint8_t *>(a.offs);
     const uint8_t *src[CPT];
     int32_t fixed[CPT], kk[CPT];
@@ -301,15 +374,22 @@ __global__ __launch_bounds__(NT) void k_cellwise(CwArgs a) {
     __shared__ int32_t s_id[kChunk];
     __shared__ int64_t s_rows[2];
     const int tid = threadIdx.x;
+    if (MODE != CW_GATHER && a.fused_scan && blockIdx.x == 0) {
+        __shared__ int64_t s_tmp[kScanNT / dev::kWave + 1];
+        rowscan_single_block(a.scan, s_tmp, a.err_hdr);
+        return;
+    }
+    const int64_t bid = (int64_t)blockIdx.x - a.fused_scan;  // cell walker index
+    const int64_t G = (int64_t)gridDim.x - a.fused_scan;     // cell walkers
     if (MODE != CW_GATHER) s_lut[tid] = a.lut[a.revcomp ? complement((uint32_t)tid) : (uint32_t)tid];
     int64_t total = a.ncells;
     if (total < 0) total = a.out_offs[a.n] - a.base;
     const int64_t limit = total < a.cap ? total : a.cap;
-    if (blockIdx.x == 0 && tid == 0 && total > a.cap) dev::raise_error(a.err_hdr, DNATOK_DERR_CAPACITY);
+    if (bid == 0 && tid == 0 && total > a.cap) dev::raise_error(a.err_hdr, DNATOK_DERR_CAPACITY);
     uint32_t err = 0;
     __syncthreads();
 
-    for (int64_t c0 = (int64_t)blockIdx.x * kChunk; c0 < limit; c0 += (int64_t)gridDim.x * kChunk) {
+    for (int64_t c0 = bid * kChunk; c0 < limit; c0 += G * kChunk) {
         const int64_t cend = limit - c0 < kChunk ? limit : c0 + kChunk;
         if (MODE != CW_GATHER && !a.padded) {
             // the chunk's first and last rows, one wave each
@@ -409,10 +489,13 @@ template <int MODE, int UB, bool K8>
 int launch_cw(const CwArgs &a, int64_t max_cells, hipStream_t stream) {
     int per_cu = 0;
     DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cellwise<MODE, UB, K8>, NT, 0));
-    int64_t g = (int64_t)device_cu_count() * (per_cu > 0 ? per_cu : 1);
+    // several blocks per resident slot: a block that ends need not wait for
+    // its stores, where a walker's next chunk would
+    int64_t g = kGridPerSlot * (int64_t)device_cu_count() * (per_cu > 0 ? per_cu : 1);
     const int64_t chunks = (max_cells + kChunk - 1) / kChunk;
     if (g > chunks) g = chunks;
     if (g < 1) g = 1;
+    g += a.fused_scan;
     hipLaunchKernelGGL((k_cellwise<MODE, UB, K8>), dim3((unsigned)g), dim3(NT), 0, stream, a);
     DNATOK_HIP(hipGetLastError());
     return DNATOK_OK;
@@ -472,23 +555,41 @@ int setup_encode(CwArgs &a, const dnatok_vocab *v, const uint8_t *d_bytes, int64
     a.sep_id = v->sep_id;
     a.lut = v->d_lut;
 
-    RowScanSpec sp;
-    sp.offs = d_offsets;
-    sp.n = n;
-    sp.nbytes = nbytes;
-    sp.out = d_out_offsets;
-    sp.k = a.k;
-    sp.kmer = kmer ? 1 : 0;
-    sp.overlap = a.overlap;
-    sp.cls = a.cls;
-    sp.padded = a.padded;
-    sp.W = a.W;
-    sp.base = a.base;
-    int rc = launch_rowscan_spec(sp, stream);
-    if (rc) return rc;
     Workspace *ws = nullptr;
-    rc = get_workspace(stream, 1, &ws);
+    int rc = get_workspace(stream, 1, &ws);
     if (rc) return rc;
+    a.fused_scan = (a.padded && n <= kFuseMaxRows) ? 1 : 0;
+    if (a.fused_scan) {
+        RowScanArgs &sc = a.scan;
+        sc = RowScanArgs{};
+        sc.offs = d_offsets;
+        sc.n = n;
+        sc.nbytes = nbytes;
+        sc.out_offs = d_out_offsets;
+        sc.k = a.k;
+        sc.kinv = a.kinv;
+        sc.kmer = kmer ? 1 : 0;
+        sc.overlap = a.overlap;
+        sc.cls = a.cls;
+        sc.padded = 1;
+        sc.W = a.W;
+        sc.base = a.base;
+    } else {
+        RowScanSpec sp;
+        sp.offs = d_offsets;
+        sp.n = n;
+        sp.nbytes = nbytes;
+        sp.out = d_out_offsets;
+        sp.k = a.k;
+        sp.kmer = kmer ? 1 : 0;
+        sp.overlap = a.overlap;
+        sp.cls = a.cls;
+        sp.padded = a.padded;
+        sp.W = a.W;
+        sp.base = a.base;
+        rc = launch_rowscan_spec(sp, stream);
+        if (rc) return rc;
+    }
     a.err_hdr = ws->d_hdr;
     a.ncells = a.padded ? (int64_t)n * a.W : -1;
     *max_cells = a.padded ? a.ncells : -1;

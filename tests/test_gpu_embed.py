@@ -242,6 +242,50 @@ def test_embed_ids_bpe_and_out_of_range():
     assert (got[[1, 2, 4]] == 0).all()
 
 
+# ---------------------------------------------------------------- captured graph of variant encodes
+
+def test_variant_encodes_in_a_graph():
+    # reverse-complement and overlapping encodes captured once, replayed over
+    # changing input bytes with eager work in between; every replay equals
+    # the oracle on the bytes it saw
+    torch = _torch()
+    data, offs = _ragged(500, n=200)
+    d_bytes, d_offs = _dev(data), _dev(offs)
+    cases = [(dt.Vocab(dt.KMER, k=6), RC | OV, dt.PADDED), (dt.Vocab(dt.KMER, k=4), RC, dt.PACKED),
+             (dt.Vocab(dt.SINGLE), RC, dt.PADDED)]
+    calls, outs = [], []
+    for v, variant, layout in cases:
+        total, W = dt.plan(v, offs, add_cls_sep=True, variant=variant)
+        cap = len(offs[:-1]) * W if layout == dt.PADDED else total
+        ids = torch.empty(cap, dtype=torch.int32, device="cuda")
+        oo = torch.empty(len(offs), dtype=torch.int64, device="cuda")
+        mask = torch.empty(cap, dtype=torch.int8, device="cuda") if layout == dt.PADDED else None
+        calls.append(dict(vocab=v, d_bytes=d_bytes, d_offsets=d_offs, d_ids=ids, d_out_offsets=oo, d_mask=mask,
+                          add_cls_sep=True, layout=layout, pad_to=W if layout == dt.PADDED else 0, variant=variant))
+        outs.append((ids, oo, mask, W))
+    g = dt.Graph(calls)
+    rng = np.random.default_rng(9)
+    for rep in range(3):
+        cur = data.copy()
+        flip = rng.choice(len(cur), 2000, replace=False)
+        cur[flip] = np.frombuffer(b"ACGTNacgtn#", np.uint8)[rng.integers(0, 11, 2000)]
+        d_bytes.copy_(torch.from_numpy(cur))
+        g.launch()
+        torch.cuda.synchronize()
+        assert dt.sync_status() == 0
+        for (v, variant, layout), (ids, oo, mask, W) in zip(cases, outs):
+            want_ids, want_off = _want(v.kind, cur, offs, v.k, variant, True)
+            assert np.array_equal(oo.cpu().numpy(), want_off)
+            if layout == dt.PADDED:
+                w_ids, w_mask = oracle.pad(want_ids, want_off, W)
+                assert np.array_equal(ids.cpu().numpy().reshape(-1, W), w_ids)
+                assert np.array_equal(mask.cpu().numpy().reshape(-1, W), w_mask)
+            else:
+                assert np.array_equal(ids.cpu().numpy(), want_ids)
+        _ = torch.ones(1 << 20, device="cuda").sum().item()  # eager work between replays
+    g.close()
+
+
 # ---------------------------------------------------------------- full-size batch, sampled rows
 
 def test_embed_full_batch_sampled_rows():
