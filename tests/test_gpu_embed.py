@@ -327,3 +327,67 @@ def test_overlap_full_batch_sampled_rows():
         o = np.array([0, len(row)])
         want, _ = oracle.encode_overlap(oracle.revcomp(row, o), o, 6, add_cls_sep=True)
         assert np.array_equal(ids[r].cpu().numpy(), want)
+
+
+# ---------------------------------------------------------------- edge cases
+
+def test_empty_batches_and_empty_rows():
+    torch = _torch()
+    v = dt.Vocab(dt.KMER, k=5)
+    table, rows = _table(3, v.vocab_size, 8, torch.float32)
+    # no rows at all
+    offs = np.zeros(1, np.int64)
+    d = torch.zeros(16, dtype=torch.uint8, device="cuda")
+    for layout in (dt.PACKED, dt.PADDED):
+        emb, oo, _, _ = dt.embed(v, d[:0], _dev(offs), table, h_offsets=offs, layout=layout, pad_to=4)
+        ids, oo2, _ = dt.encode(v, d[:0], _dev(offs), h_offsets=offs, layout=layout, pad_to=4, variant=RC | OV)
+        torch.cuda.synchronize()
+        assert dt.sync_status() == 0
+        assert oo.cpu().tolist() == [0] and oo2.cpu().tolist() == [0]
+    # only empty rows, with and without CLS/SEP
+    offs = np.zeros(9, np.int64)
+    for cls in (False, True):
+        emb, oo, ids, mask = dt.embed(v, d[:0], _dev(offs), table, h_offsets=offs, add_cls_sep=cls,
+                                      layout=dt.PADDED, pad_to=3, want_ids=True)
+        torch.cuda.synchronize()
+        assert dt.sync_status() == 0
+        want = [[2, 3, 0] if cls else [0, 0, 0]] * 8
+        assert ids.cpu().numpy().tolist() == want
+        assert np.array_equal(_emb_bytes(emb), oracle.embed(rows, np.array(want)))
+
+
+def test_bad_offsets_raise_the_flag_and_stay_in_bounds():
+    # decreasing and out-of-range offsets: each row is clamped on its own as
+    # the row scan clamps it (start into [0, nbytes], end into [start,
+    # nbytes]), DERR_OFFSETS is raised, and nothing is written past the outputs
+    torch = _torch()
+    data = synth.genome(synth.substream(72, 0), synth.substream(72, 1), 3, 1000)
+    nbytes = len(data)
+    offs = np.array([0, 100, 50, 300, nbytes + 50, nbytes], np.int64)
+    n = len(offs) - 1
+    rows = []
+    for i in range(n):
+        o0 = min(max(int(offs[i]), 0), nbytes)
+        o1 = min(max(int(offs[i + 1]), o0), nbytes)
+        rows.append(data[o0:o1])
+    assert [len(r) for r in rows] == [100, 0, 250, nbytes - 300, 0]
+    per_row = [oracle.encode_overlap(r, np.array([0, len(r)]), 3, add_cls_sep=True)[0] for r in rows]
+    want_off = np.concatenate([[0], np.cumsum([len(x) for x in per_row])])
+    W = max(len(x) for x in per_row)
+    v = dt.Vocab(dt.KMER, k=3)
+    guard = 64
+    ids = torch.full((n * W + guard,), -7, dtype=torch.int32, device="cuda")
+    mask = torch.full((n * W + guard,), -7, dtype=torch.int8, device="cuda")
+    oo = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    d_data, d_offs = _dev(data), _dev(offs)
+    opts = dt.make_opts(True, dt.PADDED, dt.PAD_RIGHT, W, variant=OV)
+    dt.dnatok_encode(v.handle, dt._ptr(d_data), nbytes, dt._ptr(d_offs), n, dt._ptr(ids), n * W, dt._ptr(oo),
+                     dt._ptr(mask), opts, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert dt.sync_status() & dt.DERR_OFFSETS
+    assert np.array_equal(oo.cpu().numpy(), want_off)
+    got = ids.cpu().numpy()
+    for i, x in enumerate(per_row):
+        assert np.array_equal(got[i * W:i * W + len(x)], x)
+        assert (got[i * W + len(x):(i + 1) * W] == 0).all()
+    assert (got[n * W:] == -7).all() and (mask.cpu().numpy()[n * W:] == -7).all()
