@@ -311,6 +311,28 @@ def test_embed_full_batch_sampled_rows():
     del emb
 
 
+def test_full_batch_lookups_back_to_back():
+    # two lookups in a row on the full batch (33.5M cells) with 2-byte rows,
+    # reverse complement and right padding in the second; every cell is
+    # compared with the oracle
+    torch = _torch()
+    data, offs = synth.workload_markov_batch()
+    d_data, d_offs = _dev(data), _dev(offs)
+    table, rows = _table(13, 11, 1, torch.bfloat16)
+    v = dt.Vocab(dt.SINGLE)
+    for variant, side in ((0, dt.PAD_LEFT), (RC, dt.PAD_RIGHT)):
+        print("full-batch lookup variant=%d side=%d" % (variant, side), flush=True)
+        emb, out_off, _, mask = dt.embed(v, d_data, d_offs, table, h_offsets=offs, add_cls_sep=True,
+                                         layout=dt.PADDED, pad_side=side, variant=variant)
+        torch.cuda.synchronize()
+        assert dt.sync_status() == 0
+        want_ids, want_off = _want(dt.SINGLE, data, offs, 1, variant, True)
+        w_ids, w_mask = oracle.pad(want_ids, want_off, int(np.diff(want_off).max()), side)
+        assert np.array_equal(_emb_bytes(emb), oracle.embed(rows, w_ids))
+        assert np.array_equal(mask.cpu().numpy(), w_mask)
+        del emb
+
+
 def test_overlap_full_batch_sampled_rows():
     torch = _torch()
     data, offs = synth.workload_markov_batch()
