@@ -476,6 +476,53 @@ def cellwise_leg(data, offs, reps: int = 10):
     return out
 
 
+def decode_leg(data, offs, reps: int = 10):
+    """Decode (ids back to bases) of the batched workload's PACKED ids with
+    CLS/SEP, for the single-nucleotide and 6-mer vocabularies: one launch per
+    call. Algorithmic bytes: 4 B per id in, the decoded bases out (1 B per
+    base; a 6-mer id decodes to 6), plus both offsets arrays."""
+    import torch
+    import paper_2601_05531_amd as dt
+
+    n = len(offs) - 1
+    d_in = torch.from_numpy(data).cuda()
+    d_off = torch.from_numpy(offs).cuda()
+    st = torch.cuda.current_stream()
+    sp = st.cuda_stream
+    out = {}
+    for name, kind, k in (("single", dt.SINGLE, 1), ("6mer", dt.KMER, 6)):
+        v = dt.Vocab(kind, k=k)
+        ids, id_off, _ = dt.encode(v, d_in, d_off, h_offsets=offs, add_cls_sep=True)
+        cap = ids.numel() * v.max_token_bytes
+        dec = torch.empty(cap, dtype=torch.uint8, device="cuda")
+        dec_off = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+
+        def call():
+            dt.dnatok_decode(v.handle, ids.data_ptr(), ids.numel(), id_off.data_ptr(), n, dec.data_ptr(), cap,
+                             dec_off.data_ptr(), sp)
+        for _ in range(3):
+            call()
+        torch.cuda.synchronize()
+        assert dt.sync_status() == 0
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        for _ in range(reps):
+            call()
+        b.record(st)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        out_bytes = int(dec_off[n].item())
+        alg = 4 * ids.numel() + out_bytes + 16 * (n + 1)
+        gbps = alg / (ms * 1e-3) / 1e9
+        out[name] = {"ms": round(ms, 4), "ids": ids.numel(), "bases_out": out_bytes, "ids_per_s": ids.numel() / (ms * 1e-3),
+                     "GBps": round(gbps, 1), "frac_hbm_peak": round(gbps / HBM_PEAK_GBS, 3)}
+        log("decode %s: %.3f ms, %.3e ids/s, %.0f GB/s (%.2f of peak)" % (name, ms, ids.numel() / (ms * 1e-3), gbps,
+                                                                        gbps / HBM_PEAK_GBS))
+        v.close()
+    out["workload"] = "PACKED ids (CLS/SEP) of the 4096 x 8192-base batch back to uppercase bases"
+    return out
+
+
 BPE_TABLE = os.path.join(ROOT, "tests", "golden", "bpe4096_order5_64M.txt")
 
 
@@ -752,6 +799,7 @@ def main():
     ap.add_argument("--no-small", action="store_true", help="skip the small-batch eager/graph leg")
     ap.add_argument("--no-cellwise", action="store_true",
                     help="skip the embedding-lookup and encode-variant leg")
+    ap.add_argument("--no-decode", action="store_true", help="skip the decode leg")
     ap.add_argument("--no-per-vocab", action="store_true", help="skip the four single-vocabulary launches")
     ap.add_argument("--tuning", type=str, default=None,
                     help="TILE,BLOCKS: fixed tiling of the one-pass encode instead of the autotuner's")
@@ -789,6 +837,9 @@ def main():
     cellwise = None
     if not args.no_cellwise:
         cellwise = cellwise_leg(enc["data"], enc["offs"])
+    decode = None
+    if not args.no_decode:
+        decode = decode_leg(enc["data"], enc["offs"])
     serve = None
     if not args.no_serve:
         serve = serve_leg(args.serve_requests)
@@ -830,6 +881,7 @@ def main():
         "serve": serve,
         "small_batch": small,
         "embed_and_variants": cellwise,
+        "decode": decode,
     }
     print(json.dumps(line), flush=True)
 

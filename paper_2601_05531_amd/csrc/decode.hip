@@ -2,9 +2,12 @@
 // future work, Discussion, "Decode Operations": the same LUT principle run
 // backwards). Not on the hot path.
 //
-// One launch, same structure as encode: tiles of TT token positions, each
-// tile's output bytes are contiguous, a one-pass look-back turns per-tile
-// byte counts into output positions.
+// Tiles of TT token positions, each tile's output bytes contiguous. Three
+// launches: per-tile byte totals, their scan (one workgroup), and the write,
+// where each tile stages its bytes in LDS and writes them with 16-byte
+// stores. No tile waits on another and no ticket counter is involved (one
+// device-wide counter serializes at about 12 ns per ticket, which at
+// tens of thousands of tiles outweighs the decode itself).
 #include "common.hpp"
 #include "device.hpp"
 
@@ -15,6 +18,7 @@ namespace {
 constexpr int NT = 256;
 constexpr int TPT = 8;  // tokens per thread
 constexpr int TT = NT * TPT;
+constexpr int kStage = 32768;  // bytes of one tile's output staged in LDS
 
 struct DecodeArgs {
     const int32_t *ids;
@@ -31,7 +35,8 @@ struct DecodeArgs {
     const int64_t *tok_off;
     const uint8_t *tok_chars;
     int64_t ntiles;
-    dev::TileQueue q;
+    int64_t *tile_pre;   // per-tile output bytes, then their exclusive scan (ntiles + 1)
+    uint32_t *err_hdr;
 };
 
 __device__ __forceinline__ bool is_silent(int32_t id) {
@@ -72,46 +77,110 @@ __device__ __forceinline__ void write_token(const DecodeArgs &a, int32_t id, int
     else err |= DNATOK_DERR_CAPACITY;
 }
 
-__global__ __launch_bounds__(NT) void k_decode(DecodeArgs a) {
-    __shared__ int64_t s_pre[TT + 1];
+// The bytes of one id written to LDS at p (no bounds: the tile's staged
+// output fits the stage).
+__device__ __forceinline__ void stage_token(const DecodeArgs &a, int32_t id, uint8_t *p) {
+    if (is_silent(id)) return;
+    if (a.kind == DNATOK_KMER) {
+        const bool known = id >= 5 && id < a.vocab;
+        uint32_t v = known ? (uint32_t)(id - 5) : 0u;
+        for (int j = a.k - 1; j >= 0; --j) {
+            p[j] = known ? (uint8_t)"ACGT"[v & 3] : (uint8_t)'N';
+            v >>= 2;
+        }
+        return;
+    }
+    if (a.kind == DNATOK_BPE && id >= 10 && id < a.vocab) {
+        const int64_t L = a.tok_len[id], o = a.tok_off[id];
+        for (int64_t j = 0; j < L; ++j) p[j] = a.tok_chars[o + j];
+        return;
+    }
+    p[0] = (id >= 5 && id <= 8) ? (uint8_t)"ACGT"[id - 5] : (uint8_t)'N';
+}
+
+// The ids of tile t this thread holds (TPT consecutive positions; ids
+// outside the rows read as PAD, which decodes to nothing).
+__device__ __forceinline__ int64_t load_tile_ids(const DecodeArgs &a, int64_t t, int64_t first, int64_t last,
+                                                 int32_t (&idv)[TPT]) {
+    int64_t mine = 0;
+#pragma unroll
+    for (int j = 0; j < TPT; ++j) {
+        const int64_t p = t * TT + (int64_t)threadIdx.x * TPT + j;
+        const bool live = p >= first && p < last && p < a.n_ids && p >= 0;
+        idv[j] = live ? a.ids[p] : DNATOK_ID_PAD;
+        mine += width_of(a, idv[j]);
+    }
+    return mine;
+}
+
+// 1. Output bytes of every tile (and the offsets check).
+__global__ __launch_bounds__(NT) void k_decode_count(DecodeArgs a) {
     __shared__ int64_t s_tmp[NT / dev::kWave + 1];
-    __shared__ int64_t s_ticket, s_ia, s_ib, s_excl;
-    __shared__ uint32_t s_err;
-    const int tid = threadIdx.x;
-    const uint32_t parity = dev::ld_relaxed32(a.q.hdr + 2);
-    uint64_t *st = parity ? a.q.status1 : a.q.status0;
-    uint64_t *st_other = parity ? a.q.status0 : a.q.status1;
     const int64_t first = (a.n > 0) ? a.offs[0] : 0;
     const int64_t last = (a.n > 0) ? a.offs[a.n] : 0;
-
-    for (;;) {
-        if (tid == 0) {
-            s_ticket = (int64_t)atomicAdd(a.q.hdr + 0, 1u);
-            s_err = 0;
-        }
-        __syncthreads();
-        const int64_t t = s_ticket;
-        if (t >= a.ntiles) break;
-        uint32_t err = 0;
-        for (int64_t j = t + (int64_t)tid * a.ntiles; j < a.q.clear_n; j += (int64_t)NT * a.ntiles) st_other[j] = 0;
-        for (int64_t i = t + (int64_t)tid * a.ntiles; i < a.n; i += (int64_t)NT * a.ntiles) {
-            int64_t o0 = a.offs[i], o1 = a.offs[i + 1];
+    uint32_t err = 0;
+    for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        for (int64_t i = t + (int64_t)threadIdx.x * a.ntiles; i < a.n; i += (int64_t)NT * a.ntiles) {
+            const int64_t o0 = a.offs[i], o1 = a.offs[i + 1];
             if (o0 < 0 || o1 < o0 || o1 > a.n_ids) err |= DNATOK_DERR_OFFSETS;
         }
-        const int64_t P0 = t * TT;
-        const int64_t P1 = P0 + TT;
-
         int32_t idv[TPT];
+        const int64_t sum = dev::block_sum<NT>(load_tile_ids(a, t, first, last, idv), s_tmp);
+        if (threadIdx.x == 0) a.tile_pre[t] = sum;
+    }
+    if (err) dev::raise_error(a.err_hdr, err);
+}
+
+// 2. Exclusive scan of the tile totals in place (one workgroup); the total
+// goes to tile_pre[ntiles] and out_offs[n].
+__global__ __launch_bounds__(NT) void k_decode_scan(DecodeArgs a) {
+    __shared__ int64_t s_tmp[NT / dev::kWave + 1];
+    constexpr int PER = 16;
+    int64_t run = 0;
+    for (int64_t c0 = 0; c0 < a.ntiles; c0 += (int64_t)NT * PER) {
+        const int64_t i0 = c0 + (int64_t)threadIdx.x * PER;
+        int64_t v[PER];
         int64_t mine = 0;
 #pragma unroll
-        for (int j = 0; j < TPT; ++j) {
-            const int64_t p = P0 + (int64_t)tid * TPT + j;
-            const bool live = p >= first && p < last && p < a.n_ids && p >= 0;
-            idv[j] = live ? a.ids[p] : DNATOK_ID_PAD;
-            mine += width_of(a, idv[j]);
+        for (int j = 0; j < PER; ++j) {
+            v[j] = (i0 + j < a.ntiles) ? a.tile_pre[i0 + j] : 0;
+            mine += v[j];
         }
+        int64_t tot;
+        int64_t pre = run + dev::block_excl_scan<NT>(mine, s_tmp, &tot);
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            if (i0 + j < a.ntiles) a.tile_pre[i0 + j] = pre;
+            pre += v[j];
+        }
+        run += tot;
+    }
+    if (threadIdx.x == 0) {
+        a.tile_pre[a.ntiles] = run;
+        a.out_offs[a.n] = run;
+    }
+}
+
+// 3. Each tile's bytes, staged in LDS at their 16-byte phase in the output
+// and written with 16-byte stores (partial first and last units byte by
+// byte); a tile whose output exceeds the stage, or that would cross the
+// capacity, writes its tokens directly. Rows starting in the tile get their
+// output offsets.
+__global__ __launch_bounds__(NT) void k_decode_write(DecodeArgs a) {
+    __shared__ __align__(16) uint8_t s_out[kStage + 16];
+    __shared__ int64_t s_pre[TT + 1];
+    __shared__ int64_t s_tmp[NT / dev::kWave + 1];
+    __shared__ int64_t s_ia, s_ib;
+    const int tid = threadIdx.x;
+    const int64_t first = (a.n > 0) ? a.offs[0] : 0;
+    const int64_t last = (a.n > 0) ? a.offs[a.n] : 0;
+    uint32_t err = 0;
+    for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        const int64_t P0 = t * TT, P1 = P0 + TT;
+        int32_t idv[TPT];
+        const int64_t mine = load_tile_ids(a, t, first, last, idv);
         int64_t agg;
-        int64_t pre = dev::block_excl_scan<NT>(mine, s_tmp, &agg);
+        const int64_t pre = dev::block_excl_scan<NT>(mine, s_tmp, &agg);
         {
             int64_t run = pre;
 #pragma unroll
@@ -121,46 +190,64 @@ __global__ __launch_bounds__(NT) void k_decode(DecodeArgs a) {
             }
             if (tid == NT - 1) s_pre[TT] = run;
         }
-        if (tid == 0) {
-            s_excl = dev::lookback(st, t, agg);
-            int64_t lo = 0, hi = a.n;  // first row with offs[i] >= P0
-            while (lo < hi) {
-                int64_t mid = (lo + hi) >> 1;
-                if (a.offs[mid] >= P0) hi = mid;
-                else lo = mid + 1;
-            }
-            s_ia = lo;
-            hi = a.n;
-            if (t == a.ntiles - 1) {
-                lo = a.n;
-            } else {
-                while (lo < hi) {
-                    int64_t mid = (lo + hi) >> 1;
-                    if (a.offs[mid] >= P1) hi = mid;
-                    else lo = mid + 1;
+        {
+            // rows starting in the tile: [first row with offs >= P0, first
+            // row with offs >= P1), one 64-way search per wave (the last
+            // tile takes every remaining row)
+            const int w = tid / dev::kWave;
+            if (w < 2) {
+                int64_t r = a.n;
+                if (w == 0 || t != a.ntiles - 1) {
+                    const int64_t key = w == 0 ? P0 : P1;
+                    r = dev::wave_lower_bound(0, a.n, [&](int64_t q) { return a.offs[q] >= key; });
+                }
+                if ((tid & (dev::kWave - 1)) == 0) {
+                    if (w == 0) s_ia = r;
+                    else s_ib = r;
                 }
             }
-            s_ib = lo;
+        }
+        const int64_t base = a.tile_pre[t];
+        const int64_t ph = (int64_t)((reinterpret_cast<uintptr_t>(a.out) + (uintptr_t)base) & 15);
+        const bool staged = agg <= kStage && base + agg <= a.cap;
+        if (staged) {
+            int64_t pos = pre;
+#pragma unroll
+            for (int j = 0; j < TPT; ++j) {
+                stage_token(a, idv[j], s_out + ph + pos);
+                pos += width_of(a, idv[j]);
+            }
+        } else {
+            int64_t pos = base + pre;
+#pragma unroll
+            for (int j = 0; j < TPT; ++j) {
+                write_token(a, idv[j], pos, err);
+                pos += width_of(a, idv[j]);
+            }
         }
         __syncthreads();
-        const int64_t base = s_excl;
-        int64_t pos = base + pre;
-#pragma unroll
-        for (int j = 0; j < TPT; ++j) {
-            write_token(a, idv[j], pos, err);
-            pos += width_of(a, idv[j]);
+        if (staged && agg > 0) {
+            // s_out[ph + i] is output byte base + i; unit u covers stage bytes
+            // [16u, 16u + 16), i.e. output base - ph + 16u, 16-byte aligned
+            uint8_t *ob = a.out + base - ph;
+            const int64_t nu = (ph + agg + 15) / 16;
+            for (int64_t u = tid; u < nu; u += NT) {
+                const int64_t lo = 16 * u, hi = lo + 16;
+                if (lo >= ph && hi <= ph + agg) {
+                    *reinterpret_cast<uint4 *>(ob + lo) = *reinterpret_cast<const uint4 *>(s_out + lo);
+                } else {
+                    for (int64_t b = (lo > ph ? lo : ph); b < hi && b < ph + agg; ++b) ob[b] = s_out[b];
+                }
+            }
         }
         for (int64_t i = s_ia + tid; i < s_ib; i += NT) {
             int64_t rel = a.offs[i] - P0;
             rel = rel < 0 ? 0 : (rel > TT ? TT : rel);
             a.out_offs[i] = base + s_pre[rel];
         }
-        if (t == a.ntiles - 1 && tid == 0) a.out_offs[a.n] = base + agg;
-        if (err) atomicOr(&s_err, err);
         __syncthreads();
-        if (tid == 0 && s_err) dev::raise_error(a.q.hdr, s_err);
     }
-    if (tid == 0) dev::finish_block(a.q.hdr);
+    if (err) dev::raise_error(a.err_hdr, err);
 }
 
 }  // namespace
@@ -183,19 +270,22 @@ int launch_decode(const dnatok_vocab *v, const int32_t *d_ids, int64_t n_ids, co
     a.tok_chars = v->bpe.d_tok_chars;
     a.ntiles = n_ids / TT + 1;
     Workspace *ws = nullptr;
-    int rc = get_workspace(stream, a.ntiles, &ws);
+    int rc = get_workspace(stream, 1, &ws);
     if (rc) return rc;
-    a.q.hdr = ws->d_hdr;
-    a.q.status0 = ws->d_status;
-    a.q.status1 = ws->d_status + ws->cap;
-    if (a.ntiles > ws->high_water) ws->high_water = a.ntiles;
-    a.q.clear_n = ws->high_water;
+    rc = ensure_scratch(ws, 8 * (a.ntiles + 1));
+    if (rc) return rc;
+    a.tile_pre = reinterpret_cast<int64_t *>(ws->d_scratch);
+    a.err_hdr = ws->d_hdr;
     int per_cu = 0;
-    DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_decode, NT, 0));
+    DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_decode_write, NT, 0));
     if (per_cu < 1) per_cu = 1;
-    int64_t grid = (int64_t)device_cu_count() * per_cu;
+    int64_t grid = 4 * (int64_t)device_cu_count() * per_cu;
     if (grid > a.ntiles) grid = a.ntiles;
-    hipLaunchKernelGGL(k_decode, dim3((unsigned)grid), dim3(NT), 0, stream, a);
+    hipLaunchKernelGGL(k_decode_count, dim3((unsigned)grid), dim3(NT), 0, stream, a);
+    DNATOK_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_decode_scan, dim3(1), dim3(NT), 0, stream, a);
+    DNATOK_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_decode_write, dim3((unsigned)grid), dim3(NT), 0, stream, a);
     DNATOK_HIP(hipGetLastError());
     return DNATOK_OK;
 }
