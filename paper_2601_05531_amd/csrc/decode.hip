@@ -36,6 +36,7 @@ struct DecodeArgs {
     const uint8_t *tok_chars;
     int64_t ntiles;
     int64_t *tile_pre;   // per-tile output bytes, then their exclusive scan (ntiles + 1)
+    int64_t *first_row;  // first row starting at or after each tile's first position (ntiles + 1)
     uint32_t *err_hdr;
 };
 
@@ -113,20 +114,46 @@ __device__ __forceinline__ int64_t load_tile_ids(const DecodeArgs &a, int64_t t,
     return mine;
 }
 
-// 1. Output bytes of every tile (and the offsets check).
+// 1. Output bytes of every tile, CT tiles per pass so each thread has
+// CT * TPT ids in flight; the first row of every tile; the offsets check.
+// Row i is the first row at or after position t * TT exactly for the tiles t
+// with floor(off[i-1] / TT) < t <= floor(off[i] / TT) (row n stands for the
+// end: every tile past the last row start). Bad offsets only raise the flag;
+// the tile range is clamped, and the write pass clamps what it reads.
 __global__ __launch_bounds__(NT) void k_decode_count(DecodeArgs a) {
-    __shared__ int64_t s_tmp[NT / dev::kWave + 1];
+    constexpr int CT = 4;
+    __shared__ int64_t s_part[NT / dev::kWave][CT];
     const int64_t first = (a.n > 0) ? a.offs[0] : 0;
     const int64_t last = (a.n > 0) ? a.offs[a.n] : 0;
+    const int w = threadIdx.x / dev::kWave, lane = threadIdx.x & (dev::kWave - 1);
     uint32_t err = 0;
-    for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-        for (int64_t i = t + (int64_t)threadIdx.x * a.ntiles; i < a.n; i += (int64_t)NT * a.ntiles) {
-            const int64_t o0 = a.offs[i], o1 = a.offs[i + 1];
-            if (o0 < 0 || o1 < o0 || o1 > a.n_ids) err |= DNATOK_DERR_OFFSETS;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i <= a.n; i += (int64_t)gridDim.x * NT) {
+        const int64_t prev = (i == 0) ? -1 : a.offs[i - 1];
+        const int64_t cur = (i == a.n) ? -1 : a.offs[i];
+        if (i < a.n && (cur < 0 || (i + 1 <= a.n && a.offs[i + 1] < cur) || a.offs[i + 1] > a.n_ids))
+            err |= DNATOK_DERR_OFFSETS;
+        int64_t lo = (i == 0) ? 0 : (prev < 0 ? 0 : prev / TT + 1);
+        int64_t hi = (i == a.n) ? a.ntiles : (cur < 0 ? -1 : cur / TT);
+        if (hi > a.ntiles) hi = a.ntiles;
+        for (int64_t t = lo; t <= hi; ++t) a.first_row[t] = i;
+    }
+    for (int64_t t0 = (int64_t)blockIdx.x * CT; t0 < a.ntiles; t0 += (int64_t)gridDim.x * CT) {
+        int32_t idv[CT][TPT];
+        int64_t part[CT];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) part[c] = load_tile_ids(a, t0 + c, first, last, idv[c]);
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            const int64_t v = dev::wave_sum(part[c]);
+            if (lane == 0) s_part[w][c] = v;
         }
-        int32_t idv[TPT];
-        const int64_t sum = dev::block_sum<NT>(load_tile_ids(a, t, first, last, idv), s_tmp);
-        if (threadIdx.x == 0) a.tile_pre[t] = sum;
+        __syncthreads();
+        if (threadIdx.x < CT && t0 + threadIdx.x < a.ntiles) {
+            int64_t sum = 0;
+            for (int q = 0; q < NT / dev::kWave; ++q) sum += s_part[q][threadIdx.x];
+            a.tile_pre[t0 + threadIdx.x] = sum;
+        }
+        __syncthreads();
     }
     if (err) dev::raise_error(a.err_hdr, err);
 }
@@ -190,22 +217,14 @@ __global__ __launch_bounds__(NT) void k_decode_write(DecodeArgs a) {
             }
             if (tid == NT - 1) s_pre[TT] = run;
         }
-        {
-            // rows starting in the tile: [first row with offs >= P0, first
-            // row with offs >= P1), one 64-way search per wave (the last
-            // tile takes every remaining row)
-            const int w = tid / dev::kWave;
-            if (w < 2) {
-                int64_t r = a.n;
-                if (w == 0 || t != a.ntiles - 1) {
-                    const int64_t key = w == 0 ? P0 : P1;
-                    r = dev::wave_lower_bound(0, a.n, [&](int64_t q) { return a.offs[q] >= key; });
-                }
-                if ((tid & (dev::kWave - 1)) == 0) {
-                    if (w == 0) s_ia = r;
-                    else s_ib = r;
-                }
-            }
+        if (tid == 0) {
+            // rows starting in the tile (clamped: bad offsets leave the
+            // table unchecked, and they raise the flag in the count pass)
+            int64_t ia = a.first_row[t], ib = (t == a.ntiles - 1) ? a.n : a.first_row[t + 1];
+            ia = ia < 0 ? 0 : (ia > a.n ? a.n : ia);
+            ib = ib < ia ? ia : (ib > a.n ? a.n : ib);
+            s_ia = ia;
+            s_ib = ib;
         }
         const int64_t base = a.tile_pre[t];
         const int64_t ph = (int64_t)((reinterpret_cast<uintptr_t>(a.out) + (uintptr_t)base) & 15);
@@ -272,9 +291,10 @@ int launch_decode(const dnatok_vocab *v, const int32_t *d_ids, int64_t n_ids, co
     Workspace *ws = nullptr;
     int rc = get_workspace(stream, 1, &ws);
     if (rc) return rc;
-    rc = ensure_scratch(ws, 8 * (a.ntiles + 1));
+    rc = ensure_scratch(ws, 16 * (a.ntiles + 1));
     if (rc) return rc;
     a.tile_pre = reinterpret_cast<int64_t *>(ws->d_scratch);
+    a.first_row = a.tile_pre + (a.ntiles + 1);
     a.err_hdr = ws->d_hdr;
     int per_cu = 0;
     DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_decode_write, NT, 0));
