@@ -18,7 +18,7 @@ namespace {
 constexpr int NT = 256;
 constexpr int TPT = 8;  // tokens per thread
 constexpr int TT = NT * TPT;
-constexpr int kStage = 32768;  // bytes of one tile's output staged in LDS
+constexpr int kStage = 16384;  // bytes of one tile's output staged in LDS (2,048 k-mers of k <= 8)
 
 struct DecodeArgs {
     const int32_t *ids;
@@ -78,6 +78,11 @@ __device__ __forceinline__ void write_token(const DecodeArgs &a, int32_t id, int
     else err |= DNATOK_DERR_CAPACITY;
 }
 
+// Slot of tile position q (thread q / TPT, its j = q % TPT) in the prefix
+// table: j * NT + thread, so the TPT writes of a wave each hit consecutive
+// slots (thread-major order would put every lane of a write on two banks).
+__device__ __forceinline__ int32_t pre_slot(int32_t q) { return (q % TPT) * NT + q / TPT; }
+
 // The bytes of one id written to LDS at p (no bounds: the tile's staged
 // output fits the stage).
 __device__ __forceinline__ void stage_token(const DecodeArgs &a, int32_t id, uint8_t *p) {
@@ -100,17 +105,46 @@ __device__ __forceinline__ void stage_token(const DecodeArgs &a, int32_t id, uin
 }
 
 // The ids of tile t this thread holds (TPT consecutive positions; ids
-// outside the rows read as PAD, which decodes to nothing).
+// outside the rows read as PAD, which decodes to nothing). Every load is
+// unconditional, so a thread's loads go out together: a tile inside the rows
+// reads its TPT ids as 16-byte vectors, other tiles read clamped positions
+// and select.
 __device__ __forceinline__ int64_t load_tile_ids(const DecodeArgs &a, int64_t t, int64_t first, int64_t last,
                                                  int32_t (&idv)[TPT]) {
+    const int64_t p0 = t * TT + (int64_t)threadIdx.x * TPT;
+    const bool inside = t * TT >= first && (t + 1) * TT <= last && (t + 1) * TT <= a.n_ids &&
+                        (reinterpret_cast<uintptr_t>(a.ids) & 15) == 0;  // uniform over the block
+    if (inside) {
+        const int4 *q = reinterpret_cast<const int4 *>(a.ids + p0);
+#pragma unroll
+        for (int j = 0; j < TPT; j += 4) {
+            const int4 v = q[j / 4];
+            idv[j] = v.x;
+            idv[j + 1] = v.y;
+            idv[j + 2] = v.z;
+            idv[j + 3] = v.w;
+        }
+    } else if (a.n_ids > 0) {
+        int32_t v[TPT];
+#pragma unroll
+        for (int j = 0; j < TPT; ++j) {
+            const int64_t p = p0 + j;
+            const bool live = p >= first && p < last && p < a.n_ids && p >= 0;
+            v[j] = a.ids[live ? p : 0];
+        }
+#pragma unroll
+        for (int j = 0; j < TPT; ++j) {
+            const int64_t p = p0 + j;
+            const bool live = p >= first && p < last && p < a.n_ids && p >= 0;
+            idv[j] = live ? v[j] : DNATOK_ID_PAD;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < TPT; ++j) idv[j] = DNATOK_ID_PAD;
+    }
     int64_t mine = 0;
 #pragma unroll
-    for (int j = 0; j < TPT; ++j) {
-        const int64_t p = t * TT + (int64_t)threadIdx.x * TPT + j;
-        const bool live = p >= first && p < last && p < a.n_ids && p >= 0;
-        idv[j] = live ? a.ids[p] : DNATOK_ID_PAD;
-        mine += width_of(a, idv[j]);
-    }
+    for (int j = 0; j < TPT; ++j) mine += width_of(a, idv[j]);
     return mine;
 }
 
@@ -140,8 +174,32 @@ __global__ __launch_bounds__(NT) void k_decode_count(DecodeArgs a) {
     for (int64_t t0 = (int64_t)blockIdx.x * CT; t0 < a.ntiles; t0 += (int64_t)gridDim.x * CT) {
         int32_t idv[CT][TPT];
         int64_t part[CT];
+        const bool inside = t0 * TT >= first && (t0 + CT) * TT <= last && (t0 + CT) * TT <= a.n_ids &&
+                            (reinterpret_cast<uintptr_t>(a.ids) & 15) == 0;  // uniform over the block
+        if (inside) {
+            // all CT tiles inside the rows: every load of the pass goes out at once
 #pragma unroll
-        for (int c = 0; c < CT; ++c) part[c] = load_tile_ids(a, t0 + c, first, last, idv[c]);
+            for (int c = 0; c < CT; ++c) {
+                const int4 *q = reinterpret_cast<const int4 *>(a.ids + (t0 + c) * TT + (int64_t)threadIdx.x * TPT);
+#pragma unroll
+                for (int j = 0; j < TPT; j += 4) {
+                    const int4 v = q[j / 4];
+                    idv[c][j] = v.x;
+                    idv[c][j + 1] = v.y;
+                    idv[c][j + 2] = v.z;
+                    idv[c][j + 3] = v.w;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                part[c] = 0;
+#pragma unroll
+                for (int j = 0; j < TPT; ++j) part[c] += width_of(a, idv[c][j]);
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < CT; ++c) part[c] = load_tile_ids(a, t0 + c, first, last, idv[c]);
+        }
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
             const int64_t v = dev::wave_sum(part[c]);
@@ -195,7 +253,7 @@ __global__ __launch_bounds__(NT) void k_decode_scan(DecodeArgs a) {
 // output offsets.
 __global__ __launch_bounds__(NT) void k_decode_write(DecodeArgs a) {
     __shared__ __align__(16) uint8_t s_out[kStage + 16];
-    __shared__ int64_t s_pre[TT + 1];
+    __shared__ int32_t s_pre[TT + 1];  // bytes before each tile position (in-tile, so 32-bit), position-major
     __shared__ int64_t s_tmp[NT / dev::kWave + 1];
     __shared__ int64_t s_ia, s_ib;
     const int tid = threadIdx.x;
@@ -212,10 +270,10 @@ __global__ __launch_bounds__(NT) void k_decode_write(DecodeArgs a) {
             int64_t run = pre;
 #pragma unroll
             for (int j = 0; j < TPT; ++j) {
-                s_pre[tid * TPT + j] = run;
+                s_pre[pre_slot(tid * TPT + j)] = (int32_t)run;  // lanes write consecutive slots: no bank conflicts
                 run += width_of(a, idv[j]);
             }
-            if (tid == NT - 1) s_pre[TT] = run;
+            if (tid == NT - 1) s_pre[TT] = (int32_t)run;
         }
         if (tid == 0) {
             // rows starting in the tile (clamped: bad offsets leave the
@@ -262,7 +320,7 @@ __global__ __launch_bounds__(NT) void k_decode_write(DecodeArgs a) {
         for (int64_t i = s_ia + tid; i < s_ib; i += NT) {
             int64_t rel = a.offs[i] - P0;
             rel = rel < 0 ? 0 : (rel > TT ? TT : rel);
-            a.out_offs[i] = base + s_pre[rel];
+            a.out_offs[i] = base + s_pre[rel == TT ? TT : pre_slot((int32_t)rel)];
         }
         __syncthreads();
     }
