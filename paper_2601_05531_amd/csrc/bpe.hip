@@ -929,7 +929,10 @@ __global__ __launch_bounds__(NTE) void k_scan_counts(ScanArgs a) {
         int64_t mine = 0;
 #pragma unroll
         for (int j = 0; j < kScanPerThread; ++j) {
-            v[j] = (i0 + j < total) ? a.cnt[i0 + j] : 0;
+            // unconditional load of a clamped entry (an empty batch, total
+            // 0, loads nothing), so the thread's loads go out together
+            const int64_t x = total > 0 ? a.cnt[i0 + j < total ? i0 + j : total - 1] : 0;
+            v[j] = (i0 + j < total) ? x : 0;
             mine += v[j];
         }
         int64_t utot;

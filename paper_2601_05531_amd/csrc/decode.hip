@@ -228,7 +228,10 @@ __global__ __launch_bounds__(NT) void k_decode_scan(DecodeArgs a) {
         int64_t mine = 0;
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
-            v[j] = (i0 + j < a.ntiles) ? a.tile_pre[i0 + j] : 0;
+            // unconditional load of a clamped entry (ntiles >= 1), so the
+            // thread's loads go out together
+            const int64_t x = a.tile_pre[i0 + j < a.ntiles ? i0 + j : a.ntiles - 1];
+            v[j] = (i0 + j < a.ntiles) ? x : 0;
             mine += v[j];
         }
         int64_t tot;
