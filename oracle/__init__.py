@@ -91,6 +91,67 @@ def encode(kind: int, data, offsets, k: int = 1, lut=None, merges=None, add_cls_
     return ids[:total].copy(), out_off
 
 
+def split_rows(offsets, parts: int):
+    """Cut rows [0, n) into at most ``parts`` contiguous ranges of about equal
+    bytes (a static partition of the sequences by bytes). Returns the range
+    bounds as a list of row indices [r0 = 0, r1, ..., n]."""
+    offsets = np.asarray(offsets, dtype=np.int64)
+    n = len(offsets) - 1
+    if n <= 0 or parts <= 1:
+        return [0, max(n, 0)]
+    span = int(offsets[-1] - offsets[0])
+    cuts = [0]
+    for p in range(1, parts):
+        r = int(np.searchsorted(offsets, offsets[0] + span * p // parts, side="left"))
+        r = min(max(r, cuts[-1]), n)
+        if r > cuts[-1]:
+            cuts.append(r)
+    if cuts[-1] != n:
+        cuts.append(n)
+    return cuts
+
+
+def encode_threads(kind: int, data, offsets, threads: int | None = None, **kw):
+    """``encode`` with rows split into contiguous ranges of about equal bytes,
+    one range per thread (the C oracle runs unchanged in each; ctypes releases
+    the interpreter lock during the call). Same result as ``encode``."""
+    from concurrent.futures import ThreadPoolExecutor
+    data = _c(data, np.uint8)
+    offsets = _c(offsets, np.int64)
+    threads = threads or os.cpu_count() or 1
+    cuts = split_rows(offsets, threads)
+    if len(cuts) <= 2:
+        return encode(kind, data, offsets, **kw)
+    with ThreadPoolExecutor(max_workers=len(cuts) - 1) as ex:
+        parts = list(ex.map(lambda j: encode(kind, data, offsets[cuts[j]:cuts[j + 1] + 1], **kw),
+                            range(len(cuts) - 1)))
+    ids = np.concatenate([p[0] for p in parts])
+    out_off = np.empty(len(offsets), dtype=np.int64)
+    base = 0
+    for j, (pi, po) in enumerate(parts):
+        out_off[cuts[j]:cuts[j + 1] + 1] = po + base
+        base += int(po[-1])
+    return ids, out_off
+
+
+def pad_threads(ids, out_offsets, width: int, side: int = RIGHT, pad_id: int = PAD, threads: int | None = None):
+    """``pad`` with rows split into contiguous ranges, one per thread."""
+    from concurrent.futures import ThreadPoolExecutor
+    out_offsets = _c(out_offsets, np.int64)
+    threads = threads or os.cpu_count() or 1
+    cuts = split_rows(out_offsets, threads)
+    if len(cuts) <= 2:
+        return pad(ids, out_offsets, width, side, pad_id)
+
+    def one(j):
+        o = out_offsets[cuts[j]:cuts[j + 1] + 1]
+        return pad(ids[o[0]:o[-1]], o - o[0], width, side, pad_id)
+
+    with ThreadPoolExecutor(max_workers=len(cuts) - 1) as ex:
+        parts = list(ex.map(one, range(len(cuts) - 1)))
+    return np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts])
+
+
 def revcomp(data, offsets):
     """Reverse complement of every row (A<->T, C<->G, case kept, other bytes
     unchanged; rows stay at their offsets). Returns uint8[len(data)]."""

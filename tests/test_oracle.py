@@ -14,6 +14,7 @@ import pytest
 
 import oracle
 from oracle import brute
+import synth
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -463,3 +464,25 @@ def test_embed_identity_table_recovers_ids_and_rejects_range():
         oracle.embed(table, np.array([10]))
     with pytest.raises(ValueError):
         oracle.embed(table, np.array([-1]))
+
+
+def test_threaded_oracle_equals_single_thread():
+    """encode_threads / pad_threads split rows by bytes over threads; their
+    result must be exactly the single call's (empty rows and batches too)."""
+    data, offs = synth.workload_markov_batch(300, 1000)
+    offs = offs.copy()
+    offs[5:9] = offs[5]  # a run of empty rows
+    for threads in (1, 2, 7, 64):
+        for kind, k in ((oracle.SINGLE, 1), (oracle.KMER, 5)):
+            a = oracle.encode(kind, data, offs, k=k, add_cls_sep=True)
+            b = oracle.encode_threads(kind, data, offs, threads=threads, k=k, add_cls_sep=True)
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+            W = int(np.diff(a[1]).max()) + 3
+            for side in (oracle.RIGHT, oracle.LEFT):
+                p = oracle.pad(a[0], a[1], W, side)
+                q = oracle.pad_threads(a[0], a[1], W, side, threads=threads)
+                assert np.array_equal(p[0], q[0]) and np.array_equal(p[1], q[1])
+    cuts = oracle.split_rows(offs, 7)
+    assert cuts[0] == 0 and cuts[-1] == len(offs) - 1 and all(x < y for x, y in zip(cuts, cuts[1:]))
+    e = oracle.encode_threads(oracle.SINGLE, data[:0], np.zeros(1, np.int64), threads=4)
+    assert e[0].size == 0 and np.array_equal(e[1], [0])
