@@ -442,7 +442,7 @@ typedef struct dnatok_server_opts {
     int64_t budget_bytes;     /* device bytes for requests: inputs, outputs, offsets and BPE scratch */
     int32_t n_streams;        /* batches in flight at once, 1..16 */
     int32_t max_batch;        /* most requests in one batch, >= 1 */
-    int64_t max_batch_bytes;  /* most input bytes in one batch (a larger single request runs alone) */
+    int64_t max_batch_bytes;  /* most input bytes in one batch, and in one request (a larger request: EBUDGET) */
     int64_t staging_bytes;    /* pinned host staging per stream for pageable inputs, >= max_batch_bytes */
 } dnatok_server_opts;
 
@@ -464,7 +464,9 @@ int dnatok_server_create(const dnatok_server_opts *opts, dnatok_server **out);
  * copied before the call returns when pageable; pinned memory is read by the
  * device later and must stay unchanged until the request is done. The
  * vocabulary must outlive the request. Errors: EINVAL, EBUDGET (the request
- * alone exceeds the budget), ESTATE (server shutting down).
+ * is longer than max_batch_bytes, whose size the per-stream scratch is
+ * reserved for, or its input and output alone exceed the arena), ESTATE
+ * (server shutting down). A rejected request leaves nothing queued.
  */
 int dnatok_server_submit(dnatok_server *s, const dnatok_vocab *v, const uint8_t *h_bytes, int64_t nbytes,
                          int32_t add_cls_sep, uint64_t *ticket);

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <memory>
 #include <cstdarg>
+#include <cstdlib>
 #include <map>
 #include <unordered_set>
 
@@ -29,6 +30,45 @@ int set_error(int code, const char *fmt, ...) {
 }
 
 void clear_error() { g_err = "no error"; }
+
+namespace {
+std::mutex g_fail_mu;
+std::string g_fail_value;
+int64_t g_fail_count = 0;
+
+// Whether the allocation being made is the one DNATOK_TEST_FAIL_ALLOC names.
+bool injected_alloc_failure() {
+    const char *e = std::getenv("DNATOK_TEST_FAIL_ALLOC");
+    std::lock_guard<std::mutex> lk(g_fail_mu);
+    if (!e || !*e) {
+        g_fail_value.clear();
+        g_fail_count = 0;
+        return false;
+    }
+    if (g_fail_value != e) {
+        g_fail_value = e;
+        g_fail_count = 0;
+    }
+    const long long n = std::atoll(e);
+    return n >= 1 && ++g_fail_count == n;
+}
+}  // namespace
+
+hipError_t dev_alloc(void **p, size_t bytes) {
+    if (injected_alloc_failure()) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+}
+
+hipError_t host_alloc(void **p, size_t bytes) {
+    if (injected_alloc_failure()) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipHostMalloc(p, bytes, hipHostMallocDefault);
+}
 
 int device_cu_count() {
     int dev = 0;
@@ -99,7 +139,7 @@ int get_workspace(hipStream_t stream, int64_t tiles, Workspace **out) {
         }
         size_t bytes = 256 + (size_t)cap * 2 * sizeof(uint64_t);
         void *p = nullptr;
-        DNATOK_HIP(hipMalloc(&p, bytes));
+        DNATOK_HIP(dev_alloc(&p, bytes));
         // zero on the workspace's own stream and wait: a plain hipMemset runs on
         // the null stream, which does not order non-blocking streams
         DNATOK_HIP(hipMemsetAsync(p, 0, bytes, stream));
@@ -127,7 +167,7 @@ int ensure_scratch(Workspace *ws, int64_t bytes) {
     ws->d_scratch = nullptr;
     ws->scratch_bytes = 0;
     void *p = nullptr;
-    DNATOK_HIP(hipMalloc(&p, (size_t)nb));
+    DNATOK_HIP(dev_alloc(&p, (size_t)nb));
     ws->d_scratch = static_cast<uint8_t *>(p);
     ws->scratch_bytes = nb;
     return DNATOK_OK;
@@ -234,7 +274,7 @@ int dnatok_vocab_create(const dnatok_vocab_desc *d, dnatok_vocab **out) {
         v->vocab_size = 10 + d->n_merges;
     }
     void *p = nullptr;
-    DNATOK_HIP(hipMalloc(&p, 256 * sizeof(int32_t)));
+    DNATOK_HIP(dev_alloc(&p, 256 * sizeof(int32_t)));
     v->d_lut = static_cast<int32_t *>(p);
     DNATOK_HIP(hipMemcpy(v->d_lut, lut, sizeof(lut), hipMemcpyHostToDevice));
     if (d->kind == DNATOK_BPE) {

@@ -119,19 +119,19 @@ int build_bpe_tables(dnatok_vocab *v) {
     t.nbk = nbk;
 
     void *p = nullptr;
-    DNATOK_HIP(hipMalloc(&p, sizeof(uint32_t) * bucket.size()));
+    DNATOK_HIP(dev_alloc(&p, sizeof(uint32_t) * bucket.size()));
     t.d_bucket = static_cast<uint32_t *>(p);
     DNATOK_HIP(hipMemcpy(t.d_bucket, bucket.data(), sizeof(uint32_t) * bucket.size(), hipMemcpyHostToDevice));
-    DNATOK_HIP(hipMalloc(&p, sizeof(uint32_t) * pair.size()));
+    DNATOK_HIP(dev_alloc(&p, sizeof(uint32_t) * pair.size()));
     t.d_pair = static_cast<uint32_t *>(p);
     DNATOK_HIP(hipMemcpy(t.d_pair, pair.data(), sizeof(uint32_t) * pair.size(), hipMemcpyHostToDevice));
-    DNATOK_HIP(hipMalloc(&p, sizeof(int32_t) * (size_t)V));
+    DNATOK_HIP(dev_alloc(&p, sizeof(int32_t) * (size_t)V));
     t.d_tok_len = static_cast<int32_t *>(p);
     DNATOK_HIP(hipMemcpy(t.d_tok_len, len.data(), sizeof(int32_t) * (size_t)V, hipMemcpyHostToDevice));
-    DNATOK_HIP(hipMalloc(&p, sizeof(int64_t) * (size_t)V));
+    DNATOK_HIP(dev_alloc(&p, sizeof(int64_t) * (size_t)V));
     t.d_tok_off = static_cast<int64_t *>(p);
     DNATOK_HIP(hipMemcpy(t.d_tok_off, off.data(), sizeof(int64_t) * (size_t)V, hipMemcpyHostToDevice));
-    DNATOK_HIP(hipMalloc(&p, chars.size()));
+    DNATOK_HIP(dev_alloc(&p, chars.size()));
     t.d_tok_chars = static_cast<uint8_t *>(p);
     DNATOK_HIP(hipMemcpy(t.d_tok_chars, chars.data(), chars.size(), hipMemcpyHostToDevice));
     return DNATOK_OK;
@@ -939,7 +939,7 @@ __global__ __launch_bounds__(NTE) void k_scan_counts(ScanArgs a) {
         const int64_t pre = dev::block_excl_scan<NTE>(mine, s_tmp, &utot);
         if (tid < dev::kWave) {
             if (tid == 0) dev::publish_aggregate(st, u, utot);
-            const int64_t ex = dev::wave_lookback(st, u, utot);
+            const int64_t ex = dev::wave_lookback(st, u, utot, a.q.hdr);
             if (tid == 0) s_excl = ex;
         }
         __syncthreads();

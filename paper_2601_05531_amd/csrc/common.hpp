@@ -27,6 +27,16 @@ void clear_error();
                                        "%s failed: %s", #call, hipGetErrorString(_e));        \
     } while (0)
 
+// ---- allocation -----------------------------------------------------------------
+//
+// Every device and pinned host allocation of the library goes through these,
+// so a test can make one of them fail: with the environment variable
+// DNATOK_TEST_FAIL_ALLOC=n (n >= 1), the n-th allocation after the variable
+// took that value returns hipErrorOutOfMemory (later ones succeed; counting
+// restarts when the value changes; unset, nothing fails).
+hipError_t dev_alloc(void **p, size_t bytes);
+hipError_t host_alloc(void **p, size_t bytes);
+
 // ---- vocabulary ----------------------------------------------------------------
 
 // Pair -> rank lookup shared by the host (table build) and the device: a

@@ -6,6 +6,8 @@
 
 #include <cstdint>
 
+#include "../../include/dnatok.h"
+
 namespace dnatok {
 namespace dev {
 
@@ -175,6 +177,16 @@ __device__ __forceinline__ void publish_aggregate(uint64_t *status, int64_t tile
     st_relaxed(status + tile, (tile == 0 ? kFlagInc : kFlagAgg) | (uint64_t)agg);
 }
 
+// Most polls of a predecessor's status word before the look-back gives up.
+// Every predecessor is held by a block that is already running (tiles go
+// out in ticket order) and publishes within microseconds; a million polls
+// (each one a global load and a short sleep) is about a second, so reaching
+// the cap means the protocol was broken (e.g. two launches sharing one
+// workspace at once), never a slow peer.
+constexpr uint32_t kLookbackMaxPolls = 1u << 20;
+
+__device__ __forceinline__ void raise_error(uint32_t *hdr, uint32_t flag) { atomicOr(hdr + 3, flag); }
+
 // Exclusive prefix of all tiles before `tile`, computed by one full wave
 // (all 64 lanes call it): each round reads the 64 nearest unread
 // predecessors at once, sums back to the closest one that already knows its
@@ -183,10 +195,14 @@ __device__ __forceinline__ void publish_aggregate(uint64_t *status, int64_t tile
 // prefix of 0. Afterwards lane 0 publishes this tile's inclusive prefix.
 // Tiles are handed out in ticket order, so every predecessor is held by a
 // block that started earlier and never waits on a later tile: the wait ends.
-__device__ __forceinline__ int64_t wave_lookback(uint64_t *status, int64_t tile, int64_t agg) {
+// Should a predecessor stay unpublished for kLookbackMaxPolls polls, the
+// wave raises DNATOK_DERR_INTERNAL in hdr, counts what it has, and still
+// publishes, so no later tile waits on it and the launch drains.
+__device__ __forceinline__ int64_t wave_lookback(uint64_t *status, int64_t tile, int64_t agg, uint32_t *hdr) {
     const int lane = threadIdx.x & (kWave - 1);
     int64_t excl = 0;
     int64_t top = tile - 1;
+    uint32_t polls = 0;
     while (top >= 0) {
         const int64_t j = top - lane;
         uint64_t w = (j >= 0) ? ld_relaxed(status + j) : kFlagInc;
@@ -196,9 +212,13 @@ __device__ __forceinline__ int64_t wave_lookback(uint64_t *status, int64_t tile,
         const int first_inc = inc_mask ? __builtin_ctzll(inc_mask) : kWave;
         // lanes that must be known: 0 .. first_inc (all 64 if no inclusive one)
         const uint64_t need = (first_inc >= kWave - 1) ? ~0ull : ((2ull << first_inc) - 1);
-        if (zero_mask & need) {
+        if ((zero_mask & need) && ++polls < kLookbackMaxPolls) {
             __builtin_amdgcn_s_sleep(1);
             continue;
+        }
+        if (zero_mask & need) {
+            if (lane == 0) raise_error(hdr, DNATOK_DERR_INTERNAL);
+            break;
         }
         int64_t v = (lane <= first_inc) ? (int64_t)(w & kValMask) : 0;
         excl += wave_sum(v);
@@ -209,30 +229,6 @@ __device__ __forceinline__ int64_t wave_lookback(uint64_t *status, int64_t tile,
     return excl;
 }
 
-// Single-lane variant: publish the aggregate and walk back one tile at a time.
-__device__ __forceinline__ int64_t lookback(uint64_t *status, int64_t tile, int64_t agg) {
-    if (tile == 0) {
-        st_relaxed(status, kFlagInc | (uint64_t)agg);
-        return 0;
-    }
-    st_relaxed(status + tile, kFlagAgg | (uint64_t)agg);
-    int64_t excl = 0;
-    int64_t j = tile - 1;
-    for (;;) {
-        uint64_t w = ld_relaxed(status + j);
-        uint64_t f = w & ~kValMask;
-        if (f == 0) {
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-        }
-        excl += (int64_t)(w & kValMask);
-        if (f == kFlagInc) break;
-        --j;
-    }
-    st_relaxed(status + tile, kFlagInc | (uint64_t)(excl + agg));
-    return excl;
-}
-
 // Workspace header protocol shared by one-pass kernels.
 struct TileQueue {
     uint32_t *hdr;       // [ticket, done, parity, err]
@@ -240,8 +236,6 @@ struct TileQueue {
     uint64_t *status1;   // parity 1 status words
     int64_t clear_n;     // status words of the other parity to zero
 };
-
-__device__ __forceinline__ void raise_error(uint32_t *hdr, uint32_t flag) { atomicOr(hdr + 3, flag); }
 
 // Called by thread 0 of every block after its last tile: the last block to
 // finish resets the counters and, for kernels that used (and cleared) the

@@ -178,7 +178,7 @@ __global__ __launch_bounds__(NT) void k_rowscan(RowScanArgs a) {
         const int64_t total = rowscan_unit(a, u * kUnitRows, s_tmp, err, [&](int64_t tot) {
             if (threadIdx.x < dev::kWave) {
                 if (threadIdx.x == 0) dev::publish_aggregate(st, u, tot);
-                const int64_t ex = dev::wave_lookback(st, u, tot);
+                const int64_t ex = dev::wave_lookback(st, u, tot, a.q.hdr);
                 if (threadIdx.x == 0) s_excl = ex;
             }
             __syncthreads();

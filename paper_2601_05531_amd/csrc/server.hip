@@ -31,58 +31,13 @@
 #include <vector>
 
 #include "common.hpp"
+#include "hostbook.hpp"
 
 namespace dnatok {
 namespace {
 
 constexpr int64_t kAlign = 256;
 inline int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-// First-fit allocator over the arena's byte range, free blocks coalesced.
-class Arena {
-  public:
-    void reset(int64_t size) {
-        free_.clear();
-        if (size > 0) free_[0] = size;
-        used_ = peak_ = 0;
-    }
-    // Offset of a block of `size` bytes, or -1.
-    int64_t alloc(int64_t size) {
-        size = align_up(std::max<int64_t>(size, 1));
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second < size) continue;
-            const int64_t off = it->first, rest = it->second - size;
-            free_.erase(it);
-            if (rest > 0) free_[off + size] = rest;
-            used_ += size;
-            peak_ = std::max(peak_, used_);
-            return off;
-        }
-        return -1;
-    }
-    void release(int64_t off, int64_t size) {
-        size = align_up(std::max<int64_t>(size, 1));
-        used_ -= size;
-        auto it = free_.emplace(off, size).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-    int64_t peak() const { return peak_; }
-
-  private:
-    std::map<int64_t, int64_t> free_;
-    int64_t used_ = 0, peak_ = 0;
-};
 
 using Clock = std::chrono::steady_clock;
 
@@ -384,14 +339,17 @@ int dnatok_server_create(const dnatok_server_opts *opts, dnatok_server **out) {
     s->t0 = Clock::now();
     DNATOK_HIP(hipGetDevice(&s->device));
     void *p = nullptr;
-    DNATOK_HIP(hipMalloc(&p, (size_t)arena));
+    DNATOK_HIP(dev_alloc(&p, (size_t)arena));
     s->d_arena = static_cast<uint8_t *>(p);
     s->arena_bytes = arena;
     s->arena.reset(arena);
     s->slots.resize(o.n_streams);
     auto cleanup = [&](int rc) {
         for (Slot &sl : s->slots) {
-            if (sl.stream) (void)hipStreamDestroy(sl.stream);
+            if (sl.stream) {
+                drop_workspace(sl.stream);
+                (void)hipStreamDestroy(sl.stream);
+            }
             if (sl.done) (void)hipEventDestroy(sl.done);
             if (sl.staging) (void)hipHostFree(sl.staging);
             if (sl.h_offs) (void)hipHostFree(sl.h_offs);
@@ -404,13 +362,13 @@ int dnatok_server_create(const dnatok_server_opts *opts, dnatok_server **out) {
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
             return cleanup(set_error(DNATOK_EDEVICE, "stream/event creation failed"));
-        if (hipHostMalloc(&p, (size_t)o.staging_bytes, 0) != hipSuccess)
+        if (host_alloc(&p, (size_t)o.staging_bytes) != hipSuccess)
             return cleanup(set_error(DNATOK_ENOMEM, "pinned staging (%lld bytes)", (long long)o.staging_bytes));
         sl.staging = static_cast<uint8_t *>(p);
-        if (hipHostMalloc(&p, sizeof(int64_t) * (size_t)(o.max_batch + 1), 0) != hipSuccess)
+        if (host_alloc(&p, sizeof(int64_t) * (size_t)(o.max_batch + 1)) != hipSuccess)
             return cleanup(set_error(DNATOK_ENOMEM, "pinned offsets"));
         sl.h_offs = static_cast<int64_t *>(p);
-        if (hipHostMalloc(&p, sizeof(int64_t) * (size_t)(o.max_batch + 1), 0) != hipSuccess)
+        if (host_alloc(&p, sizeof(int64_t) * (size_t)(o.max_batch + 1)) != hipSuccess)
             return cleanup(set_error(DNATOK_ENOMEM, "pinned offsets"));
         sl.h_oofs = static_cast<int64_t *>(p);
         // grow the stream's workspace now so no batch allocates on the hot path
@@ -484,8 +442,11 @@ int dnatok_server_wait(dnatok_server *s, uint64_t ticket, dnatok_request_result 
     std::unique_lock<std::mutex> lk(s->mu);
     auto it = s->reqs.find(ticket);
     if (it == s->reqs.end()) return set_error(DNATOK_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
-    s->cv_done.wait(lk, [&] { return it->second.done; });
-    *out = it->second.res;
+    // A submission made while this thread waits may rehash the map, which
+    // invalidates iterators but never references to its elements.
+    const Request &r = it->second;
+    s->cv_done.wait(lk, [&] { return r.done; });
+    *out = r.res;
     return DNATOK_OK;
 }
 

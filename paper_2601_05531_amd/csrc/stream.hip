@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "hostbook.hpp"
 
 namespace {
 
@@ -77,9 +78,9 @@ static int ensure_offs(dnatok_stream *s, int i, int64_t entries) {
     s->h_offs[i] = nullptr;
     s->offs_cap[i] = 0;
     void *p = nullptr;
-    DNATOK_HIP(hipMalloc(&p, sizeof(int64_t) * (size_t)cap));
+    DNATOK_HIP(dev_alloc(&p, sizeof(int64_t) * (size_t)cap));
     s->d_offs[i] = static_cast<int64_t *>(p);
-    DNATOK_HIP(hipHostMalloc(&p, sizeof(int64_t) * (size_t)cap, hipHostMallocDefault));
+    DNATOK_HIP(host_alloc(&p, sizeof(int64_t) * (size_t)cap));
     s->h_offs[i] = static_cast<int64_t *>(p);
     s->offs_cap[i] = cap;
     return DNATOK_OK;
@@ -132,7 +133,7 @@ int dnatok_stream_create(const dnatok_vocab *v, const dnatok_stream_opts *opts, 
     const int64_t per_chunk_windows = o.chunk_bytes / o.window + 64;
     for (int i = 0; i < n; ++i) {
         void *p = nullptr;
-        hipError_t e = hipMalloc(&p, (size_t)(s->pre + round_up(o.chunk_bytes, kAlign) + kAlign));
+        hipError_t e = dev_alloc(&p, (size_t)(s->pre + round_up(o.chunk_bytes, kAlign) + kAlign));
         if (e != hipSuccess) return fail(set_error(DNATOK_ENOMEM, "slot %d: %s", i, hipGetErrorString(e)));
         s->d_slot[i] = static_cast<uint8_t *>(p);
         if ((rc = ensure_offs(s, i, per_chunk_windows + 1))) return fail(rc);
@@ -141,15 +142,15 @@ int dnatok_stream_create(const dnatok_vocab *v, const dnatok_stream_opts *opts, 
             return fail(set_error(DNATOK_EDEVICE, "event creation failed"));
     }
     void *p = nullptr;
-    if (hipMalloc(&p, 2 * sizeof(int64_t)) != hipSuccess) return fail(set_error(DNATOK_ENOMEM, "tail offsets"));
+    if (dev_alloc(&p, 2 * sizeof(int64_t)) != hipSuccess) return fail(set_error(DNATOK_ENOMEM, "tail offsets"));
     s->d_tail_offs = static_cast<int64_t *>(p);
-    if (hipHostMalloc(&p, 2 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess)
+    if (host_alloc(&p, 2 * sizeof(int64_t)) != hipSuccess)
         return fail(set_error(DNATOK_ENOMEM, "tail offsets"));
     s->h_tail_offs = static_cast<int64_t *>(p);
-    if (hipMalloc(&p, sizeof(int32_t) * (size_t)std::max<int64_t>(o.max_tokens, 1)) != hipSuccess)
+    if (dev_alloc(&p, sizeof(int32_t) * (size_t)std::max<int64_t>(o.max_tokens, 1)) != hipSuccess)
         return fail(set_error(DNATOK_ENOMEM, "output ids (%lld tokens)", (long long)o.max_tokens));
     s->d_ids = static_cast<int32_t *>(p);
-    if (hipMalloc(&p, sizeof(int64_t) * (size_t)(o.max_windows + 1)) != hipSuccess)
+    if (dev_alloc(&p, sizeof(int64_t) * (size_t)(o.max_windows + 1)) != hipSuccess)
         return fail(set_error(DNATOK_ENOMEM, "window offsets"));
     s->d_woff = static_cast<int64_t *>(p);
     *out = s;
@@ -200,29 +201,9 @@ int dnatok_stream_push(dnatok_stream *s, const uint8_t *h, int64_t nbytes, const
     if (s->copied_pending[slot]) DNATOK_HIP(hipEventSynchronize(s->ev_copied[slot]));
 
     // Cut windows over S = carry ++ chunk (coordinates from the carry's first byte).
-    const int64_t W = o.window;
     const int64_t cl = s->carry_len, slen = cl + nbytes;
     std::vector<int64_t> cuts;
-    cuts.reserve((size_t)(slen / W + n_ends + 2));
-    cuts.push_back(0);
-    int64_t cur = 0;
-    int32_t ei = 0;
-    for (;;) {
-        const int64_t target = cur + W;
-        const int64_t re = (ei < n_ends) ? ends[ei] + cl : INT64_MAX;
-        if (re <= target) {
-            if (re > cur) {
-                cuts.push_back(re);
-                cur = re;
-            }
-            ++ei;
-        } else if (target <= slen) {
-            cuts.push_back(target);
-            cur = target;
-        } else {
-            break;
-        }
-    }
+    const int64_t cur = cut_windows(cl, nbytes, o.window, ends, n_ends, cuts);
     const int64_t nwin = (int64_t)cuts.size() - 1;
     int64_t toks = 0;
     for (int64_t w = 0; w < nwin; ++w) toks += window_tokens(s->v, cuts[w + 1] - cuts[w], o.add_cls_sep);
