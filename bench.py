@@ -240,13 +240,34 @@ STREAM_WINDOW = 6000
 STREAM_K = 6
 
 
-def stream_leg(passes: int = 3):
+def _h2d_passes(h, passes: int):
+    """Pinned host -> device copy rate (copy engine): 64 MiB copies of the
+    whole buffer back to back into a 3-slot device ring, one rate per pass."""
+    import torch
+    ring = [torch.empty(STREAM_CHUNK, dtype=torch.uint8, device="cuda") for _ in range(3)]
+    rates = []
+    for p in range(passes):
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for i, c0 in enumerate(range(0, STREAM_BYTES, STREAM_CHUNK)):
+            ring[i % 3].copy_(h[c0:c0 + STREAM_CHUNK], non_blocking=True)
+        b.record()
+        torch.cuda.synchronize()
+        rates.append(STREAM_BYTES / (a.elapsed_time(b) * 1e-3) / 1e9)
+    del ring
+    return rates
+
+
+def stream_leg(passes: int = 5):
     """End-to-end pinned host -> device stream: 2 GiB of synthetic chromosomes
     (16 records, log-uniform lengths scaled to 2 GiB, same genome model as
     the batched workload) pushed in 64 MiB chunks, cut into 6000-base windows
-    and encoded as 6-mers on the device. Reported against the pinned H2D rate
-    measured on the same buffer (64 MiB copies back to back into a 3-slot
-    ring), for the overlapped stream and the sequential baseline."""
+    and encoded as 6-mers on the device, overlapped and sequential. Both the
+    stream and the plain pinned H2D rate of the same buffer take the best of
+    ``passes`` passes; the H2D passes run before and after the stream, and
+    the denominator is the best of all of them. Returns (summary, the host
+    buffer and record lengths, the overlapped stream's ids on the host)."""
     import torch
     import paper_2601_05531_amd as dt
     import synth
@@ -263,30 +284,17 @@ def stream_leg(passes: int = 3):
         full, rem = divmod(int(L), STREAM_WINDOW)
         n_tokens += full * (-(-STREAM_WINDOW // STREAM_K)) + (-(-rem // STREAM_K))
 
-    # measured pinned H2D rate (copy engine), same chunking
-    ring = [torch.empty(STREAM_CHUNK, dtype=torch.uint8, device="cuda") for _ in range(3)]
-    rates = []
-    for p in range(passes):
-        torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        for i, c0 in enumerate(range(0, STREAM_BYTES, STREAM_CHUNK)):
-            ring[i % 3].copy_(h[c0:c0 + STREAM_CHUNK], non_blocking=True)
-        b.record()
-        torch.cuda.synchronize()
-        rates.append(STREAM_BYTES / (a.elapsed_time(b) * 1e-3) / 1e9)
-    h2d = float(np.median(rates))
-    del ring
-
+    before = _h2d_passes(h, passes)
     v = dt.Vocab(dt.KMER, k=STREAM_K)
-    out = {"h2d_GBps": round(h2d, 2), "h2d_passes_GBps": [round(r, 2) for r in rates],
-           "bytes": STREAM_BYTES, "windows": n_windows, "tokens": n_tokens}
+    out = {"bytes": STREAM_BYTES, "windows": n_windows, "tokens": n_tokens, "chunk_bytes": STREAM_CHUNK,
+           "slots": 3, "passes": passes}
     sample_ok = None
+    got_ids = None
+    runs = {}
     for mode, overlap in (("overlap", True), ("baseline", False)):
         st = dt.Stream(v, STREAM_WINDOW, STREAM_CHUNK, n_tokens, n_windows, n_slots=3, overlap=overlap)
         times = []
-        reps = 5  # one pass is about 40 ms of wall clock: a host hiccup moves a single pass by several percent
-        for rep in range(reps):
+        for rep in range(passes):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for c0 in range(0, STREAM_BYTES, STREAM_CHUNK):
@@ -298,16 +306,89 @@ def stream_leg(passes: int = 3):
             assert r.n_tokens == n_tokens and r.n_windows == n_windows
             if sample_ok is None:
                 sample_ok = _stream_window_check(lens, woff, n_windows)
-            if rep < reps - 1:
+            if overlap and rep == passes - 1:
+                got_ids = ids.cpu().numpy()
+            if rep < passes - 1:
                 st.reset()
         st.close()
+        runs[mode] = times
+    after = _h2d_passes(h, passes)
+    h2d = max(before + after)
+    out["h2d"] = {"best_GBps": round(h2d, 2), "median_GBps": round(float(np.median(before + after)), 2),
+                  "before_GBps": [round(x, 2) for x in before], "after_GBps": [round(x, 2) for x in after]}
+    for mode, times in runs.items():
         t = min(times)
-        out[mode] = {"s": round(t, 4), "tokens_per_s": n_tokens / t, "GBps": STREAM_BYTES / t / 1e9,
+        out[mode] = {"s": round(t, 4), "tokens_per_s": n_tokens / t, "GBps": round(STREAM_BYTES / t / 1e9, 2),
+                     "median_GBps": round(STREAM_BYTES / float(np.median(times)) / 1e9, 2),
                      "frac_of_h2d": round(STREAM_BYTES / t / 1e9 / h2d, 4)}
-        log("stream %s: %.3e tokens/s, %.1f GB/s (%.0f%% of pinned H2D %.1f GB/s)" % (
+        log("stream %s: %.3e tokens/s, %.1f GB/s (%.0f%% of the best pinned H2D pass, %.1f GB/s)" % (
             mode, n_tokens / t, STREAM_BYTES / t / 1e9, 100 * STREAM_BYTES / t / 1e9 / h2d, h2d))
     out["window_offsets_check"] = sample_ok
-    del h
+    v.close()
+    return out, (h, lens), got_ids
+
+
+IDS_CONFIGS = ((4096, 512), (8192, 512), (2048, 2048))
+
+
+def ids_leg(reps: int = 5, warmup: int = 2):
+    """The paper's IDs path and its ablation (staging width x overlap) on its
+    three microbenchmark shapes (B x T equal-length strings): host map
+    through the single-nucleotide table into pinned staging, H2D per
+    micro-batch (token budget 1,048,576), on-device widen for int32
+    staging, and the embedding lookup (11 x 128 bf16 table, the paper's
+    vocabulary size and width). Per arm: end-to-end tokens/s (wall clock from
+    the host map to the last row written; best and median of ``reps``), the
+    host map alone, and the H2D rate (staged bytes / the copies' event
+    time)."""
+    import torch
+    import paper_2601_05531_amd as dt
+    import synth
+
+    v = dt.Vocab(dt.SINGLE)
+    g = torch.Generator().manual_seed(42)
+    table = torch.randn((11, 128), generator=g).to(torch.bfloat16).cuda()
+    threads = _host_threads()
+    out = {"workload": "B x T equal-length synthetic strings (order-3 Markov genome, soft-masked, N runs), "
+                       "single-nucleotide table, embedding 11 x 128 bf16, token budget 1,048,576 per micro-batch, "
+                       "%d host threads" % threads}
+    for B, T in IDS_CONFIGS:
+        rows = synth.genome(synth.substream(6, B), synth.substream(6, T), 3, B * T)
+        h = torch.empty(B * T, dtype=torch.uint8, pin_memory=True)
+        h.numpy()[:] = rows
+        d_out = torch.empty((B, T, 128), dtype=torch.bfloat16, device="cuda")
+        cfg = {}
+        for width in (8, 4):
+            for overlap in (False, True):
+                p = dt.IdsPath(v, width=width, overlap=overlap, threads=threads)
+                res = []
+                for r in range(warmup + reps):
+                    x = p.run(h, B, T, T, table=table, d_out=d_out)
+                    if r >= warmup:
+                        res.append(x)
+                assert dt.sync_status() == 0
+                p.close()
+                tot = sorted(x.total_s for x in res)
+                name = "%s_%s" % ("int32" if width == 4 else "int64", "pipelined" if overlap else "sequential")
+                cfg[name] = {
+                    "tokens_per_s": B * T / tot[0],
+                    "median_tokens_per_s": B * T / float(np.median(tot)),
+                    "host_map_tokens_per_s": B * T / min(x.map_s for x in res),
+                    "h2d_GBps": round(max(x.h2d_bytes / x.h2d_s for x in res) / 1e9, 2),
+                    "micro_batches": int(res[0].n_micro),
+                }
+        base = cfg["int64_sequential"]["tokens_per_s"]
+        cfg["ablation_vs_baseline"] = {
+            "baseline": 1.0,
+            "int32_only": round(cfg["int32_sequential"]["tokens_per_s"] / base, 3),
+            "overlap_only": round(cfg["int64_pipelined"]["tokens_per_s"] / base, 3),
+            "both": round(cfg["int32_pipelined"]["tokens_per_s"] / base, 3),
+        }
+        out["B%d_T%d" % (B, T)] = cfg
+        log("ids path B=%d T=%d: %s" % (B, T, {k: "%.3e" % v["tokens_per_s"] for k, v in cfg.items()
+                                                if "tokens_per_s" in v}))
+        del d_out, h
+    v.close()
     return out
 
 
@@ -629,7 +710,7 @@ def bpe_leg(reps: int = 10, tuning=None, per_seq_leg: bool = True):
     return out, data, offs, merges
 
 
-SERVE_REQUESTS = 6000
+SERVE_REQUESTS = 20000
 SERVE_RATE = 2000.0
 
 
@@ -753,28 +834,76 @@ def serve_leg(n_requests: int = SERVE_REQUESTS):
             "p99_speedup": round(plain["p99_ms"] / server["p99_ms"], 2)}
 
 
-def cpu_baseline(data, offs, budget_s: float = 12.0, bpe=None):
-    """The CPU oracle as written (single thread) on a bounded sample: whole
-    rows of the same batch, all four k, until about ``budget_s`` seconds."""
+def _host_threads():
+    """Worker threads for the oracle: the CPUs this process may run on, at
+    most 16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(data, offs, budget_s: float = 12.0, bpe=None, stream=None):
+    """The CPU oracle as written on a bounded sample: whole rows of the same
+    batch, all four k, for about ``budget_s`` seconds single-threaded and the
+    same again with the rows split over the host's threads (a static
+    partition by bytes). Also times the oracle's BPE on the first rows of the
+    BPE batch and, given the stream leg's buffer and ids, the oracle over all
+    2 GiB of stream windows (threaded), checking the GPU stream's ids against
+    it id for id."""
     import oracle
+    threads = _host_threads()
     rows = 256
     sub = offs[:rows + 1]
     chunk = data[:sub[-1]]
-    t_total, tok_total, reps = 0.0, 0, 0
-    while t_total < budget_s:
-        for k in KS:
-            t0 = time.perf_counter()
-            ids, oo = oracle.encode(oracle.KMER, chunk, sub, k=k, add_cls_sep=True)
-            W = int(np.diff(oo).max())
-            oracle.pad(ids, oo, W)
-            t_total += time.perf_counter() - t0
-            tok_total += int(oo[-1])
-        reps += 1
-    res = {"value": tok_total / t_total, "unit": "tokens/s", "cores": 1, "kind": "oracle",
+
+    def timed(fn, budget):
+        t_total, tok_total, reps = 0.0, 0, 0
+        while t_total < budget:
+            for k in KS:
+                t0 = time.perf_counter()
+                ids, oo = fn(k)
+                t_total += time.perf_counter() - t0
+                tok_total += int(oo[-1])
+            reps += 1
+        return tok_total / t_total, t_total, reps
+
+    def one(k):
+        ids, oo = oracle.encode(oracle.KMER, chunk, sub, k=k, add_cls_sep=True)
+        oracle.pad(ids, oo, int(np.diff(oo).max()))
+        return ids, oo
+
+    v1, t1, r1 = timed(one, budget_s)
+    big = offs[:min(len(offs), 2048 + 1)]
+    big_chunk = data[:big[-1]]
+
+    def many(k):
+        ids, oo = oracle.encode_threads(oracle.KMER, big_chunk, big, threads=threads, k=k, add_cls_sep=True)
+        oracle.pad_threads(ids, oo, int(np.diff(oo).max()), threads=threads)
+        return ids, oo
+
+    vt, tt, rt = timed(many, budget_s / 2)
+    res = {"value": v1, "unit": "tokens/s", "cores": 1, "kind": "oracle",
            "sample": "%d reps of %d of the %d rows (%d bases), k=3,4,5,6, CLS/SEP, right-padded, "
-                     "single-threaded C oracle, %.1f s" % (reps, rows, N_SEQS, int(sub[-1]), t_total)}
+                     "single-threaded C oracle, %.1f s" % (r1, rows, N_SEQS, int(sub[-1]), t1),
+           "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+           "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
+           "threaded": {"value": vt, "unit": "tokens/s", "cores": threads,
+                        "sample": "%d reps of %d rows (%d bases), k=3,4,5,6, CLS/SEP, right-padded, rows split by "
+                                  "bytes over %d threads, %.1f s" % (rt, len(big) - 1, int(big[-1]), threads, tt)}}
     if bpe is not None:
-        # the oracle's BPE on the first rows of the BPE batch, about 4 s
+        # the oracle's BPE on the first rows of the BPE batch, about 1 s
         b_data, b_offs, merges = bpe
         rows = 48
         sub = b_offs[:rows + 1]
@@ -783,6 +912,16 @@ def cpu_baseline(data, offs, budget_s: float = 12.0, bpe=None):
         t = time.perf_counter() - t0
         res["bpe"] = {"value": int(oo[-1]) / t, "unit": "tokens/s", "cores": 1,
                       "sample": "first %d of the 1024 BPE rows (%d bases), %.1f s" % (rows, int(sub[-1]), t)}
+    if stream is not None:
+        (h, lens), got = stream
+        woffs = oracle.windows(lens, STREAM_WINDOW)
+        t0 = time.perf_counter()
+        want, want_off = oracle.encode_threads(oracle.KMER, h.numpy(), woffs, threads=threads, k=STREAM_K)
+        t = time.perf_counter() - t0
+        res["stream"] = {"value": len(want) / t, "unit": "tokens/s", "cores": threads,
+                         "sample": "all %d windows of the 2 GiB stream, 6-mers, rows split by bytes over %d "
+                                   "threads, %.1f s" % (len(woffs) - 1, threads, t),
+                         "gpu_stream_ids_match_oracle": bool(got is not None and np.array_equal(got, want))}
     return res
 
 
@@ -800,6 +939,7 @@ def main():
     ap.add_argument("--no-cellwise", action="store_true",
                     help="skip the embedding-lookup and encode-variant leg")
     ap.add_argument("--no-decode", action="store_true", help="skip the decode leg")
+    ap.add_argument("--no-ids", action="store_true", help="skip the IDs path ablation leg")
     ap.add_argument("--no-per-vocab", action="store_true", help="skip the four single-vocabulary launches")
     ap.add_argument("--tuning", type=str, default=None,
                     help="TILE,BLOCKS: fixed tiling of the one-pass encode instead of the autotuner's")
@@ -828,9 +968,13 @@ def main():
         copy = copy_leg()
         enc["roofline"]["device_copy"] = copy
         log("device copy: %s" % copy)
-    stream = None
+    stream = stream_keep = None
     if not args.no_stream:
-        stream = stream_leg()
+        stream, stream_buf, stream_ids = stream_leg()
+        stream_keep = (stream_buf, stream_ids)
+    ids = None
+    if not args.no_ids:
+        ids = ids_leg()
     small = None
     if not args.no_small:
         small = small_leg()
@@ -850,8 +994,12 @@ def main():
         bpe_in = (b_data, b_offs, merges)
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(enc["data"], enc["offs"], bpe=bpe_in)
-        log("cpu oracle: %.3e tokens/s" % cpu["value"])
+        cpu = cpu_baseline(enc["data"], enc["offs"], bpe=bpe_in, stream=stream_keep)
+        log("cpu oracle: %.3e tokens/s (one thread), %.3e tokens/s (%d threads)" % (
+            cpu["value"], cpu["threaded"]["value"], cpu["threaded"]["cores"]))
+        if stream is not None and "stream" in cpu:
+            stream["ids_match_oracle"] = cpu["stream"]["gpu_stream_ids_match_oracle"]
+    stream_keep = None
     line = {
         "metric": METRIC,
         "value": enc["value"],
@@ -882,6 +1030,7 @@ def main():
         "small_batch": small,
         "embed_and_variants": cellwise,
         "decode": decode,
+        "ids_path": ids,
     }
     print(json.dumps(line), flush=True)
 

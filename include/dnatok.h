@@ -350,6 +350,84 @@ int dnatok_stream_reset(dnatok_stream *s);
 
 int dnatok_stream_destroy(dnatok_stream *s);
 
+/* ---- IDs path (host mapping, staged id transfer) ------------------------------
+ *
+ * The paper's other encoding path (Design, "IDs path (CPU staging)"; the
+ * host-side branch of the EmbedFromStrings algorithm; "Pipelined
+ * streaming"): equal-length strings are mapped to ids on the host through
+ * the 256-entry table into persistent pinned staging (int32 or int64),
+ * left-padded to token_len, sent to the device one micro-batch at a time,
+ * widened to int64 on the device when staged as int32, and handed to the
+ * embedder (here the library's embedding lookup). Micro-batches hold
+ * b = min(B_emb, max(1, floor(M / T'))) rows for a token budget M. The
+ * sequential form copies and computes each micro-batch in order on one
+ * stream (the paper's streaming baseline); the pipelined form copies
+ * micro-batch n + 1 on a side stream into the other of two ping-pong device
+ * buffers while micro-batch n is widened and embedded (two int64 buffers
+ * with int64 staging; two int32 copy buffers plus two int64 buffers with
+ * int32 staging), events ordering the two streams. The bytes path
+ * (dnatok_encode, dnatok_stream_*) is this library's main path; this one
+ * exists for callers and comparisons that want the paper's host mapping.
+ */
+typedef struct dnatok_ids dnatok_ids;
+
+typedef struct dnatok_ids_opts {
+    int32_t width;        /* bytes per staged id: 4 (int32, widened on the device) or 8 (int64) */
+    int32_t overlap;      /* 1: pipelined (ping-pong buffers, copy stream); 0: sequential baseline */
+    int32_t threads;      /* host mapping threads, 0 = the host's hardware threads (at most 16) */
+    int32_t reserved;
+    int64_t token_budget; /* M: ids per micro-batch call (0 = 1,048,576, the paper's default) */
+    int64_t max_rows;     /* B_emb: most rows per micro-batch (0 = no cap) */
+} dnatok_ids_opts;
+
+typedef struct dnatok_ids_result {
+    int64_t rows;            /* B */
+    int64_t token_len;       /* T' */
+    int64_t micro_rows;      /* b */
+    int64_t n_micro;         /* micro-batches */
+    int64_t h2d_bytes;       /* staged id bytes copied to the device */
+    double map_s;            /* host mapping time (wall clock) */
+    double h2d_s;            /* sum of the copies' device times (HIP events on the copying stream) */
+    double total_s;          /* the whole call, mapping to the last output written (wall clock) */
+} dnatok_ids_result;
+
+/*
+ * Create an IDs path for vocabulary v (SINGLE or LUT256: the kinds whose ids
+ * are a byte table; others EVOCAB). Its device work runs on compute_stream
+ * (the copies of the pipelined form on a side stream it owns). Buffers are
+ * sized by the first run and grow when a later run needs more (synchronous,
+ * outside the timed loop). Errors: EINVAL, EVOCAB, ENOMEM, EDEVICE.
+ */
+int dnatok_ids_create(const dnatok_vocab *v, const dnatok_ids_opts *opts, void *compute_stream, dnatok_ids **out);
+
+/*
+ * Run the IDs path on n_rows strings of row_len bytes each, back to back in
+ * host memory h_bytes (pageable or pinned), left-padded to token_len ids
+ * (0 = row_len; must be >= row_len). Outputs (either may be NULL, not both):
+ *  d_ids   device int64[n_rows x T'], the ids the embedder received.
+ *  d_out   device [n_rows x T'] rows of row_bytes: row c = d_table row of
+ *          id c (d_table: n_table_rows rows of row_bytes, any element type).
+ * Returns when every output is written (the call synchronizes), with
+ * timings in *res (may be NULL). Errors: EINVAL, ENOMEM, EDEVICE; an id
+ * outside the table raises DNATOK_DERR_IDS (dnatok_sync_status on the
+ * compute stream).
+ */
+int dnatok_ids_run(dnatok_ids *p, const uint8_t *h_bytes, int64_t n_rows, int64_t row_len, int64_t token_len,
+                   int64_t *d_ids, const void *d_table, int64_t n_table_rows, int64_t row_bytes, void *d_out,
+                   dnatok_ids_result *res);
+
+int dnatok_ids_destroy(dnatok_ids *p);
+
+/*
+ * The host mapping step alone (host memory only, no device involved): rows
+ * of row_len bytes -> ids through lut256 (256 int32), left-padded with
+ * pad_id to token_len, written as int32 (width 4) or int64 (width 8) to
+ * h_out[n_rows x token_len], on `threads` threads (0 = hardware threads, at
+ * most 16). Errors: EINVAL.
+ */
+int dnatok_ids_map(const int32_t *lut256, int32_t pad_id, const uint8_t *h_bytes, int64_t n_rows, int64_t row_len,
+                   int64_t token_len, int32_t width, void *h_out, int32_t threads);
+
 /* ---- tuning, autotuner and captured graphs ----------------------------------
  *
  * The paper attributes much of the remaining cost of batched encoding to
@@ -364,6 +442,10 @@ typedef struct dnatok_tuning {
     int32_t blocks_per_cu;  /* SINGLE/LUT256/KMER: workgroups per CU, 0 = as many as fit */
     int32_t bpe_item_bytes; /* BPE: nominal item length S, power of two 1024..65536 (0 = 8192) */
     int32_t bpe_max_waves;  /* BPE: most waves per workgroup of the length classes: 1, 2, 4 or 8 (0 = 8) */
+    int32_t spread;         /* SINGLE/LUT256/KMER: 0 = every workgroup walks a static share of the tiles;
+                               1..100 = one tile per workgroup: the first resident round by workgroup
+                               index, the rest from a ticket counter, with this percentage of the tiles
+                               as extra workgroups, so the parts of the chip that finish early take more */
 } dnatok_tuning;
 
 int dnatok_get_tuning(const dnatok_vocab *v, dnatok_tuning *out);

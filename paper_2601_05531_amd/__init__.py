@@ -87,6 +87,7 @@ class dnatok_tuning(ctypes.Structure):
         ("blocks_per_cu", ctypes.c_int32),
         ("bpe_item_bytes", ctypes.c_int32),
         ("bpe_max_waves", ctypes.c_int32),
+        ("spread", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -128,6 +129,30 @@ class dnatok_request_result(ctypes.Structure):
         ("t_submit", ctypes.c_double),
         ("t_start", ctypes.c_double),
         ("t_done", ctypes.c_double),
+    ]
+
+
+class dnatok_ids_opts(ctypes.Structure):
+    _fields_ = [
+        ("width", ctypes.c_int32),
+        ("overlap", ctypes.c_int32),
+        ("threads", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("token_budget", ctypes.c_int64),
+        ("max_rows", ctypes.c_int64),
+    ]
+
+
+class dnatok_ids_result(ctypes.Structure):
+    _fields_ = [
+        ("rows", ctypes.c_int64),
+        ("token_len", ctypes.c_int64),
+        ("micro_rows", ctypes.c_int64),
+        ("n_micro", ctypes.c_int64),
+        ("h2d_bytes", ctypes.c_int64),
+        ("map_s", ctypes.c_double),
+        ("h2d_s", ctypes.c_double),
+        ("total_s", ctypes.c_double),
     ]
 
 
@@ -189,6 +214,10 @@ def lib():
         L.dnatok_embed.argtypes = [vp, vp, i64, vp, i32, vp, i64, i64, vp, i64, vp, vp, vp,
                                    ctypes.POINTER(dnatok_encode_opts), vp]
         L.dnatok_embed_ids.argtypes = [vp, i64, vp, i64, i64, vp, vp]
+        L.dnatok_ids_create.argtypes = [vp, ctypes.POINTER(dnatok_ids_opts), vp, ctypes.POINTER(vp)]
+        L.dnatok_ids_run.argtypes = [vp, vp, i64, i64, i64, vp, vp, i64, i64, vp, ctypes.POINTER(dnatok_ids_result)]
+        L.dnatok_ids_destroy.argtypes = [vp]
+        L.dnatok_ids_map.argtypes = [vp, i32, vp, i64, i64, i64, i32, vp, i32]
         for name in ("dnatok_vocab_create", "dnatok_vocab_destroy", "dnatok_vocab_info", "dnatok_encode_plan",
                      "dnatok_encode", "dnatok_sync_status", "dnatok_decode", "dnatok_stream_create",
                      "dnatok_stream_push", "dnatok_stream_flush", "dnatok_stream_reset", "dnatok_stream_destroy",
@@ -196,7 +225,8 @@ def lib():
                      "dnatok_server_release", "dnatok_server_stats", "dnatok_server_destroy", "dnatok_get_tuning",
                      "dnatok_set_tuning", "dnatok_autotune", "dnatok_graph_create", "dnatok_graph_launch",
                      "dnatok_graph_destroy", "dnatok_encode_multi", "dnatok_autotune_multi", "dnatok_embed",
-                     "dnatok_embed_ids"):
+                     "dnatok_embed_ids", "dnatok_ids_create", "dnatok_ids_run",
+                     "dnatok_ids_destroy", "dnatok_ids_map"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -645,8 +675,8 @@ def dnatok_autotune(vocab, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d
     return t, ms.value
 
 
-def set_tuning(vocab: Vocab, tile_bytes=0, blocks_per_cu=0, bpe_item_bytes=0, bpe_max_waves=0):
-    dnatok_set_tuning(vocab.handle, dnatok_tuning(tile_bytes, blocks_per_cu, bpe_item_bytes, bpe_max_waves))
+def set_tuning(vocab: Vocab, tile_bytes=0, blocks_per_cu=0, bpe_item_bytes=0, bpe_max_waves=0, spread=0):
+    dnatok_set_tuning(vocab.handle, dnatok_tuning(tile_bytes, blocks_per_cu, bpe_item_bytes, bpe_max_waves, spread))
 
 
 def autotune(vocab: Vocab, d_bytes, d_offsets, h_offsets=None, add_cls_sep=False, layout=PACKED, pad_side=PAD_RIGHT,
@@ -773,3 +803,58 @@ def encode_multi(vocabs, d_bytes, d_offsets, h_offsets=None, add_cls_sep=False, 
         else:
             res.append((ids[:total], oo, None))
     return res
+
+
+# ---- IDs path (host mapping, staged id transfer) ----------------------------------
+
+def dnatok_ids_map(lut256, pad_id: int, h_bytes: np.ndarray, n_rows: int, row_len: int, token_len: int, width: int,
+                   threads: int = 0) -> np.ndarray:
+    """Host mapping step alone: returns int32 or int64 ids [n_rows, T']."""
+    lut = np.ascontiguousarray(lut256, dtype=np.int32)
+    assert lut.shape == (256,)
+    src = np.ascontiguousarray(h_bytes, dtype=np.uint8)
+    T = token_len or row_len
+    out = np.empty((n_rows, T), dtype=np.int32 if width == 4 else np.int64)
+    _check(lib().dnatok_ids_map(lut.ctypes.data, pad_id, src.ctypes.data if src.size else None, n_rows, row_len,
+                                token_len, width, out.ctypes.data if out.size else None, threads))
+    return out
+
+
+class IdsPath:
+    """Owning wrapper of a ``dnatok_ids`` (see ``dnatok_ids_*``)."""
+
+    def __init__(self, vocab: Vocab, width: int = 8, overlap: bool = False, threads: int = 0, token_budget: int = 0,
+                 max_rows: int = 0, stream=None):
+        o = dnatok_ids_opts(width, int(overlap), threads, 0, token_budget, max_rows)
+        h = ctypes.c_void_p()
+        _check(lib().dnatok_ids_create(vocab.handle, ctypes.byref(o), _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h.value
+        self.vocab = vocab
+
+    def run(self, h_bytes, n_rows: int, row_len: int, token_len: int = 0, d_ids=None, table=None, d_out=None):
+        """``h_bytes``: host uint8 (numpy array or pinned tensor) of n_rows x
+        row_len; ``d_ids`` int64 device tensor of n_rows x T' and/or
+        ``d_out`` device tensor of n_rows x T' table rows. Returns the
+        ``dnatok_ids_result``."""
+        if isinstance(h_bytes, np.ndarray):
+            src = np.ascontiguousarray(h_bytes, dtype=np.uint8)
+            ptr = src.ctypes.data if src.size else None
+        else:
+            ptr = h_bytes.data_ptr()
+        r = dnatok_ids_result()
+        n_rows_t = 0 if table is None else table.shape[0]
+        row_bytes = 0 if table is None else table[0].numel() * table.element_size()
+        _check(lib().dnatok_ids_run(self.handle, ptr, n_rows, row_len, token_len, _ptr(d_ids), _ptr(table), n_rows_t,
+                                    row_bytes, _ptr(d_out), ctypes.byref(r)))
+        return r
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(lib().dnatok_ids_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

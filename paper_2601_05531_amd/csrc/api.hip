@@ -442,7 +442,8 @@ int dnatok_embed_ids(const int32_t *d_ids, int64_t n_ids, const void *d_table, i
     if (rc) return rc;
     clear_error();
     if (n_ids == 0) return DNATOK_OK;
-    return launch_embed_ids(d_ids, n_ids, d_table, n_rows, row_bytes, d_out, static_cast<hipStream_t>(stream));
+    return launch_embed_ids(d_ids, nullptr, n_ids, d_table, n_rows, row_bytes, d_out,
+                            static_cast<hipStream_t>(stream));
 }
 
 int dnatok_sync_status(void *stream, uint32_t *flags) {

@@ -76,7 +76,8 @@ struct CwArgs {
     const int32_t *lut;
     int32_t *ids;            // optional for EMBED
     int8_t *mask;            // PADDED, optional for EMBED
-    const int32_t *ids_in;   // GATHER
+    const int32_t *ids_in;   // GATHER: int32 ids (or)
+    const int64_t *ids_in64; // GATHER: int64 ids
     const uint8_t *table;
     int64_t n_rows;
     int64_t row_bytes;
@@ -414,8 +415,9 @@ __global__ __launch_bounds__(NT) void k_cellwise(CwArgs a) {
 #pragma unroll
             for (int i = 0; i < CPT; ++i) {
                 if (cb + i < cend) {
-                    id[i] = a.ids_in[cb + i];
-                    if (id[i] < 0 || id[i] >= a.n_rows) {
+                    const int64_t x = a.ids_in64 ? a.ids_in64[cb + i] : (int64_t)a.ids_in[cb + i];
+                    id[i] = (int32_t)x;
+                    if (x < 0 || x >= a.n_rows) {
                         err |= DNATOK_DERR_IDS;
                         id[i] = -1;
                     }
@@ -631,14 +633,15 @@ int launch_embed(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, 
     return launch_cw_units<CW_EMBED>(a, max_cells, stream);
 }
 
-int launch_embed_ids(const int32_t *d_ids, int64_t n_ids, const void *d_table, int64_t n_rows, int64_t row_bytes,
-                     void *d_out, hipStream_t stream) {
+int launch_embed_ids(const int32_t *d_ids, const int64_t *d_ids64, int64_t n_ids, const void *d_table,
+                     int64_t n_rows, int64_t row_bytes, void *d_out, hipStream_t stream) {
     CwArgs a = CwArgs{};
     Workspace *ws = nullptr;
     int rc = get_workspace(stream, 1, &ws);
     if (rc) return rc;
     a.err_hdr = ws->d_hdr;
     a.ids_in = d_ids;
+    a.ids_in64 = d_ids64;
     a.ncells = n_ids;
     a.cap = n_ids;
     a.table = static_cast<const uint8_t *>(d_table);

@@ -86,7 +86,7 @@ struct BpeTables {
 struct dnatok_vocab {
     // Scheduling knobs (dnatok_set_tuning / dnatok_autotune); 0 = default.
     // They change how work is tiled, never the ids.
-    std::atomic<int32_t> tune_tile{0}, tune_blocks{0}, tune_item{0}, tune_waves{0};
+    std::atomic<int32_t> tune_tile{0}, tune_blocks{0}, tune_item{0}, tune_waves{0}, tune_spread{0};
     int32_t kind = 0;
     int32_t k = 1;
     int32_t pad_id = DNATOK_ID_PAD, cls_id = DNATOK_ID_CLS, sep_id = DNATOK_ID_SEP;
@@ -140,6 +140,7 @@ int device_cu_count();
 struct EncodeTuning {
     int64_t tile_bytes;  // bytes of input per tile (multiple of 16)
     int blocks_per_cu;   // 0 = as many as occupancy allows
+    int spread;          // 0 = static walkers; > 0: ticketed tiles plus this percentage of extra workgroups
 };
 EncodeTuning encode_tuning(const dnatok_vocab *v, int64_t nbytes);
 constexpr int32_t kBpeItemBytesDefault = 8192;  // nominal BPE item length S
@@ -209,8 +210,9 @@ int launch_embed(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, 
                  const void *d_table, int64_t n_rows, int64_t row_bytes, void *d_out, int64_t out_rows,
                  int64_t *d_out_offsets, int32_t *d_ids, int8_t *d_mask, const dnatok_encode_opts &o,
                  hipStream_t stream);
-int launch_embed_ids(const int32_t *d_ids, int64_t n_ids, const void *d_table, int64_t n_rows, int64_t row_bytes,
-                     void *d_out, hipStream_t stream);
+// Lookup of given ids: int32 ids (d_ids) or int64 ids (d_ids64, the other NULL).
+int launch_embed_ids(const int32_t *d_ids, const int64_t *d_ids64, int64_t n_ids, const void *d_table,
+                     int64_t n_rows, int64_t row_bytes, void *d_out, hipStream_t stream);
 
 int launch_decode(const dnatok_vocab *v, const int32_t *d_ids, int64_t n_ids, const int64_t *d_offsets,
                   int32_t n, uint8_t *d_out, int64_t out_capacity, int64_t *d_out_offsets, hipStream_t stream);

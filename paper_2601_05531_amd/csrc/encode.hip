@@ -226,6 +226,14 @@ struct CellArgs {
     int32_t fused_packed;   // PACKED, <= kFusePackedRows rows: each block scans the row lengths into LDS
     int32_t prefix_off;     // byte offset of that scan in the dynamic LDS
     int32_t lut_off;        // byte offset of the 256-entry table in the dynamic LDS (SINGLE, LUT256)
+    // Ticketed tiles (nticket > 0): blocks [0, lead) run the fused row scans
+    // (the first nv of them) or nothing; tile block b = blockIdx - lead takes
+    // tile xcd_tile(b, nstat) when b < nstat, else the next ticket's tile
+    // nstat + ticket, or nothing once the tickets pass the last tile.
+    int32_t lead;
+    int64_t nstat;
+    int64_t nticket;        // blocks that take a ticket (the last one resets the counter)
+    uint32_t *ticket;
     uint32_t *err_hdr;
     VocabOut vo[kMaxMultiVocabs];
     RowScanArgs scan[kMaxMultiVocabs];
@@ -353,17 +361,49 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
     __shared__ int64_t s_tmp[NT / dev::kWave + 1];
     __shared__ int64_t s_ia, s_ib;
     __shared__ uint32_t s_err;
+    __shared__ uint32_t s_tk;
 
     const int tid = threadIdx.x;
-    // Fused PADDED row scans: the last nv blocks, one vocabulary each. They
-    // start as the first tile walkers retire, so no walker waits for a slot.
     const int nscan = a.fused_scan ? a.nv : 0;
-    const int64_t G = (int64_t)gridDim.x - nscan;  // tile walkers
-    if ((int64_t)blockIdx.x >= G) {
-        rowscan_single_block(a.scan[blockIdx.x - G], s_tmp, a.err_hdr);
-        return;
+    int64_t bid, G;       // tile block index and the walkers' stride
+    int64_t t_fixed = -1;  // ticketed launch: this block's one tile
+    if (a.nticket > 0) {
+        // Fused row scans first: every later block is a tile block, so they
+        // never wait behind the tiles for a slot.
+        if ((int64_t)blockIdx.x < a.lead) {
+            if ((int)blockIdx.x < nscan) rowscan_single_block(a.scan[blockIdx.x], s_tmp, a.err_hdr);
+            return;
+        }
+        bid = (int64_t)blockIdx.x - a.lead;
+        if (bid < a.nstat) {
+            t_fixed = xcd_tile(bid, a.nstat);
+        } else {
+            // Blocks that start late (a slot freed up) take the next tile in
+            // line. Every ticket block takes exactly one ticket, so the one
+            // that draws the last ticket can reset the counter for the next
+            // launch: no block of this launch reads it again.
+            if (tid == 0) {
+                const uint32_t tk = atomicAdd(a.ticket, 1u);
+                if ((int64_t)tk == a.nticket - 1) dev::st_relaxed32(a.ticket, 0u);
+                s_tk = tk;
+            }
+            __syncthreads();
+            const int64_t tk = s_tk;
+            if (a.nstat + tk >= a.ntiles) return;  // an extra block with no tile left
+            t_fixed = a.nstat + tk;
+        }
+        G = a.ntiles;  // one pass of the tile loop
+    } else {
+        // Fused PADDED row scans: the last nv blocks, one vocabulary each.
+        // They start as the first tile walkers retire, so no walker waits
+        // for a slot.
+        G = (int64_t)gridDim.x - nscan;  // tile walkers
+        if ((int64_t)blockIdx.x >= G) {
+            rowscan_single_block(a.scan[blockIdx.x - G], s_tmp, a.err_hdr);
+            return;
+        }
+        bid = blockIdx.x;
     }
-    const int64_t bid = blockIdx.x;
     int32_t *lut_s = reinterpret_cast<int32_t *>(dyn + a.lut_off);
     if (!KMER)
         for (int i = tid; i < 256; i += NT) lut_s[i] = a.vo[0].lut[i];
@@ -469,15 +509,15 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
     // (not interior) are read byte by byte when staged. With PF the next
     // tile's probe is put in flight with its bytes (probed).
     bool pf = false, probed = false;
-    if (PF && bid < a.ntiles) {
+    if (PF && t_fixed < 0 && bid < a.ntiles) {
         const int64_t t0 = xcd_tile(bid, a.ntiles);
         probe_load(t0 * B - a.shift);
         probed = true;
         pf = tile_interior<U>(a, t0);
         if (pf) fetch_tile<U>(a, t0, v, halo, tid);
     }
-    for (int64_t L = bid; L < a.ntiles; L += G) {
-        const int64_t t = xcd_tile(L, a.ntiles);
+    for (int64_t L = (t_fixed >= 0 ? 0 : bid); L < a.ntiles; L += G) {
+        const int64_t t = (t_fixed >= 0) ? t_fixed : xcd_tile(L, a.ntiles);
         // The staging addresses are recomputed per tile from a copy of the
         // thread index the compiler cannot see through: hoisted out of the
         // loop they would hold some 5 registers per chunk through the writes.
@@ -938,6 +978,7 @@ EncodeTuning encode_tuning(const dnatok_vocab *v, int64_t nbytes) {
         t.tile_bytes = want;
     }
     t.blocks_per_cu = v->tune_blocks.load(std::memory_order_relaxed);
+    t.spread = v->tune_spread.load(std::memory_order_relaxed);
     return t;
 }
 
@@ -1044,6 +1085,30 @@ int launch_encode_multi(const dnatok_vocab *const *vs, int nv, const uint8_t *d_
         const int64_t gmax = (int64_t)device_cu_count() * per_cu;
         per_block = (a.ntiles + gmax - 1) / gmax;
         if (per_block == 1) break;  // one tile each: no prefetch
+    }
+    a.lead = 0;
+    a.nstat = 0;
+    a.nticket = 0;
+    a.ticket = ws->d_hdr + HDR_TICKET;
+    if (tune.spread > 0) {
+        // One tile per workgroup: the first resident round by index, the
+        // rest by ticket, plus spread% of the tiles as extra workgroups.
+        // Workgroups go to the XCDs in turn whatever their speed, so extra
+        // ones let an XCD that finishes early draw more of the tickets.
+        int per_cu = 0;
+        rc = kmer ? blocks_per_cu<true, false>(U, dyn, &per_cu) : blocks_per_cu<false, false>(U, dyn, &per_cu);
+        if (rc) return rc;
+        if (per_cu < 1) per_cu = 1;
+        if (tune.blocks_per_cu > 0 && tune.blocks_per_cu < per_cu) per_cu = tune.blocks_per_cu;
+        const int64_t resident = (int64_t)device_cu_count() * per_cu;
+        if (a.ntiles > resident) {
+            a.lead = a.fused_scan ? 8 : 0;  // keeps tile block b on XCD b % 8
+            a.nstat = resident;
+            a.nticket = (a.ntiles - resident) + (a.ntiles * tune.spread + 99) / 100;
+            const int64_t grid = a.lead + a.nstat + a.nticket;
+            return kmer ? launch_cells<true, false>(a, U, grid, dyn, stream)
+                        : launch_cells<false, false>(a, U, grid, dyn, stream);
+        }
     }
     const bool pf = per_block > 1;
     int64_t grid = (a.ntiles + per_block - 1) / per_block;

@@ -4,9 +4,14 @@
 #pragma once
 
 #include <algorithm>
+#include <atomic>
+#include <condition_variable>
 #include <cstdint>
+#include <functional>
 #include <iterator>
 #include <map>
+#include <mutex>
+#include <thread>
 #include <vector>
 
 namespace dnatok {
@@ -97,6 +102,102 @@ inline int64_t cut_windows(int64_t carry, int64_t nbytes, int64_t window, const 
         }
     }
     return cur;
+}
+
+// A fixed set of worker threads that runs one parallel loop at a time: run()
+// hands out parts [0, parts) to the workers and the calling thread and
+// returns when every part is done. Created once per owner and reused, so a
+// call costs a wake-up, not a thread start.
+class WorkerPool {
+  public:
+    explicit WorkerPool(int threads) {
+        const int extra = std::max(threads, 1) - 1;
+        for (int i = 0; i < extra; ++i) workers_.emplace_back([this] { loop(); });
+    }
+    ~WorkerPool() {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto &t : workers_) t.join();
+    }
+    WorkerPool(const WorkerPool &) = delete;
+    WorkerPool &operator=(const WorkerPool &) = delete;
+    int size() const { return (int)workers_.size() + 1; }
+
+    void run(int parts, const std::function<void(int)> &fn) {
+        if (parts <= 0) return;
+        if (workers_.empty() || parts == 1) {
+            for (int p = 0; p < parts; ++p) fn(p);
+            return;
+        }
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            fn_ = &fn;
+            parts_ = parts;
+            next_.store(0);
+            left_ = parts;
+            ++gen_;
+        }
+        cv_.notify_all();
+        work();
+        std::unique_lock<std::mutex> lk(mu_);
+        done_cv_.wait(lk, [this] { return left_ == 0; });
+        fn_ = nullptr;
+    }
+
+  private:
+    void work() {
+        for (;;) {
+            const int p = next_.fetch_add(1);
+            if (p >= parts_) return;
+            (*fn_)(p);
+            std::lock_guard<std::mutex> lk(mu_);
+            if (--left_ == 0) done_cv_.notify_all();
+        }
+    }
+    void loop() {
+        uint64_t seen = 0;
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+                if (stop_) return;
+                seen = gen_;
+            }
+            work();
+        }
+    }
+    std::vector<std::thread> workers_;
+    std::mutex mu_;
+    std::condition_variable cv_, done_cv_;
+    const std::function<void(int)> *fn_ = nullptr;
+    int parts_ = 0;
+    std::atomic<int> next_{0};
+    int left_ = 0;
+    uint64_t gen_ = 0;
+    bool stop_ = false;
+};
+
+// The host-side IDs path of the EmbedFromStrings algorithm for rows
+// [r0, r1) of equal-length strings: each byte of a row of row_len bytes is
+// mapped through the 256-entry table, and a row is left-padded with pad_id
+// to token_len ids (>= row_len), the original positions right-aligned. Row i
+// goes to dst[i * token_len ..).
+template <class T>
+inline void map_rows_to_ids(const int32_t *lut, int32_t pad_id, const uint8_t *src, int64_t r0, int64_t r1,
+                            int64_t row_len, int64_t token_len, T *dst) {
+    T table[256];
+    for (int b = 0; b < 256; ++b) table[b] = (T)lut[b];
+    const int64_t lead = token_len - row_len;
+    for (int64_t i = r0; i < r1; ++i) {
+        const uint8_t *s = src + i * row_len;
+        T *d = dst + i * token_len;
+        for (int64_t j = 0; j < lead; ++j) d[j] = (T)pad_id;
+        d += lead;
+        for (int64_t j = 0; j < row_len; ++j) d[j] = table[s[j]];
+    }
 }
 
 }  // namespace dnatok

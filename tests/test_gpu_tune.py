@@ -52,6 +52,45 @@ def test_every_kmer_tiling_matches_oracle(k):
     assert np.array_equal(ids.cpu().numpy(), want_ids)
 
 
+def test_ticketed_tiles_match_oracle():
+    """Batches with more tiles than resident workgroups, cut with ticketed
+    tiles (spread > 0): one and four vocabularies, PADDED (row scans fused
+    into the launch) and PACKED, launched back to back (the ticket counter
+    resets itself between launches)."""
+    torch = _torch()
+    data, offs = synth.workload_markov_batch(3000, 8192)
+    data[::7919] = ord("x")
+    d_in, d_off = _dev(data), _dev(offs)
+    ks = (3, 4, 5, 6)
+    vs = [dt.Vocab(dt.KMER, k=k) for k in ks]
+    want = {k: oracle.encode_threads(dt.KMER, data, offs, k=k, add_cls_sep=True) for k in ks}
+    for tile in (4096, 16384):
+        for sp in (10, 100):
+            print("ticketed tiles: tile=%d spread=%d" % (tile, sp), flush=True)
+            for v in vs:
+                dt.set_tuning(v, tile_bytes=tile, spread=sp)
+            for rep in range(2):
+                outs = dt.encode_multi(vs, d_in, d_off, h_offsets=offs, add_cls_sep=True, layout=dt.PADDED)
+                torch.cuda.synchronize()
+                assert dt.sync_status() == 0
+                for k, (ids, oo, mask) in zip(ks, outs):
+                    w_ids, w_off = want[k]
+                    wp, wm = oracle.pad_threads(w_ids, w_off, int(np.diff(w_off).max()))
+                    assert np.array_equal(oo.cpu().numpy(), w_off)
+                    assert np.array_equal(ids.cpu().numpy(), wp) and np.array_equal(mask.cpu().numpy(), wm)
+            ids, oo, _ = dt.encode(vs[1], d_in, d_off, h_offsets=offs, add_cls_sep=True)
+            torch.cuda.synchronize()
+            assert dt.sync_status() == 0
+            assert np.array_equal(oo.cpu().numpy(), want[4][1]) and np.array_equal(ids.cpu().numpy(), want[4][0])
+    single = dt.Vocab(dt.SINGLE)
+    dt.set_tuning(single, tile_bytes=8192, spread=25)
+    w_ids, w_off = oracle.encode_threads(dt.SINGLE, data, offs, add_cls_sep=True)
+    ids, oo, _ = dt.encode(single, d_in, d_off, h_offsets=offs, add_cls_sep=True)
+    torch.cuda.synchronize()
+    assert dt.sync_status() == 0
+    assert np.array_equal(oo.cpu().numpy(), w_off) and np.array_equal(ids.cpu().numpy(), w_ids)
+
+
 def test_every_bpe_tiling_matches_oracle():
     torch = _torch()
     corpus = synth.bpe_corpus(n=1 << 20, seed=synth.substream(92, 0))
@@ -76,7 +115,7 @@ def test_every_bpe_tiling_matches_oracle():
 def test_bad_tuning_is_rejected():
     v = dt.Vocab(dt.KMER, k=3)
     for kw in ({"tile_bytes": 5000}, {"tile_bytes": 1 << 20}, {"blocks_per_cu": -1}, {"bpe_item_bytes": 512},
-               {"bpe_max_waves": 3}):
+               {"bpe_max_waves": 3}, {"spread": -1}, {"spread": 101}):
         with pytest.raises(dt.DnatokError) as e:
             dt.set_tuning(v, **kw)
         assert e.value.code == dt.EINVAL
