@@ -607,6 +607,30 @@ def decode_leg(data, offs, reps: int = 10):
 BPE_TABLE = os.path.join(ROOT, "tests", "golden", "bpe4096_order5_64M.txt")
 
 
+def _bpe_rounds(ids, out_off, merges):
+    """Merge rounds per row, from the output alone: a round applies one
+    rank, and every rank applied to a row is in the merge tree of one of its
+    final tokens (a merged symbol either survives or is merged again), so
+    the rounds are the distinct merge ids over the rows' token trees."""
+    R = len(merges)
+    tree = [None] * R
+    for r in range(R):
+        t = {r}
+        for x in merges[r]:
+            if x >= 10:
+                t |= tree[x - 10]
+        tree[r] = frozenset(t)
+    n = len(out_off) - 1
+    rounds = np.zeros(n, dtype=np.int64)
+    for i in range(n):
+        row = np.unique(ids[out_off[i]:out_off[i + 1]])
+        seen = set()
+        for x in row[row >= 10]:
+            seen |= tree[int(x) - 10]
+        rounds[i] = len(seen)
+    return rounds
+
+
 def bpe_leg(reps: int = 10, tuning=None, per_seq_leg: bool = True):
     """Ragged BPE batch: 1,024 sequences, lengths log-uniform in [500, 20000]
     bases, fresh walk of the order-5 Markov chain the 4096-merge table was
@@ -658,16 +682,27 @@ def bpe_leg(reps: int = 10, tuning=None, per_seq_leg: bool = True):
     torch.cuda.synchronize()
     fused_ms = float(np.median([a.elapsed_time(b) for a, b in evs]))
 
+    rounds = _bpe_rounds(ids[:tokens].cpu().numpy(), h_oo, merges)
     out = {
         "workload": "1024 sequences, log-uniform 500-20000 bases (%d bases), order-5 Markov, BPE 4096 merges "
                     "(oracle trainer, 64 Mbase), PACKED, no specials" % nbytes,
         "tokens": tokens,
+        "rounds_per_row": {
+            "note": "merge rounds each row needs (distinct ranks in its tokens' merge trees; every row is one "
+                    "ACGT run, so one item); the fused call's critical path is the row with the most",
+            "max": int(rounds.max()), "p50": float(np.median(rounds)), "p90": float(np.percentile(rounds, 90)),
+            "mean": float(rounds.mean()),
+            "hist_edges": [0, 100, 200, 400, 800, 1200, 1600, 2400],
+            "hist": np.histogram(rounds, bins=[0, 100, 200, 400, 800, 1200, 1600, 2400])[0].tolist(),
+            "longest_row_bases": int(np.diff(offs)[int(np.argmax(rounds))]),
+        },
         ("autotuned" if tuning is None else "tiling"): {"bpe_item_bytes": tune["bpe_item_bytes"],
                                                         "bpe_max_waves": tune["bpe_max_waves"]},
         "fused_ms": round(fused_ms, 4),
         "fused_tokens_per_s": tokens / (fused_ms * 1e-3),
         "fused_bases_per_s": nbytes / (fused_ms * 1e-3),
     }
+    out["us_per_round_on_critical_path"] = round(fused_ms * 1e3 / max(1, int(rounds.max())), 3)
     if not per_seq_leg:
         log("bpe: fused %.3f ms (%.3e tokens/s)" % (fused_ms, out["fused_tokens_per_s"]))
         return out, data, offs, merges

@@ -446,6 +446,9 @@ typedef struct dnatok_tuning {
                                1..100 = one tile per workgroup: the first resident round by workgroup
                                index, the rest from a ticket counter, with this percentage of the tiles
                                as extra workgroups, so the parts of the chip that finish early take more */
+    int32_t bands;          /* SINGLE/LUT256/KMER, PADDED layout: 0 = default, 1 = row bands (a workgroup
+                               stages the bytes of a few whole rows, at most tile_bytes, and writes all
+                               their cells; used when pad_to admits such rows), 2 = tiles */
 } dnatok_tuning;
 
 int dnatok_get_tuning(const dnatok_vocab *v, dnatok_tuning *out);

@@ -88,6 +88,7 @@ class dnatok_tuning(ctypes.Structure):
         ("bpe_item_bytes", ctypes.c_int32),
         ("bpe_max_waves", ctypes.c_int32),
         ("spread", ctypes.c_int32),
+        ("bands", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -675,8 +676,9 @@ def dnatok_autotune(vocab, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d
     return t, ms.value
 
 
-def set_tuning(vocab: Vocab, tile_bytes=0, blocks_per_cu=0, bpe_item_bytes=0, bpe_max_waves=0, spread=0):
-    dnatok_set_tuning(vocab.handle, dnatok_tuning(tile_bytes, blocks_per_cu, bpe_item_bytes, bpe_max_waves, spread))
+def set_tuning(vocab: Vocab, tile_bytes=0, blocks_per_cu=0, bpe_item_bytes=0, bpe_max_waves=0, spread=0, bands=0):
+    dnatok_set_tuning(vocab.handle, dnatok_tuning(tile_bytes, blocks_per_cu, bpe_item_bytes, bpe_max_waves, spread,
+                                                  bands))
 
 
 def autotune(vocab: Vocab, d_bytes, d_offsets, h_offsets=None, add_cls_sep=False, layout=PACKED, pad_side=PAD_RIGHT,

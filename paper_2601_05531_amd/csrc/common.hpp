@@ -86,7 +86,7 @@ struct BpeTables {
 struct dnatok_vocab {
     // Scheduling knobs (dnatok_set_tuning / dnatok_autotune); 0 = default.
     // They change how work is tiled, never the ids.
-    std::atomic<int32_t> tune_tile{0}, tune_blocks{0}, tune_item{0}, tune_waves{0}, tune_spread{0};
+    std::atomic<int32_t> tune_tile{0}, tune_blocks{0}, tune_item{0}, tune_waves{0}, tune_spread{0}, tune_bands{0};
     int32_t kind = 0;
     int32_t k = 1;
     int32_t pad_id = DNATOK_ID_PAD, cls_id = DNATOK_ID_CLS, sep_id = DNATOK_ID_SEP;
@@ -141,6 +141,7 @@ struct EncodeTuning {
     int64_t tile_bytes;  // bytes of input per tile (multiple of 16)
     int blocks_per_cu;   // 0 = as many as occupancy allows
     int spread;          // 0 = static walkers; > 0: ticketed tiles plus this percentage of extra workgroups
+    int bands;           // PADDED: 0 = default, 1 = row bands, 2 = tiles
 };
 EncodeTuning encode_tuning(const dnatok_vocab *v, int64_t nbytes);
 constexpr int32_t kBpeItemBytesDefault = 8192;  // nominal BPE item length S
@@ -153,6 +154,14 @@ int launch_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes,
 // One pass over the input writing the same batch for several vocabularies of
 // one kind (SINGLE/LUT256: one; KMER: up to 8, any k), options alike but for
 // pad_to and offset_base.
+// PADDED encode by row bands (bands.hip). Launches and sets *used when the
+// batch suits bands (every row pad_to admits fits stage_bytes), else leaves
+// *used false and launches nothing.
+int launch_encode_bands(const dnatok_vocab *const *vs, int nv, const uint8_t *d_bytes, int64_t nbytes,
+                        const int64_t *d_offsets, int32_t n, int32_t *const *d_ids, const int64_t *caps,
+                        int8_t *const *d_masks, const dnatok_encode_opts *os, int64_t stage_bytes,
+                        int64_t *const *d_out_offsets, hipStream_t stream, bool *used);
+
 int launch_encode_multi(const dnatok_vocab *const *vs, int nv, const uint8_t *d_bytes, int64_t nbytes,
                         const int64_t *d_offsets, int32_t n, int32_t *const *d_ids, const int64_t *caps,
                         int64_t *const *d_out_offsets, int8_t *const *d_masks, const dnatok_encode_opts *os,

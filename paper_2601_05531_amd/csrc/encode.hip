@@ -979,6 +979,7 @@ EncodeTuning encode_tuning(const dnatok_vocab *v, int64_t nbytes) {
     }
     t.blocks_per_cu = v->tune_blocks.load(std::memory_order_relaxed);
     t.spread = v->tune_spread.load(std::memory_order_relaxed);
+    t.bands = v->tune_bands.load(std::memory_order_relaxed);
     return t;
 }
 
@@ -991,6 +992,12 @@ int launch_encode_multi(const dnatok_vocab *const *vs, int nv, const uint8_t *d_
     const dnatok_encode_opts &o = os[0];
     const bool kmer = (v->kind == DNATOK_KMER);
     const EncodeTuning tune = encode_tuning(v, nbytes);
+    if (o.layout == DNATOK_PADDED && tune.bands == 1) {
+        bool used = false;
+        int rc = launch_encode_bands(vs, nv, d_bytes, nbytes, d_offsets, n, d_ids, caps, d_masks, os,
+                                     tune.tile_bytes, d_out_offsets, stream, &used);
+        if (rc || used) return rc;
+    }
     int U = 1;  // staging loads per thread: tiles are U * NT * 16 bytes
     while (U < 16 && (int64_t)U * NT * 16 < tune.tile_bytes) U <<= 1;
     const int64_t B = (int64_t)U * NT * 16;

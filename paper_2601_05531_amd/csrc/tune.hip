@@ -26,6 +26,7 @@ int check_tuning(const dnatok_tuning &t) {
         t.bpe_max_waves != 8)
         return set_error(DNATOK_EINVAL, "bpe_max_waves must be 0, 1, 2, 4 or 8");
     if (t.spread < 0 || t.spread > 100) return set_error(DNATOK_EINVAL, "spread must be 0..100");
+    if (t.bands < 0 || t.bands > 2) return set_error(DNATOK_EINVAL, "bands must be 0, 1 or 2");
     return DNATOK_OK;
 }
 
@@ -35,6 +36,7 @@ void store(dnatok_vocab *v, const dnatok_tuning &t) {
     v->tune_item.store(t.bpe_item_bytes, std::memory_order_relaxed);
     v->tune_waves.store(t.bpe_max_waves, std::memory_order_relaxed);
     v->tune_spread.store(t.spread, std::memory_order_relaxed);
+    v->tune_bands.store(t.bands, std::memory_order_relaxed);
 }
 
 dnatok_tuning load(const dnatok_vocab *v) {
@@ -44,6 +46,7 @@ dnatok_tuning load(const dnatok_vocab *v) {
     t.bpe_item_bytes = v->tune_item.load(std::memory_order_relaxed);
     t.bpe_max_waves = v->tune_waves.load(std::memory_order_relaxed);
     t.spread = v->tune_spread.load(std::memory_order_relaxed);
+    t.bands = v->tune_bands.load(std::memory_order_relaxed);
     return t;
 }
 
@@ -87,12 +90,12 @@ int autotune_loop(dnatok_vocab *v, hipStream_t st, int32_t reps, Run run, dnatok
     std::vector<dnatok_tuning> cand;
     if (v->kind == DNATOK_BPE) {
         for (int32_t S : {2048, 4096, 8192, 16384, 32768})
-            for (int32_t w : {8, 4, 2, 1}) cand.push_back(dnatok_tuning{0, 0, S, w, 0});
+            for (int32_t w : {8, 4, 2, 1}) cand.push_back(dnatok_tuning{0, 0, S, w, 0, 0});
     } else {
         for (int32_t tile : {4096, 8192, 16384, 32768, 65536})
-            for (int32_t b : {0, 1, 2, 4}) cand.push_back(dnatok_tuning{tile, b, 0, 0, 0});
+            for (int32_t b : {0, 1, 2, 4}) cand.push_back(dnatok_tuning{tile, b, 0, 0, 0, 0});
         for (int32_t tile : {4096, 8192, 16384})
-            for (int32_t sp : {10, 25, 50}) cand.push_back(dnatok_tuning{tile, 0, 0, 0, sp});
+            for (int32_t sp : {10, 25, 50}) cand.push_back(dnatok_tuning{tile, 0, 0, 0, sp, 0});
     }
     const dnatok_tuning saved = load(v);
     hipEvent_t e0 = nullptr, e1 = nullptr;
