@@ -196,6 +196,28 @@ int dnatok_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes,
                   const dnatok_encode_opts *opts, void *stream);
 
 /*
+ * dnatok_encode for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Arguments, outputs and errors are those of dnatok_encode (every kind,
+ * layout and variant; the same kernels), but the call allocates nothing:
+ * the scan counters, status words and multi-pass scratch the kernels need
+ * live in one fixed 32 MiB device array per GPU, part of the library's code
+ * object, held from the first call on that GPU until the process ends. A
+ * batch whose needs exceed it fails with DNATOK_EBUDGET before anything is
+ * enqueued: more than 16,384 scan tiles (about 67 million rows), or, for
+ * BPE, more scratch than the array holds (about 4 bytes per input byte plus
+ * 48 per row: batches up to about 8 million bases). Every call on a GPU shares that
+ * GPU's array: calls that overlap on one GPU (on different streams, or from
+ * different threads) race and give wrong results; order them. Device-side
+ * error flags of these calls are reported by dnatok_sync_status on any
+ * stream of the device. The first call on a GPU also enqueues a small kernel
+ * on `stream` that clears the array's counters.
+ */
+int dnatok_encode_noalloc(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets,
+                          int32_t n, int32_t *d_ids, int64_t ids_capacity, int64_t *d_out_offsets, int8_t *d_mask,
+                          const dnatok_encode_opts *opts, void *stream);
+
+/*
  * Encode one ragged batch for several k-mer vocabularies (any k, 1..8 of
  * them) in a single pass over its bytes: each tile is read and classified
  * once and every vocabulary's ids (and mask) are written from it. The

@@ -185,6 +185,8 @@ def lib():
                                          ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.dnatok_encode.argtypes = [vp, vp, i64, vp, i32, vp, i64, vp, vp,
                                     ctypes.POINTER(dnatok_encode_opts), vp]
+        L.dnatok_encode_noalloc.argtypes = [vp, vp, i64, vp, i32, vp, i64, vp, vp,
+                                            ctypes.POINTER(dnatok_encode_opts), vp]
         L.dnatok_sync_status.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32)]
         L.dnatok_encode_multi.argtypes = [vp, i32, vp, i64, vp, i32, vp, vp, vp, vp, vp, vp]
         L.dnatok_autotune_multi.argtypes = [vp, i32, vp, i64, vp, i32, vp, vp, vp, vp, vp, vp, i32,
@@ -226,7 +228,7 @@ def lib():
                      "dnatok_server_release", "dnatok_server_stats", "dnatok_server_destroy", "dnatok_get_tuning",
                      "dnatok_set_tuning", "dnatok_autotune", "dnatok_graph_create", "dnatok_graph_launch",
                      "dnatok_graph_destroy", "dnatok_encode_multi", "dnatok_autotune_multi", "dnatok_embed",
-                     "dnatok_embed_ids", "dnatok_ids_create", "dnatok_ids_run",
+                     "dnatok_embed_ids", "dnatok_encode_noalloc", "dnatok_ids_create", "dnatok_ids_run",
                      "dnatok_ids_destroy", "dnatok_ids_map"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -277,6 +279,12 @@ def dnatok_encode(handle, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_
                   stream) -> int:
     return _check(lib().dnatok_encode(handle, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets,
                                       d_mask, ctypes.byref(opts), stream))
+
+
+def dnatok_encode_noalloc(handle, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets, d_mask, opts,
+                          stream) -> int:
+    return _check(lib().dnatok_encode_noalloc(handle, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity,
+                                              d_out_offsets, d_mask, ctypes.byref(opts), stream))
 
 
 def dnatok_embed(handle, d_bytes, nbytes, d_offsets, n, d_table, n_rows, row_bytes, d_out, out_rows, d_out_offsets,

@@ -114,7 +114,21 @@ static int grow_allowed(hipStream_t stream) {
     return DNATOK_OK;
 }
 
+namespace {
+thread_local Workspace *t_fixed_ws = nullptr;
+}  // namespace
+
+FixedWorkspaceScope::FixedWorkspaceScope(Workspace *ws) : prev_(t_fixed_ws) { t_fixed_ws = ws; }
+FixedWorkspaceScope::~FixedWorkspaceScope() { t_fixed_ws = prev_; }
+
 int get_workspace(hipStream_t stream, int64_t tiles, Workspace **out) {
+    if (t_fixed_ws) {
+        if (tiles > t_fixed_ws->cap)
+            return set_error(DNATOK_EBUDGET, "the batch needs %lld scan tiles, the fixed scratch holds %lld",
+                             (long long)tiles, (long long)t_fixed_ws->cap);
+        *out = t_fixed_ws;
+        return DNATOK_OK;
+    }
     int dev = 0;
     DNATOK_HIP(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lk(g_ws_mu);
@@ -159,6 +173,9 @@ int get_workspace(hipStream_t stream, int64_t tiles, Workspace **out) {
 
 int ensure_scratch(Workspace *ws, int64_t bytes) {
     if (bytes <= ws->scratch_bytes) return DNATOK_OK;
+    if (ws->fixed)
+        return set_error(DNATOK_EBUDGET, "the batch needs %lld bytes of scratch, the fixed scratch holds %lld",
+                         (long long)bytes, (long long)ws->scratch_bytes);
     int rc = grow_allowed(ws->stream);
     if (rc) return rc;
     int64_t nb = std::max<int64_t>(bytes, 2 * ws->scratch_bytes);
@@ -170,6 +187,85 @@ int ensure_scratch(Workspace *ws, int64_t bytes) {
     DNATOK_HIP(dev_alloc(&p, (size_t)nb));
     ws->d_scratch = static_cast<uint8_t *>(p);
     ws->scratch_bytes = nb;
+    return DNATOK_OK;
+}
+
+// ---- fixed scratch (dnatok_encode_noalloc) ---------------------------------------
+//
+// One array per device, allocated with the code object when it loads and held
+// until the process ends: a 256-byte header, the status words of both scan
+// parities, then the scratch of multi-pass kernels. In host code `scratch`
+// names a host-side stand-in, never the device array: every use goes through
+// the address hipGetSymbolAddress returns for the current device.
+constexpr size_t kFixedScratchBytes = (size_t)32 << 20;
+constexpr int64_t kFixedTiles = 16384;  // status words per parity
+constexpr size_t kFixedHeadBytes = 256 + (size_t)kFixedTiles * 2 * sizeof(uint64_t);
+static_assert(kFixedHeadBytes % 256 == 0, "the scratch area stays 256-byte aligned");
+static __device__ __align__(256) uint8_t scratch[kFixedScratchBytes];
+
+namespace {
+std::mutex g_fixed_mu;
+std::map<int, Workspace *> g_fixed;  // device -> its view of the array
+
+__global__ void k_zero_words(uint64_t *p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+}  // namespace
+
+// The fixed workspace of the current device. The first call on a device
+// resolves the array's device address (with that device current) and clears
+// the header and status words with a fill kernel on `stream`, which orders
+// the clear before the launches of the call that follows.
+static int fixed_workspace(hipStream_t stream, Workspace **out) {
+    int dev = 0;
+    DNATOK_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_fixed_mu);
+    auto it = g_fixed.find(dev);
+    if (it != g_fixed.end()) {
+        *out = it->second;
+        return DNATOK_OK;
+    }
+    uint8_t *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(reinterpret_cast<void **>(&ptr), HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return set_error(DNATOK_EDEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                         hipGetErrorString(e));
+    hipLaunchKernelGGL(k_zero_words, dim3(64), dim3(256), 0, stream, reinterpret_cast<uint64_t *>(ptr),
+                       (int64_t)(kFixedHeadBytes / sizeof(uint64_t)));
+    DNATOK_HIP(hipGetLastError());
+    std::unique_ptr<Workspace> ws(new Workspace());
+    ws->device = dev;
+    ws->stream = nullptr;
+    ws->d_hdr = reinterpret_cast<uint32_t *>(ptr);
+    ws->d_status = reinterpret_cast<uint64_t *>(ptr + 256);
+    ws->cap = kFixedTiles;
+    ws->high_water = 0;
+    ws->d_scratch = ptr + kFixedHeadBytes;
+    ws->scratch_bytes = (int64_t)(kFixedScratchBytes - kFixedHeadBytes);
+    ws->fixed = true;
+    *out = ws.get();
+    g_fixed[dev] = ws.release();
+    return DNATOK_OK;
+}
+
+// Device flags raised by fixed-scratch calls on the current device (cleared).
+static int take_fixed_flags(hipStream_t s, uint32_t *flags) {
+    int dev = 0;
+    DNATOK_HIP(hipGetDevice(&dev));
+    Workspace *ws = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_fixed_mu);
+        auto it = g_fixed.find(dev);
+        if (it != g_fixed.end()) ws = it->second;
+    }
+    *flags = 0;
+    if (!ws) return DNATOK_OK;
+    DNATOK_HIP(hipMemcpy(flags, ws->d_hdr + HDR_ERR, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    if (*flags) {
+        DNATOK_HIP(hipMemsetAsync(ws->d_hdr + HDR_ERR, 0, sizeof(uint32_t), s));
+        DNATOK_HIP(hipStreamSynchronize(s));
+    }
     return DNATOK_OK;
 }
 
@@ -377,6 +473,27 @@ int dnatok_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes,
                          static_cast<hipStream_t>(stream));
 }
 
+int dnatok_encode_noalloc(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets,
+                          int32_t n, int32_t *d_ids, int64_t ids_capacity, int64_t *d_out_offsets, int8_t *d_mask,
+                          const dnatok_encode_opts *opts, void *stream) {
+    dnatok_encode_opts o = {};
+    if (opts) o = *opts;
+    int rc = check_encode(v, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets, d_mask, o);
+    if (rc) return rc;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    Workspace *ws = nullptr;
+    rc = fixed_workspace(s, &ws);
+    if (rc) return rc;
+    clear_error();
+    FixedWorkspaceScope scope(ws);
+    if (v->kind == DNATOK_BPE)
+        return launch_bpe_encode(v, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets, d_mask, o, s);
+    if (o.variant)
+        return launch_encode_variant(v, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets, d_mask, o,
+                                     s);
+    return launch_encode(v, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets, d_mask, o, s);
+}
+
 int dnatok_encode_multi(const dnatok_vocab *const *vocabs, int32_t n_vocabs, const uint8_t *d_bytes, int64_t nbytes,
                         const int64_t *d_offsets, int32_t n, int32_t *const *d_ids, const int64_t *ids_capacity,
                         int64_t *const *d_out_offsets, int8_t *const *d_mask, const dnatok_encode_opts *opts,
@@ -456,7 +573,10 @@ int dnatok_sync_status(void *stream, uint32_t *flags) {
         DNATOK_HIP(hipMemsetAsync(ws->d_hdr + HDR_ERR, 0, sizeof(uint32_t), s));
         DNATOK_HIP(hipStreamSynchronize(s));
     }
-    if (flags) *flags = f;
+    uint32_t ff = 0;
+    int rc = take_fixed_flags(s, &ff);
+    if (rc) return rc;
+    if (flags) *flags = f | ff;
     return DNATOK_OK;
 }
 

@@ -121,13 +121,29 @@ struct Workspace {
     int64_t high_water = 0;        // tiles that may hold non-zero status
     uint8_t *d_scratch = nullptr;  // general scratch for multi-pass kernels (BPE)
     int64_t scratch_bytes = 0;
+    bool fixed = false;            // lives in the library's fixed device array: never grows
 };
 
 // Workspace for (current device, stream) with room for `tiles` tiles, grown
-// (synchronously, outside graph capture) when needed.
+// (synchronously, outside graph capture) when needed. While a
+// FixedWorkspaceScope is open on the calling thread, every launcher gets that
+// fixed workspace instead, and a request beyond its size fails with EBUDGET
+// (nothing is allocated).
 int get_workspace(hipStream_t stream, int64_t tiles, Workspace **out);
-// Ensure the workspace scratch holds at least `bytes` bytes.
+// Ensure the workspace scratch holds at least `bytes` bytes (a fixed
+// workspace: EBUDGET when it does not).
 int ensure_scratch(Workspace *ws, int64_t bytes);
+// Routes the calling thread's launches to `ws` until the scope ends.
+class FixedWorkspaceScope {
+  public:
+    explicit FixedWorkspaceScope(Workspace *ws);
+    ~FixedWorkspaceScope();
+    FixedWorkspaceScope(const FixedWorkspaceScope &) = delete;
+    FixedWorkspaceScope &operator=(const FixedWorkspaceScope &) = delete;
+
+  private:
+    Workspace *prev_;
+};
 // Workspace of (current device, stream) if one exists.
 Workspace *find_workspace(hipStream_t stream);
 // Free the workspace of (current device, stream); the stream must be idle.
