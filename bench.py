@@ -122,7 +122,9 @@ def encode_leg(steps: int, warmup: int, tuning=None, per_vocab: bool = True):
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(),
-            "kernel": "k_cells<KMER> writing k = 3, 4, 5, 6 in one pass",
+            "kernel": ("k_bands<KMER> (row bands, %d-byte stage)" % tune_multi["tile_bytes"]
+                       if tune_multi.get("bands") == 1 else "k_cells<KMER> (tiles)") +
+                      " writing k = 3, 4, 5, 6 in one pass",
             "per_launch_bytes": "1 B per input byte (read once) + 16 B per row of offsets + per vocabulary "
                                 "5 B per cell (4 B id + 1 B mask over n x pad_to) = %d B" % bytes_launch,
         },
@@ -524,6 +526,8 @@ def cellwise_leg(data, offs, reps: int = 10):
         else:
             ids = torch.empty(cells, dtype=torch.int32, device="cuda")
             out_bytes = cells * 5
+            tuned, _ = dt.autotune(v, d_in, d_off, h_offsets=offs, add_cls_sep=True, layout=dt.PADDED, pad_to=W,
+                                   variant=variant)
 
             def call():
                 dt.dnatok_encode(v.handle, d_in.data_ptr(), data.size, d_off.data_ptr(), n, ids.data_ptr(), cells,
@@ -543,6 +547,8 @@ def cellwise_leg(data, offs, reps: int = 10):
         gbps = alg / (ms * 1e-3) / 1e9
         out[name] = {"ms": round(ms, 4), "cells": cells, "cells_per_s": cells / (ms * 1e-3),
                      "algorithmic_bytes": alg, "GBps": round(gbps, 1), "frac_hbm_peak": round(gbps / HBM_PEAK_GBS, 3)}
+        if not V:
+            out[name]["autotuned"] = {"tile_bytes": tuned["tile_bytes"], "bands": tuned["bands"]}
         log("%s: %.3f ms, %.3e cells/s, %.0f GB/s (%.2f of peak)" % (name, ms, cells / (ms * 1e-3), gbps,
                                                                      gbps / HBM_PEAK_GBS))
         del call

@@ -690,14 +690,14 @@ def set_tuning(vocab: Vocab, tile_bytes=0, blocks_per_cu=0, bpe_item_bytes=0, bp
 
 
 def autotune(vocab: Vocab, d_bytes, d_offsets, h_offsets=None, add_cls_sep=False, layout=PACKED, pad_side=PAD_RIGHT,
-             pad_to=None, reps=3, stream=None):
+             pad_to=None, reps=3, stream=None, variant=0):
     """Time every candidate tiling on this batch and keep the fastest in the
     vocabulary. Returns (tuning dict, median ms)."""
     import torch
     n = d_offsets.numel() - 1
     if h_offsets is None:
         h_offsets = d_offsets.cpu().numpy()
-    total, max_len = plan(vocab, h_offsets, add_cls_sep)
+    total, max_len = plan(vocab, h_offsets, add_cls_sep, variant)
     if layout == PADDED:
         W = max_len if pad_to is None else int(pad_to)
         cap = n * W
@@ -707,8 +707,8 @@ def autotune(vocab: Vocab, d_bytes, d_offsets, h_offsets=None, add_cls_sep=False
     oo = torch.empty(n + 1, dtype=torch.int64, device=d_bytes.device)
     mask = torch.empty(max(cap, 1), dtype=torch.int8, device=d_bytes.device) if layout == PADDED else None
     t, ms = dnatok_autotune(vocab.handle, _ptr(d_bytes), d_bytes.numel(), _ptr(d_offsets), n, _ptr(ids), ids.numel(),
-                            _ptr(oo), _ptr(mask), make_opts(add_cls_sep, layout, pad_side, W), _stream_ptr(stream),
-                            reps)
+                            _ptr(oo), _ptr(mask), make_opts(add_cls_sep, layout, pad_side, W, variant=variant),
+                            _stream_ptr(stream), reps)
     return t.as_dict(), ms
 
 

@@ -51,6 +51,8 @@ struct BandArgs {
     int32_t n;
     int32_t nv;
     int32_t cls, left;
+    int32_t overlap;       // KMER: stride-1 windows (L - k + 1 of them; one UNK for 0 < L < k)
+    int32_t revcomp;       // encode each row's reverse complement
     int32_t R;             // rows per band
     int32_t stage_chunks;  // 16-byte chunks the LDS stage holds
     int64_t nbands;
@@ -73,9 +75,10 @@ __device__ __forceinline__ uint32_t umod_w(uint32_t x, uint32_t W, uint32_t winv
     return r;
 }
 
-// Digits (most significant first) and validity of k bytes read one by one
-// from global memory, positions clamped to the input (slow path).
-__device__ __forceinline__ int32_t kmer_global(const BandArgs &a, int64_t pos, int32_t k) {
+// Digits (most significant first) of k bytes read one by one from global
+// memory, positions clamped to the input (slow path); -1 if any byte is not
+// A/C/G/T in either case.
+__device__ __forceinline__ int64_t kmer_global(const BandArgs &a, int64_t pos, int32_t k) {
     uint32_t v = 0;
     bool ok = true;
     for (int32_t j = 0; j < k; ++j) {
@@ -86,39 +89,119 @@ __device__ __forceinline__ int32_t kmer_global(const BandArgs &a, int64_t pos, i
         ok = ok && d >= 0;
         v = (v << 2) | (uint32_t)(d & 3);
     }
-    return ok ? (int32_t)(5 + v) : DNATOK_ID_UNK;
+    return ok ? (int64_t)v : -1;
 }
 
-// Ids of k-mers from the staged windows (as the tile kernel stages them):
-// win64[m] holds the digits of chunks m and m + 1, val32[m] their validity.
-__device__ __forceinline__ int32_t kmer_lds(const uint64_t *win64, const uint32_t *val32, uint32_t idx, int32_t k) {
+// The k 2-bit digits of v in reverse order (k <= 16).
+__device__ __forceinline__ uint32_t rev_digits(uint32_t v, int32_t k) {
+    uint32_t r = __builtin_bitreverse32(v);
+    r = ((r >> 1) & 0x55555555u) | ((r & 0x55555555u) << 1);
+    return r >> (32 - 2 * k);
+}
+
+// Id of a k-mer whose forward digits are fv (or -1: a byte outside ACGT);
+// the reverse complement reverses and complements the digits.
+__device__ __forceinline__ int32_t kmer_id(int64_t fv, int32_t k, bool rc) {
+    if (fv < 0) return DNATOK_ID_UNK;
+    const uint32_t dm = (1u << (2 * k)) - 1u;
+    return 5 + (int32_t)(rc ? (rev_digits((uint32_t)fv, k) ^ dm) : (uint32_t)fv);
+}
+
+__device__ __forceinline__ uint32_t complement_byte(uint32_t b) {
+    switch (b) {
+    case 'A': return 'T';
+    case 'T': return 'A';
+    case 'C': return 'G';
+    case 'G': return 'C';
+    case 'a': return 't';
+    case 't': return 'a';
+    case 'c': return 'g';
+    case 'g': return 'c';
+    default: return b;
+    }
+}
+
+// Forward digits of the k-mer at staged byte idx (staged windows as the
+// tile kernel stages them: win64[m] holds the digits of chunks m and m + 1,
+// val32[m] their validity), or -1 if a byte is not A/C/G/T.
+__device__ __forceinline__ int64_t kmer_lds(const uint64_t *win64, const uint32_t *val32, uint32_t idx, int32_t k) {
     const uint32_t w = idx >> 4, o = idx & 15;
     const uint32_t digits = (uint32_t)(win64[w] >> (64 - 2 * (o + (uint32_t)k))) & ((1u << (2 * k)) - 1);
     const uint32_t km = (1u << k) - 1;
     const bool ok = ((val32[w] >> (32 - o - (uint32_t)k)) & km) == km;
-    return ok ? (int32_t)(5 + digits) : DNATOK_ID_UNK;
+    return ok ? (int64_t)digits : -1;
 }
 
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-// Four consecutive k-mers (k <= 8) from staged byte idx0 on.
-__device__ __forceinline__ i32x4 kmer4_lds(const uint64_t *win64, const uint32_t *val32, uint32_t idx0, int32_t k) {
+// Four ids from the 32 staged bases starting at byte idx0: id q is the
+// k-mer whose forward digits start at base p0 + q * dp of that window
+// (p0 + 3 * dp + k <= 32), reverse complemented if rc.
+__device__ __forceinline__ i32x4 kmer4_lds(const uint64_t *win64, const uint32_t *val32, uint32_t idx0, int32_t k,
+                                           int32_t p0, int32_t dp, bool rc) {
     const uint32_t w = idx0 >> 4, o = idx0 & 15;
     const uint64_t w0 = win64[w], w1 = win64[w + 1];
     const uint32_t v0 = val32[w], v1 = val32[w + 1];
     const uint64_t X = (w0 << (2 * o)) | (((uint64_t)(uint32_t)w1 << (2 * o)) >> 32);
     const uint32_t nV = ~(uint32_t)((((uint64_t)v0 << 32) | (uint64_t)(v1 << 16)) << o >> 32);
     const uint32_t dm = (1u << (2 * k)) - 1u;
+    const uint32_t km = (1u << k) - 1u;
     i32x4 r;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const uint32_t sh = 64u - 2u * (uint32_t)(k * (q + 1));
-        const uint32_t vm = ((1u << k) - 1u) << (32 - k * (q + 1));
-        const int32_t id = 5 + (int32_t)((uint32_t)(X >> sh) & dm);
-        r[q] = (nV & vm) == 0 ? id : DNATOK_ID_UNK;
+        const int32_t p = p0 + q * dp;
+        const uint32_t fv = (uint32_t)(X >> (64 - 2 * (p + k))) & dm;
+        const bool bad = ((nV >> (32 - p - k)) & km) != 0;
+        r[q] = bad ? DNATOK_ID_UNK : 5 + (int32_t)(rc ? (rev_digits(fv, k) ^ dm) : fv);
     }
     return r;
+}
+
+// Row scan of one vocabulary's token counts by one workgroup (the fused
+// PADDED case, a few thousand rows), four rows per thread per pass: the same
+// validation and totals as the stand-alone scan, in few registers, so the
+// band workgroups that share the kernel keep their occupancy.
+__device__ void band_rowscan(const RowScanArgs &a, int64_t *s_tmp, uint32_t *err_hdr) {
+    constexpr int RPT = 4;
+    uint32_t err = 0;
+    int64_t run = 0;
+    for (int64_t row0 = 0; row0 < a.n; row0 += (int64_t)NTB * RPT) {
+        const int64_t i0 = row0 + (int64_t)threadIdx.x * RPT;
+        int64_t off[RPT + 1];
+#pragma unroll
+        for (int j = 0; j <= RPT; ++j) off[j] = a.offs[i0 + j < a.n ? i0 + j : a.n];
+        int64_t len[RPT];
+        int64_t mine = 0;
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            len[j] = 0;
+            if (i0 + j < a.n) {
+                int64_t o0 = off[j], o1 = off[j + 1];
+                if (o0 < 0 || o1 < o0 || o1 > a.nbytes) err |= DNATOK_DERR_OFFSETS;
+                o0 = o0 < 0 ? 0 : (o0 > a.nbytes ? a.nbytes : o0);
+                o1 = o1 < o0 ? o0 : (o1 > a.nbytes ? a.nbytes : o1);
+                const int64_t L = o1 - o0;
+                const int64_t nb = !a.kmer ? L
+                                   : a.overlap ? (L >= a.k ? L - a.k + 1 : (L > 0 ? 1 : 0))
+                                               : div_k(L + a.k - 1, a.k, a.kinv);
+                const int64_t l = nb + 2 * a.cls;
+                if (l > a.W) err |= DNATOK_DERR_ROW_WIDTH;
+                len[j] = l;
+                mine += l;
+            }
+        }
+        int64_t tot;
+        int64_t pre = a.base + run + dev::block_excl_scan<NTB>(mine, s_tmp, &tot);
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            if (i0 + j < a.n) a.out_offs[i0 + j] = pre;
+            pre += len[j];
+        }
+        run += tot;
+    }
+    if (threadIdx.x == 0) a.out_offs[a.n] = a.base + run;
+    if (err) dev::raise_error(err_hdr, err);
 }
 
 template <bool KMER>
@@ -132,13 +215,13 @@ __global__ __launch_bounds__(NTB) void k_bands(BandArgs a) {
     __shared__ int64_t s_tmp[NTB / dev::kWave + 1];
     const int tid = threadIdx.x;
     if ((int)blockIdx.x < a.lead) {
-        if ((int)blockIdx.x < a.nscan) rowscan_single_block(a.scan[blockIdx.x], s_tmp, a.err_hdr);
+        if ((int)blockIdx.x < a.nscan) band_rowscan(a.scan[blockIdx.x], s_tmp, a.err_hdr);
         return;
     }
     const int64_t band = (int64_t)blockIdx.x - a.lead;
     const int64_t r0 = band * a.R;
     const int nr = (int)min((int64_t)a.R, (int64_t)a.n - r0);
-    if (!KMER) s_lut[tid] = a.lut[tid];
+    if (!KMER) s_lut[tid] = a.lut[a.revcomp ? complement_byte((uint32_t)tid) : (uint32_t)tid];
     // row byte ranges, validated and clamped as the row scan does
     if (tid < nr) {
         int64_t o0 = a.offs[r0 + tid], o1 = a.offs[r0 + tid + 1];
@@ -225,123 +308,112 @@ __global__ __launch_bounds__(NTB) void k_bands(BandArgs a) {
         const int vi = t / nr, r = t - vi * nr;
         const int64_t L = s_o1[r] - s_o0[r];
         const int32_t k = KMER ? a.vo[vi].k : 1;
-        s_nb[vi * kMaxBandRows + r] = (int32_t)(KMER ? div_k(L + k - 1, k, 0xFFFFFFFFu / (uint32_t)k) : L);
+        s_nb[vi * kMaxBandRows + r] = (int32_t)(!KMER ? L
+                                                : a.overlap ? (L >= k ? L - k + 1 : (L > 0 ? 1 : 0))
+                                                            : div_k(L + k - 1, k, 0xFFFFFFFFu / (uint32_t)k));
     }
     __syncthreads();
 
+    // Every vocabulary, every row of the band: the row's facts are uniform
+    // across the workgroup, so a store group inside the row's full frames
+    // costs one staged window read and the four ids; groups at the row's
+    // edges (CLS, SEP, the short final frame, pads, the neighbouring rows'
+    // cells) go cell by cell and store only this row's cells.
     for (int vi = 0; vi < a.nv; ++vi) {
         const BandVocab &o = a.vo[vi];
         const int32_t k = KMER ? o.k : 1;
-        const int64_t W = o.W;
-        const int64_t E0 = r0 * W, E1 = E0 + (int64_t)nr * W;  // this band's cells
-        const int64_t g0 = (E0 + o.al) >> 2, g1 = (E1 - 1 + o.al) >> 2;
+        const int32_t W = (int32_t)o.W;
         const bool mask4 = ((reinterpret_cast<uintptr_t>(o.mask) - (uintptr_t)o.al) & 3) == 0;
-        // id and mask of band cell f (row f / W, column f % W); m = 2 marks a
-        // row too long for pad_to, which writes nothing (the row scan raised
-        // the flag). body4: this cell and the next three are full body
-        // tokens of one row, the first at staged byte idx.
-        const int32_t W32 = (int32_t)W;
-        const int32_t *nbv = s_nb + vi * kMaxBandRows;
-        auto cell = [&](uint32_t f, int32_t &id, uint32_t &m, bool &body4, uint32_t &idx) {
-            uint32_t r;
-            const int32_t c = (int32_t)umod_w(f, (uint32_t)W, o.winv, &r);
-            const int32_t nb = nbv[r];
+        for (int r = 0; r < nr; ++r) {
+            const int32_t nb = __builtin_amdgcn_readfirstlane(s_nb[vi * kMaxBandRows + r]);
+            const int32_t L = __builtin_amdgcn_readfirstlane((int32_t)(s_o1[r] - s_o0[r]));
+            const uint32_t ro = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)s_ro[r]);
             const int32_t len = nb + 2 * a.cls;
-            const int32_t tt = c - (a.left ? W32 - len : 0);
-            id = o.pad_id;
-            m = 0;
-            body4 = false;
-            idx = 0;
-            if (len > W32) {
-                m = 2;
-                return;
-            }
-            if (tt < 0 || tt >= len) return;
-            m = 1;
-            if (a.cls && tt == 0) {
-                id = o.cls_id;
-            } else if (a.cls && tt == len - 1) {
-                id = o.sep_id;
-            } else {
-                const int32_t j = tt - a.cls;
-                const int64_t L = s_o1[r] - s_o0[r];
-                const bool tail = KMER && (int64_t)nb * k != L;
-                if (tail && j == nb - 1) {
-                    id = DNATOK_ID_UNK;
-                } else if (staged) {
-                    idx = s_ro[r] + (uint32_t)(j * k);
-                    id = KMER ? kmer_lds(win64, val32, idx, k) : s_lut[raw[idx]];
-                    body4 = j + 4 <= nb - (tail ? 1 : 0);
-                } else {
-                    const int64_t pos = s_o0[r] + (int64_t)j * k;
-                    id = KMER ? kmer_global(a, pos, k) : s_lut[a.abase[a.shift + pos]];
+            if (len > W) continue;  // too long for pad_to: the row writes nothing (the row scan raised the flag)
+            const int32_t lead = a.left ? W - len : 0;
+            // the one short token: a short final frame, or the single window of a row shorter than k
+            const bool tail = KMER && (a.overlap ? (L > 0 && L < k) : nb * k != L);
+            const int32_t st = (KMER && !a.overlap) ? k : 1;  // bytes between token starts
+            const int32_t bA = lead + a.cls;                 // first body cell
+            const int32_t bF = bA + nb - (tail ? 1 : 0);     // end of the full frames
+            const int64_t E0 = (r0 + r) * (int64_t)W;        // the row's first cell
+            const int64_t gf = (E0 + o.al) >> 2, gl = (E0 + W - 1 + o.al) >> 2;
+            for (int64_t g = gf + tid; g <= gl; g += NTB) {
+                const int64_t e = 4 * g - o.al;
+                const int32_t c0 = (int32_t)(e - E0);
+                int32_t *dst = o.ids + e;
+                if (c0 >= bA && c0 + 4 <= bF && staged && (!KMER || 3 * st + k <= 32)) {
+                    const int32_t j = c0 - bA;
+                    i32x4 y;
+                    if (KMER) {
+                        // tokens j .. j + 3 read one 32-base window: forward from
+                        // their first start, reverse complemented from the last
+                        // one's start (token j + q starts at L - (j + q) * st - k)
+                        y = a.revcomp ? kmer4_lds(win64, val32, ro + (uint32_t)(L - (j + 3) * st - k), k, 3 * st, -st, true)
+                                      : kmer4_lds(win64, val32, ro + (uint32_t)(j * st), k, 0, st, false);
+                    } else if (a.revcomp) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) y[q] = s_lut[raw[ro + (uint32_t)(L - 1 - j - q)]];
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) y[q] = s_lut[raw[ro + (uint32_t)(j + q)]];
+                    }
+                    __builtin_nontemporal_store(y, reinterpret_cast<i32x4 *>(dst));
+                    if (mask4)
+                        __builtin_nontemporal_store(0x01010101u, reinterpret_cast<uint32_t *>(o.mask + e));
+                    else
+                        for (int q = 0; q < 4; ++q) o.mask[e + q] = 1;
+                    continue;
                 }
-            }
-        };
-        for (int64_t g = g0 + tid; g <= g1; g += NTB) {
-            const int64_t e = 4 * g - o.al;
-            int32_t v[4];
-            uint32_t mk = 0;
-            bool in[4], all_in = true;
-            const bool inside = e >= E0 && e + 3 < E1;
-            int32_t id0 = 0;
-            uint32_t m0 = 0, idx0 = 0;
-            bool b4 = false;
-            if (inside) cell((uint32_t)(e - E0), id0, m0, b4, idx0);
-            if (b4 && (!KMER || k <= 8)) {
-                // four body tokens of one row from one staged read
-                if (KMER) {
-                    const i32x4 y = kmer4_lds(win64, val32, idx0, k);
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) v[q] = y[q];
-                } else {
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) v[q] = s_lut[raw[idx0 + q]];
-                }
-                mk = 0x01010101u;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) in[q] = true;
-            } else {
+                int32_t v[4];
+                uint32_t mk = 0;
+                bool in[4], all_in = true;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int64_t eq = e + q;
-                    in[q] = eq >= E0 && eq < E1;
-                    v[q] = o.pad_id;
-                    if (!in[q]) {
-                        all_in = false;
-                        continue;
-                    }
-                    int32_t id;
-                    uint32_t m, ix;
-                    bool bb;
-                    if (q == 0 && inside) {
-                        id = id0;
-                        m = m0;
-                    } else {
-                        cell((uint32_t)(eq - E0), id, m, bb, ix);
-                    }
-                    if (m == 2) {
-                        in[q] = false;
-                        all_in = false;
-                        continue;
+                    const int32_t c = c0 + q;
+                    in[q] = c >= 0 && c < W;
+                    all_in = all_in && in[q];
+                    int32_t id = o.pad_id;
+                    uint32_t m = 0;
+                    const int32_t tt = c - lead;
+                    if (in[q] && tt >= 0 && tt < len) {
+                        m = 1;
+                        if (a.cls && tt == 0) {
+                            id = o.cls_id;
+                        } else if (a.cls && tt == len - 1) {
+                            id = o.sep_id;
+                        } else {
+                            const int32_t j = tt - a.cls;
+                            // first byte of token j (of its mirror window when reverse complemented)
+                            const int32_t b0 = !a.revcomp ? j * st : (KMER ? L - j * st - k : L - 1 - j);
+                            if (tail && j == nb - 1) {
+                                id = DNATOK_ID_UNK;
+                            } else if (staged) {
+                                const uint32_t idx = ro + (uint32_t)b0;
+                                id = KMER ? kmer_id(kmer_lds(win64, val32, idx, k), k, a.revcomp) : s_lut[raw[idx]];
+                            } else {
+                                const int64_t pos = s_o0[r] + b0;
+                                id = KMER ? kmer_id(kmer_global(a, pos, k), k, a.revcomp)
+                                          : s_lut[a.abase[a.shift + pos]];
+                            }
+                        }
                     }
                     v[q] = id;
                     mk |= m << (8 * q);
                 }
-            }
-            int32_t *dst = o.ids + e;
-            if (all_in) {
-                __builtin_nontemporal_store(i32x4{v[0], v[1], v[2], v[3]}, reinterpret_cast<i32x4 *>(dst));
-                if (mask4)
-                    __builtin_nontemporal_store(mk, reinterpret_cast<uint32_t *>(o.mask + e));
-                else
-                    for (int q = 0; q < 4; ++q) o.mask[e + q] = (int8_t)((mk >> (8 * q)) & 1);
-            } else {
+                if (all_in) {
+                    __builtin_nontemporal_store(i32x4{v[0], v[1], v[2], v[3]}, reinterpret_cast<i32x4 *>(dst));
+                    if (mask4)
+                        __builtin_nontemporal_store(mk, reinterpret_cast<uint32_t *>(o.mask + e));
+                    else
+                        for (int q = 0; q < 4; ++q) o.mask[e + q] = (int8_t)((mk >> (8 * q)) & 1);
+                } else {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (!in[q]) continue;
-                    dst[q] = v[q];
-                    o.mask[e + q] = (int8_t)((mk >> (8 * q)) & 1);
+                    for (int q = 0; q < 4; ++q) {
+                        if (!in[q]) continue;
+                        dst[q] = v[q];
+                        o.mask[e + q] = (int8_t)((mk >> (8 * q)) & 1);
+                    }
                 }
             }
         }
@@ -368,17 +440,20 @@ int launch_encode_bands(const dnatok_vocab *const *vs, int nv, const uint8_t *d_
     const dnatok_vocab *v = vs[0];
     const bool kmer = (v->kind == DNATOK_KMER);
     const dnatok_encode_opts &o = os[0];
-    if (o.layout != DNATOK_PADDED || o.variant) return DNATOK_OK;
+    if (o.layout != DNATOK_PADDED) return DNATOK_OK;
     BandArgs a = {};
     a.cls = o.add_cls_sep ? 1 : 0;
     a.left = (o.pad_side == DNATOK_PAD_LEFT) ? 1 : 0;
+    a.overlap = (kmer && (o.variant & DNATOK_VARIANT_OVERLAP)) ? 1 : 0;
+    a.revcomp = (o.variant & DNATOK_VARIANT_REVCOMP) ? 1 : 0;
     // longest row any vocabulary's pad_to admits, in bytes
     int64_t maxrow = INT64_MAX;
     for (int vi = 0; vi < nv; ++vi) {
         const int64_t k = kmer ? vs[vi]->k : 1;
         const int64_t W = os[vi].pad_to;
         if (W >= (1ll << 31)) return DNATOK_OK;
-        maxrow = std::min(maxrow, std::max<int64_t>(0, W - 2 * a.cls) * k);
+        const int64_t tok = std::max<int64_t>(0, W - 2 * a.cls);  // tokens a row may have
+        maxrow = std::min(maxrow, a.overlap ? (tok > 0 ? tok + k - 1 : 0) : tok * k);
     }
     if (maxrow > stage_bytes) return DNATOK_OK;
     int64_t R = maxrow > 0 ? stage_bytes / maxrow : kMaxBandRows;
@@ -428,7 +503,7 @@ int launch_encode_bands(const dnatok_vocab *const *vs, int nv, const uint8_t *d_
         sp.out = d_out_offsets[vi];
         sp.k = bv.k;
         sp.kmer = kmer ? 1 : 0;
-        sp.overlap = 0;
+        sp.overlap = a.overlap;
         sp.cls = a.cls;
         sp.padded = 1;
         sp.W = bv.W;
@@ -442,7 +517,7 @@ int launch_encode_bands(const dnatok_vocab *const *vs, int nv, const uint8_t *d_
             s.k = bv.k;
             s.kinv = 0xFFFFFFFFu / (uint32_t)bv.k;
             s.kmer = kmer ? 1 : 0;
-            s.overlap = 0;
+            s.overlap = a.overlap;
             s.cls = a.cls;
             s.padded = 1;
             s.W = bv.W;

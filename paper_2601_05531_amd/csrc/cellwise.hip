@@ -603,6 +603,13 @@ int setup_encode(CwArgs &a, const dnatok_vocab *v, const uint8_t *d_bytes, int64
 int launch_encode_variant(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets,
                           int32_t n, int32_t *d_ids, int64_t cap, int64_t *d_out_offsets, int8_t *d_mask,
                           const dnatok_encode_opts &o, hipStream_t stream) {
+    const EncodeTuning tune = encode_tuning(v, nbytes);
+    if (o.layout == DNATOK_PADDED && tune.bands == 1) {
+        bool used = false;
+        int rc = launch_encode_bands(&v, 1, d_bytes, nbytes, d_offsets, n, &d_ids, &cap, &d_mask, &o,
+                                     tune.tile_bytes, &d_out_offsets, stream, &used);
+        if (rc || used) return rc;
+    }
     CwArgs a;
     int64_t max_cells = 0;
     int rc = setup_encode(a, v, d_bytes, nbytes, d_offsets, n, d_out_offsets, o, stream, &max_cells);

@@ -81,7 +81,8 @@ namespace {
 // Times every candidate tiling of v with `run` (one encode on `st`): one
 // warm-up and `reps` timed launches each, median; keeps the fastest in v.
 template <class Run>
-int autotune_loop(dnatok_vocab *v, hipStream_t st, int32_t reps, Run run, dnatok_tuning *best, float *best_ms) {
+int autotune_loop(dnatok_vocab *v, hipStream_t st, int32_t reps, bool padded, Run run, dnatok_tuning *best,
+                  float *best_ms) {
     if (!v) return set_error(DNATOK_EINVAL, "null vocabulary");
     if (reps < 1 || reps > 100) return set_error(DNATOK_EINVAL, "reps must be 1..100");
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -96,6 +97,8 @@ int autotune_loop(dnatok_vocab *v, hipStream_t st, int32_t reps, Run run, dnatok
             for (int32_t b : {0, 1, 2, 4}) cand.push_back(dnatok_tuning{tile, b, 0, 0, 0, 0});
         for (int32_t tile : {4096, 8192, 16384})
             for (int32_t sp : {10, 25, 50}) cand.push_back(dnatok_tuning{tile, 0, 0, 0, sp, 0});
+        if (padded)  // row bands, staged through LDS stages of 4 to 64 KiB
+            for (int32_t tile : {4096, 8192, 16384, 32768, 65536}) cand.push_back(dnatok_tuning{tile, 0, 0, 0, 0, 1});
     }
     const dnatok_tuning saved = load(v);
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -147,7 +150,8 @@ int dnatok_autotune(dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, con
                     int32_t *d_ids, int64_t ids_capacity, int64_t *d_out_offsets, int8_t *d_mask,
                     const dnatok_encode_opts *opts, void *stream, int32_t reps, dnatok_tuning *best,
                     float *best_ms) {
-    return autotune_loop(v, static_cast<hipStream_t>(stream), reps, [&] {
+    const bool padded = opts && opts->layout == DNATOK_PADDED;
+    return autotune_loop(v, static_cast<hipStream_t>(stream), reps, padded, [&] {
         return dnatok_encode(v, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity, d_out_offsets, d_mask, opts,
                              stream);
     }, best, best_ms);
@@ -158,7 +162,8 @@ int dnatok_autotune_multi(dnatok_vocab *const *vocabs, int32_t n_vocabs, const u
                           int64_t *const *d_out_offsets, int8_t *const *d_mask, const dnatok_encode_opts *opts,
                           void *stream, int32_t reps, dnatok_tuning *best, float *best_ms) {
     if (!vocabs || n_vocabs < 1) return set_error(DNATOK_EINVAL, "no vocabularies");
-    return autotune_loop(vocabs[0], static_cast<hipStream_t>(stream), reps, [&] {
+    const bool padded = opts && opts[0].layout == DNATOK_PADDED;
+    return autotune_loop(vocabs[0], static_cast<hipStream_t>(stream), reps, padded, [&] {
         return dnatok_encode_multi(vocabs, n_vocabs, d_bytes, nbytes, d_offsets, n, d_ids, ids_capacity,
                                    d_out_offsets, d_mask, opts, stream);
     }, best, best_ms);

@@ -211,3 +211,68 @@ def test_bands_device_errors_are_flagged_and_bounded():
                          out_off.data_ptr(), pm.data_ptr(), dt.make_opts(layout=dt.PADDED, pad_to=W), stream)
         assert dt.sync_status() & dt.DERR_OFFSETS
         assert np.all(pid.cpu().numpy()[n * W:] == -7)
+
+
+def _want_variant(kind, k, data, offs, cls, variant, lut=None):
+    src = oracle.revcomp(data, offs) if variant & dt.VARIANT_REVCOMP else data
+    if variant & dt.VARIANT_OVERLAP:
+        return oracle.encode_overlap(src, offs, k, add_cls_sep=cls)
+    return oracle.encode(kind, src, offs, k=k, lut=lut, add_cls_sep=cls)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5, 6, 8, 9, 15])
+def test_bands_variants_kmer(k):
+    torch = _torch()
+    data, offs = _fuzz_batch(3500 + k, 1200, 150)
+    n = len(offs) - 1
+    for stage in (4096, 32768):
+        v = _banded(dt.Vocab(dt.KMER, k=k), stage)
+        for variant in (dt.VARIANT_REVCOMP, dt.VARIANT_OVERLAP, dt.VARIANT_REVCOMP | dt.VARIANT_OVERLAP):
+            for cls, side, extra in ((True, dt.PAD_RIGHT, 0), (False, dt.PAD_LEFT, 3)):
+                w_ids, w_off = _want_variant(dt.KMER, k, data, offs, cls, variant)
+                W = max(1, int(np.diff(w_off).max()) + extra)
+                p_ids, p_mask = oracle.pad(w_ids, w_off, W, side)
+                print("bands variant k=%d stage=%d variant=%d cls=%d side=%d" % (k, stage, variant, cls, side),
+                      flush=True)
+                ids, oo, mask = dt.encode(v, _dev(data), _dev(offs), h_offsets=offs, add_cls_sep=cls,
+                                          layout=dt.PADDED, pad_side=side, pad_to=W, variant=variant)
+                torch.cuda.synchronize()
+                assert dt.sync_status() == 0
+                assert np.array_equal(oo.cpu().numpy(), w_off)
+                g = ids.cpu().numpy()
+                bad = np.argwhere(g != p_ids)
+                assert bad.size == 0, "first mismatch at %s: got %d want %d" % (
+                    bad[0], g[tuple(bad[0])], p_ids[tuple(bad[0])])
+                assert np.array_equal(mask.cpu().numpy(), p_mask)
+                assert ids.shape == (n, W)
+        v.close()
+
+
+def test_bands_variants_tables_and_full_batch():
+    torch = _torch()
+    data, offs = _fuzz_batch(3600, 1500, 150)
+    lut = oracle.fallback_lut()
+    for kind, kw in ((dt.SINGLE, {}), (dt.LUT256, {"lut256": lut})):
+        v = _banded(dt.Vocab(kind, **kw), 8192)
+        for cls, side in ((True, dt.PAD_LEFT), (False, dt.PAD_RIGHT)):
+            w_ids, w_off = _want_variant(kind, 1, data, offs, cls, dt.VARIANT_REVCOMP, lut=kw.get("lut256"))
+            W = int(np.diff(w_off).max()) + 1
+            p_ids, p_mask = oracle.pad(w_ids, w_off, W, side)
+            ids, oo, mask = dt.encode(v, _dev(data), _dev(offs), h_offsets=offs, add_cls_sep=cls, layout=dt.PADDED,
+                                      pad_side=side, pad_to=W, variant=dt.VARIANT_REVCOMP)
+            torch.cuda.synchronize()
+            assert dt.sync_status() == 0
+            assert np.array_equal(ids.cpu().numpy(), p_ids) and np.array_equal(mask.cpu().numpy(), p_mask)
+    # the batched workload, 6-mers, as the benchmark's variant legs run it
+    data, offs = synth.workload_markov_batch()
+    for variant in (dt.VARIANT_REVCOMP, dt.VARIANT_REVCOMP | dt.VARIANT_OVERLAP):
+        v = _banded(dt.Vocab(dt.KMER, k=6), 16384)
+        w_ids, w_off = _want_variant(dt.KMER, 6, data, offs, True, variant)
+        W = int(np.diff(w_off).max())
+        p_ids, p_mask = oracle.pad_threads(w_ids, w_off, W)
+        ids, oo, mask = dt.encode(v, _dev(data), _dev(offs), h_offsets=offs, add_cls_sep=True, layout=dt.PADDED,
+                                  pad_to=W, variant=variant)
+        torch.cuda.synchronize()
+        assert dt.sync_status() == 0
+        assert np.array_equal(oo.cpu().numpy(), w_off)
+        assert np.array_equal(ids.cpu().numpy(), p_ids) and np.array_equal(mask.cpu().numpy(), p_mask)
