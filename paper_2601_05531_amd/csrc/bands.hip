@@ -54,6 +54,9 @@ struct BandArgs {
     int32_t overlap;       // KMER: stride-1 windows (L - k + 1 of them; one UNK for 0 < L < k)
     int32_t revcomp;       // encode each row's reverse complement
     int32_t R;             // rows per band
+    int32_t P;             // parts per row (P > 1: R = 1, part p takes the tokens starting in bytes [pU, (p+1)U))
+    int64_t U;             // bytes per part
+    int32_t kmax;          // the longest k among the vocabularies (a part stages U + kmax bytes)
     int32_t stage_chunks;  // 16-byte chunks the LDS stage holds
     int64_t nbands;
     int32_t lead;          // blocks before the bands (fused row scans, then idle)
@@ -218,7 +221,9 @@ __global__ __launch_bounds__(NTB) void k_bands(BandArgs a) {
         if ((int)blockIdx.x < a.nscan) band_rowscan(a.scan[blockIdx.x], s_tmp, a.err_hdr);
         return;
     }
-    const int64_t band = (int64_t)blockIdx.x - a.lead;
+    const int64_t unit = (int64_t)blockIdx.x - a.lead;
+    const int64_t band = unit / a.P;
+    const int part = (int)(unit - band * a.P);
     const int64_t r0 = band * a.R;
     const int nr = (int)min((int64_t)a.R, (int64_t)a.n - r0);
     if (!KMER) s_lut[tid] = a.lut[a.revcomp ? complement_byte((uint32_t)tid) : (uint32_t)tid];
@@ -243,7 +248,24 @@ __global__ __launch_bounds__(NTB) void k_bands(BandArgs a) {
             hi = max(hi, (int64_t)__shfl_xor(hi, d, dev::kWave));
         }
         if (tid == 0) {
-            s_lo = lo == INT64_MAX ? 0 : lo;
+            lo = lo == INT64_MAX ? 0 : lo;
+            if (a.P > 1) {
+                // one row: the bytes of this part's tokens (forward: from pU,
+                // up to k - 1 bytes past the part; reverse complement: the
+                // mirrored range)
+                const int64_t L = hi - lo;
+                int64_t b0 = (int64_t)part * a.U, b1 = b0 + a.U + a.kmax;
+                if (a.revcomp) {
+                    const int64_t m0 = L - b1, m1 = L - b0;
+                    b0 = m0;
+                    b1 = m1;
+                }
+                b0 = b0 < 0 ? 0 : (b0 > L ? L : b0);
+                b1 = b1 < b0 ? b0 : (b1 > L ? L : b1);
+                hi = lo + b1;
+                lo = lo + b0;
+            }
+            s_lo = lo;
             s_hi = hi;
         }
     }
@@ -337,12 +359,25 @@ __global__ __launch_bounds__(NTB) void k_bands(BandArgs a) {
             const int32_t bA = lead + a.cls;                 // first body cell
             const int32_t bF = bA + nb - (tail ? 1 : 0);     // end of the full frames
             const int64_t E0 = (r0 + r) * (int64_t)W;        // the row's first cell
-            const int64_t gf = (E0 + o.al) >> 2, gl = (E0 + W - 1 + o.al) >> 2;
+            // the row's cells this workgroup writes: all of them, or with
+            // parts the tokens starting in the part's bytes, the first part
+            // also the leading pads and CLS, the last non-empty one the rest
+            int32_t clo = 0, chi = W;
+            if (a.P > 1) {
+                const int64_t jlo = ((int64_t)part * a.U + st - 1) / st, jhi = ((int64_t)(part + 1) * a.U + st - 1) / st;
+                const int64_t plast = L > 0 ? (L - 1) / a.U : 0;
+                if (part > plast) continue;
+                clo = part == 0 ? 0 : bA + (int32_t)min(jlo, (int64_t)nb);
+                chi = part == plast ? W : bA + (int32_t)min(jhi, (int64_t)nb);
+            }
+            if (clo >= chi) continue;
+            const int64_t gf = (E0 + clo + o.al) >> 2, gl = (E0 + chi - 1 + o.al) >> 2;
             for (int64_t g = gf + tid; g <= gl; g += NTB) {
                 const int64_t e = 4 * g - o.al;
                 const int32_t c0 = (int32_t)(e - E0);
                 int32_t *dst = o.ids + e;
-                if (c0 >= bA && c0 + 4 <= bF && staged && (!KMER || 3 * st + k <= 32)) {
+                if (c0 >= bA && c0 + 4 <= bF && c0 >= clo && c0 + 4 <= chi && staged &&
+                    (!KMER || 3 * st + k <= 32)) {
                     const int32_t j = c0 - bA;
                     i32x4 y;
                     if (KMER) {
@@ -371,7 +406,7 @@ __global__ __launch_bounds__(NTB) void k_bands(BandArgs a) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int32_t c = c0 + q;
-                    in[q] = c >= 0 && c < W;
+                    in[q] = c >= clo && c < chi;
                     all_in = all_in && in[q];
                     int32_t id = o.pad_id;
                     uint32_t m = 0;
@@ -455,10 +490,20 @@ int launch_encode_bands(const dnatok_vocab *const *vs, int nv, const uint8_t *d_
         const int64_t tok = std::max<int64_t>(0, W - 2 * a.cls);  // tokens a row may have
         maxrow = std::min(maxrow, a.overlap ? (tok > 0 ? tok + k - 1 : 0) : tok * k);
     }
-    if (maxrow > stage_bytes) return DNATOK_OK;
-    int64_t R = maxrow > 0 ? stage_bytes / maxrow : kMaxBandRows;
-    R = std::max<int64_t>(1, std::min<int64_t>(R, kMaxBandRows));
-    if (n > 0 && (int64_t)n < R) R = n;
+    int32_t kmax = 1;
+    for (int vi = 0; vi < nv; ++vi) kmax = std::max<int32_t>(kmax, kmer ? vs[vi]->k : 1);
+    // rows that fit the stage go R to a band; longer ones are cut into P parts
+    // of U bytes (each staging U + kmax bytes)
+    int64_t R = 1, P = 1, U = stage_bytes;
+    if (maxrow <= stage_bytes) {
+        R = maxrow > 0 ? stage_bytes / maxrow : kMaxBandRows;
+        R = std::max<int64_t>(1, std::min<int64_t>(R, kMaxBandRows));
+        if (n > 0 && (int64_t)n < R) R = n;
+    } else {
+        P = (maxrow + U - 1) / U;
+        if (P > 4096 || maxrow >= (1ll << 31)) return DNATOK_OK;
+        U = ((maxrow + P - 1) / P + 15) / 16 * 16;  // even parts
+    }
     // a band's cells are indexed in 32 bits
     int64_t Wmax = 0;
     for (int vi = 0; vi < nv; ++vi) Wmax = std::max<int64_t>(Wmax, os[vi].pad_to);
@@ -472,10 +517,15 @@ int launch_encode_bands(const dnatok_vocab *const *vs, int nv, const uint8_t *d_
     a.n = n;
     a.nv = nv;
     a.R = (int32_t)R;
-    // a band of valid rows spans at most R * maxrow bytes: its chunks plus
-    // the partial ones at both ends and the two spare ones
-    a.stage_chunks = (int32_t)((R * std::max<int64_t>(maxrow, 1) + 15) / 16 + 4);
-    a.nbands = n > 0 ? (n + R - 1) / R : 0;
+    a.P = (int32_t)P;
+    a.U = U;
+    a.kmax = kmax;
+    // a band of valid rows spans at most R * maxrow bytes (a part U + kmax):
+    // its chunks plus the partial ones at both ends and the two spare ones
+    const int64_t span = P > 1 ? U + kmax : R * std::max<int64_t>(maxrow, 1);
+    a.stage_chunks = (int32_t)((span + 15) / 16 + 4);
+    a.nbands = n > 0 ? ((n + R - 1) / R) * P : 0;
+    if (a.nbands + 8 >= (1ll << 31)) return DNATOK_OK;
     a.lut = v->d_lut;
     Workspace *ws = nullptr;
     int rc = get_workspace(stream, 1, &ws);

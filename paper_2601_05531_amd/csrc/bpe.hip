@@ -320,23 +320,6 @@ __device__ __forceinline__ uint32_t block_min(const uint16_t *prk, uint32_t b) {
     return m;
 }
 
-// Bit i set where the rank of position 64b + i equals r.
-__device__ __forceinline__ uint64_t block_match(const uint16_t *prk, uint32_t b, uint32_t r) {
-    const uint4 *src = reinterpret_cast<const uint4 *>(prk + (size_t)b * 64);
-    uint64_t m = 0;
-#pragma unroll
-    for (int v = 0; v < 8; ++v) {
-        const uint4 x = src[v];
-        const uint32_t w[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-        for (int h = 0; h < 4; ++h) {
-            m |= (uint64_t)((w[h] & 0xFFFF) == r) << (v * 8 + h * 2);
-            m |= (uint64_t)((w[h] >> 16) == r) << (v * 8 + h * 2 + 1);
-        }
-    }
-    return m;
-}
-
 struct WaveArgs {
     const uint8_t *bytes;
     const int64_t *item_start;
@@ -540,25 +523,35 @@ __device__ __forceinline__ void wave_item(const WaveArgs &a, const RankTab &tab,
         uint32_t carry_q = kNone;
         int32_t carry_off = 0;
         for (uint32_t base = 0; base < ncb;) {
-            // gather up to 64 occurrences from the next blocks
-            const uint32_t j = base + lane;
-            uint64_t mm = 0;
-            uint32_t b = 0;
-            if (j < ncb) {
-                b = cblk[j];
-                mm = block_match(prk, b, rs);
-            }
-            const uint32_t c = (uint32_t)__popcll(mm);
-            const uint32_t inc = dev::wave_incl_sum_u32(c);
-            const uint32_t m = (uint32_t)__popcll(__ballot(j < ncb && inc <= 64));
-            if ((uint32_t)lane < m) {
-                uint32_t o = inc - c;
-                while (mm) {
-                    list[o++] = (uint16_t)(b * 64 + (uint32_t)__builtin_ctzll(mm));
-                    mm &= mm - 1;
+            // gather up to 64 occurrences from the next blocks, the wave
+            // reading each block together (lane i: position 64b + i, one
+            // ballot per block), four blocks' reads in flight at a time
+            uint32_t nc = 0, m = 0;
+            bool full = false;
+            while (!full && base + m < ncb) {
+                uint32_t bq[4], rk[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t jb = base + m + (uint32_t)u;
+                    bq[u] = cblk[jb < ncb ? jb : ncb - 1];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) rk[u] = prk[bq[u] * 64 + (uint32_t)lane];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (full || base + m >= ncb) break;
+                    const uint64_t mm = __ballot(rk[u] == rs);
+                    const uint32_t c = (uint32_t)__popcll(mm);
+                    if (nc + c > 64) {
+                        full = true;
+                        break;
+                    }
+                    if ((mm >> lane) & 1ull)
+                        list[nc + (uint32_t)__popcll(mm & ((1ull << lane) - 1ull))] = (uint16_t)(bq[u] * 64 + (uint32_t)lane);
+                    nc += c;
+                    ++m;
                 }
             }
-            const uint32_t nc = dev::wave_read_u32(inc, m - 1);
             wave_sync();
             // which occurrences merge: all, or for (X, X) every other one of a run
             const bool valid = (uint32_t)lane < nc;
@@ -614,9 +607,15 @@ __device__ __forceinline__ void wave_item(const WaveArgs &a, const RankTab &tab,
             own_dirty |= (uint32_t)(dw >> (b0 & 31)) & ((k2 >= 32) ? ~0u : ((1u << k2) - 1u));
         }
         if (own_dirty) {
+            // one block per pass: the wave makes as many passes as its
+            // busiest lane has changed blocks (a per-k test would run a pass
+            // for every k that any lane needs)
+            for (uint32_t dm = own_dirty; dm; dm &= dm - 1) {
+                const uint32_t kk = (uint32_t)__builtin_ctz(dm);
+                const uint32_t m = block_min(prk, b0 + kk);
 #pragma unroll
-            for (int k = 0; k < kK2Max; ++k)
-                if ((own_dirty >> k) & 1u) bm[k] = block_min(prk, b0 + k);
+                for (int k = 0; k < kK2Max; ++k) bm[k] = ((uint32_t)k == kk) ? m : bm[k];
+            }
             l2 = kNoRank;
 #pragma unroll
             for (int k = 0; k < kK2Max; ++k) l2 = min(l2, bm[k]);

@@ -141,7 +141,7 @@ def test_bands_multi_vocab_fuzz_and_wide_padding():
 def test_bands_full_batched_workload():
     data, offs = synth.workload_markov_batch()
     ks = [3, 4, 5, 6]
-    for stage in (8192, 32768):
+    for stage in (4096, 8192, 32768):
         vs = [dt.Vocab(dt.KMER, k=k) for k in ks]
         _banded(vs[0], stage)
         _check(vs, [(dt.KMER, k) for k in ks], data, offs, True, dt.PAD_RIGHT)
@@ -276,3 +276,43 @@ def test_bands_variants_tables_and_full_batch():
         assert dt.sync_status() == 0
         assert np.array_equal(oo.cpu().numpy(), w_off)
         assert np.array_equal(ids.cpu().numpy(), p_ids) and np.array_equal(mask.cpu().numpy(), p_mask)
+
+
+def test_bands_rows_longer_than_the_stage_go_in_parts():
+    """Rows longer than the stage are cut into parts (tokens owned by the part
+    their first byte falls in; the first part writes the leading pads and
+    CLS, the last non-empty part SEP and the trailing pads): ragged rows of
+    up to 20,000 bytes through a 4 KiB stage, every kind and variant, both
+    pad sides, extra padding, misaligned input and output."""
+    torch = _torch()
+    data, offs = _fuzz_batch(3700, 90, 20000)
+    lut = oracle.fallback_lut()
+    cases = [(dt.KMER, k, var) for k in (1, 3, 6, 8, 13) for var in (0, dt.VARIANT_REVCOMP, dt.VARIANT_OVERLAP,
+                                                                         dt.VARIANT_REVCOMP | dt.VARIANT_OVERLAP)]
+    cases += [(dt.SINGLE, 1, 0), (dt.SINGLE, 1, dt.VARIANT_REVCOMP), (dt.LUT256, 1, dt.VARIANT_REVCOMP)]
+    n = len(offs) - 1
+    for kind, k, variant in cases:
+        v = _banded(dt.Vocab(kind, k=k, lut256=lut if kind == dt.LUT256 else None), 4096)
+        for cls, side, extra in ((True, dt.PAD_RIGHT, 5), (False, dt.PAD_LEFT, 0)):
+            w_ids, w_off = _want_variant(kind, k, data, offs, cls, variant, lut=lut if kind == dt.LUT256 else None)
+            W = max(1, int(np.diff(w_off).max()) + extra)
+            p_ids, p_mask = oracle.pad(w_ids, w_off, W, side)
+            print("parts kind=%d k=%d variant=%d cls=%d side=%d" % (kind, k, variant, cls, side), flush=True)
+            ids, oo, mask = dt.encode(v, _dev(data), _dev(offs), h_offsets=offs, add_cls_sep=cls, layout=dt.PADDED,
+                                      pad_side=side, pad_to=W, variant=variant)
+            torch.cuda.synchronize()
+            assert dt.sync_status() == 0
+            assert np.array_equal(oo.cpu().numpy(), w_off)
+            g = ids.cpu().numpy()
+            bad = np.argwhere(g != p_ids)
+            assert bad.size == 0, "first mismatch at %s: got %d want %d" % (
+                bad[0], g[tuple(bad[0])], p_ids[tuple(bad[0])])
+            assert np.array_equal(mask.cpu().numpy(), p_mask)
+        v.close()
+    # several vocabularies, misaligned input and outputs, through 4 KiB parts
+    ks = [2, 3, 5, 6]
+    vs = [dt.Vocab(dt.KMER, k=k) for k in ks]
+    _banded(vs[0], 4096)
+    _check(vs, [(dt.KMER, k) for k in ks], data, offs, True, dt.PAD_RIGHT, byte_shift=3, id_shift=1)
+    _check(vs, [(dt.KMER, k) for k in ks], data, offs, False, dt.PAD_LEFT, pad_extra=9)
+    assert n == 90
