@@ -123,7 +123,9 @@ def encode_leg(steps: int, warmup: int, tuning=None, per_vocab: bool = True):
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(),
             "kernel": ("k_bands<KMER> (row bands, %d-byte stage)" % tune_multi["tile_bytes"]
-                       if tune_multi.get("bands") == 1 else "k_cells<KMER> (tiles)") +
+                       if tune_multi.get("bands") == 1 else
+                       "k_bands_loop<KMER> (row bands, resident workgroups, %d-byte stage)" % tune_multi["tile_bytes"]
+                       if tune_multi.get("bands") == 3 else "k_cells<KMER> (tiles)") +
                       " writing k = 3, 4, 5, 6 in one pass",
             "per_launch_bytes": "1 B per input byte (read once) + 16 B per row of offsets + per vocabulary "
                                 "5 B per cell (4 B id + 1 B mask over n x pad_to) = %d B" % bytes_launch,

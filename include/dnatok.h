@@ -469,8 +469,10 @@ typedef struct dnatok_tuning {
                                index, the rest from a ticket counter, with this percentage of the tiles
                                as extra workgroups, so the parts of the chip that finish early take more */
     int32_t bands;          /* SINGLE/LUT256/KMER, PADDED layout: 0 = default, 1 = row bands (a workgroup
-                               stages the bytes of a few whole rows, at most tile_bytes, and writes all
-                               their cells; used when pad_to admits such rows), 2 = tiles */
+                               stages the bytes of a few whole rows, or of a part of a longer row, at most
+                               tile_bytes, and writes all their cells), 2 = tiles, 3 = row bands taken by
+                               resident workgroups in turn, the next band's bytes fetched while the current
+                               one is written (stages up to 16 KiB) */
 } dnatok_tuning;
 
 int dnatok_get_tuning(const dnatok_vocab *v, dnatok_tuning *out);

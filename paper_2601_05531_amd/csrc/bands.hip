@@ -207,6 +207,134 @@ __device__ void band_rowscan(const RowScanArgs &a, int64_t *s_tmp, uint32_t *err
     if (err) dev::raise_error(err_hdr, err);
 }
 
+// What the write phase of one unit (a band, or a part of a row) reads.
+
+// Writes every cell of the unit for every vocabulary (ids and mask).
+template <bool KMER>
+__device__ __forceinline__ void band_write(const BandArgs &a, int64_t r0, int nr, int part, bool staged,
+                                           const uint64_t *win64, const uint32_t *val32, const uint8_t *raw,
+                                           const int64_t *s_o0, const int64_t *s_o1, const int32_t *s_nb,
+                                           const uint32_t *s_ro, const int32_t *s_lut) {
+    const int tid = threadIdx.x;
+    // Every vocabulary, every row of the band: the row's facts are uniform
+    // across the workgroup, so a store group inside the row's full frames
+    // costs one staged window read and the four ids; groups at the row's
+    // edges (CLS, SEP, the short final frame, pads, the neighbouring rows'
+    // cells) go cell by cell and store only this row's cells.
+    for (int vi = 0; vi < a.nv; ++vi) {
+        const BandVocab o = a.vo[vi];
+        const int32_t k = KMER ? o.k : 1;
+        const int32_t W = (int32_t)o.W;
+        const bool mask4 = ((reinterpret_cast<uintptr_t>(o.mask) - (uintptr_t)o.al) & 3) == 0;
+        for (int r = 0; r < nr; ++r) {
+            const int32_t nb = __builtin_amdgcn_readfirstlane(s_nb[vi * kMaxBandRows + r]);
+            const int32_t L = __builtin_amdgcn_readfirstlane((int32_t)(s_o1[r] - s_o0[r]));
+            const uint32_t ro = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)s_ro[r]);
+            const int32_t len = nb + 2 * a.cls;
+            if (len > W) continue;  // too long for pad_to: the row writes nothing (the row scan raised the flag)
+            const int32_t lead = a.left ? W - len : 0;
+            // the one short token: a short final frame, or the single window of a row shorter than k
+            const bool tail = KMER && (a.overlap ? (L > 0 && L < k) : nb * k != L);
+            const int32_t st = (KMER && !a.overlap) ? k : 1;  // bytes between token starts
+            const int32_t bA = lead + a.cls;                 // first body cell
+            const int32_t bF = bA + nb - (tail ? 1 : 0);     // end of the full frames
+            const int64_t E0 = (r0 + r) * (int64_t)W;        // the row's first cell
+            // the row's cells this workgroup writes: all of them, or with
+            // parts the tokens starting in the part's bytes, the first part
+            // also the leading pads and CLS, the last non-empty one the rest
+            int32_t clo = 0, chi = W;
+            if (a.P > 1) {
+                const int64_t jlo = ((int64_t)part * a.U + st - 1) / st, jhi = ((int64_t)(part + 1) * a.U + st - 1) / st;
+                const int64_t plast = L > 0 ? (L - 1) / a.U : 0;
+                if (part > plast) continue;
+                clo = part == 0 ? 0 : bA + (int32_t)min(jlo, (int64_t)nb);
+                chi = part == plast ? W : bA + (int32_t)min(jhi, (int64_t)nb);
+            }
+            if (clo >= chi) continue;
+            const int64_t gf = (E0 + clo + o.al) >> 2, gl = (E0 + chi - 1 + o.al) >> 2;
+            for (int64_t g = gf + tid; g <= gl; g += NTB) {
+                const int64_t e = 4 * g - o.al;
+                const int32_t c0 = (int32_t)(e - E0);
+                int32_t *dst = o.ids + e;
+                if (c0 >= bA && c0 + 4 <= bF && c0 >= clo && c0 + 4 <= chi && staged &&
+                    (!KMER || 3 * st + k <= 32)) {
+                    const int32_t j = c0 - bA;
+                    i32x4 y;
+                    if (KMER) {
+                        // tokens j .. j + 3 read one 32-base window: forward from
+                        // their first start, reverse complemented from the last
+                        // one's start (token j + q starts at L - (j + q) * st - k)
+                        y = a.revcomp ? kmer4_lds(win64, val32, ro + (uint32_t)(L - (j + 3) * st - k), k, 3 * st, -st, true)
+                                      : kmer4_lds(win64, val32, ro + (uint32_t)(j * st), k, 0, st, false);
+                    } else if (a.revcomp) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) y[q] = s_lut[raw[ro + (uint32_t)(L - 1 - j - q)]];
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) y[q] = s_lut[raw[ro + (uint32_t)(j + q)]];
+                    }
+                    __builtin_nontemporal_store(y, reinterpret_cast<i32x4 *>(dst));
+                    if (mask4)
+                        __builtin_nontemporal_store(0x01010101u, reinterpret_cast<uint32_t *>(o.mask + e));
+                    else
+                        for (int q = 0; q < 4; ++q) o.mask[e + q] = 1;
+                    continue;
+                }
+                int32_t v[4];
+                uint32_t mk = 0;
+                bool in[4], all_in = true;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int32_t c = c0 + q;
+                    in[q] = c >= clo && c < chi;
+                    all_in = all_in && in[q];
+                    int32_t id = o.pad_id;
+                    uint32_t m = 0;
+                    const int32_t tt = c - lead;
+                    if (in[q] && tt >= 0 && tt < len) {
+                        m = 1;
+                        if (a.cls && tt == 0) {
+                            id = o.cls_id;
+                        } else if (a.cls && tt == len - 1) {
+                            id = o.sep_id;
+                        } else {
+                            const int32_t j = tt - a.cls;
+                            // first byte of token j (of its mirror window when reverse complemented)
+                            const int32_t b0 = !a.revcomp ? j * st : (KMER ? L - j * st - k : L - 1 - j);
+                            if (tail && j == nb - 1) {
+                                id = DNATOK_ID_UNK;
+                            } else if (staged) {
+                                const uint32_t idx = ro + (uint32_t)b0;
+                                id = KMER ? kmer_id(kmer_lds(win64, val32, idx, k), k, a.revcomp) : s_lut[raw[idx]];
+                            } else {
+                                const int64_t pos = s_o0[r] + b0;
+                                id = KMER ? kmer_id(kmer_global(a, pos, k), k, a.revcomp)
+                                          : s_lut[a.abase[a.shift + pos]];
+                            }
+                        }
+                    }
+                    v[q] = id;
+                    mk |= m << (8 * q);
+                }
+                if (all_in) {
+                    __builtin_nontemporal_store(i32x4{v[0], v[1], v[2], v[3]}, reinterpret_cast<i32x4 *>(dst));
+                    if (mask4)
+                        __builtin_nontemporal_store(mk, reinterpret_cast<uint32_t *>(o.mask + e));
+                    else
+                        for (int q = 0; q < 4; ++q) o.mask[e + q] = (int8_t)((mk >> (8 * q)) & 1);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        if (!in[q]) continue;
+                        dst[q] = v[q];
+                        o.mask[e + q] = (int8_t)((mk >> (8 * q)) & 1);
+                    }
+                }
+            }
+        }
+    }
+}
+
 template <bool KMER>
 __global__ __launch_bounds__(NTB) void k_bands(BandArgs a) {
     extern __shared__ __align__(16) uint8_t dyn[];
@@ -336,122 +464,200 @@ __global__ __launch_bounds__(NTB) void k_bands(BandArgs a) {
     }
     __syncthreads();
 
-    // Every vocabulary, every row of the band: the row's facts are uniform
-    // across the workgroup, so a store group inside the row's full frames
-    // costs one staged window read and the four ids; groups at the row's
-    // edges (CLS, SEP, the short final frame, pads, the neighbouring rows'
-    // cells) go cell by cell and store only this row's cells.
-    for (int vi = 0; vi < a.nv; ++vi) {
-        const BandVocab &o = a.vo[vi];
-        const int32_t k = KMER ? o.k : 1;
-        const int32_t W = (int32_t)o.W;
-        const bool mask4 = ((reinterpret_cast<uintptr_t>(o.mask) - (uintptr_t)o.al) & 3) == 0;
-        for (int r = 0; r < nr; ++r) {
-            const int32_t nb = __builtin_amdgcn_readfirstlane(s_nb[vi * kMaxBandRows + r]);
-            const int32_t L = __builtin_amdgcn_readfirstlane((int32_t)(s_o1[r] - s_o0[r]));
-            const uint32_t ro = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)s_ro[r]);
-            const int32_t len = nb + 2 * a.cls;
-            if (len > W) continue;  // too long for pad_to: the row writes nothing (the row scan raised the flag)
-            const int32_t lead = a.left ? W - len : 0;
-            // the one short token: a short final frame, or the single window of a row shorter than k
-            const bool tail = KMER && (a.overlap ? (L > 0 && L < k) : nb * k != L);
-            const int32_t st = (KMER && !a.overlap) ? k : 1;  // bytes between token starts
-            const int32_t bA = lead + a.cls;                 // first body cell
-            const int32_t bF = bA + nb - (tail ? 1 : 0);     // end of the full frames
-            const int64_t E0 = (r0 + r) * (int64_t)W;        // the row's first cell
-            // the row's cells this workgroup writes: all of them, or with
-            // parts the tokens starting in the part's bytes, the first part
-            // also the leading pads and CLS, the last non-empty one the rest
-            int32_t clo = 0, chi = W;
-            if (a.P > 1) {
-                const int64_t jlo = ((int64_t)part * a.U + st - 1) / st, jhi = ((int64_t)(part + 1) * a.U + st - 1) / st;
-                const int64_t plast = L > 0 ? (L - 1) / a.U : 0;
-                if (part > plast) continue;
-                clo = part == 0 ? 0 : bA + (int32_t)min(jlo, (int64_t)nb);
-                chi = part == plast ? W : bA + (int32_t)min(jhi, (int64_t)nb);
+    band_write<KMER>(a, r0, nr, part, staged, win64, val32, raw, s_o0, s_o1, s_nb, s_ro, s_lut);
+}
+
+// Persistent form: as many workgroups as are resident, each taking units
+// u, u + G, ... and putting the next unit's bytes in flight (in registers)
+// before writing the current one, so its load latency hides behind the
+// writes. A vector load waits for the wave's earlier stores as well, so the
+// one wait per unit (for the prefetched bytes) also drains the previous
+// unit's stores; the row offsets run two units ahead so no other wait is
+// needed. Units of at most kLoopChunks 16-byte chunks per thread.
+constexpr int kLoopChunks = 4;
+constexpr int kLoopRows = dev::kWave - 1;  // a unit's row offsets fit one wave
+
+template <bool KMER>
+__global__ __launch_bounds__(NTB) void k_bands_loop(BandArgs a) {
+    extern __shared__ __align__(16) uint8_t dyn[];
+    __shared__ int64_t s_o0[kMaxBandRows], s_o1[kMaxBandRows];
+    __shared__ int32_t s_nb[kBandVocabs * kMaxBandRows];
+    __shared__ uint32_t s_ro[kMaxBandRows];
+    __shared__ int32_t s_lut[256];
+    __shared__ int64_t s_nlo, s_nhi;  // the next unit's staging window
+    __shared__ int64_t s_tmp[NTB / dev::kWave + 1];
+    const int tid = threadIdx.x, lane = tid & (dev::kWave - 1);
+    if ((int)blockIdx.x < a.lead) {
+        if ((int)blockIdx.x < a.nscan) band_rowscan(a.scan[blockIdx.x], s_tmp, a.err_hdr);
+        return;
+    }
+    const int64_t G = (int64_t)gridDim.x - a.lead;
+    const int64_t nunits = a.nbands;
+    if (!KMER) s_lut[tid] = a.lut[a.revcomp ? complement_byte((uint32_t)tid) : (uint32_t)tid];
+    uint64_t *win64 = reinterpret_cast<uint64_t *>(dyn);
+    uint32_t *val32 = reinterpret_cast<uint32_t *>(win64 + a.stage_chunks);
+    uint8_t *raw = dyn;
+    const int64_t lim = a.shift + a.nbytes;
+
+    auto rows_of = [&](int64_t u, int64_t &r0, int &nr, int &part) {
+        const int64_t band = u / a.P;
+        part = (int)(u - band * a.P);
+        r0 = band * a.R;
+        nr = (int)min((int64_t)a.R, (int64_t)a.n - r0);
+    };
+    // wave 0, lane t <= nr: the raw offset of the unit's row boundary t
+    auto load_offs = [&](int64_t u) -> int64_t {
+        if (u >= nunits || tid >= dev::kWave) return 0;
+        int64_t r0;
+        int nr, part;
+        rows_of(u, r0, nr, part);
+        const int64_t i = r0 + (lane <= nr ? lane : nr);
+        return a.offs[i];
+    };
+    // wave 0: clamp the unit's rows from the lanes' raw offsets; optionally
+    // write them to LDS; return the unit's staging window (uniform)
+    auto rows_window = [&](int64_t u, int64_t raw_off, bool to_lds, int64_t &wlo, int64_t &whi) {
+        int64_t r0;
+        int nr, part;
+        rows_of(u, r0, nr, part);
+        const int64_t nxt = __shfl_down(raw_off, 1, dev::kWave);
+        int64_t o0 = raw_off < 0 ? 0 : (raw_off > a.nbytes ? a.nbytes : raw_off);
+        int64_t o1 = nxt < o0 ? o0 : (nxt > a.nbytes ? a.nbytes : nxt);
+        const bool row = lane < nr;
+        if (to_lds && row) {
+            s_o0[lane] = o0;
+            s_o1[lane] = o1;
+        }
+        int64_t lo = row ? o0 : INT64_MAX, hi = row ? o1 : 0;
+#pragma unroll
+        for (int d = dev::kWave / 2; d > 0; d >>= 1) {
+            lo = min(lo, (int64_t)__shfl_xor(lo, d, dev::kWave));
+            hi = max(hi, (int64_t)__shfl_xor(hi, d, dev::kWave));
+        }
+        lo = lo == INT64_MAX ? 0 : lo;
+        if (a.P > 1) {
+            const int64_t L = hi - lo;
+            int64_t b0 = (int64_t)part * a.U, b1 = b0 + a.U + a.kmax;
+            if (a.revcomp) {
+                const int64_t m0 = L - b1, m1 = L - b0;
+                b0 = m0;
+                b1 = m1;
             }
-            if (clo >= chi) continue;
-            const int64_t gf = (E0 + clo + o.al) >> 2, gl = (E0 + chi - 1 + o.al) >> 2;
-            for (int64_t g = gf + tid; g <= gl; g += NTB) {
-                const int64_t e = 4 * g - o.al;
-                const int32_t c0 = (int32_t)(e - E0);
-                int32_t *dst = o.ids + e;
-                if (c0 >= bA && c0 + 4 <= bF && c0 >= clo && c0 + 4 <= chi && staged &&
-                    (!KMER || 3 * st + k <= 32)) {
-                    const int32_t j = c0 - bA;
-                    i32x4 y;
-                    if (KMER) {
-                        // tokens j .. j + 3 read one 32-base window: forward from
-                        // their first start, reverse complemented from the last
-                        // one's start (token j + q starts at L - (j + q) * st - k)
-                        y = a.revcomp ? kmer4_lds(win64, val32, ro + (uint32_t)(L - (j + 3) * st - k), k, 3 * st, -st, true)
-                                      : kmer4_lds(win64, val32, ro + (uint32_t)(j * st), k, 0, st, false);
-                    } else if (a.revcomp) {
+            b0 = b0 < 0 ? 0 : (b0 > L ? L : b0);
+            b1 = b1 < b0 ? b0 : (b1 > L ? L : b1);
+            hi = lo + b1;
+            lo = lo + b0;
+        }
+        wlo = lo;
+        whi = max(hi, lo);
+    };
+    // the staging chunks of a window: first chunk and count (two spare)
+    auto chunks_of = [&](int64_t wlo, int64_t whi, int64_t &c0, int64_t &nch) {
+        const int64_t q0 = wlo + a.shift, q1 = whi + a.shift;
+        c0 = q0 >> 4;
+        nch = ((q1 + 15) >> 4) - c0 + 2;
+    };
+    auto fetch = [&](int64_t c0, int64_t nch, uint4 (&x)[kLoopChunks]) {
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) y[q] = s_lut[raw[ro + (uint32_t)(L - 1 - j - q)]];
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) y[q] = s_lut[raw[ro + (uint32_t)(j + q)]];
-                    }
-                    __builtin_nontemporal_store(y, reinterpret_cast<i32x4 *>(dst));
-                    if (mask4)
-                        __builtin_nontemporal_store(0x01010101u, reinterpret_cast<uint32_t *>(o.mask + e));
-                    else
-                        for (int q = 0; q < 4; ++q) o.mask[e + q] = 1;
-                    continue;
-                }
-                int32_t v[4];
-                uint32_t mk = 0;
-                bool in[4], all_in = true;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int32_t c = c0 + q;
-                    in[q] = c >= clo && c < chi;
-                    all_in = all_in && in[q];
-                    int32_t id = o.pad_id;
-                    uint32_t m = 0;
-                    const int32_t tt = c - lead;
-                    if (in[q] && tt >= 0 && tt < len) {
-                        m = 1;
-                        if (a.cls && tt == 0) {
-                            id = o.cls_id;
-                        } else if (a.cls && tt == len - 1) {
-                            id = o.sep_id;
-                        } else {
-                            const int32_t j = tt - a.cls;
-                            // first byte of token j (of its mirror window when reverse complemented)
-                            const int32_t b0 = !a.revcomp ? j * st : (KMER ? L - j * st - k : L - 1 - j);
-                            if (tail && j == nb - 1) {
-                                id = DNATOK_ID_UNK;
-                            } else if (staged) {
-                                const uint32_t idx = ro + (uint32_t)b0;
-                                id = KMER ? kmer_id(kmer_lds(win64, val32, idx, k), k, a.revcomp) : s_lut[raw[idx]];
-                            } else {
-                                const int64_t pos = s_o0[r] + b0;
-                                id = KMER ? kmer_id(kmer_global(a, pos, k), k, a.revcomp)
-                                          : s_lut[a.abase[a.shift + pos]];
-                            }
-                        }
-                    }
-                    v[q] = id;
-                    mk |= m << (8 * q);
-                }
-                if (all_in) {
-                    __builtin_nontemporal_store(i32x4{v[0], v[1], v[2], v[3]}, reinterpret_cast<i32x4 *>(dst));
-                    if (mask4)
-                        __builtin_nontemporal_store(mk, reinterpret_cast<uint32_t *>(o.mask + e));
-                    else
-                        for (int q = 0; q < 4; ++q) o.mask[e + q] = (int8_t)((mk >> (8 * q)) & 1);
-                } else {
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        if (!in[q]) continue;
-                        dst[q] = v[q];
-                        o.mask[e + q] = (int8_t)((mk >> (8 * q)) & 1);
-                    }
-                }
+        for (int w = 0; w < kLoopChunks; ++w) {
+            const int64_t m = (int64_t)w * NTB + tid;
+            const int64_t q = (c0 + m) << 4;
+            if (m < nch && q >= a.shift && q + 16 <= lim) {
+                const u32x4 t = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(a.abase + q));
+                x[w] = make_uint4(t[0], t[1], t[2], t[3]);
+            } else {
+                uint32_t wd[4] = {0, 0, 0, 0};
+                if (m < nch)
+                    for (int b = 0; b < 16; ++b)
+                        if (q + b >= a.shift && q + b < lim) wd[b >> 2] |= (uint32_t)a.abase[q + b] << (8 * (b & 3));
+                x[w] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
             }
         }
+    };
+
+    int64_t u = (int64_t)blockIdx.x - a.lead;
+    // prologue: offsets of the first two units, the first unit's bytes in flight
+    int64_t off_cur = load_offs(u);
+    int64_t off_nxt = load_offs(u + G);
+    if (tid < dev::kWave) {
+        int64_t wlo, whi;
+        rows_window(u, off_cur, false, wlo, whi);
+        if (tid == 0) {
+            s_nlo = wlo;
+            s_nhi = whi;
+        }
+    }
+    __syncthreads();
+    int64_t c0, nch;
+    chunks_of(s_nlo, s_nhi, c0, nch);
+    bool staged = nch <= a.stage_chunks && nch <= (int64_t)kLoopChunks * NTB;
+    uint4 x[kLoopChunks];
+    if (staged) fetch(c0, nch, x);
+    for (; u < nunits; u += G) {
+        __syncthreads();  // the previous unit's writes are done with the stage
+        if (staged) {
+#pragma unroll
+            for (int w = 0; w < kLoopChunks; ++w) {
+                const int64_t m = (int64_t)w * NTB + tid;
+                if (m >= nch) continue;
+                if (KMER) {
+                    uint32_t c, vb;
+                    dev::classify16(x[w], c, vb);
+                    uint32_t *w32 = reinterpret_cast<uint32_t *>(win64);
+                    uint16_t *v16 = reinterpret_cast<uint16_t *>(val32);
+                    w32[2 * m + 1] = c;
+                    v16[2 * m + 1] = (uint16_t)(vb >> 16);
+                    if (m > 0) {
+                        w32[2 * m - 2] = c;
+                        v16[2 * m - 2] = (uint16_t)(vb >> 16);
+                    }
+                } else {
+                    reinterpret_cast<uint4 *>(raw)[m] = x[w];
+                }
+            }
+            if (KMER && tid == 0) {
+                reinterpret_cast<uint32_t *>(win64)[2 * (nch - 1)] = 0;
+                reinterpret_cast<uint16_t *>(val32)[2 * (nch - 1)] = 0;
+            }
+        }
+        int64_t r0;
+        int nr, part;
+        rows_of(u, r0, nr, part);
+        const int64_t sbase = c0 << 4;
+        const bool cur_staged = staged;
+        if (tid < dev::kWave) {
+            int64_t wlo, whi;
+            rows_window(u, off_cur, true, wlo, whi);  // this unit's rows to LDS
+            if (u + G < nunits) {
+                rows_window(u + G, off_nxt, false, wlo, whi);  // the next unit's window
+                if (tid == 0) {
+                    s_nlo = wlo;
+                    s_nhi = whi;
+                }
+            }
+            if (tid < nr) s_ro[tid] = (uint32_t)(s_o0[tid] + a.shift - sbase);
+        }
+        __syncthreads();
+        for (int t = tid; t < a.nv * nr; t += NTB) {
+            const int vi = t / nr, r = t - vi * nr;
+            const int64_t L = s_o1[r] - s_o0[r];
+            const int32_t k = KMER ? a.vo[vi].k : 1;
+            s_nb[vi * kMaxBandRows + r] = (int32_t)(!KMER ? L
+                                                    : a.overlap ? (L >= k ? L - k + 1 : (L > 0 ? 1 : 0))
+                                                                : div_k(L + k - 1, k, 0xFFFFFFFFu / (uint32_t)k));
+        }
+        // the next unit's bytes and the offsets of the one after go out now
+        int64_t off_nn = 0;
+        if (u + G < nunits) {
+            chunks_of(s_nlo, s_nhi, c0, nch);
+            staged = nch <= a.stage_chunks && nch <= (int64_t)kLoopChunks * NTB;
+            if (staged) fetch(c0, nch, x);
+            off_nn = load_offs(u + 2 * G);
+        }
+        __syncthreads();
+        band_write<KMER>(a, r0, nr, part, cur_staged, win64, val32, raw, s_o0, s_o1, s_nb, s_ro, s_lut);
+        off_cur = off_nxt;
+        off_nxt = off_nn;
     }
 }
 
@@ -468,7 +674,7 @@ int band_occupancy(size_t dyn, int *per_cu) {
 // not suit bands (a row could exceed the largest stage).
 int launch_encode_bands(const dnatok_vocab *const *vs, int nv, const uint8_t *d_bytes, int64_t nbytes,
                         const int64_t *d_offsets, int32_t n, int32_t *const *d_ids, const int64_t *caps,
-                        int8_t *const *d_masks, const dnatok_encode_opts *os, int64_t stage_bytes,
+                        int8_t *const *d_masks, const dnatok_encode_opts *os, int64_t stage_bytes, bool persistent,
                         int64_t *const *d_out_offsets, hipStream_t stream, bool *used) {
     *used = false;
     if (nv < 1 || nv > kBandVocabs) return DNATOK_OK;
@@ -497,7 +703,7 @@ int launch_encode_bands(const dnatok_vocab *const *vs, int nv, const uint8_t *d_
     int64_t R = 1, P = 1, U = stage_bytes;
     if (maxrow <= stage_bytes) {
         R = maxrow > 0 ? stage_bytes / maxrow : kMaxBandRows;
-        R = std::max<int64_t>(1, std::min<int64_t>(R, kMaxBandRows));
+        R = std::max<int64_t>(1, std::min<int64_t>(R, persistent ? kLoopRows : kMaxBandRows));
         if (n > 0 && (int64_t)n < R) R = n;
     } else {
         P = (maxrow + U - 1) / U;
@@ -582,6 +788,24 @@ int launch_encode_bands(const dnatok_vocab *const *vs, int nv, const uint8_t *d_
     if (dyn > 64 * 1024) {
         DNATOK_HIP(hipFuncSetAttribute(kmer ? (const void *)k_bands<true> : (const void *)k_bands<false>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+    }
+    persistent = persistent && a.stage_chunks <= kLoopChunks * NTB && a.nbands > 0;
+    if (persistent) {
+        if (dyn > 64 * 1024)
+            DNATOK_HIP(hipFuncSetAttribute(kmer ? (const void *)k_bands_loop<true> : (const void *)k_bands_loop<false>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+        int per_cu = 0;
+        DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, kmer ? (const void *)k_bands_loop<true> : (const void *)k_bands_loop<false>, NTB, dyn));
+        const int64_t walkers = std::min<int64_t>(a.nbands, (int64_t)device_cu_count() * std::max(per_cu, 1));
+        const int64_t grid = a.lead + walkers;
+        if (kmer)
+            hipLaunchKernelGGL(k_bands_loop<true>, dim3((unsigned)grid), dim3(NTB), dyn, stream, a);
+        else
+            hipLaunchKernelGGL(k_bands_loop<false>, dim3((unsigned)grid), dim3(NTB), dyn, stream, a);
+        DNATOK_HIP(hipGetLastError());
+        *used = true;
+        return DNATOK_OK;
     }
     const int64_t grid = a.lead + a.nbands;
     if (grid > 0) {

@@ -604,10 +604,10 @@ int launch_encode_variant(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t
                           int32_t n, int32_t *d_ids, int64_t cap, int64_t *d_out_offsets, int8_t *d_mask,
                           const dnatok_encode_opts &o, hipStream_t stream) {
     const EncodeTuning tune = encode_tuning(v, nbytes);
-    if (o.layout == DNATOK_PADDED && tune.bands == 1) {
+    if (o.layout == DNATOK_PADDED && (tune.bands == 1 || tune.bands == 3)) {
         bool used = false;
         int rc = launch_encode_bands(&v, 1, d_bytes, nbytes, d_offsets, n, &d_ids, &cap, &d_mask, &o,
-                                     tune.tile_bytes, &d_out_offsets, stream, &used);
+                                     tune.tile_bytes, tune.bands == 3, &d_out_offsets, stream, &used);
         if (rc || used) return rc;
     }
     CwArgs a;

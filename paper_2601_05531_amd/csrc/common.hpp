@@ -157,7 +157,7 @@ struct EncodeTuning {
     int64_t tile_bytes;  // bytes of input per tile (multiple of 16)
     int blocks_per_cu;   // 0 = as many as occupancy allows
     int spread;          // 0 = static walkers; > 0: ticketed tiles plus this percentage of extra workgroups
-    int bands;           // PADDED: 0 = default, 1 = row bands, 2 = tiles
+    int bands;           // PADDED: 0 = default, 1 = row bands, 2 = tiles, 3 = persistent row bands
 };
 EncodeTuning encode_tuning(const dnatok_vocab *v, int64_t nbytes);
 constexpr int32_t kBpeItemBytesDefault = 8192;  // nominal BPE item length S
@@ -175,7 +175,7 @@ int launch_encode(const dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes,
 // *used false and launches nothing.
 int launch_encode_bands(const dnatok_vocab *const *vs, int nv, const uint8_t *d_bytes, int64_t nbytes,
                         const int64_t *d_offsets, int32_t n, int32_t *const *d_ids, const int64_t *caps,
-                        int8_t *const *d_masks, const dnatok_encode_opts *os, int64_t stage_bytes,
+                        int8_t *const *d_masks, const dnatok_encode_opts *os, int64_t stage_bytes, bool persistent,
                         int64_t *const *d_out_offsets, hipStream_t stream, bool *used);
 
 int launch_encode_multi(const dnatok_vocab *const *vs, int nv, const uint8_t *d_bytes, int64_t nbytes,

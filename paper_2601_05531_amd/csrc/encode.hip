@@ -992,10 +992,10 @@ int launch_encode_multi(const dnatok_vocab *const *vs, int nv, const uint8_t *d_
     const dnatok_encode_opts &o = os[0];
     const bool kmer = (v->kind == DNATOK_KMER);
     const EncodeTuning tune = encode_tuning(v, nbytes);
-    if (o.layout == DNATOK_PADDED && tune.bands == 1) {
+    if (o.layout == DNATOK_PADDED && (tune.bands == 1 || tune.bands == 3)) {
         bool used = false;
         int rc = launch_encode_bands(vs, nv, d_bytes, nbytes, d_offsets, n, d_ids, caps, d_masks, os,
-                                     tune.tile_bytes, d_out_offsets, stream, &used);
+                                     tune.tile_bytes, tune.bands == 3, d_out_offsets, stream, &used);
         if (rc || used) return rc;
     }
     int U = 1;  // staging loads per thread: tiles are U * NT * 16 bytes

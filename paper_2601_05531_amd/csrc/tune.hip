@@ -26,7 +26,7 @@ int check_tuning(const dnatok_tuning &t) {
         t.bpe_max_waves != 8)
         return set_error(DNATOK_EINVAL, "bpe_max_waves must be 0, 1, 2, 4 or 8");
     if (t.spread < 0 || t.spread > 100) return set_error(DNATOK_EINVAL, "spread must be 0..100");
-    if (t.bands < 0 || t.bands > 2) return set_error(DNATOK_EINVAL, "bands must be 0, 1 or 2");
+    if (t.bands < 0 || t.bands > 3) return set_error(DNATOK_EINVAL, "bands must be 0, 1, 2 or 3");
     return DNATOK_OK;
 }
 
@@ -97,8 +97,10 @@ int autotune_loop(dnatok_vocab *v, hipStream_t st, int32_t reps, bool padded, Ru
             for (int32_t b : {0, 1, 2, 4}) cand.push_back(dnatok_tuning{tile, b, 0, 0, 0, 0});
         for (int32_t tile : {4096, 8192, 16384})
             for (int32_t sp : {10, 25, 50}) cand.push_back(dnatok_tuning{tile, 0, 0, 0, sp, 0});
-        if (padded)  // row bands, staged through LDS stages of 4 to 64 KiB
+        if (padded) {  // row bands, staged through LDS stages of 4 to 64 KiB; persistent ones up to 16 KiB
             for (int32_t tile : {4096, 8192, 16384, 32768, 65536}) cand.push_back(dnatok_tuning{tile, 0, 0, 0, 0, 1});
+            for (int32_t tile : {4096, 8192, 16384}) cand.push_back(dnatok_tuning{tile, 0, 0, 0, 0, 3});
+        }
     }
     const dnatok_tuning saved = load(v);
     hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -1,4 +1,5 @@
-"""GPU parity of the PADDED row-band kernel (tuning bands=1) against the
+"""GPU parity of the PADDED row-band kernels (tuning bands=1: a workgroup
+per band; bands=3: resident workgroups taking bands in turn) against the
 oracle, id by id and mask byte by mask byte: every kind, k = 1..8 and 15,
 several vocabularies in one pass, both pad sides, with and without CLS/SEP,
 wide padding, stage sizes from one short row to many rows per band,
@@ -38,8 +39,17 @@ def _fuzz_batch(seed, n, max_len):
     return data, synth.offsets_from_lengths(lens)
 
 
+MODE = {"bands": 1}
+
+
+@pytest.fixture(autouse=True, params=[1, 3], ids=["per_band", "persistent"])
+def band_mode(request):
+    MODE["bands"] = request.param
+    yield request.param
+
+
 def _banded(v, stage):
-    dt.set_tuning(v, tile_bytes=stage, bands=1)
+    dt.set_tuning(v, tile_bytes=stage, bands=MODE["bands"])
     return v
 
 
@@ -64,8 +74,8 @@ def _check(vs, kinds_k, data, offs, cls, side, pad_extra=0, byte_shift=0, id_shi
         oo = torch.empty(n + 1, dtype=torch.int64, device="cuda")
         outs.append((ids, oo, mask))
         opts.append(dt.make_opts(cls, dt.PADDED, side, W))
-    print("bands: n=%d nbytes=%d vocabs=%s cls=%d side=%d extra=%d shifts=%d/%d" % (
-        n, len(data), kinds_k, cls, side, pad_extra, byte_shift, id_shift), flush=True)
+    print("bands(%d): n=%d nbytes=%d vocabs=%s cls=%d side=%d extra=%d shifts=%d/%d" % (
+        MODE["bands"], n, len(data), kinds_k, cls, side, pad_extra, byte_shift, id_shift), flush=True)
     stream = torch.cuda.current_stream().cuda_stream
     if len(vs) == 1:
         ids, oo, mask = outs[0]
