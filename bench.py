@@ -85,21 +85,23 @@ def encode_leg(steps: int, warmup: int, tuning=None, per_vocab: bool = True):
         calls[s % IN_SETS].run(stream)
     torch.cuda.synchronize()
     assert dt.sync_status() == 0
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    # HIP events on the launch stream bracket the K back-to-back launches:
+    # their span / K is the average launch duration (an event pair around
+    # each launch would add its own release and timestamp to every launch)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    ev0.record(stream)
     for s in range(steps):
-        a, b = ev[s]
-        a.record(stream)
         calls[s % IN_SETS].run(stream)
-        b.record(stream)
+    ev1.record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     flags = dt.sync_status()
     if flags:
         raise RuntimeError("device error flags %d during the timed region" % flags)
     elapsed = t1 - t0
-    launch_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    launch_ms = ev0.elapsed_time(ev1) / steps
     # algorithmic bytes of one launch: the input once, its offsets once, and
     # per vocabulary the ids + mask of every cell and the output offsets
     bytes_launch = nbytes + 8 * (n + 1) + sum(8 * (n + 1) + 5 * n * plans[k][1] for k in KS)
@@ -113,6 +115,7 @@ def encode_leg(steps: int, warmup: int, tuning=None, per_vocab: bool = True):
         "value": tokens_per_step * steps / elapsed,
         "launch_ms": launch_ms,
         "bytes_per_launch": bytes_launch,
+        "bytes_written_per_launch": sum(8 * (n + 1) + 5 * n * plans[k][1] for k in KS),
         "tuning": tune_multi,
         "per_vocab": None,
         "roofline": {
@@ -210,30 +213,48 @@ def measured_traffic():
         return None
 
 
-def copy_leg(sizes=(45 << 20, 1 << 30), reps: int = 20):
-    """Plain device-to-device copies (torch's copy kernel), timed per launch
-    with HIP events like the encode: the practical HBM rate at the encode's
-    traffic size (45 MiB copy = 90 MiB moved, about one k=3 launch) and in
-    steady state (1 GiB), and the reference that calibrates the FETCH_SIZE /
-    WRITE_SIZE counters (2 * size bytes per copy)."""
+def copy_leg(sizes=(45 << 20, 1 << 30), reps: int = 20, encode_bytes: int = 0, fill_bytes: int = 0):
+    """Plain device-to-device copies (torch's copy kernel), timed like the
+    encode (events around back-to-back launches): the practical HBM rate at the encode's
+    traffic size (45 MiB copy = 90 MiB moved, about one k=3 launch; a copy
+    moving the bytes of one multi-k encode launch) and in steady state
+    (1 GiB), and the reference that calibrates the FETCH_SIZE / WRITE_SIZE
+    counters (2 * size bytes per copy). Also a write-only fill of as many
+    bytes as the multi-k encode writes. Buffers rotate over four copies so
+    no launch finds its data in the 256 MB last-level cache."""
     import torch
     out = {}
+    if fill_bytes:
+        bufs = [torch.empty(fill_bytes, dtype=torch.uint8, device="cuda") for _ in range(4)]
+        for i in range(3):
+            bufs[i].fill_(1)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for i in range(reps):
+            bufs[i % 4].fill_(i & 127)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        out["fill_%d_B" % fill_bytes] = {"ms": round(ms, 5), "GBps": round(fill_bytes / (ms * 1e-3) / 1e9, 1)}
+        del bufs
+    if encode_bytes:
+        sizes = (sizes[0], encode_bytes // 2) + tuple(sizes[1:])
     for nbytes in sizes:
         srcs = [torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(7) for _ in range(4)]
         dsts = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(4)]
         for i in range(3):
             dsts[i % 4].copy_(srcs[i % 4])
         torch.cuda.synchronize()
-        evs = []
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
         for i in range(reps):
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record()
             dsts[i % 4].copy_(srcs[(i + 1) % 4])
-            b.record()
-            evs.append((a, b))
+        b.record()
         torch.cuda.synchronize()
-        ms = float(np.median([a.elapsed_time(b) for a, b in evs]))
-        out["%d_MiB" % (nbytes >> 20)] = {"ms": round(ms, 5), "GBps": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
+        ms = a.elapsed_time(b) / reps
+        key = "%d_MiB" % (nbytes >> 20) if nbytes % (1 << 20) == 0 else "%d_B" % nbytes
+        out[key] = {"ms": round(ms, 5), "GBps": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
         del srcs, dsts
     return out
 
@@ -1008,7 +1029,7 @@ def main():
     enc = encode_leg(args.steps, args.warmup, tuning=tuning, per_vocab=not args.no_per_vocab)
     copy = None
     if not args.no_copy:
-        copy = copy_leg()
+        copy = copy_leg(encode_bytes=enc["bytes_per_launch"], fill_bytes=enc["bytes_written_per_launch"])
         enc["roofline"]["device_copy"] = copy
         log("device copy: %s" % copy)
     stream = stream_keep = None

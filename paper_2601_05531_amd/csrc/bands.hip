@@ -274,8 +274,11 @@ __device__ __forceinline__ void band_write(const BandArgs &a, int64_t r0, int nr
                         for (int q = 0; q < 4; ++q) y[q] = s_lut[raw[ro + (uint32_t)(j + q)]];
                     }
                     __builtin_nontemporal_store(y, reinterpret_cast<i32x4 *>(dst));
+                    // mask words through the cache: a wave's 4-byte stores
+                    // cover a line only together, which L2 merges (streamed
+                    // past it, they cost 7% of the launch)
                     if (mask4)
-                        __builtin_nontemporal_store(0x01010101u, reinterpret_cast<uint32_t *>(o.mask + e));
+                        *reinterpret_cast<uint32_t *>(o.mask + e) = 0x01010101u;
                     else
                         for (int q = 0; q < 4; ++q) o.mask[e + q] = 1;
                     continue;
@@ -319,7 +322,7 @@ __device__ __forceinline__ void band_write(const BandArgs &a, int64_t r0, int nr
                 if (all_in) {
                     __builtin_nontemporal_store(i32x4{v[0], v[1], v[2], v[3]}, reinterpret_cast<i32x4 *>(dst));
                     if (mask4)
-                        __builtin_nontemporal_store(mk, reinterpret_cast<uint32_t *>(o.mask + e));
+                        *reinterpret_cast<uint32_t *>(o.mask + e) = mk;
                     else
                         for (int q = 0; q < 4; ++q) o.mask[e + q] = (int8_t)((mk >> (8 * q)) & 1);
                 } else {

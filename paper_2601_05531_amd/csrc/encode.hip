@@ -761,7 +761,7 @@ __global__ __launch_bounds__(NT) void k_cells(CellArgs a) {
                             __builtin_nontemporal_store(y, d4 + j);
                             if (a.padded) {
                                 if (mask4)
-                                    __builtin_nontemporal_store(0x01010101u, reinterpret_cast<uint32_t *>(m1 + 4 * j));
+                                    *reinterpret_cast<uint32_t *>(m1 + 4 * j) = 0x01010101u;  // cached: L2 merges the words
                                 else
                                     for (int rr = 0; rr < 4; ++rr) m1[4 * j + rr] = 1;
                             }
