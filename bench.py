@@ -78,7 +78,8 @@ def encode_leg(steps: int, warmup: int, tuning=None, per_vocab: bool = True):
         tune_multi, tune_ms = calls[0].autotune(reps=3)
         log("autotuned (one pass, k=3..6): %s %.4f ms" % (tune_multi, tune_ms))
     else:
-        dt.set_tuning(vocabs[KS[0]], tile_bytes=tuning[0], blocks_per_cu=tuning[1])
+        dt.set_tuning(vocabs[KS[0]], tile_bytes=tuning[0], blocks_per_cu=tuning[1],
+                      bands=tuning[2] if len(tuning) > 2 else 0)
         tune_multi = dt.dnatok_get_tuning(vocabs[KS[0]].handle).as_dict()
         log("tiling set: %s" % tune_multi)
     for s in range(warmup):
@@ -187,7 +188,7 @@ def encode_leg(steps: int, warmup: int, tuning=None, per_vocab: bool = True):
     return res
 
 
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_cells_multi_k_batch_traffic.md")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "encode_multi_k_batch_traffic.md")
 
 
 def measured_traffic():
@@ -1006,7 +1007,7 @@ def main():
     ap.add_argument("--no-ids", action="store_true", help="skip the IDs path ablation leg")
     ap.add_argument("--no-per-vocab", action="store_true", help="skip the four single-vocabulary launches")
     ap.add_argument("--tuning", type=str, default=None,
-                    help="TILE,BLOCKS: fixed tiling of the one-pass encode instead of the autotuner's")
+                    help="TILE,BLOCKS[,BANDS]: fixed tiling of the one-pass encode instead of the autotuner's")
     ap.add_argument("--bpe-tuning", type=str, default=None,
                     help="ITEM_BYTES,WAVES: fixed BPE tiling instead of the autotuner's")
     ap.add_argument("--no-bpe-per-seq", action="store_true",
