@@ -2,12 +2,18 @@
 // future work, Discussion, "Decode Operations": the same LUT principle run
 // backwards). Not on the hot path.
 //
-// Tiles of TT token positions, each tile's output bytes contiguous. Three
-// launches: per-tile byte totals, their scan (one workgroup), and the write,
-// where each tile stages its bytes in LDS and writes them with 16-byte
-// stores. No tile waits on another and no ticket counter is involved (one
-// device-wide counter serializes at about 12 ns per ticket, which at
-// tens of thousands of tiles outweighs the decode itself).
+// Tiles of TT token positions, each tile's output bytes contiguous. Two
+// launches: a row pass (each tile's first row, the offsets check, and the
+// tile status words cleared), then one workgroup per tile that reads its
+// ids once, sums its output bytes, takes its output position by a
+// decoupled look-back over the tiles before it (Merrill and Garland's
+// single-pass prefix scan), stages its bytes in LDS at their 16-byte phase
+// in the output and writes them with 16-byte stores. Tiles follow the
+// workgroup index: a workgroup starts only after every lower-indexed one
+// on its XCD, and the XCDs take workgroups in index order, so the tile
+// with the lowest index still running never waits and the look-back ends
+// (with no ticket counter: one device-wide counter serializes at about
+// 12 ns per ticket, which at thousands of tiles outweighs the decode).
 #include "common.hpp"
 #include "device.hpp"
 
@@ -16,9 +22,9 @@ namespace dnatok {
 namespace {
 
 constexpr int NT = 256;
-constexpr int TPT = 8;  // tokens per thread
+constexpr int TPT = 16;  // tokens per thread (fewer, smaller tiles measured slower for every kind)
 constexpr int TT = NT * TPT;
-constexpr int kStage = 16384;  // bytes of one tile's output staged in LDS (2,048 k-mers of k <= 8)
+constexpr int kMaxStage = 32768;  // most bytes of one tile's output staged in LDS
 
 struct DecodeArgs {
     const int32_t *ids;
@@ -35,7 +41,8 @@ struct DecodeArgs {
     const int64_t *tok_off;
     const uint8_t *tok_chars;
     int64_t ntiles;
-    int64_t *tile_pre;   // per-tile output bytes, then their exclusive scan (ntiles + 1)
+    int32_t stage;       // bytes of the LDS stage (a tile with more output writes its tokens directly)
+    uint64_t *status;    // tile status words of the look-back (ntiles), cleared by the row pass
     int64_t *first_row;  // first row starting at or after each tile's first position (ntiles + 1)
     uint32_t *err_hdr;
 };
@@ -44,64 +51,75 @@ __device__ __forceinline__ bool is_silent(int32_t id) {
     return id == DNATOK_ID_PAD || id == DNATOK_ID_CLS || id == DNATOK_ID_SEP || id == DNATOK_ID_MASK;
 }
 
-__device__ __forceinline__ int64_t width_of(const DecodeArgs &a, int32_t id) {
+// Output bytes of one id. KIND is the vocabulary kind (a template
+// parameter, so each kind's kernel holds only its own branch).
+template <int KIND>
+__device__ __forceinline__ int32_t width_of(const DecodeArgs &a, int32_t id) {
     if (is_silent(id)) return 0;
-    if (a.kind == DNATOK_KMER) return a.k;
-    if (a.kind == DNATOK_BPE && id >= 10 && id < a.vocab) return a.tok_len[id];
+    if (KIND == DNATOK_KMER) return a.k;
+    if (KIND == DNATOK_BPE && id >= 10 && id < a.vocab) return a.tok_len[id];
     return 1;
 }
 
+// The letter of 2-bit code c (0..3: A, C, G, T) from one packed word: a
+// table in memory would cost a dependent load per base.
+__device__ __forceinline__ uint8_t base_letter(uint32_t c) { return (uint8_t)(0x54474341u >> (8 * (c & 3))); }
+
+// The letter of a single-nucleotide id (N and unknown ids: 'N').
+__device__ __forceinline__ uint8_t single_letter(int32_t id) {
+    return (id >= 5 && id <= 8) ? base_letter((uint32_t)(id - 5)) : (uint8_t)'N';
+}
+
+template <int KIND>
 __device__ __forceinline__ void write_token(const DecodeArgs &a, int32_t id, int64_t pos, uint32_t &err) {
     if (is_silent(id)) return;
-    const uint8_t base4[4] = {'A', 'C', 'G', 'T'};
-    if (a.kind == DNATOK_KMER) {
+    if (KIND == DNATOK_KMER) {
         const bool known = id >= 5 && id < a.vocab;
         uint32_t v = known ? (uint32_t)(id - 5) : 0u;
+#pragma unroll 1
         for (int j = a.k - 1; j >= 0; --j) {
             int64_t p = pos + j;
-            if (p < a.cap) a.out[p] = known ? base4[v & 3] : (uint8_t)'N';
+            if (p < a.cap) a.out[p] = known ? base_letter(v) : (uint8_t)'N';
             else err |= DNATOK_DERR_CAPACITY;
             v >>= 2;
         }
         return;
     }
-    if (a.kind == DNATOK_BPE && id >= 10 && id < a.vocab) {
+    if (KIND == DNATOK_BPE && id >= 10 && id < a.vocab) {
         const int64_t L = a.tok_len[id], o = a.tok_off[id];
+#pragma unroll 1
         for (int64_t j = 0; j < L; ++j) {
             if (pos + j < a.cap) a.out[pos + j] = a.tok_chars[o + j];
             else err |= DNATOK_DERR_CAPACITY;
         }
         return;
     }
-    uint8_t c = (id >= 5 && id <= 8) ? base4[id - 5] : (uint8_t)'N';
-    if (pos < a.cap) a.out[pos] = c;
+    if (pos < a.cap) a.out[pos] = single_letter(id);
     else err |= DNATOK_DERR_CAPACITY;
 }
 
-// Slot of tile position q (thread q / TPT, its j = q % TPT) in the prefix
-// table: j * NT + thread, so the TPT writes of a wave each hit consecutive
-// slots (thread-major order would put every lane of a write on two banks).
-__device__ __forceinline__ int32_t pre_slot(int32_t q) { return (q % TPT) * NT + q / TPT; }
-
 // The bytes of one id written to LDS at p (no bounds: the tile's staged
 // output fits the stage).
+template <int KIND>
 __device__ __forceinline__ void stage_token(const DecodeArgs &a, int32_t id, uint8_t *p) {
     if (is_silent(id)) return;
-    if (a.kind == DNATOK_KMER) {
+    if (KIND == DNATOK_KMER) {
+        // digit j (most significant first) is the letter at p[j]; unknown
+        // ids decode to k letters N (0x4E in every byte)
         const bool known = id >= 5 && id < a.vocab;
-        uint32_t v = known ? (uint32_t)(id - 5) : 0u;
-        for (int j = a.k - 1; j >= 0; --j) {
-            p[j] = known ? (uint8_t)"ACGT"[v & 3] : (uint8_t)'N';
-            v >>= 2;
-        }
+        const uint32_t v = (uint32_t)(id - 5);
+#pragma unroll 1
+        for (int j = 0; j < a.k; ++j)
+            p[j] = known ? base_letter(v >> (2 * (a.k - 1 - j))) : (uint8_t)'N';
         return;
     }
-    if (a.kind == DNATOK_BPE && id >= 10 && id < a.vocab) {
+    if (KIND == DNATOK_BPE && id >= 10 && id < a.vocab) {
         const int64_t L = a.tok_len[id], o = a.tok_off[id];
+#pragma unroll 1
         for (int64_t j = 0; j < L; ++j) p[j] = a.tok_chars[o + j];
         return;
     }
-    p[0] = (id >= 5 && id <= 8) ? (uint8_t)"ACGT"[id - 5] : (uint8_t)'N';
+    p[0] = single_letter(id);
 }
 
 // The ids of tile t this thread holds (TPT consecutive positions; ids
@@ -109,6 +127,7 @@ __device__ __forceinline__ void stage_token(const DecodeArgs &a, int32_t id, uin
 // unconditional, so a thread's loads go out together: a tile inside the rows
 // reads its TPT ids as 16-byte vectors, other tiles read clamped positions
 // and select.
+template <int KIND>
 __device__ __forceinline__ int64_t load_tile_ids(const DecodeArgs &a, int64_t t, int64_t first, int64_t last,
                                                  int32_t (&idv)[TPT]) {
     const int64_t p0 = t * TT + (int64_t)threadIdx.x * TPT;
@@ -142,26 +161,22 @@ __device__ __forceinline__ int64_t load_tile_ids(const DecodeArgs &a, int64_t t,
 #pragma unroll
         for (int j = 0; j < TPT; ++j) idv[j] = DNATOK_ID_PAD;
     }
-    int64_t mine = 0;
+    int32_t mine = 0;  // a thread's 16 tokens of at most 2^20 bases each: 32 bits
 #pragma unroll
-    for (int j = 0; j < TPT; ++j) mine += width_of(a, idv[j]);
+    for (int j = 0; j < TPT; ++j) mine += width_of<KIND>(a, idv[j]);
     return mine;
 }
 
-// 1. Output bytes of every tile, CT tiles per pass so each thread has
-// CT * TPT ids in flight; the first row of every tile; the offsets check.
-// Row i is the first row at or after position t * TT exactly for the tiles t
-// with floor(off[i-1] / TT) < t <= floor(off[i] / TT) (row n stands for the
-// end: every tile past the last row start). Bad offsets only raise the flag;
-// the tile range is clamped, and the write pass clamps what it reads.
-__global__ __launch_bounds__(NT) void k_decode_count(DecodeArgs a) {
-    constexpr int CT = 4;
-    __shared__ int64_t s_part[NT / dev::kWave][CT];
-    const int64_t first = (a.n > 0) ? a.offs[0] : 0;
-    const int64_t last = (a.n > 0) ? a.offs[a.n] : 0;
-    const int w = threadIdx.x / dev::kWave, lane = threadIdx.x & (dev::kWave - 1);
+// 1. The row pass: the first row of every tile, the offsets check, and the
+// tile status words cleared for the write pass. Row i is the first row at or
+// after position t * TT exactly for the tiles t with
+// floor(off[i-1] / TT) < t <= floor(off[i] / TT) (row n stands for the end:
+// every tile past the last row start). Bad offsets only raise the flag; the
+// tile range is clamped, and the write pass clamps what it reads.
+__global__ __launch_bounds__(NT) void k_decode_rows(DecodeArgs a) {
     uint32_t err = 0;
-    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i <= a.n; i += (int64_t)gridDim.x * NT) {
+    const int64_t G = (int64_t)gridDim.x * NT;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i <= a.n; i += G) {
         const int64_t prev = (i == 0) ? -1 : a.offs[i - 1];
         const int64_t cur = (i == a.n) ? -1 : a.offs[i];
         if (i < a.n && (cur < 0 || (i + 1 <= a.n && a.offs[i + 1] < cur) || a.offs[i + 1] > a.n_ids))
@@ -171,162 +186,111 @@ __global__ __launch_bounds__(NT) void k_decode_count(DecodeArgs a) {
         if (hi > a.ntiles) hi = a.ntiles;
         for (int64_t t = lo; t <= hi; ++t) a.first_row[t] = i;
     }
-    for (int64_t t0 = (int64_t)blockIdx.x * CT; t0 < a.ntiles; t0 += (int64_t)gridDim.x * CT) {
-        int32_t idv[CT][TPT];
-        int64_t part[CT];
-        const bool inside = t0 * TT >= first && (t0 + CT) * TT <= last && (t0 + CT) * TT <= a.n_ids &&
-                            (reinterpret_cast<uintptr_t>(a.ids) & 15) == 0;  // uniform over the block
-        if (inside) {
-            // all CT tiles inside the rows: every load of the pass goes out at once
-#pragma unroll
-            for (int c = 0; c < CT; ++c) {
-                const int4 *q = reinterpret_cast<const int4 *>(a.ids + (t0 + c) * TT + (int64_t)threadIdx.x * TPT);
-#pragma unroll
-                for (int j = 0; j < TPT; j += 4) {
-                    const int4 v = q[j / 4];
-                    idv[c][j] = v.x;
-                    idv[c][j + 1] = v.y;
-                    idv[c][j + 2] = v.z;
-                    idv[c][j + 3] = v.w;
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < CT; ++c) {
-                part[c] = 0;
-#pragma unroll
-                for (int j = 0; j < TPT; ++j) part[c] += width_of(a, idv[c][j]);
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < CT; ++c) part[c] = load_tile_ids(a, t0 + c, first, last, idv[c]);
-        }
-#pragma unroll
-        for (int c = 0; c < CT; ++c) {
-            const int64_t v = dev::wave_sum(part[c]);
-            if (lane == 0) s_part[w][c] = v;
-        }
-        __syncthreads();
-        if (threadIdx.x < CT && t0 + threadIdx.x < a.ntiles) {
-            int64_t sum = 0;
-            for (int q = 0; q < NT / dev::kWave; ++q) sum += s_part[q][threadIdx.x];
-            a.tile_pre[t0 + threadIdx.x] = sum;
-        }
-        __syncthreads();
-    }
+    for (int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x; t < a.ntiles; t += G) a.status[t] = 0;
     if (err) dev::raise_error(a.err_hdr, err);
 }
 
-// 2. Exclusive scan of the tile totals in place (one workgroup); the total
-// goes to tile_pre[ntiles] and out_offs[n].
-__global__ __launch_bounds__(NT) void k_decode_scan(DecodeArgs a) {
-    __shared__ int64_t s_tmp[NT / dev::kWave + 1];
-    constexpr int PER = 16;
-    int64_t run = 0;
-    for (int64_t c0 = 0; c0 < a.ntiles; c0 += (int64_t)NT * PER) {
-        const int64_t i0 = c0 + (int64_t)threadIdx.x * PER;
-        int64_t v[PER];
-        int64_t mine = 0;
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            // unconditional load of a clamped entry (ntiles >= 1), so the
-            // thread's loads go out together
-            const int64_t x = a.tile_pre[i0 + j < a.ntiles ? i0 + j : a.ntiles - 1];
-            v[j] = (i0 + j < a.ntiles) ? x : 0;
-            mine += v[j];
-        }
-        int64_t tot;
-        int64_t pre = run + dev::block_excl_scan<NT>(mine, s_tmp, &tot);
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            if (i0 + j < a.ntiles) a.tile_pre[i0 + j] = pre;
-            pre += v[j];
-        }
-        run += tot;
-    }
-    if (threadIdx.x == 0) {
-        a.tile_pre[a.ntiles] = run;
-        a.out_offs[a.n] = run;
-    }
-}
-
-// 3. Each tile's bytes, staged in LDS at their 16-byte phase in the output
-// and written with 16-byte stores (partial first and last units byte by
-// byte); a tile whose output exceeds the stage, or that would cross the
-// capacity, writes its tokens directly. Rows starting in the tile get their
-// output offsets.
+// 2. One workgroup per tile (tile = workgroup index): the tile's ids are
+// read once; their byte total is published for later tiles before the
+// look-back, which wave 0 runs while the other waves go on to the barrier.
+// The bytes are staged in LDS at their 16-byte phase in the output and
+// written with 16-byte stores (partial first and last units byte by byte);
+// a tile whose output exceeds the stage, or would cross the capacity,
+// writes its tokens directly. Rows starting in the tile get their output
+// offsets; the last tile writes the total.
+template <int KIND>
 __global__ __launch_bounds__(NT) void k_decode_write(DecodeArgs a) {
-    __shared__ __align__(16) uint8_t s_out[kStage + 16];
-    __shared__ int32_t s_pre[TT + 1];  // bytes before each tile position (in-tile, so 32-bit), position-major
+    extern __shared__ __align__(16) uint8_t s_out[];
+    __shared__ int64_t s_tpre[NT + 1];  // in-tile bytes before each thread's first position (and the total)
     __shared__ int64_t s_tmp[NT / dev::kWave + 1];
-    __shared__ int64_t s_ia, s_ib;
+    __shared__ int64_t s_ia, s_ib, s_base;
     const int tid = threadIdx.x;
+    const int64_t t = blockIdx.x;
+    const int64_t P0 = t * TT;
+    // the tile's rows go out with its ids (neither depends on the other)
+    int64_t ia = 0, ib = 0;
+    if (tid == 0) {
+        ia = a.first_row[t];
+        ib = (t == a.ntiles - 1) ? a.n : a.first_row[t + 1];
+    }
     const int64_t first = (a.n > 0) ? a.offs[0] : 0;
     const int64_t last = (a.n > 0) ? a.offs[a.n] : 0;
-    uint32_t err = 0;
-    for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-        const int64_t P0 = t * TT, P1 = P0 + TT;
-        int32_t idv[TPT];
-        const int64_t mine = load_tile_ids(a, t, first, last, idv);
-        int64_t agg;
-        const int64_t pre = dev::block_excl_scan<NT>(mine, s_tmp, &agg);
-        {
-            int64_t run = pre;
-#pragma unroll
-            for (int j = 0; j < TPT; ++j) {
-                s_pre[pre_slot(tid * TPT + j)] = (int32_t)run;  // lanes write consecutive slots: no bank conflicts
-                run += width_of(a, idv[j]);
-            }
-            if (tid == NT - 1) s_pre[TT] = (int32_t)run;
-        }
+    int32_t idv[TPT];
+    const int64_t mine = load_tile_ids<KIND>(a, t, first, last, idv);
+    int64_t agg;
+    const int64_t pre = dev::block_excl_scan<NT>(mine, s_tmp, &agg);
+    if (tid < dev::kWave) {
+        if (tid == 0) dev::publish_aggregate(a.status, t, agg);
+        const int64_t excl = dev::wave_lookback(a.status, t, agg, a.err_hdr);
         if (tid == 0) {
             // rows starting in the tile (clamped: bad offsets leave the
-            // table unchecked, and they raise the flag in the count pass)
-            int64_t ia = a.first_row[t], ib = (t == a.ntiles - 1) ? a.n : a.first_row[t + 1];
+            // table unchecked, and they raise the flag in the row pass)
             ia = ia < 0 ? 0 : (ia > a.n ? a.n : ia);
             ib = ib < ia ? ia : (ib > a.n ? a.n : ib);
             s_ia = ia;
             s_ib = ib;
+            s_base = excl;
         }
-        const int64_t base = a.tile_pre[t];
-        const int64_t ph = (int64_t)((reinterpret_cast<uintptr_t>(a.out) + (uintptr_t)base) & 15);
-        const bool staged = agg <= kStage && base + agg <= a.cap;
-        if (staged) {
-            int64_t pos = pre;
-#pragma unroll
-            for (int j = 0; j < TPT; ++j) {
-                stage_token(a, idv[j], s_out + ph + pos);
-                pos += width_of(a, idv[j]);
-            }
-        } else {
-            int64_t pos = base + pre;
-#pragma unroll
-            for (int j = 0; j < TPT; ++j) {
-                write_token(a, idv[j], pos, err);
-                pos += width_of(a, idv[j]);
-            }
-        }
-        __syncthreads();
-        if (staged && agg > 0) {
-            // s_out[ph + i] is output byte base + i; unit u covers stage bytes
-            // [16u, 16u + 16), i.e. output base - ph + 16u, 16-byte aligned
-            uint8_t *ob = a.out + base - ph;
-            const int64_t nu = (ph + agg + 15) / 16;
-            for (int64_t u = tid; u < nu; u += NT) {
-                const int64_t lo = 16 * u, hi = lo + 16;
-                if (lo >= ph && hi <= ph + agg) {
-                    *reinterpret_cast<uint4 *>(ob + lo) = *reinterpret_cast<const uint4 *>(s_out + lo);
-                } else {
-                    for (int64_t b = (lo > ph ? lo : ph); b < hi && b < ph + agg; ++b) ob[b] = s_out[b];
-                }
-            }
-        }
-        for (int64_t i = s_ia + tid; i < s_ib; i += NT) {
-            int64_t rel = a.offs[i] - P0;
-            rel = rel < 0 ? 0 : (rel > TT ? TT : rel);
-            a.out_offs[i] = base + s_pre[rel == TT ? TT : pre_slot((int32_t)rel)];
-        }
-        __syncthreads();
     }
+    s_tpre[tid] = pre;
+    if (tid == NT - 1) s_tpre[NT] = pre + mine;
+    __syncthreads();
+    const int64_t base = s_base;
+    uint32_t err = 0;
+    const int64_t ph = (int64_t)((reinterpret_cast<uintptr_t>(a.out) + (uintptr_t)base) & 15);
+    const bool staged = ph + agg <= a.stage && base + agg <= a.cap;
+    if (staged) {
+        // in-tile positions fit 32 bits (the stage is at most 32 KiB)
+        uint32_t pos = (uint32_t)(ph + pre);
+#pragma unroll
+        for (int j = 0; j < TPT; ++j) {
+            stage_token<KIND>(a, idv[j], s_out + pos);
+            pos += (uint32_t)width_of<KIND>(a, idv[j]);
+        }
+    } else {
+        // rare (output over the stage or past the capacity): the ids again,
+        // one at a time from the cache, written straight to the output
+        int64_t pos = base + pre;
+        const int64_t p0 = t * TT + (int64_t)tid * TPT;
+#pragma unroll 1
+        for (int j = 0; j < TPT; ++j) {
+            const int64_t q = p0 + j;
+            const bool live = q >= first && q < last && q < a.n_ids;
+            const int32_t id = live ? a.ids[q] : DNATOK_ID_PAD;
+            write_token<KIND>(a, id, pos, err);
+            pos += width_of<KIND>(a, id);
+        }
+    }
+    __syncthreads();
+    if (staged && agg > 0) {
+        // s_out[ph + i] is output byte base + i; unit u covers stage bytes
+        // [16u, 16u + 16), i.e. output base - ph + 16u, 16-byte aligned
+        uint8_t *ob = a.out + base - ph;
+        const int64_t nu = (ph + agg + 15) / 16;
+        for (int64_t u = tid; u < nu; u += NT) {
+            const int64_t lo = 16 * u, hi = lo + 16;
+            if (lo >= ph && hi <= ph + agg) {
+                *reinterpret_cast<uint4 *>(ob + lo) = *reinterpret_cast<const uint4 *>(s_out + lo);
+            } else {
+                for (int64_t b = (lo > ph ? lo : ph); b < hi && b < ph + agg; ++b) ob[b] = s_out[b];
+            }
+        }
+    }
+    // rows starting in the tile: the bytes before their first position are
+    // the owning thread's prefix plus its ids before that position (read
+    // again from the cache; a tile holds a few row starts)
+    for (int64_t i = s_ia + tid; i < s_ib; i += NT) {
+        int64_t rel = a.offs[i] - P0;
+        rel = rel < 0 ? 0 : (rel > TT ? TT : rel);
+        const int th = (int)(rel / TPT);
+        int64_t sum = s_tpre[th];
+        for (int64_t q = P0 + (int64_t)th * TPT; q < P0 + rel; ++q) {
+            const bool live = q >= first && q < last && q < a.n_ids;
+            sum += width_of<KIND>(a, live ? a.ids[q] : DNATOK_ID_PAD);
+        }
+        a.out_offs[i] = base + sum;
+    }
+    if (t == a.ntiles - 1 && tid == 0) a.out_offs[a.n] = base + agg;
     if (err) dev::raise_error(a.err_hdr, err);
 }
 
@@ -349,24 +313,29 @@ int launch_decode(const dnatok_vocab *v, const int32_t *d_ids, int64_t n_ids, co
     a.tok_off = v->bpe.d_tok_off;
     a.tok_chars = v->bpe.d_tok_chars;
     a.ntiles = n_ids / TT + 1;
+    if (a.ntiles >= (1ll << 31)) return set_error(DNATOK_EINVAL, "too many ids for one decode");
+    // the stage holds a tile's output at the vocabulary's widest token
+    const int64_t wmax = v->kind == DNATOK_KMER ? v->k : (v->kind == DNATOK_BPE ? v->max_token_bytes : 1);
+    a.stage = (int32_t)(std::min<int64_t>((int64_t)TT * std::max<int64_t>(wmax, 1), kMaxStage) + 16);
     Workspace *ws = nullptr;
     int rc = get_workspace(stream, 1, &ws);
     if (rc) return rc;
     rc = ensure_scratch(ws, 16 * (a.ntiles + 1));
     if (rc) return rc;
-    a.tile_pre = reinterpret_cast<int64_t *>(ws->d_scratch);
-    a.first_row = a.tile_pre + (a.ntiles + 1);
+    a.status = reinterpret_cast<uint64_t *>(ws->d_scratch);
+    a.first_row = reinterpret_cast<int64_t *>(a.status + (a.ntiles + 1));
     a.err_hdr = ws->d_hdr;
-    int per_cu = 0;
-    DNATOK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_decode_write, NT, 0));
-    if (per_cu < 1) per_cu = 1;
-    int64_t grid = 4 * (int64_t)device_cu_count() * per_cu;
-    if (grid > a.ntiles) grid = a.ntiles;
-    hipLaunchKernelGGL(k_decode_count, dim3((unsigned)grid), dim3(NT), 0, stream, a);
+    const int64_t rows_grid = std::min<int64_t>(((int64_t)n + 1 + NT - 1) / NT + 1, 4ll * device_cu_count());
+    hipLaunchKernelGGL(k_decode_rows, dim3((unsigned)std::max<int64_t>(rows_grid, 1)), dim3(NT), 0, stream, a);
     DNATOK_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_decode_scan, dim3(1), dim3(NT), 0, stream, a);
-    DNATOK_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_decode_write, dim3((unsigned)grid), dim3(NT), 0, stream, a);
+    const dim3 grid((unsigned)a.ntiles), block(NT);
+    const size_t dyn = (size_t)a.stage;
+    if (v->kind == DNATOK_KMER)
+        hipLaunchKernelGGL(k_decode_write<DNATOK_KMER>, grid, block, dyn, stream, a);
+    else if (v->kind == DNATOK_BPE)
+        hipLaunchKernelGGL(k_decode_write<DNATOK_BPE>, grid, block, dyn, stream, a);
+    else
+        hipLaunchKernelGGL(k_decode_write<DNATOK_SINGLE>, grid, block, dyn, stream, a);
     DNATOK_HIP(hipGetLastError());
     return DNATOK_OK;
 }

@@ -179,7 +179,8 @@ __device__ __forceinline__ void publish_aggregate(uint64_t *status, int64_t tile
 
 // Most polls of a predecessor's status word before the look-back gives up.
 // Every predecessor is held by a block that is already running (tiles go
-// out in ticket order) and publishes within microseconds; a million polls
+// out in ticket order, or follow the workgroup index, which the XCDs
+// dispatch in order) and publishes within microseconds; a million polls
 // (each one a global load and a short sleep) is about a second, so reaching
 // the cap means the protocol was broken (e.g. two launches sharing one
 // workspace at once), never a slow peer.
@@ -193,8 +194,9 @@ __device__ __forceinline__ void raise_error(uint32_t *hdr, uint32_t flag) { atom
 // inclusive prefix, and stops there; otherwise it adds all 64 aggregates and
 // moves 64 tiles further back. Tile indices below 0 read as an inclusive
 // prefix of 0. Afterwards lane 0 publishes this tile's inclusive prefix.
-// Tiles are handed out in ticket order, so every predecessor is held by a
-// block that started earlier and never waits on a later tile: the wait ends.
+// Tiles are handed out in ticket order (or follow the workgroup index), so
+// every predecessor is held by a block that started earlier and never waits
+// on a later tile: the wait ends.
 // Should a predecessor stay unpublished for kLookbackMaxPolls polls, the
 // wave raises DNATOK_DERR_INTERNAL in hdr, counts what it has, and still
 // publishes, so no later tile waits on it and the launch drains.

@@ -296,6 +296,70 @@ def test_decode_matches_oracle(kind, k):
     assert np.array_equal(out.cpu().numpy()[:want_off[-1]], want)
 
 
+@pytest.mark.parametrize("kind,k", [(dt.SINGLE, 1), (dt.KMER, 6), (dt.KMER, 8), (dt.KMER, 12)])
+def test_decode_many_tiles_look_back(kind, k):
+    """Some 3M ids (hundreds of tiles of 4,096 ids, so
+    the look-back walks more than one window of 64 predecessors), specials
+    and out-of-vocabulary ids mixed in, rows from empty to 20,000 ids, the
+    output at several 16-byte phases: every byte and offset against the
+    oracle."""
+    torch = _torch()
+    rng = np.random.default_rng(100 + k)
+    vs = 10 if kind == dt.SINGLE else 5 + 4 ** k
+    n_ids = 3_000_000 if k <= 8 else 700_000
+    ids = rng.integers(5, vs, n_ids).astype(np.int32)
+    sp = rng.random(n_ids) < 0.01
+    ids[sp] = rng.integers(-2, 12, int(sp.sum()))
+    lens = rng.integers(0, 20000, 400)
+    offs = synth.offsets_from_lengths(lens)
+    offs = np.concatenate([offs[offs < n_ids], [n_ids]]).astype(np.int64)
+    v = _vocab(kind, k)
+    want, want_off = oracle.decode(kind, ids, offs, k=k)
+    d_ids, d_offs = _dev(ids), _dev(offs)
+    n = len(offs) - 1
+    cap = int(want_off[-1])
+    for shift in (0, 3, 13):
+        print("decode kind=%d k=%d shift=%d ids=%d rows=%d" % (kind, k, shift, n_ids, n), flush=True)
+        buf = torch.full((cap + 64,), 7, dtype=torch.uint8, device="cuda")
+        oo = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+        dt.dnatok_decode(v.handle, d_ids.data_ptr(), n_ids, d_offs.data_ptr(), n, buf.data_ptr() + shift, cap,
+                         oo.data_ptr(), None)
+        torch.cuda.synchronize()
+        assert dt.sync_status() == 0
+        assert np.array_equal(oo.cpu().numpy(), want_off)
+        got = buf.cpu().numpy()
+        assert np.all(got[:shift] == 7) and np.all(got[shift + cap:] == 7)
+        bad = np.nonzero(got[shift:shift + cap] != want)[0]
+        assert bad.size == 0, "first mismatch at byte %d" % bad[0]
+
+
+@pytest.mark.parametrize("kind,k", [(dt.SINGLE, 1), (dt.KMER, 6)])
+def test_decode_capacity_short(kind, k):
+    """An output buffer 1,001 bytes short: DERR_CAPACITY is raised, the
+    bytes inside the capacity are right (tiles crossing it write their
+    tokens one by one), nothing is written past it, and the output offsets
+    are still the full ones."""
+    torch = _torch()
+    rng = np.random.default_rng(300 + k)
+    vs = 10 if kind == dt.SINGLE else 5 + 4 ** k
+    n_ids = 400_000
+    ids = rng.integers(5, vs, n_ids).astype(np.int32)
+    offs = np.array([0, 1000, 150_000, n_ids], np.int64)
+    v = _vocab(kind, k)
+    want, want_off = oracle.decode(kind, ids, offs, k=k)
+    cap = int(want_off[-1]) - 1001
+    buf = torch.full((cap + 4096,), 7, dtype=torch.uint8, device="cuda")
+    oo = torch.empty(len(offs), dtype=torch.int64, device="cuda")
+    dt.dnatok_decode(v.handle, _dev(ids).data_ptr(), n_ids, _dev(offs).data_ptr(), len(offs) - 1, buf.data_ptr(), cap,
+                     oo.data_ptr(), None)
+    torch.cuda.synchronize()
+    assert dt.sync_status() == dt.DERR_CAPACITY
+    got = buf.cpu().numpy()
+    assert np.array_equal(got[:cap], want[:cap])
+    assert np.all(got[cap:] == 7)
+    assert np.array_equal(oo.cpu().numpy(), want_off)
+
+
 def test_encode_decode_roundtrip_acgt():
     torch = _torch()
     rng = np.random.default_rng(1)
