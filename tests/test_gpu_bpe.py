@@ -174,6 +174,37 @@ def test_decode_matches_oracle(trained_small):
     assert np.array_equal(out.cpu().numpy()[:len(w_bytes)], w_bytes)
 
 
+def test_decode_long_tokens_tiles_over_the_stage(trained_small):
+    """Ids of the longest merges, densely: a 4,096-id tile's output is far
+    over the 32 KiB LDS stage, so tiles write their tokens directly; mixed
+    with short ids and specials so staged and direct tiles alternate, and
+    rows start inside tiles. Every byte and offset against the oracle."""
+    torch = _torch()
+    merges = trained_small
+    R = len(merges)
+    lens = np.ones(10 + R, np.int64)
+    for r, (a, b) in enumerate(merges):
+        lens[10 + r] = lens[a] + lens[b]
+    longest = 10 + np.argsort(-lens[10:])[:16]
+    assert lens[longest[0]] >= 9
+    rng = np.random.default_rng(77)
+    n_ids = 200_000
+    ids = rng.integers(5, 10 + R, n_ids).astype(np.int32)
+    # stretches of long tokens, about half of the tiles
+    for t0 in range(0, n_ids, 8192):
+        ids[t0:t0 + 4096] = longest[rng.integers(0, len(longest), min(4096, n_ids - t0))]
+    sp = rng.random(n_ids) < 0.01
+    ids[sp] = rng.integers(0, 5, int(sp.sum()))
+    offs = np.concatenate([[0], np.sort(rng.choice(np.arange(1, n_ids), 300, replace=False)), [n_ids]]).astype(np.int64)
+    v = dt.Vocab(dt.BPE, merges=merges)
+    want, want_off = oracle.decode(oracle.BPE, ids, offs, merges=merges)
+    out, out_off = dt.decode(v, _dev(ids), _dev(offs))
+    torch.cuda.synchronize()
+    assert dt.sync_status() == 0
+    assert np.array_equal(out_off.cpu().numpy(), want_off)
+    assert np.array_equal(out.cpu().numpy()[:len(want)], want)
+
+
 def test_empty_batch_and_bad_tables():
     torch = _torch()
     merges = _random_table(4, 50)
