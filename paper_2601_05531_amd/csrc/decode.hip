@@ -41,7 +41,7 @@ struct DecodeArgs {
     const int64_t *tok_off;
     const uint8_t *tok_chars;
     int64_t ntiles;
-    int32_t stage;       // bytes of the LDS stage (a tile with more output writes its tokens directly)
+    int32_t stage;       // bytes the LDS stage holds (a tile with more output writes its tokens directly)
     uint64_t *status;    // tile status words of the look-back (ntiles), cleared by the row pass
     int64_t *first_row;  // first row starting at or after each tile's first position (ntiles + 1)
     uint32_t *err_hdr;
@@ -192,12 +192,13 @@ __global__ __launch_bounds__(NT) void k_decode_rows(DecodeArgs a) {
 
 // 2. One workgroup per tile (tile = workgroup index): the tile's ids are
 // read once; their byte total is published for later tiles before the
-// look-back, which wave 0 runs while the other waves go on to the barrier.
-// The bytes are staged in LDS at their 16-byte phase in the output and
-// written with 16-byte stores (partial first and last units byte by byte);
-// a tile whose output exceeds the stage, or would cross the capacity,
-// writes its tokens directly. Rows starting in the tile get their output
-// offsets; the last tile writes the total.
+// look-back, which wave 0 runs while the other waves stage the tile's bytes
+// in LDS. Once the output position is known, the block writes the output's
+// 16-byte units (each read from the stage realigned to the output's phase;
+// partial first and last units byte by byte), up to the capacity (past it:
+// the flag); a tile whose output exceeds the stage writes its tokens
+// directly. Rows starting in the tile get their output offsets; the last
+// tile writes the total.
 template <int KIND>
 __global__ __launch_bounds__(NT) void k_decode_write(DecodeArgs a) {
     extern __shared__ __align__(16) uint8_t s_out[];
@@ -234,22 +235,52 @@ __global__ __launch_bounds__(NT) void k_decode_write(DecodeArgs a) {
     }
     s_tpre[tid] = pre;
     if (tid == NT - 1) s_tpre[NT] = pre + mine;
-    __syncthreads();
-    const int64_t base = s_base;
-    uint32_t err = 0;
-    const int64_t ph = (int64_t)((reinterpret_cast<uintptr_t>(a.out) + (uintptr_t)base) & 15);
-    const bool staged = ph + agg <= a.stage && base + agg <= a.cap;
+    // The bytes go to LDS from stage offset 0 while wave 0 still waits on
+    // the look-back (their output position matters only to the stores).
+    const bool staged = agg <= a.stage;
     if (staged) {
         // in-tile positions fit 32 bits (the stage is at most 32 KiB)
-        uint32_t pos = (uint32_t)(ph + pre);
+        uint32_t pos = (uint32_t)pre;
 #pragma unroll
         for (int j = 0; j < TPT; ++j) {
             stage_token<KIND>(a, idv[j], s_out + pos);
             pos += (uint32_t)width_of<KIND>(a, idv[j]);
         }
+    }
+    __syncthreads();
+    const int64_t base = s_base;
+    uint32_t err = 0;
+    if (staged) {
+        // output byte base + b is stage byte b, for b below the capacity;
+        // the output's 16-byte units from out + base - ph on, each read from
+        // the stage as 5 dwords realigned by ph
+        const int64_t room = a.cap - base;
+        const int64_t lim = room <= 0 ? 0 : (room < agg ? room : agg);
+        if (lim < agg) err |= DNATOK_DERR_CAPACITY;
+        const int64_t ph = (int64_t)((reinterpret_cast<uintptr_t>(a.out) + (uintptr_t)base) & 15);
+        uint8_t *ob = a.out + base - ph;
+        const uint32_t *s32 = reinterpret_cast<const uint32_t *>(s_out);
+        const int64_t nu = lim > 0 ? (ph + lim + 15) / 16 : 0;
+        for (int64_t u = tid; u < nu; u += NT) {
+            const int64_t lo = 16 * u - ph, hi = lo + 16;  // the unit's stage bytes
+            if (lo >= 0 && hi <= lim) {
+                const uint32_t w0 = (uint32_t)lo >> 2, r = (uint32_t)lo & 3;
+                uint32_t w[5];
+#pragma unroll
+                for (int q = 0; q < 5; ++q) w[q] = s32[w0 + q];
+                uint4 o;
+                o.x = __builtin_amdgcn_alignbyte(w[1], w[0], r);
+                o.y = __builtin_amdgcn_alignbyte(w[2], w[1], r);
+                o.z = __builtin_amdgcn_alignbyte(w[3], w[2], r);
+                o.w = __builtin_amdgcn_alignbyte(w[4], w[3], r);
+                *reinterpret_cast<uint4 *>(ob + 16 * u) = o;
+            } else {
+                for (int64_t b = (lo > 0 ? lo : 0); b < hi && b < lim; ++b) ob[ph + b] = s_out[b];
+            }
+        }
     } else {
-        // rare (output over the stage or past the capacity): the ids again,
-        // one at a time from the cache, written straight to the output
+        // rare (output over the stage): the ids again, one at a time from
+        // the cache, written straight to the output
         int64_t pos = base + pre;
         const int64_t p0 = t * TT + (int64_t)tid * TPT;
 #pragma unroll 1
@@ -259,21 +290,6 @@ __global__ __launch_bounds__(NT) void k_decode_write(DecodeArgs a) {
             const int32_t id = live ? a.ids[q] : DNATOK_ID_PAD;
             write_token<KIND>(a, id, pos, err);
             pos += width_of<KIND>(a, id);
-        }
-    }
-    __syncthreads();
-    if (staged && agg > 0) {
-        // s_out[ph + i] is output byte base + i; unit u covers stage bytes
-        // [16u, 16u + 16), i.e. output base - ph + 16u, 16-byte aligned
-        uint8_t *ob = a.out + base - ph;
-        const int64_t nu = (ph + agg + 15) / 16;
-        for (int64_t u = tid; u < nu; u += NT) {
-            const int64_t lo = 16 * u, hi = lo + 16;
-            if (lo >= ph && hi <= ph + agg) {
-                *reinterpret_cast<uint4 *>(ob + lo) = *reinterpret_cast<const uint4 *>(s_out + lo);
-            } else {
-                for (int64_t b = (lo > ph ? lo : ph); b < hi && b < ph + agg; ++b) ob[b] = s_out[b];
-            }
         }
     }
     // rows starting in the tile: the bytes before their first position are
@@ -316,7 +332,7 @@ int launch_decode(const dnatok_vocab *v, const int32_t *d_ids, int64_t n_ids, co
     if (a.ntiles >= (1ll << 31)) return set_error(DNATOK_EINVAL, "too many ids for one decode");
     // the stage holds a tile's output at the vocabulary's widest token
     const int64_t wmax = v->kind == DNATOK_KMER ? v->k : (v->kind == DNATOK_BPE ? v->max_token_bytes : 1);
-    a.stage = (int32_t)(std::min<int64_t>((int64_t)TT * std::max<int64_t>(wmax, 1), kMaxStage) + 16);
+    a.stage = (int32_t)std::min<int64_t>((int64_t)TT * std::max<int64_t>(wmax, 1), kMaxStage);
     Workspace *ws = nullptr;
     int rc = get_workspace(stream, 1, &ws);
     if (rc) return rc;
@@ -329,7 +345,7 @@ int launch_decode(const dnatok_vocab *v, const int32_t *d_ids, int64_t n_ids, co
     hipLaunchKernelGGL(k_decode_rows, dim3((unsigned)std::max<int64_t>(rows_grid, 1)), dim3(NT), 0, stream, a);
     DNATOK_HIP(hipGetLastError());
     const dim3 grid((unsigned)a.ntiles), block(NT);
-    const size_t dyn = (size_t)a.stage;
+    const size_t dyn = (size_t)a.stage + 16;  // a unit's realigning reads go up to 3 bytes past the data
     if (v->kind == DNATOK_KMER)
         hipLaunchKernelGGL(k_decode_write<DNATOK_KMER>, grid, block, dyn, stream, a);
     else if (v->kind == DNATOK_BPE)
