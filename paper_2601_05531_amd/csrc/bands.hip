@@ -39,7 +39,6 @@ struct BandVocab {
     int32_t *ids;
     int8_t *mask;
     int64_t W;
-    uint32_t winv;  // floor((2^32 - 1) / W), W < 2^31
     int32_t pad_id, cls_id, sep_id;
 };
 
@@ -66,17 +65,6 @@ struct BandArgs {
     BandVocab vo[kBandVocabs];
     RowScanArgs scan[kBandVocabs];
 };
-
-__device__ __forceinline__ uint32_t umod_w(uint32_t x, uint32_t W, uint32_t winv, uint32_t *q) {
-    uint32_t d = __umulhi(x, winv);
-    uint32_t r = x - d * W;
-    if (r >= W) {
-        r -= W;
-        ++d;
-    }
-    *q = d;
-    return r;
-}
 
 // Digits (most significant first) of k bytes read one by one from global
 // memory, positions clamped to the input (slow path); -1 if any byte is not
@@ -750,7 +738,6 @@ int launch_encode_bands(const dnatok_vocab *const *vs, int nv, const uint8_t *d_
         bv.ids = d_ids[vi];
         bv.mask = d_masks[vi];
         bv.W = os[vi].pad_to;
-        bv.winv = (uint32_t)(0xFFFFFFFFull / (uint64_t)bv.W);
         bv.pad_id = vs[vi]->pad_id;
         bv.cls_id = vs[vi]->cls_id;
         bv.sep_id = vs[vi]->sep_id;
