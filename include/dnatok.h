@@ -383,7 +383,9 @@ int dnatok_stream_destroy(dnatok_stream *s);
  * embedder (here the library's embedding lookup). Micro-batches hold
  * b = min(B_emb, max(1, floor(M / T'))) rows for a token budget M. The
  * sequential form copies and computes each micro-batch in order on one
- * stream (the paper's streaming baseline); the pipelined form copies
+ * stream after mapping every row (the paper's streaming baseline); the
+ * pipelined form maps each micro-batch just before its copy, so the host
+ * maps micro-batch n + 1 while micro-batch n is copied, and copies
  * micro-batch n + 1 on a side stream into the other of two ping-pong device
  * buffers while micro-batch n is widened and embedded (two int64 buffers
  * with int64 staging; two int32 copy buffers plus two int64 buffers with
@@ -408,7 +410,7 @@ typedef struct dnatok_ids_result {
     int64_t micro_rows;      /* b */
     int64_t n_micro;         /* micro-batches */
     int64_t h2d_bytes;       /* staged id bytes copied to the device */
-    double map_s;            /* host mapping time (wall clock) */
+    double map_s;            /* host mapping time (wall clock; pipelined: the sum over micro-batches) */
     double h2d_s;            /* sum of the copies' device times (HIP events on the copying stream) */
     double total_s;          /* the whole call, mapping to the last output written (wall clock) */
 } dnatok_ids_result;

@@ -275,14 +275,24 @@ int dnatok_ids_run(dnatok_ids *p, const uint8_t *h_bytes, int64_t n_rows, int64_
     const int64_t w = p->o.width;
 
     const double t0 = now_s();
-    // host map: every row into the pinned staging, left-padded to T'
-    map_parallel(*p->pool, p->lut, p->pad_id, h_bytes, n_rows, row_len, T, (int32_t)w, p->h_stage);
-    const double t1 = now_s();
-    r.map_s = t1 - t0;
+    // host map into the pinned staging, left-padded to T': every row first
+    // (sequential form), or each micro-batch just before its copy, so that
+    // the host maps micro-batch n + 1 while the copy engine moves n
+    // (pipelined form; the copies and kernels are asynchronous)
+    if (!p->o.overlap) {
+        map_parallel(*p->pool, p->lut, p->pad_id, h_bytes, n_rows, row_len, T, (int32_t)w, p->h_stage);
+        r.map_s = now_s() - t0;
+    }
 
     const uint8_t *hs = static_cast<const uint8_t *>(p->h_stage);
     for (int64_t m = 0; m < n_micro; ++m) {
         const int64_t lo = m * b, rows = std::min(b, n_rows - lo), cells = rows * T;
+        if (p->o.overlap) {
+            const double tm = now_s();
+            map_parallel(*p->pool, p->lut, p->pad_id, h_bytes + lo * row_len, rows, row_len, T, (int32_t)w,
+                         static_cast<uint8_t *>(p->h_stage) + lo * T * w);
+            r.map_s += now_s() - tm;
+        }
         const int buf = p->o.overlap ? (int)(m & 1) : 0;
         // the ids the embedder reads: the caller's slice, else a ping-pong buffer
         int64_t *ids64 = d_ids ? d_ids + lo * T : (w == 8 ? static_cast<int64_t *>(p->d_stage[buf]) : p->d_wide[buf]);
