@@ -12,7 +12,10 @@ benchmark times:
   1 Mbase over four vocabularies (single-nucleotide, 3-mer, 6-mer,
   BPE-4096), 32 MiB / 512-request batches under a 16 GiB budget, replayed
   at the trace's arrival times, each result against the oracle's encode of
-  that sequence alone.
+  that sequence alone;
+* decode of the batched workload's PACKED ids (4096 x 8192 bases with
+  CLS/SEP: 33.6M single-nucleotide ids, 5.6M 6-mer ids), as the benchmark
+  decodes them.
 
 The oracle runs with its rows split over host threads (a static partition by
 bytes; the same result as one call)."""
@@ -192,3 +195,21 @@ def test_serving_trace_full_size_range():
             else "lengths %d vs %d" % (len(got[i]), len(res[i])))
     for row in vocab_rows:
         row[0].close()
+
+
+@pytest.mark.parametrize("kind,k", [(oracle.SINGLE, 1), (oracle.KMER, 6)])
+def test_decode_batched_workload(kind, k):
+    torch = _torch()
+    data, offs = synth.workload_markov_batch()
+    ids_h, off_h = oracle.encode_threads(kind, data, offs, threads=_threads(), k=k, add_cls_sep=True)
+    want, want_off = oracle.decode(kind, ids_h, off_h, k=k)
+    print("decode %s: %d ids -> %d bytes" % ("single" if kind == oracle.SINGLE else "6-mer", len(ids_h), len(want)),
+          flush=True)
+    v = dt.Vocab(kind, k=k)
+    out, out_off = dt.decode(v, torch.from_numpy(ids_h).cuda(), torch.from_numpy(off_h).cuda())
+    torch.cuda.synchronize()
+    assert dt.sync_status() == 0
+    assert np.array_equal(out_off.cpu().numpy(), want_off)
+    got = out[:len(want)].cpu().numpy()
+    assert np.array_equal(got, want), _first_mismatch(got, want)
+    v.close()
