@@ -107,3 +107,40 @@ def test_ids_path_edge_cases():
         dt.IdsPath(dt.Vocab(dt.KMER, k=3))
     assert e.value.code == dt.EVOCAB
     v.close()
+
+
+@pytest.mark.parametrize("B,T", [(4096, 512), (8192, 512), (2048, 2048)])
+@pytest.mark.parametrize("width,overlap", [(4, True), (8, False)])
+def test_ids_path_benchmark_shapes(B, T, width, overlap):
+    """The benchmark's three shapes with the paper's token budget (1,048,576
+    ids per micro-batch) and the single-nucleotide table: every id against
+    the oracle, and the embedding rows of the first and last micro-batch."""
+    torch = _torch()
+    v = dt.Vocab(dt.SINGLE)
+    lut = np.full(256, 1, np.int32)
+    for j, c in enumerate("ACGT"):
+        lut[ord(c)] = lut[ord(c.lower())] = 5 + j
+    lut[ord("N")] = lut[ord("n")] = 9
+    rows = _rows(B, T, 2)
+    g = torch.Generator().manual_seed(4)
+    table = torch.randn((11, 128), generator=g).to(torch.bfloat16)
+    p = dt.IdsPath(v, width=width, overlap=overlap, threads=16, token_budget=0)
+    d_ids = torch.full((B, T), -5, dtype=torch.int64, device="cuda")
+    r = p.run(rows, B, T, T, d_ids=d_ids)
+    torch.cuda.synchronize()
+    assert dt.sync_status() == 0
+    b = (1 << 20) // T
+    assert r.micro_rows == b and r.n_micro == (B + b - 1) // b
+    want = _want_ids(lut, 0, rows, T)
+    assert np.array_equal(d_ids.cpu().numpy(), want)
+    # the embedder over the first and the last micro-batch's rows
+    for lo in (0, (r.n_micro - 1) * b):
+        part = rows[lo:lo + b]
+        d_out = torch.empty((len(part), T, 128), dtype=torch.bfloat16, device="cuda")
+        p.run(np.ascontiguousarray(part), len(part), T, T, table=table.cuda(), d_out=d_out)
+        torch.cuda.synchronize()
+        assert dt.sync_status() == 0
+        emb = oracle.embed(table.view(torch.int16).numpy(), want[lo:lo + b])
+        assert np.array_equal(d_out.view(torch.int16).cpu().numpy(), emb)
+    p.close()
+    v.close()
