@@ -240,13 +240,26 @@ __device__ __forceinline__ void band_write(const BandArgs &a, int64_t r0, int nr
             }
             if (clo >= chi) continue;
             const int64_t gf = (E0 + clo + o.al) >> 2, gl = (E0 + chi - 1 + o.al) >> 2;
-            for (int64_t g = gf + tid; g <= gl; g += NTB) {
-                const int64_t e = 4 * g - o.al;
-                const int32_t c0 = (int32_t)(e - E0);
-                int32_t *dst = o.ids + e;
-                if (c0 >= bA && c0 + 4 <= bF && c0 >= clo && c0 + 4 <= chi && staged &&
-                    (!KMER || 3 * st + k <= 32)) {
-                    const int32_t j = c0 - bA;
+            // Groups whose four cells are full frames of this row (and part):
+            // [ga, gb), one staged window read and four ids each, in 32-bit
+            // arithmetic from the range's first cell; the rest (edges) below.
+            int64_t ga = gl + 1, gb = gl + 1;
+            if (staged && (!KMER || 3 * st + k <= 32)) {
+                const int32_t flo = max(bA, clo), fhi = min(bF, chi);
+                const int64_t lo_g = (E0 + flo + o.al + 3) >> 2;  // first g with 4g - al - E0 >= flo
+                const int64_t hi_g = (E0 + fhi + o.al - 4) >> 2;  // last g with 4g - al - E0 + 4 <= fhi
+                if (hi_g >= lo_g) {
+                    ga = lo_g;
+                    gb = hi_g + 1;
+                }
+            }
+            const int32_t nfast = (int32_t)(gb - ga);
+            if (nfast > 0) {
+                const int32_t jA = (int32_t)(4 * ga - o.al - E0) - bA;  // token of the first fast group's first cell
+                i32x4 *ids4 = reinterpret_cast<i32x4 *>(o.ids + (4 * ga - o.al));
+                int8_t *mask0 = o.mask + (4 * ga - o.al);
+                for (int32_t t = tid; t < nfast; t += NTB) {
+                    const int32_t j = jA + 4 * t;
                     i32x4 y;
                     if (KMER) {
                         // tokens j .. j + 3 read one 32-base window: forward from
@@ -261,16 +274,23 @@ __device__ __forceinline__ void band_write(const BandArgs &a, int64_t r0, int nr
 #pragma unroll
                         for (int q = 0; q < 4; ++q) y[q] = s_lut[raw[ro + (uint32_t)(j + q)]];
                     }
-                    __builtin_nontemporal_store(y, reinterpret_cast<i32x4 *>(dst));
+                    __builtin_nontemporal_store(y, ids4 + t);
                     // mask words through the cache: a wave's 4-byte stores
                     // cover a line only together, which L2 merges (streamed
                     // past it, they cost 7% of the launch)
                     if (mask4)
-                        *reinterpret_cast<uint32_t *>(o.mask + e) = 0x01010101u;
+                        *reinterpret_cast<uint32_t *>(mask0 + 4 * t) = 0x01010101u;
                     else
-                        for (int q = 0; q < 4; ++q) o.mask[e + q] = 1;
-                    continue;
+                        for (int q = 0; q < 4; ++q) mask0[4 * t + q] = 1;
                 }
+            }
+            // the other groups, [gf, ga) and [gb, gl], cell by cell
+            const int64_t n1 = ga - gf, ne = n1 + (gl + 1 - gb);
+            for (int64_t ie = tid; ie < ne; ie += NTB) {
+                const int64_t g = ie < n1 ? gf + ie : gb + (ie - n1);
+                const int64_t e = 4 * g - o.al;
+                const int32_t c0 = (int32_t)(e - E0);
+                int32_t *dst = o.ids + e;
                 int32_t v[4];
                 uint32_t mk = 0;
                 bool in[4], all_in = true;
