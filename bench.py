@@ -125,7 +125,7 @@ def encode_leg(steps: int, warmup: int, tuning=None, per_vocab: bool = True):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(),
+            "traffic": measured_traffic(tune_multi.get("bands", 0)),
             "kernel": ("k_bands<KMER> (row bands, %d-byte stage)" % tune_multi["tile_bytes"]
                        if tune_multi.get("bands") == 1 else
                        "k_bands_loop<KMER> (row bands, resident workgroups, %d-byte stage)" % tune_multi["tile_bytes"]
@@ -191,10 +191,12 @@ def encode_leg(steps: int, warmup: int, tuning=None, per_vocab: bool = True):
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "encode_multi_k_batch_traffic.md")
 
 
-def measured_traffic():
+def measured_traffic(bands: int):
     """HBM bytes per launch of the one-pass encode from the committed counter
     summary (FETCH_SIZE / WRITE_SIZE calibrated by a copy of known size), or
-    None when the summary is missing or the kernel source changed since."""
+    None when the summary is missing, was taken on another kernel than the
+    one this run's tiling selects (tiles, row bands, resident row bands), or
+    the kernel source changed since."""
     import hashlib
     try:
         text = open(TRAFFIC_SUMMARY).read()
@@ -205,7 +207,10 @@ def measured_traffic():
         if ":" in line and line.startswith("    "):
             key, val = line.strip().split(":", 1)
             fields[key.strip()] = val.strip()
+    family = "k_bands_loop" if bands == 3 else "k_bands" if bands == 1 else "k_cells"
     try:
+        if fields["kernel"].split("<")[0] != family:
+            return None
         src = os.path.join(ROOT, fields["kernel_source"])
         if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields["kernel_source_sha256"]:
             return None
