@@ -343,11 +343,20 @@ struct WaveArgs {
     uint32_t *hdr;   // error word at hdr + 3
 };
 
+// A round merges the ranks present in a window [rs, rs + w) at once, w <= 64,
+// as far as that equals merging them one after another; its occurrences sit
+// in a list of at most kCap entries (kCap / 64 groups of a wave).
+constexpr uint32_t kWin = 64;
+constexpr uint32_t kCap = 256;
+constexpr int kGroups = (int)(kCap / 64);
+
 // Per-wave LDS, each part 16-byte aligned: sym[np], prk[np] (16-bit),
-// alive[np/32], bmin[nb], cblk[nb] (16-bit), dirty[nb/32], list[64] (16-bit);
-// nb = np / 64 blocks of 64 positions, np a multiple of 64.
+// alive[np/32], bmin[nb], cblk[nb] (16-bit), dirty[nb/32], and the round's
+// occurrence list: list[kCap] and eq[kCap] (16-bit positions p and q),
+// einfo[kCap] (8-bit: merges << 7 | rank - rs); nb = np / 64 blocks of 64
+// positions, np a multiple of 64.
 struct WaveLayout {
-    uint32_t prk, alive, bmin, cblk, dirty, list, bytes;
+    uint32_t prk, alive, bmin, cblk, dirty, list, eq, einfo, bytes;
 };
 __host__ __device__ inline WaveLayout wave_layout(uint32_t np) {
     const uint32_t nb = np / 64;
@@ -358,7 +367,9 @@ __host__ __device__ inline WaveLayout wave_layout(uint32_t np) {
     l.cblk = l.bmin + al16(2u * nb);
     l.dirty = l.cblk + al16(2u * nb);
     l.list = l.dirty + al16(4u * ((nb + 31) / 32 + 1));
-    l.bytes = l.list + 128u;
+    l.eq = l.list + 2u * kCap;
+    l.einfo = l.eq + 2u * kCap;
+    l.bytes = l.einfo + kCap;
     return l;
 }
 __host__ __device__ inline uint32_t wave_lds_bytes(uint32_t np) { return wave_layout(np).bytes; }
@@ -440,6 +451,8 @@ __device__ __forceinline__ void wave_item(const WaveArgs &a, const RankTab &tab,
     uint16_t *cblk = reinterpret_cast<uint16_t *>(wb + lay.cblk);
     uint32_t *dirty = reinterpret_cast<uint32_t *>(wb + lay.dirty);
     uint16_t *list = reinterpret_cast<uint16_t *>(wb + lay.list);
+    uint16_t *eq = reinterpret_cast<uint16_t *>(wb + lay.eq);
+    uint8_t *einfo = wb + lay.einfo;
     const int32_t n = a.item_len[t];
     const int64_t c0 = a.item_start[t];
     const uint8_t *src = a.bytes + c0;
@@ -490,8 +503,24 @@ __device__ __forceinline__ void wave_item(const WaveArgs &a, const RankTab &tab,
         l2 = min(l2, bm[k]);
     }
 
-    // Each round refreshes every block it visits and leaves no pair of
-    // rank rs behind, so rs strictly increases: at most R rounds.
+    // A round takes the lowest rank rs present and the ranks present just
+    // above it, steps 0, 1, ... in rank order, and merges all their
+    // occurrences at once where that gives what merging the ranks one after
+    // another gives: occurrences of different ranks that share a symbol, or
+    // a pair formed at a step before the last one whose rank is at most a
+    // later step's rank, end the round's ranks before the later step
+    // concerned. Every round merges rs, so rs strictly increases: at most R
+    // rounds.
+    auto list_blocks = [&](uint32_t m) -> uint32_t {  // blocks of this lane's bits, in order, to cblk
+        const uint32_t cc = (uint32_t)__popc(m);
+        const uint32_t cinc = dev::wave_incl_sum_u32(cc);
+        uint32_t o = cinc - cc;
+        while (m) {
+            cblk[o++] = (uint16_t)(b0 + (uint32_t)__builtin_ctz(m));
+            m &= m - 1;
+        }
+        return dev::wave_read_u32(cinc, 63);
+    };
     for (int32_t round = 0;; ++round) {
         const uint32_t rs = dev::wave_min_all_u32(l2);
         if (rs == kNoRank) break;
@@ -499,106 +528,284 @@ __device__ __forceinline__ void wave_item(const WaveArgs &a, const RankTab &tab,
             if (lane == 0) dev::raise_error(a.hdr, DNATOK_DERR_INTERNAL);
             break;
         }
-        const uint32_t pr = tab.pair[rs];
-        const uint32_t L = pr & 0xFFFF, NEW = 10 + rs;
-        const bool chain = L == (pr >> 16);
-        // blocks holding rank rs, in order; they are all refreshed after the round
+        // blocks holding a rank of the widest window [rs, rs + w64)
+        const uint32_t w64 = min(kWin, (uint32_t)kNoRank - rs);
         uint32_t cm = 0;
-        if (l2 == rs) {
 #pragma unroll
-            for (int k = 0; k < kK2Max; ++k) cm |= (uint32_t)(bm[k] == rs) << k;
-        }
-        const uint32_t cc = (uint32_t)__popc(cm);
-        const uint32_t cinc = dev::wave_incl_sum_u32(cc);
-        const uint32_t ncb = dev::wave_read_u32(cinc, 63);
-        {
-            uint32_t o = cinc - cc, m = cm;
-            while (m) {
-                cblk[o++] = (uint16_t)(b0 + (uint32_t)__builtin_ctz(m));
-                m &= m - 1;
-            }
-        }
-        uint32_t own_dirty = cm;
+        for (int k = 0; k < kK2Max; ++k) cm |= (uint32_t)(bm[k] - rs < w64) << k;
+        uint32_t ncb = list_blocks(cm);
         wave_sync();
-        uint32_t carry_q = kNone;
-        int32_t carry_off = 0;
-        for (uint32_t base = 0; base < ncb;) {
-            // gather up to 64 occurrences from the next blocks, the wave
-            // reading each block together (lane i: position 64b + i, one
-            // ballot per block), four blocks' reads in flight at a time
-            uint32_t nc = 0, m = 0;
-            bool full = false;
-            while (!full && base + m < ncb) {
-                uint32_t bq[4], rk[4];
+        // the window's occurrences in position order to the list, one block
+        // per lane; a window of w64 ranks, else 8, else rs alone, whichever
+        // first fits the list
+        uint32_t D = 0, total = 0;
+        for (int tri = 0; tri < 3 && D == 0; ++tri) {
+            const uint32_t Dc = tri == 0 ? w64 : (tri == 1 ? min(8u, w64) : 1u);
+            if (tri > 0 && Dc == (tri == 1 ? w64 : min(8u, w64))) continue;  // same window as the last try
+            uint32_t cnt = 0;
+            for (uint32_t j0 = 0; j0 < ncb; j0 += 64) {
+                const uint32_t j = j0 + (uint32_t)lane;
+                uint64_t m = 0;
+                uint32_t b = 0;
+                if (j < ncb) {
+                    b = cblk[j];
+                    const uint4 *src = reinterpret_cast<const uint4 *>(prk + (size_t)b * 64);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const uint32_t jb = base + m + (uint32_t)u;
-                    bq[u] = cblk[jb < ncb ? jb : ncb - 1];
-                }
+                    for (int v = 0; v < 8; ++v) {
+                        const uint4 x = src[v];
+                        const uint32_t wd[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
-                for (int u = 0; u < 4; ++u) rk[u] = prk[bq[u] * 64 + (uint32_t)lane];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (full || base + m >= ncb) break;
-                    const uint64_t mm = __ballot(rk[u] == rs);
-                    const uint32_t c = (uint32_t)__popcll(mm);
-                    if (nc + c > 64) {
-                        full = true;
-                        break;
+                        for (int u = 0; u < 4; ++u) {
+                            m |= (uint64_t)((wd[u] & 0xFFFFu) - rs < Dc) << (8 * v + 2 * u);
+                            m |= (uint64_t)((wd[u] >> 16) - rs < Dc) << (8 * v + 2 * u + 1);
+                        }
                     }
-                    if ((mm >> lane) & 1ull)
-                        list[nc + (uint32_t)__popcll(mm & ((1ull << lane) - 1ull))] = (uint16_t)(bq[u] * 64 + (uint32_t)lane);
-                    nc += c;
-                    ++m;
+                }
+                const uint32_t c = (uint32_t)__popcll(m);
+                const uint32_t inc = dev::wave_incl_sum_u32(c);
+                for (uint32_t o = cnt + inc - c; m && o < kCap; ++o, m &= m - 1)
+                    list[o] = (uint16_t)(b * 64 + (uint32_t)__builtin_ctzll(m));
+                cnt += dev::wave_read_u32(inc, 63);
+            }
+            if (cnt <= kCap) {
+                D = Dc;
+                total = cnt;
+            }
+        }
+        uint32_t own_dirty;
+        if (D > 0) {
+            // blocks of the chosen window: they are all refreshed after the round
+            own_dirty = 0;
+#pragma unroll
+            for (int k = 0; k < kK2Max; ++k) own_dirty |= (uint32_t)(bm[k] - rs < D) << k;
+            wave_sync();
+            // pass 1, per occurrence: its neighbours, and whether it merges
+            // (all occurrences of a rank, or for (X, X) every other one of a
+            // run, leftmost first); q and the outcome go to the list
+            uint32_t Pg[kGroups], Qg[kGroups], Lg[kGroups], Q2g[kGroups], Dg[kGroups];
+            bool Mg[kGroups];
+            uint64_t pres_l = 0;
+            uint32_t carry_q = kNone, carry_d = kNone;
+            int32_t carry_off = 0;
+#pragma unroll
+            for (int g = 0; g < kGroups; ++g) {
+                Pg[g] = 0;
+                Qg[g] = Lg[g] = Q2g[g] = kNone;
+                Dg[g] = 0;
+                Mg[g] = false;
+                if ((uint32_t)(64 * g) < total) {
+                    const uint32_t e = 64u * g + (uint32_t)lane;
+                    const bool valid = e < total;
+                    const uint32_t p = valid ? (uint32_t)list[e] : 0u;
+                    const uint32_t r = valid ? (uint32_t)prk[p] : (uint32_t)kNoRank;
+                    const uint32_t d = r - rs;
+                    Neighbors nbr{kNone, kNone, kNone};
+                    if (valid) nbr = neighbors(alive, nw, p, true);
+                    const uint32_t pr = valid ? tab.pair[r] : 0u;
+                    const bool chain = valid && (pr & 0xFFFFu) == (pr >> 16);
+                    const uint32_t q_up = dev::wave_from_prev_u32(nbr.q, carry_q);
+                    const uint32_t d_up = dev::wave_from_prev_u32(d, carry_d);
+                    const bool adj = chain && q_up == p && d_up == d;
+                    const uint64_t starts = __ballot(valid && !adj);
+                    const uint64_t below = starts & (lane == 63 ? ~0ull : ((2ull << lane) - 1));
+                    const int32_t off = below ? lane - (63 - __clzll(below)) : carry_off + 1 + lane;
+                    const bool ms = valid && (!chain || (off & 1) == 0);
+                    const uint32_t last = min(total - 64u * g, 64u) - 1u;
+                    carry_q = dev::wave_read_u32(nbr.q, last);
+                    carry_d = dev::wave_read_u32(d, last);
+                    carry_off = (int32_t)dev::wave_read_u32((uint32_t)off, last);
+                    if (valid) {
+                        eq[e] = (uint16_t)nbr.q;
+                        einfo[e] = (uint8_t)((ms ? 0x80u : 0u) | d);
+                        pres_l |= 1ull << d;
+                    }
+                    Pg[g] = p;
+                    Qg[g] = nbr.q;
+                    Lg[g] = nbr.l;
+                    Q2g[g] = nbr.q2;
+                    Dg[g] = d;
+                    Mg[g] = ms;
+                }
+            }
+            // ranks present: step of rank rs + d = ranks present below it
+            const uint64_t pres = ((uint64_t)dev::wave_or_all_u32((uint32_t)(pres_l >> 32)) << 32) |
+                                  dev::wave_or_all_u32((uint32_t)pres_l);
+            const uint32_t nsteps = (uint32_t)__popcll(pres);
+            auto step_of = [&](uint32_t d) { return (uint32_t)__popcll(pres & ((1ull << d) - 1ull)); };
+            // a pair of rank r formed at step st allows steps up to this bound (exclusive)
+            auto bound = [&](uint32_t st, uint32_t r) -> uint32_t {
+                if (r == kNoRank) return nsteps;
+                const uint32_t idx = r < rs ? 0u : (r - rs >= 64u ? nsteps : step_of(r - rs));
+                return max(st + 1u, idx);
+            };
+            wave_sync();
+            // pass 2, per merging occurrence: the pairs it forms on each side,
+            // at its own step and, next to a merge of another step, at the
+            // later of the two; the bound they and shared symbols set
+            uint32_t Ag[kGroups], RFg[kGroups], RIg[kGroups], LIg[kGroups], BRg[kGroups], BLg[kGroups];
+            uint32_t cutv = nsteps;
+#pragma unroll
+            for (int g = 0; g < kGroups; ++g) {
+                Ag[g] = 0;
+                RFg[g] = RIg[g] = LIg[g] = kNoRank;
+                BRg[g] = BLg[g] = kNone;
+                if ((uint32_t)(64 * g) < total && Mg[g]) {
+                    const uint32_t e = 64u * g + (uint32_t)lane;
+                    const uint32_t d = Dg[g], st = step_of(d), NEW = 10u + rs + d;
+                    Ag[g] = st;
+                    const uint32_t q2 = Q2g[g];
+                    if (q2 != kNone) {
+                        // a merge starting at q2 is one or two entries on
+                        uint32_t jr = kNone;
+                        if (e + 1 < total && list[e + 1] == q2 && (einfo[e + 1] & 0x80u)) jr = e + 1;
+                        else if (e + 2 < total && list[e + 2] == q2 && (einfo[e + 2] & 0x80u)) jr = e + 2;
+                        const uint32_t s2 = sym[q2];
+                        if (jr != kNone) {
+                            const uint32_t dj = einfo[jr] & 63u, sj = step_of(dj);
+                            BRg[g] = sj;
+                            RFg[g] = pair_rank(tab, NEW, 10u + rs + dj);
+                            cutv = min(cutv, bound(max(st, sj), RFg[g]));
+                            if (sj > st) {
+                                RIg[g] = pair_rank(tab, NEW, s2);
+                                cutv = min(cutv, bound(st, RIg[g]));
+                            }
+                        } else {
+                            RIg[g] = pair_rank(tab, NEW, s2);
+                            cutv = min(cutv, bound(st, RIg[g]));
+                        }
+                    }
+                    const uint32_t l = Lg[g];
+                    if (l != kNone) {
+                        // a merge ending at l is one or two entries back
+                        uint32_t jl = kNone;
+                        if (e >= 1 && eq[e - 1] == l && (einfo[e - 1] & 0x80u)) jl = e - 1;
+                        else if (e >= 2 && eq[e - 2] == l && (einfo[e - 2] & 0x80u)) jl = e - 2;
+                        const uint32_t sl = jl != kNone ? step_of(einfo[jl] & 63u) : kNone;
+                        BLg[g] = sl;
+                        if (jl == kNone || sl > st) {
+                            LIg[g] = pair_rank(tab, sym[l], NEW);
+                            cutv = min(cutv, bound(st, LIg[g]));
+                        }
+                    }
+                    // the previous entry merges too and shares p: another step ends before the later one
+                    if (e >= 1 && (einfo[e - 1] & 0x80u) && eq[e - 1] == Pg[g] && (einfo[e - 1] & 63u) != d)
+                        cutv = min(cutv, max(st, step_of(einfo[e - 1] & 63u)));
+                }
+            }
+            const uint32_t cut = dev::wave_min_all_u32(cutv);
+            wave_sync();
+            // pass 3: the merges of steps below the bound; a side whose
+            // neighbouring merge also happens is written by the left one
+#pragma unroll
+            for (int g = 0; g < kGroups; ++g) {
+                if ((uint32_t)(64 * g) < total && Mg[g] && Ag[g] < cut) {
+                    const uint32_t p = Pg[g], q = Qg[g], l = Lg[g], st = Ag[g];
+                    sym[p] = (uint16_t)(10u + rs + Dg[g]);
+                    prk[p] = (uint16_t)((BRg[g] != kNone && BRg[g] < cut) ? RFg[g] : RIg[g]);
+                    prk[q] = kNoRank;
+                    atomicAnd(&alive[q >> 5], ~(1u << (q & 31)));
+                    // p's block is refreshed; q's and l's may be neighbours
+                    if ((q >> 6) != (p >> 6)) atomicOr(&dirty[(q >> 6) >> 5], 1u << ((q >> 6) & 31));
+                    if (l != kNone && (BLg[g] == kNone || (BLg[g] > st && BLg[g] >= cut))) {
+                        prk[l] = (uint16_t)LIg[g];
+                        if ((l >> 6) != (p >> 6)) atomicOr(&dirty[(l >> 6) >> 5], 1u << ((l >> 6) & 31));
+                    }
                 }
             }
             wave_sync();
-            // which occurrences merge: all, or for (X, X) every other one of a run
-            const bool valid = (uint32_t)lane < nc;
-            const uint32_t p = valid ? list[lane] : 0;
-            Neighbors nbr{kNone, kNone, kNone};
-            if (valid) nbr = neighbors(alive, nw, p, true);
-            const uint32_t q = nbr.q;
-            // lane 0 compares with the last occurrence of the previous group
-            const uint32_t q_up = dev::wave_from_prev_u32(q, carry_q);
-            const bool adj = chain && valid && q_up == p;
-            const uint64_t starts = __ballot(valid && !adj);
-            const uint64_t below = starts & (lane == 63 ? ~0ull : ((2ull << lane) - 1));
-            const int32_t off = below ? lane - (63 - __clzll(below)) : carry_off + 1 + lane;
-            const bool ms = valid && (!chain || (off & 1) == 0);
-            if (nc > 0) {
-                carry_q = dev::wave_read_u32(q, nc - 1);
-                carry_off = (int32_t)dev::wave_read_u32((uint32_t)off, nc - 1);
+        } else {
+            // rs alone overflows the list: its occurrences in groups of 64
+            cm = 0;
+            if (l2 == rs) {
+#pragma unroll
+                for (int k = 0; k < kK2Max; ++k) cm |= (uint32_t)(bm[k] == rs) << k;
             }
-            // right elements of the merges one and two occurrences back
-            const uint32_t rq = ms ? q : kNone;
-            const uint32_t rq1 = dev::wave_from_prev_u32(rq, kNone);
-            const uint32_t rq2 = dev::wave_from_prev_u32(rq1, kNone);
-            const uint32_t l = nbr.l, q2 = nbr.q2;
-            uint32_t rk_l = kNoRank, rk_r = kNoRank;
-            const bool left = ms && l != kNone && rq1 != l && rq2 != l;
-            if (ms) {
-                // an occurrence right after a merge merges too
-                const uint32_t s2 = q2 != kNone ? ((prk[q2] == rs) ? NEW : (uint32_t)sym[q2]) : 0u;
-                const uint32_t sl = left ? (uint32_t)sym[l] : 0u;
-                if (q2 != kNone) rk_r = pair_rank(tab, NEW, s2);
-                if (left) rk_l = pair_rank(tab, sl, NEW);
-            }
+            ncb = list_blocks(cm);
+            own_dirty = cm;
             wave_sync();
-            if (ms) {
-                sym[p] = (uint16_t)NEW;
-                prk[p] = (uint16_t)rk_r;
-                prk[q] = kNoRank;
-                atomicAnd(&alive[q >> 5], ~(1u << (q & 31)));
-                // p's block is a visited block; q's and l's may be neighbours
-                if ((q >> 6) != (p >> 6)) atomicOr(&dirty[(q >> 6) >> 5], 1u << ((q >> 6) & 31));
-                if (left) {
-                    prk[l] = (uint16_t)rk_l;
-                    if ((l >> 6) != (p >> 6)) atomicOr(&dirty[(l >> 6) >> 5], 1u << ((l >> 6) & 31));
+            const uint32_t pr = tab.pair[rs];
+            const uint32_t L = pr & 0xFFFF, NEW = 10 + rs;
+            const bool chain = L == (pr >> 16);
+            uint32_t carry_q = kNone;
+            int32_t carry_off = 0;
+            for (uint32_t base = 0; base < ncb;) {
+                // gather up to 64 occurrences from the next blocks, the wave
+                // reading each block together (lane i: position 64b + i, one
+                // ballot per block), four blocks' reads in flight at a time
+                uint32_t nc = 0, m = 0;
+                bool full = false;
+                while (!full && base + m < ncb) {
+                    uint32_t bq[4], rk[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const uint32_t jb = base + m + (uint32_t)u;
+                        bq[u] = cblk[jb < ncb ? jb : ncb - 1];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) rk[u] = prk[bq[u] * 64 + (uint32_t)lane];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        if (full || base + m >= ncb) break;
+                        const uint64_t mm = __ballot(rk[u] == rs);
+                        const uint32_t c = (uint32_t)__popcll(mm);
+                        if (nc + c > 64) {
+                            full = true;
+                            break;
+                        }
+                        if ((mm >> lane) & 1ull)
+                            list[nc + (uint32_t)__popcll(mm & ((1ull << lane) - 1ull))] = (uint16_t)(bq[u] * 64 + (uint32_t)lane);
+                        nc += c;
+                        ++m;
+                    }
                 }
+                wave_sync();
+                // which occurrences merge: all, or for (X, X) every other one of a run
+                const bool valid = (uint32_t)lane < nc;
+                const uint32_t p = valid ? list[lane] : 0;
+                Neighbors nbr{kNone, kNone, kNone};
+                if (valid) nbr = neighbors(alive, nw, p, true);
+                const uint32_t q = nbr.q;
+                // lane 0 compares with the last occurrence of the previous group
+                const uint32_t q_up = dev::wave_from_prev_u32(q, carry_q);
+                const bool adj = chain && valid && q_up == p;
+                const uint64_t starts = __ballot(valid && !adj);
+                const uint64_t below = starts & (lane == 63 ? ~0ull : ((2ull << lane) - 1));
+                const int32_t off = below ? lane - (63 - __clzll(below)) : carry_off + 1 + lane;
+                const bool ms = valid && (!chain || (off & 1) == 0);
+                if (nc > 0) {
+                    carry_q = dev::wave_read_u32(q, nc - 1);
+                    carry_off = (int32_t)dev::wave_read_u32((uint32_t)off, nc - 1);
+                }
+                // right elements of the merges one and two occurrences back
+                const uint32_t rq = ms ? q : kNone;
+                const uint32_t rq1 = dev::wave_from_prev_u32(rq, kNone);
+                const uint32_t rq2 = dev::wave_from_prev_u32(rq1, kNone);
+                const uint32_t l = nbr.l, q2 = nbr.q2;
+                uint32_t rk_l = kNoRank, rk_r = kNoRank;
+                const bool left = ms && l != kNone && rq1 != l && rq2 != l;
+                if (ms) {
+                    // an occurrence right after a merge merges too
+                    const uint32_t s2 = q2 != kNone ? ((prk[q2] == rs) ? NEW : (uint32_t)sym[q2]) : 0u;
+                    const uint32_t sl = left ? (uint32_t)sym[l] : 0u;
+                    if (q2 != kNone) rk_r = pair_rank(tab, NEW, s2);
+                    if (left) rk_l = pair_rank(tab, sl, NEW);
+                }
+                wave_sync();
+                if (ms) {
+                    sym[p] = (uint16_t)NEW;
+                    prk[p] = (uint16_t)rk_r;
+                    prk[q] = kNoRank;
+                    atomicAnd(&alive[q >> 5], ~(1u << (q & 31)));
+                    // p's block is a visited block; q's and l's may be neighbours
+                    if ((q >> 6) != (p >> 6)) atomicOr(&dirty[(q >> 6) >> 5], 1u << ((q >> 6) & 31));
+                    if (left) {
+                        prk[l] = (uint16_t)rk_l;
+                        if ((l >> 6) != (p >> 6)) atomicOr(&dirty[(l >> 6) >> 5], 1u << ((l >> 6) & 31));
+                    }
+                }
+                wave_sync();
+                base += m;
             }
-            wave_sync();
-            base += m;
         }
         // refresh the minima of this lane's changed blocks
         {

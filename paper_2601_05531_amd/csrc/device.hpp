@@ -78,6 +78,17 @@ __device__ __forceinline__ uint32_t wave_min_all_u32(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
+// Bitwise or over the 64 lanes, returned to every lane.
+__device__ __forceinline__ uint32_t wave_or_all_u32(uint32_t v) {
+    v |= dpp_u32<kDppRowShr1>(0u, v);
+    v |= dpp_u32<kDppRowShr2>(0u, v);
+    v |= dpp_u32<kDppRowShr4>(0u, v);
+    v |= dpp_u32<kDppRowShr8>(0u, v);
+    v |= dpp_u32<kDppRowBcast15, 0xA>(0u, v);
+    v |= dpp_u32<kDppRowBcast31, 0xC>(0u, v);
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
 // Value of lane - 1 (lane 0 gets `first`).
 __device__ __forceinline__ uint32_t wave_from_prev_u32(uint32_t v, uint32_t first) {
     return dpp_u32<kDppWaveShr1>(first, v);

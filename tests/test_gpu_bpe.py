@@ -94,6 +94,33 @@ def test_exhaustive_short_strings(trained_small):
         _packed(v, merges, data, offs, cls=False)
 
 
+def test_random_tables_runs_and_repeats():
+    # rounds that merge many ranks at once: random tables rich in (X, X)
+    # pairs and shared operands, on rows of base runs, short tandem repeats
+    # and uniform bases, up to 6000 bases (many occurrences per round)
+    rng = np.random.default_rng(23)
+    acgt = np.frombuffer(b"ACGT", np.uint8)
+    for t in range(24):
+        merges = _random_table(100 + t, int(rng.integers(1, 400)), float(rng.choice([0.05, 0.3, 0.6])))
+        lens = rng.integers(0, 6000 if t % 3 == 0 else 300, 48)
+        rows = []
+        for L in lens:
+            kind = int(rng.integers(0, 3))
+            if kind == 0:  # runs of one base
+                runs = rng.integers(1, 12, size=L + 1)
+                row = np.repeat(acgt[rng.integers(0, 4, size=L + 1)], runs)[:L]
+            elif kind == 1:  # a short motif repeated
+                motif = acgt[rng.integers(0, 4, size=int(rng.integers(1, 5)))]
+                row = np.tile(motif, L // len(motif) + 1)[:L]
+            else:
+                row = acgt[rng.integers(0, 4, size=L)]
+            rows.append(row)
+        data = np.concatenate(rows) if rows else np.zeros(0, np.uint8)
+        offs = synth.offsets_from_lengths(lens)
+        v = dt.Vocab(dt.BPE, merges=merges)
+        _packed(v, merges, data, offs, cls=False)
+
+
 def test_fuzz_barriers_and_case(trained_small):
     rng = np.random.default_rng(11)
     n = 3000
