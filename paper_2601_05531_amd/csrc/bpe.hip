@@ -521,6 +521,7 @@ __device__ __forceinline__ void wave_item(const WaveArgs &a, const RankTab &tab,
         }
         return dev::wave_read_u32(cinc, 63);
     };
+    uint32_t Dn = kWin;
     for (int32_t round = 0;; ++round) {
         const uint32_t rs = dev::wave_min_all_u32(l2);
         if (rs == kNoRank) break;
@@ -528,20 +529,17 @@ __device__ __forceinline__ void wave_item(const WaveArgs &a, const RankTab &tab,
             if (lane == 0) dev::raise_error(a.hdr, DNATOK_DERR_INTERNAL);
             break;
         }
-        // blocks holding a rank of the widest window [rs, rs + w64)
-        const uint32_t w64 = min(kWin, (uint32_t)kNoRank - rs);
-        uint32_t cm = 0;
-#pragma unroll
-        for (int k = 0; k < kK2Max; ++k) cm |= (uint32_t)(bm[k] - rs < w64) << k;
-        uint32_t ncb = list_blocks(cm);
-        wave_sync();
         // the window's occurrences in position order to the list, one block
-        // per lane; a window of w64 ranks, else 8, else rs alone, whichever
-        // first fits the list
-        uint32_t D = 0, total = 0;
-        for (int tri = 0; tri < 3 && D == 0; ++tri) {
-            const uint32_t Dc = tri == 0 ? w64 : (tri == 1 ? min(8u, w64) : 1u);
-            if (tri > 0 && Dc == (tri == 1 ? w64 : min(8u, w64))) continue;  // same window as the last try
+        // per lane: a window of Dn ranks (what the last rounds' lists
+        // suggest), narrowed fourfold while its occurrences overflow the list
+        const uint32_t w64 = min(kWin, (uint32_t)kNoRank - rs);
+        uint32_t D = 0, total = 0, Dc = min(Dn, w64), own_dirty = 0, ncb = 0;
+        for (;;) {
+            uint32_t cm = 0;
+#pragma unroll
+            for (int k = 0; k < kK2Max; ++k) cm |= (uint32_t)(bm[k] - rs < Dc) << k;
+            ncb = list_blocks(cm);
+            wave_sync();
             uint32_t cnt = 0;
             for (uint32_t j0 = 0; j0 < ncb; j0 += 64) {
                 const uint32_t j = j0 + (uint32_t)lane;
@@ -570,14 +568,23 @@ __device__ __forceinline__ void wave_item(const WaveArgs &a, const RankTab &tab,
             if (cnt <= kCap) {
                 D = Dc;
                 total = cnt;
+                own_dirty = cm;  // these blocks are all refreshed after the round
+                break;
             }
+            if (Dc == 1) break;
+            Dc = max(1u, Dc / 4);
+            wave_sync();
         }
-        uint32_t own_dirty;
+        // the next round's window: wider after a short list, narrower after a long one
+        if (D == 0)
+            Dn = 1;
+        else if (3 * total <= kCap)
+            Dn = min(kWin, 2 * D);
+        else if (3 * total > 2 * kCap)
+            Dn = max(1u, D / 2);
+        else
+            Dn = D;
         if (D > 0) {
-            // blocks of the chosen window: they are all refreshed after the round
-            own_dirty = 0;
-#pragma unroll
-            for (int k = 0; k < kK2Max; ++k) own_dirty |= (uint32_t)(bm[k] - rs < D) << k;
             wave_sync();
             // pass 1, per occurrence: its neighbours, and whether it merges
             // (all occurrences of a rank, or for (X, X) every other one of a
@@ -715,7 +722,7 @@ __device__ __forceinline__ void wave_item(const WaveArgs &a, const RankTab &tab,
             wave_sync();
         } else {
             // rs alone overflows the list: its occurrences in groups of 64
-            cm = 0;
+            uint32_t cm = 0;
             if (l2 == rs) {
 #pragma unroll
                 for (int k = 0; k < kK2Max; ++k) cm |= (uint32_t)(bm[k] == rs) << k;
