@@ -510,7 +510,10 @@ __device__ __forceinline__ void wave_item(const WaveArgs &a, const RankTab &tab,
     // a pair formed at a step before the last one whose rank is at most a
     // later step's rank, end the round's ranks before the later step
     // concerned. Every round merges rs, so rs strictly increases: at most R
-    // rounds.
+    // rounds. When rs alone has more occurrences than the list holds, the
+    // round takes them in chunks of whole blocks, each chunk gathered from
+    // the state the previous one left (a merge's right element is gone from
+    // it, and a pair between two chunks is rewritten from the later side).
     auto list_blocks = [&](uint32_t m) -> uint32_t {  // blocks of this lane's bits, in order, to cblk
         const uint32_t cc = (uint32_t)__popc(m);
         const uint32_t cinc = dev::wave_incl_sum_u32(cc);
@@ -533,6 +536,23 @@ __device__ __forceinline__ void wave_item(const WaveArgs &a, const RankTab &tab,
         // per lane: a window of Dn ranks (what the last rounds' lists
         // suggest), narrowed fourfold while its occurrences overflow the list
         const uint32_t w64 = min(kWin, (uint32_t)kNoRank - rs);
+        auto block_window = [&](uint32_t b, uint32_t w) -> uint64_t {  // positions of block b ranked in [rs, rs + w)
+            const uint4 *src = reinterpret_cast<const uint4 *>(prk + (size_t)b * 64);
+            uint64_t m = 0;
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                const uint4 x = src[v];
+                const uint32_t wd[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    m |= (uint64_t)((wd[u] & 0xFFFFu) - rs < w) << (8 * v + 2 * u);
+                    m |= (uint64_t)((wd[u] >> 16) - rs < w) << (8 * v + 2 * u + 1);
+                }
+            }
+            return m;
+        };
+        // a single rank whose occurrences overflow the list goes in chunks of whole blocks
+        bool dense = false;
         uint32_t D = 0, total = 0, Dc = min(Dn, w64), own_dirty = 0, ncb = 0;
         for (;;) {
             uint32_t cm = 0;
@@ -543,22 +563,8 @@ __device__ __forceinline__ void wave_item(const WaveArgs &a, const RankTab &tab,
             uint32_t cnt = 0;
             for (uint32_t j0 = 0; j0 < ncb; j0 += 64) {
                 const uint32_t j = j0 + (uint32_t)lane;
-                uint64_t m = 0;
-                uint32_t b = 0;
-                if (j < ncb) {
-                    b = cblk[j];
-                    const uint4 *src = reinterpret_cast<const uint4 *>(prk + (size_t)b * 64);
-#pragma unroll
-                    for (int v = 0; v < 8; ++v) {
-                        const uint4 x = src[v];
-                        const uint32_t wd[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            m |= (uint64_t)((wd[u] & 0xFFFFu) - rs < Dc) << (8 * v + 2 * u);
-                            m |= (uint64_t)((wd[u] >> 16) - rs < Dc) << (8 * v + 2 * u + 1);
-                        }
-                    }
-                }
+                const uint32_t b = j < ncb ? (uint32_t)cblk[j] : 0u;
+                uint64_t m = j < ncb ? block_window(b, Dc) : 0ull;
                 const uint32_t c = (uint32_t)__popcll(m);
                 const uint32_t inc = dev::wave_incl_sum_u32(c);
                 for (uint32_t o = cnt + inc - c; m && o < kCap; ++o, m &= m - 1)
@@ -571,12 +577,17 @@ __device__ __forceinline__ void wave_item(const WaveArgs &a, const RankTab &tab,
                 own_dirty = cm;  // these blocks are all refreshed after the round
                 break;
             }
-            if (Dc == 1) break;
+            if (Dc == 1) {
+                dense = true;
+                D = 1;
+                own_dirty = cm;
+                break;
+            }
             Dc = max(1u, Dc / 4);
             wave_sync();
         }
         // the next round's window: wider after a short list, narrower after a long one
-        if (D == 0)
+        if (dense)
             Dn = 1;
         else if (3 * total <= kCap)
             Dn = min(kWin, 2 * D);
@@ -584,7 +595,24 @@ __device__ __forceinline__ void wave_item(const WaveArgs &a, const RankTab &tab,
             Dn = max(1u, D / 2);
         else
             Dn = D;
-        if (D > 0) {
+        uint32_t jb = 0;  // dense: the next candidate block
+        do {
+            if (dense) {
+                // blocks from jb on, whole blocks while their occurrences fit the list
+                wave_sync();
+                const uint32_t j = jb + (uint32_t)lane;
+                const uint32_t b = j < ncb ? (uint32_t)cblk[j] : 0u;
+                uint64_t m = j < ncb ? block_window(b, 1u) : 0ull;
+                const uint32_t c = (uint32_t)__popcll(m);
+                const uint32_t inc = dev::wave_incl_sum_u32(c);
+                const bool take = j < ncb && inc <= kCap;  // a prefix of the lanes, at least one
+                const uint32_t ntake = (uint32_t)__popcll(__ballot(take));
+                if (take)
+                    for (uint32_t o = inc - c; m; ++o, m &= m - 1)
+                        list[o] = (uint16_t)(b * 64 + (uint32_t)__builtin_ctzll(m));
+                total = ntake ? dev::wave_read_u32(inc, ntake - 1) : 0u;
+                jb += ntake;
+            }
             wave_sync();
             // pass 1, per occurrence: its neighbours, and whether it merges
             // (all occurrences of a rank, or for (X, X) every other one of a
@@ -720,100 +748,7 @@ __device__ __forceinline__ void wave_item(const WaveArgs &a, const RankTab &tab,
                 }
             }
             wave_sync();
-        } else {
-            // rs alone overflows the list: its occurrences in groups of 64
-            uint32_t cm = 0;
-            if (l2 == rs) {
-#pragma unroll
-                for (int k = 0; k < kK2Max; ++k) cm |= (uint32_t)(bm[k] == rs) << k;
-            }
-            ncb = list_blocks(cm);
-            own_dirty = cm;
-            wave_sync();
-            const uint32_t pr = tab.pair[rs];
-            const uint32_t L = pr & 0xFFFF, NEW = 10 + rs;
-            const bool chain = L == (pr >> 16);
-            uint32_t carry_q = kNone;
-            int32_t carry_off = 0;
-            for (uint32_t base = 0; base < ncb;) {
-                // gather up to 64 occurrences from the next blocks, the wave
-                // reading each block together (lane i: position 64b + i, one
-                // ballot per block), four blocks' reads in flight at a time
-                uint32_t nc = 0, m = 0;
-                bool full = false;
-                while (!full && base + m < ncb) {
-                    uint32_t bq[4], rk[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const uint32_t jb = base + m + (uint32_t)u;
-                        bq[u] = cblk[jb < ncb ? jb : ncb - 1];
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) rk[u] = prk[bq[u] * 64 + (uint32_t)lane];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        if (full || base + m >= ncb) break;
-                        const uint64_t mm = __ballot(rk[u] == rs);
-                        const uint32_t c = (uint32_t)__popcll(mm);
-                        if (nc + c > 64) {
-                            full = true;
-                            break;
-                        }
-                        if ((mm >> lane) & 1ull)
-                            list[nc + (uint32_t)__popcll(mm & ((1ull << lane) - 1ull))] = (uint16_t)(bq[u] * 64 + (uint32_t)lane);
-                        nc += c;
-                        ++m;
-                    }
-                }
-                wave_sync();
-                // which occurrences merge: all, or for (X, X) every other one of a run
-                const bool valid = (uint32_t)lane < nc;
-                const uint32_t p = valid ? list[lane] : 0;
-                Neighbors nbr{kNone, kNone, kNone};
-                if (valid) nbr = neighbors(alive, nw, p, true);
-                const uint32_t q = nbr.q;
-                // lane 0 compares with the last occurrence of the previous group
-                const uint32_t q_up = dev::wave_from_prev_u32(q, carry_q);
-                const bool adj = chain && valid && q_up == p;
-                const uint64_t starts = __ballot(valid && !adj);
-                const uint64_t below = starts & (lane == 63 ? ~0ull : ((2ull << lane) - 1));
-                const int32_t off = below ? lane - (63 - __clzll(below)) : carry_off + 1 + lane;
-                const bool ms = valid && (!chain || (off & 1) == 0);
-                if (nc > 0) {
-                    carry_q = dev::wave_read_u32(q, nc - 1);
-                    carry_off = (int32_t)dev::wave_read_u32((uint32_t)off, nc - 1);
-                }
-                // right elements of the merges one and two occurrences back
-                const uint32_t rq = ms ? q : kNone;
-                const uint32_t rq1 = dev::wave_from_prev_u32(rq, kNone);
-                const uint32_t rq2 = dev::wave_from_prev_u32(rq1, kNone);
-                const uint32_t l = nbr.l, q2 = nbr.q2;
-                uint32_t rk_l = kNoRank, rk_r = kNoRank;
-                const bool left = ms && l != kNone && rq1 != l && rq2 != l;
-                if (ms) {
-                    // an occurrence right after a merge merges too
-                    const uint32_t s2 = q2 != kNone ? ((prk[q2] == rs) ? NEW : (uint32_t)sym[q2]) : 0u;
-                    const uint32_t sl = left ? (uint32_t)sym[l] : 0u;
-                    if (q2 != kNone) rk_r = pair_rank(tab, NEW, s2);
-                    if (left) rk_l = pair_rank(tab, sl, NEW);
-                }
-                wave_sync();
-                if (ms) {
-                    sym[p] = (uint16_t)NEW;
-                    prk[p] = (uint16_t)rk_r;
-                    prk[q] = kNoRank;
-                    atomicAnd(&alive[q >> 5], ~(1u << (q & 31)));
-                    // p's block is a visited block; q's and l's may be neighbours
-                    if ((q >> 6) != (p >> 6)) atomicOr(&dirty[(q >> 6) >> 5], 1u << ((q >> 6) & 31));
-                    if (left) {
-                        prk[l] = (uint16_t)rk_l;
-                        if ((l >> 6) != (p >> 6)) atomicOr(&dirty[(l >> 6) >> 5], 1u << ((l >> 6) & 31));
-                    }
-                }
-                wave_sync();
-                base += m;
-            }
-        }
+        } while (dense && jb < ncb);
         // refresh the minima of this lane's changed blocks
         {
             const uint32_t w0 = b0 >> 5;
