@@ -122,6 +122,24 @@ __device__ __forceinline__ void stage_token(const DecodeArgs &a, int32_t id, uin
     p[0] = single_letter(id);
 }
 
+// A thread's k-mer tokens to the stage from p on, k fixed at compile time
+// (digit shifts and store offsets become constants: the runtime-k loop cost
+// a dozen instructions per byte and, with every workgroup resident at once,
+// made the staging VALU-bound).
+template <int K>
+__device__ __forceinline__ void stage_kmers(const DecodeArgs &a, const int32_t (&idv)[TPT], uint8_t *p) {
+#pragma unroll
+    for (int j = 0; j < TPT; ++j) {
+        const int32_t id = idv[j];
+        if (is_silent(id)) continue;
+        const bool known = id >= 5 && id < a.vocab;
+        const uint32_t v = (uint32_t)(id - 5);
+#pragma unroll
+        for (int q = 0; q < K; ++q) p[q] = known ? base_letter(v >> (2 * (K - 1 - q))) : (uint8_t)'N';
+        p += K;
+    }
+}
+
 // The ids of tile t this thread holds (TPT consecutive positions; ids
 // outside the rows read as PAD, which decodes to nothing). Every load is
 // unconditional, so a thread's loads go out together: a tile inside the rows
@@ -241,10 +259,24 @@ __global__ __launch_bounds__(NT) void k_decode_write(DecodeArgs a) {
     if (staged) {
         // in-tile positions fit 32 bits (the stage is at most 32 KiB)
         uint32_t pos = (uint32_t)pre;
+        if (KIND == DNATOK_KMER && a.k <= 8) {
+            uint8_t *p = s_out + pos;
+            switch (a.k) {
+            case 1: stage_kmers<1>(a, idv, p); break;
+            case 2: stage_kmers<2>(a, idv, p); break;
+            case 3: stage_kmers<3>(a, idv, p); break;
+            case 4: stage_kmers<4>(a, idv, p); break;
+            case 5: stage_kmers<5>(a, idv, p); break;
+            case 6: stage_kmers<6>(a, idv, p); break;
+            case 7: stage_kmers<7>(a, idv, p); break;
+            default: stage_kmers<8>(a, idv, p); break;
+            }
+        } else {
 #pragma unroll
-        for (int j = 0; j < TPT; ++j) {
-            stage_token<KIND>(a, idv[j], s_out + pos);
-            pos += (uint32_t)width_of<KIND>(a, idv[j]);
+            for (int j = 0; j < TPT; ++j) {
+                stage_token<KIND>(a, idv[j], s_out + pos);
+                pos += (uint32_t)width_of<KIND>(a, idv[j]);
+            }
         }
     }
     __syncthreads();
