@@ -642,11 +642,12 @@ def decode_leg(data, offs, reps: int = 10):
 BPE_TABLE = os.path.join(ROOT, "tests", "golden", "bpe4096_order5_64M.txt")
 
 
-def _bpe_rounds(ids, out_off, merges):
-    """Merge rounds per row, from the output alone: a round applies one
-    rank, and every rank applied to a row is in the merge tree of one of its
-    final tokens (a merged symbol either survives or is merged again), so
-    the rounds are the distinct merge ids over the rows' token trees."""
+def _bpe_ranks(ids, out_off, merges):
+    """Ranks each row applies, from the output alone: every rank applied to
+    a row is in the merge tree of one of its final tokens (a merged symbol
+    either survives or is merged again), so they are the distinct merge ids
+    over the rows' token trees. Merging one rank per round, as the
+    definition reads, takes that many rounds."""
     R = len(merges)
     tree = [None] * R
     for r in range(R):
@@ -717,14 +718,16 @@ def bpe_leg(reps: int = 10, tuning=None, per_seq_leg: bool = True):
     torch.cuda.synchronize()
     fused_ms = float(np.median([a.elapsed_time(b) for a, b in evs]))
 
-    rounds = _bpe_rounds(ids[:tokens].cpu().numpy(), h_oo, merges)
+    rounds = _bpe_ranks(ids[:tokens].cpu().numpy(), h_oo, merges)
     out = {
         "workload": "1024 sequences, log-uniform 500-20000 bases (%d bases), order-5 Markov, BPE 4096 merges "
                     "(oracle trainer, 64 Mbase), PACKED, no specials" % nbytes,
         "tokens": tokens,
-        "rounds_per_row": {
-            "note": "merge rounds each row needs (distinct ranks in its tokens' merge trees; every row is one "
-                    "ACGT run, so one item); the fused call's critical path is the row with the most",
+        "ranks_per_row": {
+            "note": "ranks each row applies (distinct ranks in its tokens' merge trees; every row is one ACGT "
+                    "run, so one item): the rounds of a one-rank-per-round merge. The kernel merges the ranks "
+                    "present in a window above the lowest one in a single round where that is exact, so its "
+                    "rounds are fewer; the fused call's critical path is the row with the most ranks",
             "max": int(rounds.max()), "p50": float(np.median(rounds)), "p90": float(np.percentile(rounds, 90)),
             "mean": float(rounds.mean()),
             "hist_edges": [0, 100, 200, 400, 800, 1200, 1600, 2400],
@@ -737,7 +740,7 @@ def bpe_leg(reps: int = 10, tuning=None, per_seq_leg: bool = True):
         "fused_tokens_per_s": tokens / (fused_ms * 1e-3),
         "fused_bases_per_s": nbytes / (fused_ms * 1e-3),
     }
-    out["us_per_round_on_critical_path"] = round(fused_ms * 1e3 / max(1, int(rounds.max())), 3)
+    out["us_per_rank_on_critical_path"] = round(fused_ms * 1e3 / max(1, int(rounds.max())), 3)
     if not per_seq_leg:
         log("bpe: fused %.3f ms (%.3e tokens/s)" % (fused_ms, out["fused_tokens_per_s"]))
         return out, data, offs, merges
