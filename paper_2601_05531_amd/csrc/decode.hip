@@ -208,6 +208,39 @@ __global__ __launch_bounds__(NT) void k_decode_rows(DecodeArgs a) {
     if (err) dev::raise_error(a.err_hdr, err);
 }
 
+// The staged output of a tile (agg bytes from stage byte 0) to out + base:
+// output byte base + b is stage byte b, for b below the capacity (past it:
+// the flag); the output's 16-byte units from out + base - ph on, each read
+// from the stage as 5 dwords realigned by ph.
+__device__ __forceinline__ void store_stage(const DecodeArgs &a, const uint8_t *s_out, int64_t base, int64_t agg,
+                                            uint32_t &err) {
+    const int tid = threadIdx.x;
+    const int64_t room = a.cap - base;
+    const int64_t lim = room <= 0 ? 0 : (room < agg ? room : agg);
+    if (lim < agg) err |= DNATOK_DERR_CAPACITY;
+    const int64_t ph = (int64_t)((reinterpret_cast<uintptr_t>(a.out) + (uintptr_t)base) & 15);
+    uint8_t *ob = a.out + base - ph;
+    const uint32_t *s32 = reinterpret_cast<const uint32_t *>(s_out);
+    const int64_t nu = lim > 0 ? (ph + lim + 15) / 16 : 0;
+    for (int64_t u = tid; u < nu; u += NT) {
+        const int64_t lo = 16 * u - ph, hi = lo + 16;  // the unit's stage bytes
+        if (lo >= 0 && hi <= lim) {
+            const uint32_t w0 = (uint32_t)lo >> 2, r = (uint32_t)lo & 3;
+            uint32_t w[5];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) w[q] = s32[w0 + q];
+            uint4 o;
+            o.x = __builtin_amdgcn_alignbyte(w[1], w[0], r);
+            o.y = __builtin_amdgcn_alignbyte(w[2], w[1], r);
+            o.z = __builtin_amdgcn_alignbyte(w[3], w[2], r);
+            o.w = __builtin_amdgcn_alignbyte(w[4], w[3], r);
+            *reinterpret_cast<uint4 *>(ob + 16 * u) = o;
+        } else {
+            for (int64_t b = (lo > 0 ? lo : 0); b < hi && b < lim; ++b) ob[ph + b] = s_out[b];
+        }
+    }
+}
+
 // 2. One workgroup per tile (tile = workgroup index): the tile's ids are
 // read once; their byte total is published for later tiles before the
 // look-back, which wave 0 runs while the other waves stage the tile's bytes
@@ -283,33 +316,7 @@ __global__ __launch_bounds__(NT) void k_decode_write(DecodeArgs a) {
     const int64_t base = s_base;
     uint32_t err = 0;
     if (staged) {
-        // output byte base + b is stage byte b, for b below the capacity;
-        // the output's 16-byte units from out + base - ph on, each read from
-        // the stage as 5 dwords realigned by ph
-        const int64_t room = a.cap - base;
-        const int64_t lim = room <= 0 ? 0 : (room < agg ? room : agg);
-        if (lim < agg) err |= DNATOK_DERR_CAPACITY;
-        const int64_t ph = (int64_t)((reinterpret_cast<uintptr_t>(a.out) + (uintptr_t)base) & 15);
-        uint8_t *ob = a.out + base - ph;
-        const uint32_t *s32 = reinterpret_cast<const uint32_t *>(s_out);
-        const int64_t nu = lim > 0 ? (ph + lim + 15) / 16 : 0;
-        for (int64_t u = tid; u < nu; u += NT) {
-            const int64_t lo = 16 * u - ph, hi = lo + 16;  // the unit's stage bytes
-            if (lo >= 0 && hi <= lim) {
-                const uint32_t w0 = (uint32_t)lo >> 2, r = (uint32_t)lo & 3;
-                uint32_t w[5];
-#pragma unroll
-                for (int q = 0; q < 5; ++q) w[q] = s32[w0 + q];
-                uint4 o;
-                o.x = __builtin_amdgcn_alignbyte(w[1], w[0], r);
-                o.y = __builtin_amdgcn_alignbyte(w[2], w[1], r);
-                o.z = __builtin_amdgcn_alignbyte(w[3], w[2], r);
-                o.w = __builtin_amdgcn_alignbyte(w[4], w[3], r);
-                *reinterpret_cast<uint4 *>(ob + 16 * u) = o;
-            } else {
-                for (int64_t b = (lo > 0 ? lo : 0); b < hi && b < lim; ++b) ob[ph + b] = s_out[b];
-            }
-        }
+        store_stage(a, s_out, base, agg, err);
     } else {
         // rare (output over the stage): the ids again, one at a time from
         // the cache, written straight to the output
@@ -337,6 +344,106 @@ __global__ __launch_bounds__(NT) void k_decode_write(DecodeArgs a) {
             sum += width_of<KIND>(a, live ? a.ids[q] : DNATOK_ID_PAD);
         }
         a.out_offs[i] = base + sum;
+    }
+    if (t == a.ntiles - 1 && tid == 0) a.out_offs[a.n] = base + agg;
+    if (err) dev::raise_error(a.err_hdr, err);
+}
+
+
+// 2'. The same for single-nucleotide and k-mer vocabularies up to 8 bases
+// (every token K bytes or none, a tile's output always staged), with the
+// ids strided: thread i holds the tile's ids i, i + NT, ..., so a wave's
+// lanes hold 64 consecutive ids. Loads coalesce per instruction, and a
+// staged byte store's lanes land on consecutive dwords; with each thread
+// holding 16 consecutive ids, one store's lanes were 96 bytes apart, on a
+// few LDS banks, and the staging ran bank-conflict bound beside the
+// look-back. Positions: a wave's ballot of the non-silent ids of slice j
+// gives each lane its count below it; one scan over the 64 (slice, wave)
+// counts in id order gives the rest. The ballots also give the row starts.
+template <int KIND, int K>
+__global__ __launch_bounds__(NT) void k_decode_strided(DecodeArgs a) {
+    constexpr int NW = NT / dev::kWave;
+    extern __shared__ __align__(16) uint8_t s_out[];
+    __shared__ uint32_t s_cnt[TPT * NW + 1];  // per (slice, wave): non-silent ids, then ids before; [TPT * NW]: total
+    __shared__ uint64_t s_msk[TPT * NW];      // per (slice, wave): which lanes hold a non-silent id
+    __shared__ int64_t s_ia, s_ib, s_base;
+    const int tid = threadIdx.x, lane = tid & (dev::kWave - 1), w = tid / dev::kWave;
+    const int64_t t = blockIdx.x;
+    const int64_t P0 = t * TT;
+    if (tid == 0) {
+        int64_t ia = a.first_row[t];
+        int64_t ib = (t == a.ntiles - 1) ? a.n : a.first_row[t + 1];
+        // rows starting in the tile (clamped: bad offsets raise the flag in the row pass)
+        ia = ia < 0 ? 0 : (ia > a.n ? a.n : ia);
+        ib = ib < ia ? ia : (ib > a.n ? a.n : ib);
+        s_ia = ia;
+        s_ib = ib;
+    }
+    const int64_t first = (a.n > 0) ? a.offs[0] : 0;
+    const int64_t last = (a.n > 0) ? a.offs[a.n] : 0;
+    // ids outside the rows read as PAD (no output); loads are unconditional
+    // (clamped) so they go out together
+    int32_t idv[TPT];
+#pragma unroll
+    for (int j = 0; j < TPT; ++j) {
+        const int64_t p = P0 + (int64_t)j * NT + tid;
+        const bool live = p >= first && p < last && p < a.n_ids;
+        const int32_t v = a.n_ids > 0 ? a.ids[live ? p : 0] : 0;
+        idv[j] = live ? v : DNATOK_ID_PAD;
+    }
+    uint32_t below[TPT];  // non-silent ids of this slice and wave below this lane
+#pragma unroll
+    for (int j = 0; j < TPT; ++j) {
+        const uint64_t m = __ballot(!is_silent(idv[j]));
+        below[j] = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (lane == 0) {
+            s_cnt[j * NW + w] = (uint32_t)__popcll(m);
+            s_msk[j * NW + w] = m;
+        }
+    }
+    __syncthreads();
+    if (tid < dev::kWave) {  // ids before each (slice, wave), in id order
+        const uint32_t v = s_cnt[tid];
+        const uint32_t inc = dev::wave_incl_sum_u32(v);
+        s_cnt[tid] = inc - v;
+        if (tid == dev::kWave - 1) s_cnt[TPT * NW] = inc;
+    }
+    __syncthreads();
+    const int64_t agg = (int64_t)K * s_cnt[TPT * NW];
+    if (tid < dev::kWave) {
+        if (tid == 0) dev::publish_aggregate(a.status, t, agg);
+        const int64_t excl = dev::wave_lookback(a.status, t, agg, a.err_hdr);
+        if (tid == 0) s_base = excl;
+    }
+    // the bytes go to LDS while wave 0 still waits on the look-back
+#pragma unroll
+    for (int j = 0; j < TPT; ++j) {
+        const int32_t id = idv[j];
+        if (is_silent(id)) continue;
+        uint8_t *p = s_out + (uint32_t)K * (s_cnt[j * NW + w] + below[j]);
+        if (KIND == DNATOK_SINGLE) {
+            p[0] = single_letter(id);
+        } else {
+            const bool known = id >= 5 && id < a.vocab;
+            const uint32_t v = (uint32_t)(id - 5);
+#pragma unroll
+            for (int q = 0; q < K; ++q) p[q] = known ? base_letter(v >> (2 * (K - 1 - q))) : (uint8_t)'N';
+        }
+    }
+    __syncthreads();
+    const int64_t base = s_base;
+    uint32_t err = 0;
+    store_stage(a, s_out, base, agg, err);
+    // rows starting in the tile: K bytes per non-silent id before their first position
+    for (int64_t i = s_ia + tid; i < s_ib; i += NT) {
+        int64_t rel = a.offs[i] - P0;
+        rel = rel < 0 ? 0 : (rel > TT ? TT : rel);
+        uint32_t c = s_cnt[TPT * NW];
+        if (rel < TT) {
+            const int js = (int)(rel / NT), ws = (int)((rel % NT) / dev::kWave), l = (int)(rel % dev::kWave);
+            c = s_cnt[js * NW + ws] + (uint32_t)__popcll(s_msk[js * NW + ws] & ((1ull << l) - 1ull));
+        }
+        a.out_offs[i] = base + (int64_t)K * c;
     }
     if (t == a.ntiles - 1 && tid == 0) a.out_offs[a.n] = base + agg;
     if (err) dev::raise_error(a.err_hdr, err);
@@ -378,7 +485,20 @@ int launch_decode(const dnatok_vocab *v, const int32_t *d_ids, int64_t n_ids, co
     DNATOK_HIP(hipGetLastError());
     const dim3 grid((unsigned)a.ntiles), block(NT);
     const size_t dyn = (size_t)a.stage + 16;  // a unit's realigning reads go up to 3 bytes past the data
-    if (v->kind == DNATOK_KMER)
+    if (v->kind == DNATOK_SINGLE && a.stage >= TT) {
+        hipLaunchKernelGGL((k_decode_strided<DNATOK_SINGLE, 1>), grid, block, dyn, stream, a);
+    } else if (v->kind == DNATOK_KMER && v->k <= 8 && a.stage >= TT * v->k) {
+        switch (v->k) {
+        case 1: hipLaunchKernelGGL((k_decode_strided<DNATOK_KMER, 1>), grid, block, dyn, stream, a); break;
+        case 2: hipLaunchKernelGGL((k_decode_strided<DNATOK_KMER, 2>), grid, block, dyn, stream, a); break;
+        case 3: hipLaunchKernelGGL((k_decode_strided<DNATOK_KMER, 3>), grid, block, dyn, stream, a); break;
+        case 4: hipLaunchKernelGGL((k_decode_strided<DNATOK_KMER, 4>), grid, block, dyn, stream, a); break;
+        case 5: hipLaunchKernelGGL((k_decode_strided<DNATOK_KMER, 5>), grid, block, dyn, stream, a); break;
+        case 6: hipLaunchKernelGGL((k_decode_strided<DNATOK_KMER, 6>), grid, block, dyn, stream, a); break;
+        case 7: hipLaunchKernelGGL((k_decode_strided<DNATOK_KMER, 7>), grid, block, dyn, stream, a); break;
+        default: hipLaunchKernelGGL((k_decode_strided<DNATOK_KMER, 8>), grid, block, dyn, stream, a); break;
+        }
+    } else if (v->kind == DNATOK_KMER)
         hipLaunchKernelGGL(k_decode_write<DNATOK_KMER>, grid, block, dyn, stream, a);
     else if (v->kind == DNATOK_BPE)
         hipLaunchKernelGGL(k_decode_write<DNATOK_BPE>, grid, block, dyn, stream, a);

@@ -276,10 +276,11 @@ def test_two_streams_concurrently():
 
 # ---------------------------------------------------------------- decode
 
-@pytest.mark.parametrize("kind,k", [(dt.SINGLE, 1), (dt.KMER, 3), (dt.KMER, 6), (dt.KMER, 12)])
+@pytest.mark.parametrize("kind,k", [(dt.SINGLE, 1)] + [(dt.KMER, k) for k in range(1, 9)] + [(dt.KMER, 12)])
 def test_decode_matches_oracle(kind, k):
-    # k = 12: a tile's output (2,048 x 12 bytes) is over the LDS stage, so
-    # tokens are written directly
+    # single-nucleotide and k <= 8: the strided kernel, one instance per k;
+    # k = 12: the contiguous kernel, a tile's output (4,096 x 12 bytes) over
+    # the LDS stage, so tokens are written directly
     torch = _torch()
     rng = np.random.default_rng(k)
     vs = 10 if kind == dt.SINGLE else 5 + 4 ** k
