@@ -684,47 +684,57 @@ __device__ __forceinline__ void wave_item(const WaveArgs &a, const RankTab &tab,
                 Ag[g] = 0;
                 RFg[g] = RIg[g] = LIg[g] = kNoRank;
                 BRg[g] = BLg[g] = kNone;
-                if ((uint32_t)(64 * g) < total && Mg[g]) {
+                if ((uint32_t)(64 * g) < total) {
+                    // every read an entry may need goes out at once (indices
+                    // clamped, results selected after), then the three
+                    // lookups: branches per case kept the LDS trips apart
                     const uint32_t e = 64u * g + (uint32_t)lane;
+                    const bool ms = Mg[g];
                     const uint32_t d = Dg[g], st = step_of(d), NEW = 10u + rs + d;
-                    Ag[g] = st;
-                    const uint32_t q2 = Q2g[g];
-                    if (q2 != kNone) {
-                        // a merge starting at q2 is one or two entries on
-                        uint32_t jr = kNone;
-                        if (e + 1 < total && list[e + 1] == q2 && (einfo[e + 1] & 0x80u)) jr = e + 1;
-                        else if (e + 2 < total && list[e + 2] == q2 && (einfo[e + 2] & 0x80u)) jr = e + 2;
-                        const uint32_t s2 = sym[q2];
-                        if (jr != kNone) {
-                            const uint32_t dj = einfo[jr] & 63u, sj = step_of(dj);
+                    const uint32_t q2 = Q2g[g], l = Lg[g];
+                    const uint32_t e1 = min(e + 1, kCap - 1), e2 = min(e + 2, kCap - 1);
+                    const uint32_t m1 = e >= 1 ? e - 1 : 0u, m2 = e >= 2 ? e - 2 : 0u;
+                    const uint32_t p1 = list[e1], p2 = list[e2], i1 = einfo[e1], i2 = einfo[e2];
+                    const uint32_t qm1 = eq[m1], qm2 = eq[m2], im1 = einfo[m1], im2 = einfo[m2];
+                    const uint32_t s2 = sym[q2 != kNone ? q2 : 0u], sl = sym[l != kNone ? l : 0u];
+                    // a merge starting at q2, one or two entries on
+                    const bool r1 = q2 != kNone && e + 1 < total && p1 == q2 && (i1 & 0x80u);
+                    const bool r2 = !r1 && q2 != kNone && e + 2 < total && p2 == q2 && (i2 & 0x80u);
+                    const bool jr = r1 || r2;
+                    const uint32_t dj = (r1 ? i1 : i2) & 63u, sj = step_of(dj);
+                    // a merge ending at l, one or two entries back
+                    const bool l1 = l != kNone && e >= 1 && qm1 == l && (im1 & 0x80u);
+                    const bool l2b = !l1 && l != kNone && e >= 2 && qm2 == l && (im2 & 0x80u);
+                    const bool jl = l1 || l2b;
+                    const uint32_t sl_step = step_of((l1 ? im1 : im2) & 63u);
+                    // the pairs this merge forms: with the merge on the right
+                    // (at the later step), and with the unmerged symbol on
+                    // each side (at its own step)
+                    const uint32_t rf = pair_rank(tab, NEW, 10u + rs + dj);
+                    const uint32_t ri = pair_rank(tab, NEW, s2);
+                    const uint32_t li = pair_rank(tab, sl, NEW);
+                    const bool need_ri = q2 != kNone && (!jr || sj > st);
+                    const bool need_li = l != kNone && (!jl || sl_step > st);
+                    if (ms) {
+                        Ag[g] = st;
+                        if (jr) {
                             BRg[g] = sj;
-                            RFg[g] = pair_rank(tab, NEW, 10u + rs + dj);
-                            cutv = min(cutv, bound(max(st, sj), RFg[g]));
-                            if (sj > st) {
-                                RIg[g] = pair_rank(tab, NEW, s2);
-                                cutv = min(cutv, bound(st, RIg[g]));
-                            }
-                        } else {
-                            RIg[g] = pair_rank(tab, NEW, s2);
-                            cutv = min(cutv, bound(st, RIg[g]));
+                            RFg[g] = rf;
+                            cutv = min(cutv, bound(max(st, sj), rf));
                         }
-                    }
-                    const uint32_t l = Lg[g];
-                    if (l != kNone) {
-                        // a merge ending at l is one or two entries back
-                        uint32_t jl = kNone;
-                        if (e >= 1 && eq[e - 1] == l && (einfo[e - 1] & 0x80u)) jl = e - 1;
-                        else if (e >= 2 && eq[e - 2] == l && (einfo[e - 2] & 0x80u)) jl = e - 2;
-                        const uint32_t sl = jl != kNone ? step_of(einfo[jl] & 63u) : kNone;
-                        BLg[g] = sl;
-                        if (jl == kNone || sl > st) {
-                            LIg[g] = pair_rank(tab, sym[l], NEW);
-                            cutv = min(cutv, bound(st, LIg[g]));
+                        if (need_ri) {
+                            RIg[g] = ri;
+                            cutv = min(cutv, bound(st, ri));
                         }
+                        if (jl) BLg[g] = sl_step;
+                        if (need_li) {
+                            LIg[g] = li;
+                            cutv = min(cutv, bound(st, li));
+                        }
+                        // the previous entry merges too and shares p: another step ends before the later one
+                        if (e >= 1 && (im1 & 0x80u) && qm1 == Pg[g] && (im1 & 63u) != d)
+                            cutv = min(cutv, max(st, step_of(im1 & 63u)));
                     }
-                    // the previous entry merges too and shares p: another step ends before the later one
-                    if (e >= 1 && (einfo[e - 1] & 0x80u) && eq[e - 1] == Pg[g] && (einfo[e - 1] & 63u) != d)
-                        cutv = min(cutv, max(st, step_of(einfo[e - 1] & 63u)));
                 }
             }
             const uint32_t cut = dev::wave_min_all_u32(cutv);
@@ -755,16 +765,22 @@ __device__ __forceinline__ void wave_item(const WaveArgs &a, const RankTab &tab,
             const uint64_t dw = b0 < nb ? ((uint64_t)dirty[w0] | ((uint64_t)dirty[w0 + 1] << 32)) : 0ull;
             own_dirty |= (uint32_t)(dw >> (b0 & 31)) & ((k2 >= 32) ? ~0u : ((1u << k2) - 1u));
         }
+        // the changed blocks listed, one per lane recomputed into bmin (a
+        // pass per lane's own changed block made the wave wait for its
+        // busiest lane: 3,800 cycles per round), then each lane's minima
+        // read back
+        wave_sync();
+        const uint32_t nch = list_blocks(own_dirty);
+        wave_sync();
+        for (uint32_t j = (uint32_t)lane; j < nch; j += 64) {
+            const uint32_t b = cblk[j];
+            bmin[b] = (uint16_t)block_min(prk, b);
+        }
+        wave_sync();
         if (own_dirty) {
-            // one block per pass: the wave makes as many passes as its
-            // busiest lane has changed blocks (a per-k test would run a pass
-            // for every k that any lane needs)
-            for (uint32_t dm = own_dirty; dm; dm &= dm - 1) {
-                const uint32_t kk = (uint32_t)__builtin_ctz(dm);
-                const uint32_t m = block_min(prk, b0 + kk);
 #pragma unroll
-                for (int k = 0; k < kK2Max; ++k) bm[k] = ((uint32_t)k == kk) ? m : bm[k];
-            }
+            for (int k = 0; k < kK2Max; ++k)
+                if ((own_dirty >> k) & 1u) bm[k] = bmin[b0 + (uint32_t)k];
             l2 = kNoRank;
 #pragma unroll
             for (int k = 0; k < kK2Max; ++k) l2 = min(l2, bm[k]);
