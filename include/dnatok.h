@@ -474,7 +474,7 @@ typedef struct dnatok_tuning {
                                stages the bytes of a few whole rows, or of a part of a longer row, at most
                                tile_bytes, and writes all their cells), 2 = tiles, 3 = row bands taken by
                                resident workgroups in turn, the next band's bytes fetched while the current
-                               one is written (stages up to 16 KiB) */
+                               one is written (a band staging more than 16 KiB less 64 bytes runs as 1) */
 } dnatok_tuning;
 
 int dnatok_get_tuning(const dnatok_vocab *v, dnatok_tuning *out);
@@ -485,8 +485,10 @@ int dnatok_set_tuning(dnatok_vocab *v, const dnatok_tuning *t);
 /*
  * Time every candidate tiling of v on this batch (the arguments of
  * dnatok_encode; the outputs are overwritten) with HIP events on `stream`:
- * one warm-up and `reps` timed launches each (median). The fastest setting
- * is stored in v and returned in *best / *best_ms. Synchronizes `stream`;
+ * one warm-up and `reps` timed samples each, a sample being 4 back-to-back
+ * launches (median of the time per launch); the three fastest again, 3 *
+ * reps samples each, interleaved. The fastest setting is stored in v and
+ * returned in *best / *best_ms (ms per launch). Synchronizes `stream`;
  * not allowed during graph capture (ESTATE). Errors as dnatok_encode.
  */
 int dnatok_autotune(dnatok_vocab *v, const uint8_t *d_bytes, int64_t nbytes, const int64_t *d_offsets, int32_t n,

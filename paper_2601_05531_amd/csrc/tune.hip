@@ -79,7 +79,7 @@ int dnatok_set_tuning(dnatok_vocab *v, const dnatok_tuning *t) {
 namespace {
 
 // Times every candidate tiling of v with `run` (one encode on `st`): one
-// warm-up and `reps` timed launches each, median; keeps the fastest in v.
+// warm-up sample and `reps` timed samples of 4 launches each, median; keeps the fastest in v.
 template <class Run>
 int autotune_loop(dnatok_vocab *v, hipStream_t st, int32_t reps, bool padded, Run run, dnatok_tuning *best,
                   float *best_ms) {
@@ -97,9 +97,10 @@ int autotune_loop(dnatok_vocab *v, hipStream_t st, int32_t reps, bool padded, Ru
             for (int32_t b : {0, 1, 2, 4}) cand.push_back(dnatok_tuning{tile, b, 0, 0, 0, 0});
         for (int32_t tile : {4096, 8192, 16384})
             for (int32_t sp : {10, 25, 50}) cand.push_back(dnatok_tuning{tile, 0, 0, 0, sp, 0});
-        if (padded) {  // row bands, staged through LDS stages of 4 to 64 KiB; persistent ones up to 16 KiB
+        if (padded) {  // row bands, staged through LDS stages of 4 to 64 KiB; persistent ones of 4 and 8 KiB
+            // (a 16 KiB persistent stage holds no band of 16 KiB, so it would run as row bands)
             for (int32_t tile : {4096, 8192, 16384, 32768, 65536}) cand.push_back(dnatok_tuning{tile, 0, 0, 0, 0, 1});
-            for (int32_t tile : {4096, 8192, 16384}) cand.push_back(dnatok_tuning{tile, 0, 0, 0, 0, 3});
+            for (int32_t tile : {4096, 8192}) cand.push_back(dnatok_tuning{tile, 0, 0, 0, 0, 3});
         }
     }
     const dnatok_tuning saved = load(v);
@@ -107,21 +108,28 @@ int autotune_loop(dnatok_vocab *v, hipStream_t st, int32_t reps, bool padded, Ru
     DNATOK_HIP(hipEventCreate(&e0));
     DNATOK_HIP(hipEventCreate(&e1));
     int rc = DNATOK_OK;
-    // one timed launch (after the previous one has finished)
+    // one sample: kBatch back-to-back launches between one event pair (after
+    // the previous sample has finished), the time per launch. Timing single
+    // launches added an event's release and timestamp (about 18 us) to each,
+    // whose noise could hide a 10% difference between candidates.
+    constexpr int kBatch = 4;
     auto time_one = [&](float *ms) {
         if (hipEventRecord(e0, st) != hipSuccess) return set_error(DNATOK_EDEVICE, "hipEventRecord failed");
-        int r = run();
-        if (r != DNATOK_OK) return r;
+        for (int b = 0; b < kBatch; ++b) {
+            int r = run();
+            if (r != DNATOK_OK) return r;
+        }
         if (hipEventRecord(e1, st) != hipSuccess) return set_error(DNATOK_EDEVICE, "hipEventRecord failed");
         if (hipEventSynchronize(e1) != hipSuccess) return set_error(DNATOK_EDEVICE, "hipEventSynchronize failed");
         if (hipEventElapsedTime(ms, e0, e1) != hipSuccess) return set_error(DNATOK_EDEVICE, "hipEventElapsedTime failed");
+        *ms /= (float)kBatch;
         return DNATOK_OK;
     };
     auto median = [](std::vector<float> &ts) {
         std::nth_element(ts.begin(), ts.begin() + ts.size() / 2, ts.end());
         return ts[ts.size() / 2];
     };
-    // Screen: every candidate, one warm-up launch and reps timed ones.
+    // Screen: every candidate, one warm-up sample and reps timed ones.
     std::vector<float> med(cand.size(), 0.0f);
     for (size_t ci = 0; ci < cand.size() && rc == DNATOK_OK; ++ci) {
         store(v, cand[ci]);
@@ -129,7 +137,7 @@ int autotune_loop(dnatok_vocab *v, hipStream_t st, int32_t reps, bool padded, Ru
         for (int r = 0; r <= reps && rc == DNATOK_OK; ++r) {
             float ms = 0.0f;
             rc = time_one(&ms);
-            if (r > 0) ts.push_back(ms);  // the first launch warms up
+            if (r > 0) ts.push_back(ms);  // the first sample warms up
         }
         if (rc == DNATOK_OK) med[ci] = median(ts);
     }
