@@ -125,11 +125,11 @@ def encode_leg(steps: int, warmup: int, tuning=None, per_vocab: bool = True):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(tune_multi.get("bands", 0)),
-            "kernel": ("k_bands<KMER> (row bands, %d-byte stage)" % tune_multi["tile_bytes"]
-                       if tune_multi.get("bands") == 1 else
-                       "k_bands_loop<KMER> (row bands, resident workgroups, %d-byte stage)" % tune_multi["tile_bytes"]
-                       if tune_multi.get("bands") == 3 else "k_cells<KMER> (tiles)") +
+            "traffic": measured_traffic(kernel_family(tune_multi)),
+            "kernel": {"k_bands": "k_bands<KMER> (row bands, %d-byte stage)" % tune_multi["tile_bytes"],
+                       "k_bands_loop": "k_bands_loop<KMER> (row bands, resident workgroups, %d-byte stage)"
+                                       % tune_multi["tile_bytes"],
+                       "k_cells": "k_cells<KMER> (tiles)"}[kernel_family(tune_multi)] +
                       " writing k = 3, 4, 5, 6 in one pass",
             "per_launch_bytes": "1 B per input byte (read once) + 16 B per row of offsets + per vocabulary "
                                 "5 B per cell (4 B id + 1 B mask over n x pad_to) = %d B" % bytes_launch,
@@ -191,7 +191,17 @@ def encode_leg(steps: int, warmup: int, tuning=None, per_vocab: bool = True):
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "encode_multi_k_batch_traffic.md")
 
 
-def measured_traffic(bands: int):
+def kernel_family(tune) -> str:
+    """The kernel a tiling of the batched workload runs: row bands (1),
+    resident row bands (3; a stage over 8 KiB holds two 8,192-byte rows,
+    more than the resident form stages, and runs as row bands), else tiles."""
+    b, tile = tune.get("bands", 0), tune.get("tile_bytes", 0)
+    if b == 3 and tile <= 8192:
+        return "k_bands_loop"
+    return "k_bands" if b in (1, 3) else "k_cells"
+
+
+def measured_traffic(family: str):
     """HBM bytes per launch of the one-pass encode from the committed counter
     summary (FETCH_SIZE / WRITE_SIZE calibrated by a copy of known size), or
     None when the summary is missing, was taken on another kernel than the
@@ -207,7 +217,6 @@ def measured_traffic(bands: int):
         if ":" in line and line.startswith("    "):
             key, val = line.strip().split(":", 1)
             fields[key.strip()] = val.strip()
-    family = "k_bands_loop" if bands == 3 else "k_bands" if bands == 1 else "k_cells"
     try:
         if fields["kernel"].split("<")[0] != family:
             return None
