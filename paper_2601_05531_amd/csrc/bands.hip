@@ -215,7 +215,10 @@ __device__ __forceinline__ void band_write(const BandArgs &a, int64_t r0, int nr
     // a vocabulary: 54 -> 48 us for k = 3..6 at 8 KiB stages); fewer: the
     // whole workgroup.
     const bool by_wave = a.nv >= NTB / dev::kWave;
-    const int wid = tid / dev::kWave;
+    // the wave index is uniform across a wave, and saying so keeps each
+    // vocabulary's facts (pointers, sizes, ids) in scalar registers: as a
+    // per-lane value it held them in VGPRs, 85 instead of 49
+    const int wid = __builtin_amdgcn_readfirstlane(tid / dev::kWave);
     const int wtid = by_wave ? (tid & (dev::kWave - 1)) : tid;
     const int wstride = by_wave ? dev::kWave : NTB;
     for (int vi = by_wave ? wid : 0; vi < a.nv; vi += by_wave ? NTB / dev::kWave : 1) {
@@ -356,10 +359,7 @@ __device__ __forceinline__ void band_write(const BandArgs &a, int64_t r0, int nr
 }
 
 template <bool KMER>
-// At least six waves per SIMD: the k-mer form fits 79 VGPRs with no spill
-// (it took 85, five waves per SIMD, left to itself) and writes k = 3..6 at
-// 8 KiB stages 6% faster; eight waves per SIMD spill and run 35% slower.
-__global__ __launch_bounds__(NTB) __attribute__((amdgpu_waves_per_eu(6))) void k_bands(BandArgs a) {
+__global__ __launch_bounds__(NTB) void k_bands(BandArgs a) {
     extern __shared__ __align__(16) uint8_t dyn[];
     __shared__ int64_t s_o0[kMaxBandRows], s_o1[kMaxBandRows];
     __shared__ int32_t s_nb[kBandVocabs * kMaxBandRows];   // body tokens of (vocabulary, row)
