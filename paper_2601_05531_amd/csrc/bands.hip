@@ -212,21 +212,24 @@ __device__ __forceinline__ void band_write(const BandArgs &a, int64_t r0, int nr
     // Four or more vocabularies: one per wave, a row's groups of that
     // vocabulary in passes of 64 (a workgroup-wide pass of 256 left on
     // average a third of its lanes idle at the end of each row's share of
-    // a vocabulary: 54 -> 48 us for k = 3..6 at 8 KiB stages); fewer: the
-    // whole workgroup.
+    // a vocabulary: 54 -> 48 us for k = 3..6 at 8 KiB stages). Fewer
+    // vocabularies but four or more rows in the band: one row per wave, for
+    // the same reason (single-nucleotide ids at 32 KiB stages 49 -> 43.5 us).
+    // Otherwise the whole workgroup.
     const bool by_wave = a.nv >= NTB / dev::kWave;
+    const bool by_row = !by_wave && nr >= NTB / dev::kWave;
     // the wave index is uniform across a wave, and saying so keeps each
     // vocabulary's facts (pointers, sizes, ids) in scalar registers: as a
     // per-lane value it held them in VGPRs, 85 instead of 49
     const int wid = __builtin_amdgcn_readfirstlane(tid / dev::kWave);
-    const int wtid = by_wave ? (tid & (dev::kWave - 1)) : tid;
-    const int wstride = by_wave ? dev::kWave : NTB;
+    const int wtid = (by_wave || by_row) ? (tid & (dev::kWave - 1)) : tid;
+    const int wstride = (by_wave || by_row) ? dev::kWave : NTB;
     for (int vi = by_wave ? wid : 0; vi < a.nv; vi += by_wave ? NTB / dev::kWave : 1) {
         const BandVocab o = a.vo[vi];
         const int32_t k = KMER ? o.k : 1;
         const int32_t W = (int32_t)o.W;
         const bool mask4 = ((reinterpret_cast<uintptr_t>(o.mask) - (uintptr_t)o.al) & 3) == 0;
-        for (int r = 0; r < nr; ++r) {
+        for (int r = by_row ? wid : 0; r < nr; r += by_row ? NTB / dev::kWave : 1) {
             const int32_t nb = __builtin_amdgcn_readfirstlane(s_nb[vi * kMaxBandRows + r]);
             const int32_t L = __builtin_amdgcn_readfirstlane((int32_t)(s_o1[r] - s_o0[r]));
             const uint32_t ro = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)s_ro[r]);
