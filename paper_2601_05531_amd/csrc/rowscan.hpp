@@ -94,7 +94,7 @@ __device__ __forceinline__ int64_t rowscan_unit(const RowScanArgs &a, int64_t ro
 }
 
 // Whole batch by one block, units in order (the fused PADDED case).
-__device__ void rowscan_single_block(const RowScanArgs &a, int64_t *s_tmp, uint32_t *err_hdr) {
+[[maybe_unused]] __device__ void rowscan_single_block(const RowScanArgs &a, int64_t *s_tmp, uint32_t *err_hdr) {
     uint32_t err = 0;
     int64_t run = 0;
     for (int64_t row0 = 0; row0 < a.n; row0 += kUnitRows) {
