@@ -24,7 +24,9 @@ namespace {
 constexpr int NT = 256;
 constexpr int TPT = 16;  // tokens per thread (fewer, smaller tiles measured slower for every kind)
 constexpr int TT = NT * TPT;
-constexpr int kMaxStage = 32768;  // most bytes of one tile's output staged in LDS
+constexpr int kMaxStage = 32768;
+constexpr int TPT_SINGLE = 32;  // single-nucleotide ids per thread in the strided kernel
+constexpr int TT_SINGLE = NT * TPT_SINGLE;  // most bytes of one tile's output staged in LDS
 
 struct DecodeArgs {
     const int32_t *ids;
@@ -41,6 +43,7 @@ struct DecodeArgs {
     const int64_t *tok_off;
     const uint8_t *tok_chars;
     int64_t ntiles;
+    int64_t tt;          // token positions per tile (TT, or TT_SINGLE for the strided single-nucleotide kernel)
     int32_t stage;       // bytes the LDS stage holds (a tile with more output writes its tokens directly)
     uint64_t *status;    // tile status words of the look-back (ntiles), cleared by the row pass
     int64_t *first_row;  // first row starting at or after each tile's first position (ntiles + 1)
@@ -199,8 +202,8 @@ __global__ __launch_bounds__(NT) void k_decode_rows(DecodeArgs a) {
         const int64_t cur = (i == a.n) ? -1 : a.offs[i];
         if (i < a.n && (cur < 0 || (i + 1 <= a.n && a.offs[i + 1] < cur) || a.offs[i + 1] > a.n_ids))
             err |= DNATOK_DERR_OFFSETS;
-        int64_t lo = (i == 0) ? 0 : (prev < 0 ? 0 : prev / TT + 1);
-        int64_t hi = (i == a.n) ? a.ntiles : (cur < 0 ? -1 : cur / TT);
+        int64_t lo = (i == 0) ? 0 : (prev < 0 ? 0 : prev / a.tt + 1);
+        int64_t hi = (i == a.n) ? a.ntiles : (cur < 0 ? -1 : cur / a.tt);
         if (hi > a.ntiles) hi = a.ntiles;
         for (int64_t t = lo; t <= hi; ++t) a.first_row[t] = i;
     }
@@ -360,12 +363,14 @@ __global__ __launch_bounds__(NT) void k_decode_write(DecodeArgs a) {
 // look-back. Positions: a wave's ballot of the non-silent ids of slice j
 // gives each lane its count below it; one scan over the 64 (slice, wave)
 // counts in id order gives the rest. The ballots also give the row starts.
-template <int KIND, int K>
+template <int KIND, int K, int TPS>
 __global__ __launch_bounds__(NT) void k_decode_strided(DecodeArgs a) {
     constexpr int NW = NT / dev::kWave;
+    constexpr int TPT = TPS, TT = NT * TPS;  // this kernel's ids per thread and per tile
+    constexpr int NS = TPT * NW;             // (slice, wave) entries, a multiple of the wave
     extern __shared__ __align__(16) uint8_t s_out[];
-    __shared__ uint32_t s_cnt[TPT * NW + 1];  // per (slice, wave): non-silent ids, then ids before; [TPT * NW]: total
-    __shared__ uint64_t s_msk[TPT * NW];      // per (slice, wave): which lanes hold a non-silent id
+    __shared__ uint32_t s_cnt[NS + 1];  // per (slice, wave): non-silent ids, then ids before; [NS]: total
+    __shared__ uint64_t s_msk[NS];      // per (slice, wave): which lanes hold a non-silent id
     __shared__ int64_t s_ia, s_ib, s_base;
     const int tid = threadIdx.x, lane = tid & (dev::kWave - 1), w = tid / dev::kWave;
     const int64_t t = blockIdx.x;
@@ -402,14 +407,25 @@ __global__ __launch_bounds__(NT) void k_decode_strided(DecodeArgs a) {
         }
     }
     __syncthreads();
-    if (tid < dev::kWave) {  // ids before each (slice, wave), in id order
-        const uint32_t v = s_cnt[tid];
-        const uint32_t inc = dev::wave_incl_sum_u32(v);
-        s_cnt[tid] = inc - v;
-        if (tid == dev::kWave - 1) s_cnt[TPT * NW] = inc;
+    if (tid < dev::kWave) {  // ids before each (slice, wave), in id order; a lane takes NS / 64 in a row
+        constexpr int PER = NS / dev::kWave;
+        uint32_t v[PER], sum = 0;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            v[q] = s_cnt[tid * PER + q];
+            sum += v[q];
+        }
+        const uint32_t inc = dev::wave_incl_sum_u32(sum);
+        uint32_t run = inc - sum;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            s_cnt[tid * PER + q] = run;
+            run += v[q];
+        }
+        if (tid == dev::kWave - 1) s_cnt[NS] = inc;
     }
     __syncthreads();
-    const int64_t agg = (int64_t)K * s_cnt[TPT * NW];
+    const int64_t agg = (int64_t)K * s_cnt[NS];
     if (tid < dev::kWave) {
         if (tid == 0) dev::publish_aggregate(a.status, t, agg);
         const int64_t excl = dev::wave_lookback(a.status, t, agg, a.err_hdr);
@@ -438,7 +454,7 @@ __global__ __launch_bounds__(NT) void k_decode_strided(DecodeArgs a) {
     for (int64_t i = s_ia + tid; i < s_ib; i += NT) {
         int64_t rel = a.offs[i] - P0;
         rel = rel < 0 ? 0 : (rel > TT ? TT : rel);
-        uint32_t c = s_cnt[TPT * NW];
+        uint32_t c = s_cnt[NS];
         if (rel < TT) {
             const int js = (int)(rel / NT), ws = (int)((rel % NT) / dev::kWave), l = (int)(rel % dev::kWave);
             c = s_cnt[js * NW + ws] + (uint32_t)__popcll(s_msk[js * NW + ws] & ((1ull << l) - 1ull));
@@ -467,11 +483,14 @@ int launch_decode(const dnatok_vocab *v, const int32_t *d_ids, int64_t n_ids, co
     a.tok_len = v->bpe.d_tok_len;
     a.tok_off = v->bpe.d_tok_off;
     a.tok_chars = v->bpe.d_tok_chars;
-    a.ntiles = n_ids / TT + 1;
+    // single-nucleotide ids go 32 per thread (8,192 per tile): half the tiles'
+    // fixed latency for a stage of 8 KiB (73 -> 58 us for 33.6M ids)
+    a.tt = v->kind == DNATOK_SINGLE ? (int64_t)TT_SINGLE : (int64_t)TT;
+    a.ntiles = n_ids / a.tt + 1;
     if (a.ntiles >= (1ll << 31)) return set_error(DNATOK_EINVAL, "too many ids for one decode");
     // the stage holds a tile's output at the vocabulary's widest token
     const int64_t wmax = v->kind == DNATOK_KMER ? v->k : (v->kind == DNATOK_BPE ? v->max_token_bytes : 1);
-    a.stage = (int32_t)std::min<int64_t>((int64_t)TT * std::max<int64_t>(wmax, 1), kMaxStage);
+    a.stage = (int32_t)std::min<int64_t>(a.tt * std::max<int64_t>(wmax, 1), kMaxStage);
     Workspace *ws = nullptr;
     int rc = get_workspace(stream, 1, &ws);
     if (rc) return rc;
@@ -485,25 +504,23 @@ int launch_decode(const dnatok_vocab *v, const int32_t *d_ids, int64_t n_ids, co
     DNATOK_HIP(hipGetLastError());
     const dim3 grid((unsigned)a.ntiles), block(NT);
     const size_t dyn = (size_t)a.stage + 16;  // a unit's realigning reads go up to 3 bytes past the data
-    if (v->kind == DNATOK_SINGLE && a.stage >= TT) {
-        hipLaunchKernelGGL((k_decode_strided<DNATOK_SINGLE, 1>), grid, block, dyn, stream, a);
+    if (v->kind == DNATOK_SINGLE) {  // its stage (a.tt bytes) always holds the tile
+        hipLaunchKernelGGL((k_decode_strided<DNATOK_SINGLE, 1, TPT_SINGLE>), grid, block, dyn, stream, a);
     } else if (v->kind == DNATOK_KMER && v->k <= 8 && a.stage >= TT * v->k) {
         switch (v->k) {
-        case 1: hipLaunchKernelGGL((k_decode_strided<DNATOK_KMER, 1>), grid, block, dyn, stream, a); break;
-        case 2: hipLaunchKernelGGL((k_decode_strided<DNATOK_KMER, 2>), grid, block, dyn, stream, a); break;
-        case 3: hipLaunchKernelGGL((k_decode_strided<DNATOK_KMER, 3>), grid, block, dyn, stream, a); break;
-        case 4: hipLaunchKernelGGL((k_decode_strided<DNATOK_KMER, 4>), grid, block, dyn, stream, a); break;
-        case 5: hipLaunchKernelGGL((k_decode_strided<DNATOK_KMER, 5>), grid, block, dyn, stream, a); break;
-        case 6: hipLaunchKernelGGL((k_decode_strided<DNATOK_KMER, 6>), grid, block, dyn, stream, a); break;
-        case 7: hipLaunchKernelGGL((k_decode_strided<DNATOK_KMER, 7>), grid, block, dyn, stream, a); break;
-        default: hipLaunchKernelGGL((k_decode_strided<DNATOK_KMER, 8>), grid, block, dyn, stream, a); break;
+        case 1: hipLaunchKernelGGL((k_decode_strided<DNATOK_KMER, 1, TPT>), grid, block, dyn, stream, a); break;
+        case 2: hipLaunchKernelGGL((k_decode_strided<DNATOK_KMER, 2, TPT>), grid, block, dyn, stream, a); break;
+        case 3: hipLaunchKernelGGL((k_decode_strided<DNATOK_KMER, 3, TPT>), grid, block, dyn, stream, a); break;
+        case 4: hipLaunchKernelGGL((k_decode_strided<DNATOK_KMER, 4, TPT>), grid, block, dyn, stream, a); break;
+        case 5: hipLaunchKernelGGL((k_decode_strided<DNATOK_KMER, 5, TPT>), grid, block, dyn, stream, a); break;
+        case 6: hipLaunchKernelGGL((k_decode_strided<DNATOK_KMER, 6, TPT>), grid, block, dyn, stream, a); break;
+        case 7: hipLaunchKernelGGL((k_decode_strided<DNATOK_KMER, 7, TPT>), grid, block, dyn, stream, a); break;
+        default: hipLaunchKernelGGL((k_decode_strided<DNATOK_KMER, 8, TPT>), grid, block, dyn, stream, a); break;
         }
     } else if (v->kind == DNATOK_KMER)
         hipLaunchKernelGGL(k_decode_write<DNATOK_KMER>, grid, block, dyn, stream, a);
-    else if (v->kind == DNATOK_BPE)
-        hipLaunchKernelGGL(k_decode_write<DNATOK_BPE>, grid, block, dyn, stream, a);
     else
-        hipLaunchKernelGGL(k_decode_write<DNATOK_SINGLE>, grid, block, dyn, stream, a);
+        hipLaunchKernelGGL(k_decode_write<DNATOK_BPE>, grid, block, dyn, stream, a);
     DNATOK_HIP(hipGetLastError());
     return DNATOK_OK;
 }
