@@ -297,6 +297,29 @@ def test_decode_matches_oracle(kind, k):
     assert np.array_equal(out.cpu().numpy()[:want_off[-1]], want)
 
 
+@pytest.mark.parametrize("kind,k", [(dt.SINGLE, 1), (dt.KMER, 6)])
+def test_decode_empty_and_tile_edges(kind, k):
+    # no ids (rows all empty, or no rows), exactly one tile of 4,096 and of
+    # 8,192 ids, one id past it, and rows ending on tile edges
+    torch = _torch()
+    v = _vocab(kind, k)
+    rng = np.random.default_rng(40 + k)
+    vs = 10 if kind == dt.SINGLE else 5 + 4 ** k
+    cases = [(0, [0, 0, 0, 0]), (0, [0]), (4096, [0, 4096]), (8192, [0, 8192]), (8193, [0, 4096, 8192, 8193]),
+             (16384, [0, 1, 4095, 4096, 8191, 8192, 12288, 16384])]
+    for n_ids, offs in cases:
+        offs = np.array(offs, np.int64)
+        ids = rng.integers(-3, vs + 5, n_ids).astype(np.int32)
+        print("decode edges kind=%d k=%d ids=%d rows=%d" % (kind, k, n_ids, len(offs) - 1), flush=True)
+        want, want_off = oracle.decode(kind, ids, offs, k=k)
+        d_ids = _dev(ids) if n_ids else torch.zeros(0, dtype=torch.int32, device="cuda")
+        out, out_off = dt.decode(v, d_ids, _dev(offs))
+        torch.cuda.synchronize()
+        assert dt.sync_status() == 0
+        assert np.array_equal(out_off.cpu().numpy(), want_off)
+        assert np.array_equal(out.cpu().numpy()[:want_off[-1]], want)
+
+
 @pytest.mark.parametrize("kind,k", [(dt.SINGLE, 1), (dt.KMER, 6), (dt.KMER, 8), (dt.KMER, 12)])
 def test_decode_many_tiles_look_back(kind, k):
     """Some 3M ids (hundreds of tiles of 4,096 ids, so
