@@ -1033,7 +1033,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the tokenizer shards by sequences with no collective on the hot path, "
-              "and multi-GPU runs are out of scope for this build (run with --gpus 1)", file=sys.stderr)
+              "so each GPU runs this same step on its share and there is nothing to measure across GPUs "
+              "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
